@@ -1,0 +1,588 @@
+/*
+ * jlb_oracle.c -- plain, slow, FP64 CPU oracle for the electromagnetic
+ * lattice Boltzmann (EM-LBM) solve of TM^z plane-wave scattering off a
+ * circular Janus cylinder, and for the time-averaged Maxwell-stress contour
+ * integral that gives drag, lift and torque.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this file's library.  It shares
+ * no code, header, table or helper with the HIP library under
+ * paper_2509_22308_amd/; the two are written independently from the paper.
+ *
+ * What it follows (arXiv 2509.22308, "Radiation Forces and Torques on Janus
+ * Cylinders"):
+ *   - Sec. II, Fig. (schematic): disk of radius a split by a diameter into
+ *     region II (eps_r1) and region III (PEC or eps_r2), vacuum outside.
+ *   - Sec. III, Eq. (LBGK equation): e_i(r+c_i,t+1) = 2 e_i^eq - e_i, same for h.
+ *   - Sec. III, Eq. (equilibrium distribution functions):
+ *       e_i^eq = (E - c_i x H)/6 (i != 0), e_0^eq = (eps_r - 1) E,
+ *       h_i^eq = (H + c_i x E)/6 (i != 0), h_0^eq = (mu_r - 1) H, mu_r = 1.
+ *     Fields are the moments: E = sum_i e_i / eps_r, H = sum_i h_i / mu_r.
+ *   - Sec. III: square domain, wave enters through the left edge, the other
+ *     edges are open ("first-order extrapolation").
+ *   - Sec. II.B, Eqs. (stress tensor average), (force), (torque): the
+ *     time-averaged Maxwell stress integrated on a closed contour.
+ *   - Sec. II.B: F0 = pi a eps0 E0^2 / 4, M0 = 2 F0 a.
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - lattice units dx = dt = 1, eps0 = mu0 = 1; the model's vacuum wave speed
+ *     is 1/3, so omega = 2 pi / (3 lambda), period T = 3 lambda steps;
+ *   - D3Q7 velocity set c_0 = 0, c_{1..6} = +x,-x,+y,-y,+z,-z; in 2-D the +-z
+ *     populations stream in place;
+ *   - source: the populations entering through the left edge are the
+ *     equilibria of the incident wave E_z = E_inc(n), H_y = -E_inc(n) (a ghost
+ *     column in equilibrium at time n), with E_inc(n) = E0 r(n) cos(omega n)
+ *     and r a raised-cosine ramp over the first ramp_periods periods (the
+ *     cosine phase leaves the ramped wave without a zero-frequency part);
+ *   - open edges (right, bottom, top): extrapolation of the scattered part.
+ *     The undisturbed incident wave on the lattice, I, is y-uniform; it is
+ *     carried by a one-row companion lattice (the "strip") stepped with the
+ *     same update, fed by the same source and closed on the right by zero
+ *     entering populations (the incident wave only moves right).  The
+ *     population entering a boundary cell x_b is
+ *       f_q(x_b, n+1) = I_q(ghost, n) + (1 - delta) [f*_q(x_b, n) - I_q(x_b, n)]
+ *     with delta = 1/20: zero-gradient (first order) for the scattered part,
+ *     relaxed by delta so that non-radiating static fields around a PEC body
+ *     are not fed by the edges.  At the right edge I_q = 0; at the bottom and
+ *     top I_q(ghost) = I_q(x_b) = strip value in the same column;
+ *   - PEC: link-wise reflection with the wall half-way along the link;
+ *     electric components tangential to the wall and the magnetic component
+ *     normal to it are reflected with a sign change, the others without;
+ *     PEC cells carry no populations and report zero fields;
+ *   - staircase geometry on node coordinates, centre ((nx-1)/2, (ny-1)/2),
+ *     inside when |d|^2 <= a^2, region II on the side of
+ *     n_II = (-sin phi0, -cos phi0) when d.n_II > 1e-9, otherwise region III;
+ *   - contour: circle of radius a + offset, N_c midpoint samples, bilinear
+ *     field interpolation, uniform weights; the time average is taken over
+ *     the last avg_periods * T steps using the fields at the end of each step.
+ *
+ * Two state modes:
+ *   literal (1): 7 velocities x 3-vector e_i and h_i, i.e. 42 scalars per
+ *                cell, exactly the printed equations;
+ *   reduced (0): the 11 scalars per cell that TM^z with mu_r = 1 leaves
+ *                independent (see reduced_* below).
+ * The test-suite checks that both modes agree.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_E_ARG -1
+#define ORC_E_GEOMETRY -2
+#define ORC_E_OOM -3
+
+enum { MAT_VACUUM = 0, MAT_REGION2 = 1, MAT_REGION3 = 2, MAT_PEC = 3 };
+
+typedef struct {
+    int32_t nx, ny;
+    double radius;
+    double cx, cy;            /* NaN selects the grid centre */
+    int32_t kind;             /* 0 homogeneous (eps1), 1 dielectric Janus, 2 metallo-dielectric Janus */
+    double eps1, eps2;
+    double phi0;              /* radians */
+    double wavelength;        /* lambda in cells; 3*lambda must be an integer */
+    double e0;                /* incident amplitude */
+    int64_t steps;
+    int32_t avg_periods;
+    int32_t ramp_periods;
+    double contour_offset;
+    int32_t contour_points;   /* 0 selects 8*ceil(2*pi*R_c/8) */
+    int32_t boundary;         /* 0 open edges with the left-edge source, 1 periodic without source,
+                                 2 (test harness) open in x with the source, periodic in y */
+    int32_t literal;          /* 1 literal 42-scalar populations, 0 reduced 11 */
+    int32_t threads;          /* OpenMP threads, <= 0 selects 1 */
+} orc_params;
+
+typedef struct {
+    double fx, fy, tz;              /* F~x, F~y, M~z */
+    double fx_raw, fy_raw, tz_raw;  /* per unit length, lattice units */
+    double energy_final;            /* sum over cells of (eps Ez^2 + Hx^2 + Hy^2)/2 */
+    int64_t window_steps;           /* number of time samples in the average */
+    int32_t contour_points;
+    int32_t pad;
+} orc_result;
+
+/* ------------------------------------------------------------------------ */
+/* Geometry (Sec. II, Fig. schematic)                                        */
+/* ------------------------------------------------------------------------ */
+
+static void centre_of(const orc_params *p, double *cx, double *cy)
+{
+    *cx = isnan(p->cx) ? 0.5 * (p->nx - 1) : p->cx;
+    *cy = isnan(p->cy) ? 0.5 * (p->ny - 1) : p->cy;
+}
+
+int orc_mask(const orc_params *p, uint8_t *mat)
+{
+    if (!p || !mat || p->nx < 1 || p->ny < 1) return ORC_E_ARG;
+    double cx, cy;
+    centre_of(p, &cx, &cy);
+    double sp = sin(p->phi0), cp = cos(p->phi0);
+    for (int j = 0; j < p->ny; ++j) {
+        for (int i = 0; i < p->nx; ++i) {
+            double dx = i - cx, dy = j - cy;
+            uint8_t m = MAT_VACUUM;
+            if (dx * dx + dy * dy <= p->radius * p->radius) {
+                if (p->kind == 0) {
+                    m = MAT_REGION2;
+                } else {
+                    double s = -dx * sp - dy * cp;   /* signed distance towards region II */
+                    if (s > 1e-9) m = MAT_REGION2;
+                    else m = (p->kind == 1) ? MAT_REGION3 : MAT_PEC;
+                }
+            }
+            mat[(size_t)j * p->nx + i] = m;
+        }
+    }
+    return ORC_OK;
+}
+
+static double eps_of(const orc_params *p, uint8_t m)
+{
+    if (m == MAT_REGION2) return p->eps1;
+    if (m == MAT_REGION3) return p->eps2;
+    return 1.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Incident wave and its ramp (Sec. III: wave through the left boundary)     */
+/* ------------------------------------------------------------------------ */
+
+static double incident_ez(const orc_params *p, int64_t n)
+{
+    double period = 3.0 * p->wavelength;
+    double omega = 2.0 * M_PI / period;
+    double ramp = 1.0;
+    double tr = (double)p->ramp_periods * period;
+    if (p->ramp_periods > 0 && (double)n < tr) ramp = 0.5 * (1.0 - cos(M_PI * (double)n / tr));
+    return p->e0 * ramp * cos(omega * (double)n);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Contour samples (Sec. II.B, Eqs. force and torque)                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int n;
+    double rc;
+    double *nxv, *nyv;       /* outward normal */
+    double *px, *py;         /* sample position */
+} contour_t;
+
+static int contour_build(const orc_params *p, contour_t *c)
+{
+    double cx, cy;
+    centre_of(p, &cx, &cy);
+    c->rc = p->radius + p->contour_offset;
+    c->n = p->contour_points > 0 ? p->contour_points : 8 * (int)ceil(2.0 * M_PI * c->rc / 8.0);
+    c->nxv = malloc(sizeof(double) * c->n);
+    c->nyv = malloc(sizeof(double) * c->n);
+    c->px = malloc(sizeof(double) * c->n);
+    c->py = malloc(sizeof(double) * c->n);
+    if (!c->nxv || !c->nyv || !c->px || !c->py) return ORC_E_OOM;
+    for (int k = 0; k < c->n; ++k) {
+        double th = 2.0 * M_PI * (k + 0.5) / c->n;
+        c->nxv[k] = cos(th);
+        c->nyv[k] = sin(th);
+        c->px[k] = cx + c->rc * c->nxv[k];
+        c->py[k] = cy + c->rc * c->nyv[k];
+        if (c->px[k] < 0.0 || c->py[k] < 0.0 || c->px[k] >= p->nx - 1 || c->py[k] >= p->ny - 1)
+            return ORC_E_GEOMETRY;
+    }
+    return ORC_OK;
+}
+
+static void contour_free(contour_t *c)
+{
+    free(c->nxv); free(c->nyv); free(c->px); free(c->py);
+}
+
+/* Bilinear value of a node field at (px, py). */
+static double bilinear(const double *f, int nx, double px, double py)
+{
+    int i0 = (int)floor(px), j0 = (int)floor(py);
+    double fx = px - i0, fy = py - j0;
+    const double *r0 = f + (size_t)j0 * nx + i0;
+    const double *r1 = r0 + nx;
+    return (1.0 - fx) * (1.0 - fy) * r0[0] + fx * (1.0 - fy) * r0[1]
+         + (1.0 - fx) * fy * r1[0] + fx * fy * r1[1];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reduced 11-population state.                                              */
+/*                                                                           */
+/* TM^z keeps E = (0,0,Ez), H = (Hx,Hy,0).  With mu_r = 1, h_0 = 0 for ever. */
+/* The +-z populations stream in place, so they merge with the rest one      */
+/* ("_r" below).  Along each in-plane link one combination of an e and an h  */
+/* population has zero equilibrium and stays zero from a zero start:         */
+/*   hy_{+x} = -e_{+x}, hy_{-x} = e_{-x}, hx_{+y} = e_{+y}, hx_{-y} = -e_{-y}. */
+/* What is left:                                                             */
+/*   0 e_r   1 e_{+x}  2 e_{-x}  3 e_{+y}  4 e_{-y}                          */
+/*   5 hx_r  6 hx_{+x} 7 hx_{-x}                                             */
+/*   8 hy_r  9 hy_{+y} 10 hy_{-y}                                            */
+/* Equilibria from the printed ones:                                          */
+/*   e_{+-x} = (Ez -+ Hy)/6, e_{+-y} = (Ez +- Hx)/6, e_r = (eps - 2/3) Ez,    */
+/*   hx_{+-x} = Hx/6, hy_{+-y} = Hy/6, hx_r = Hx/3, hy_r = Hy/3.             */
+/* ------------------------------------------------------------------------ */
+
+#define NPOP 11
+/* how a step treats the domain edges */
+enum { EDGE_OPEN = 0, EDGE_PERIODIC = 1, EDGE_STRIP = 2, EDGE_XOPEN = 3 };
+#define OPEN_DELTA (1.0 / 20.0)
+static const int pop_cx[NPOP] = {0, 1, -1, 0, 0, 0, 1, -1, 0, 0, 0};
+static const int pop_cy[NPOP] = {0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1};
+static const int pop_opp[NPOP] = {0, 2, 1, 4, 3, 5, 7, 6, 8, 10, 9};
+
+static void reduced_moments(const double f[NPOP], double eps, double *ez, double *hx, double *hy)
+{
+    double dz = f[0] + f[1] + f[2] + (f[3] + f[4]);
+    *ez = dz / eps;
+    *hx = f[5] + f[6] + f[7] + (f[3] - f[4]);
+    *hy = f[8] + (f[9] + f[10]) + (f[2] - f[1]);
+}
+
+static void reduced_equilibrium(double eps, double ez, double hx, double hy, double q[NPOP])
+{
+    q[0] = (eps - 2.0 / 3.0) * ez;
+    q[1] = (ez - hy) / 6.0;
+    q[2] = (ez + hy) / 6.0;
+    q[3] = (ez + hx) / 6.0;
+    q[4] = (ez - hx) / 6.0;
+    q[5] = hx / 3.0;
+    q[6] = hx / 6.0;
+    q[7] = hx / 6.0;
+    q[8] = hy / 3.0;
+    q[9] = hy / 6.0;
+    q[10] = hy / 6.0;
+}
+
+/* One time step: post-collision state src (time n) -> post-collision dst
+ * (time n+1); fields at n+1 go to ez/hx/hy.  `strip` is the incident-wave
+ * row at time n (EDGE_OPEN only).  In EDGE_STRIP mode the grid is the one-row
+ * companion lattice: +-y populations stay in their cell (the row is uniform
+ * in y) and nothing enters through the right edge. */
+static void reduced_step(const orc_params *p, int edges, int nx, int ny, const uint8_t *mat,
+                         const double *src, double *dst, const double *strip,
+                         double *ez, double *hx, double *hy, double einc)
+{
+    const size_t plane = (size_t)nx * ny;
+    /* incident-wave equilibria of the populations entering at the left edge */
+    double inc[NPOP];
+    reduced_equilibrium(1.0, einc, 0.0, -einc, inc);
+#pragma omp parallel for schedule(static) num_threads(p->threads > 0 ? p->threads : 1)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            size_t c = (size_t)j * nx + i;
+            if (mat && mat[c] == MAT_PEC) {
+                for (int q = 0; q < NPOP; ++q) dst[q * plane + c] = 0.0;
+                ez[c] = hx[c] = hy[c] = 0.0;
+                continue;
+            }
+            double f[NPOP];
+            for (int q = 0; q < NPOP; ++q) {
+                int si = i - pop_cx[q], sj = j - pop_cy[q];
+                if (pop_cx[q] == 0 && pop_cy[q] == 0) {
+                    f[q] = src[q * plane + c];
+                    continue;
+                }
+                if (edges == EDGE_STRIP && pop_cx[q] == 0) sj = j;    /* uniform in y */
+                if (edges == EDGE_XOPEN) sj = (sj + ny) % ny;          /* test harness: periodic in y */
+                int outside = si < 0 || si >= nx || sj < 0 || sj >= ny;
+                if (outside && edges == EDGE_PERIODIC) {
+                    si = (si + nx) % nx;
+                    sj = (sj + ny) % ny;
+                    outside = 0;
+                }
+                if (outside) {
+                    double own = src[q * plane + c];
+                    if (pop_cx[q] == 1) f[q] = inc[q];                 /* left edge: the source */
+                    else if (edges == EDGE_STRIP) f[q] = 0.0;          /* strip: right edge */
+                    else if (pop_cx[q] == -1) f[q] = (1.0 - OPEN_DELTA) * own;            /* right */
+                    else f[q] = (1.0 - OPEN_DELTA) * own + OPEN_DELTA * strip[q * (size_t)nx + i]; /* top, bottom */
+                } else {
+                    size_t s = (size_t)sj * nx + si;
+                    if (mat && mat[s] == MAT_PEC) f[q] = -src[pop_opp[q] * plane + c];
+                    else f[q] = src[q * plane + s];
+                }
+            }
+            double eps = mat ? eps_of(p, mat[c]) : 1.0;
+            double e, a, b;
+            reduced_moments(f, eps, &e, &a, &b);
+            double eq[NPOP];
+            reduced_equilibrium(eps, e, a, b, eq);
+            for (int q = 0; q < NPOP; ++q) dst[q * plane + c] = 2.0 * eq[q] - f[q];
+            ez[c] = e; hx[c] = a; hy[c] = b;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Literal state: e_i and h_i are 3-vectors for the 7 D3Q7 velocities.       */
+/* Layout [field e/h][velocity i][component][cell].                          */
+/* ------------------------------------------------------------------------ */
+
+static const int lit_c[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+static const int lit_opp[7] = {0, 2, 1, 4, 3, 6, 5};
+
+static void cross3(const double a[3], const double b[3], double r[3])
+{
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Printed equilibria for velocity i at permittivity eps (mu_r = 1). */
+static void literal_equilibrium(int i, double eps, const double E[3], const double H[3], double eeq[3], double heq[3])
+{
+    if (i == 0) {
+        for (int k = 0; k < 3; ++k) { eeq[k] = (eps - 1.0) * E[k]; heq[k] = 0.0 * H[k]; }
+        return;
+    }
+    double c[3] = {lit_c[i][0], lit_c[i][1], lit_c[i][2]};
+    double cxh[3], cxe[3];
+    cross3(c, H, cxh);
+    cross3(c, E, cxe);
+    for (int k = 0; k < 3; ++k) {
+        eeq[k] = (E[k] - cxh[k]) / 6.0;
+        heq[k] = (H[k] + cxe[k]) / 6.0;
+    }
+}
+
+#define LIDX(field, i, k) ((((size_t)(field) * 7 + (i)) * 3 + (k)) * plane)
+
+static void literal_step(const orc_params *p, int edges, int nx, int ny, const uint8_t *mat,
+                         const double *src, double *dst, const double *strip,
+                         double *ez, double *hx, double *hy, double einc)
+{
+    const size_t plane = (size_t)nx * ny;
+    const size_t splane = (size_t)nx;   /* the strip is one row */
+    double Einc[3] = {0.0, 0.0, einc}, Hinc[3] = {0.0, -einc, 0.0};
+#pragma omp parallel for schedule(static) num_threads(p->threads > 0 ? p->threads : 1)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            size_t c = (size_t)j * nx + i;
+            if (mat && mat[c] == MAT_PEC) {
+                for (size_t q = 0; q < 42; ++q) dst[q * plane + c] = 0.0;
+                ez[c] = hx[c] = hy[c] = 0.0;
+                continue;
+            }
+            double e[7][3], h[7][3];
+            for (int v = 0; v < 7; ++v) {
+                int si = i - lit_c[v][0], sj = j - lit_c[v][1];
+                int moves = lit_c[v][0] != 0 || lit_c[v][1] != 0;
+                if (edges == EDGE_STRIP && lit_c[v][0] == 0) moves = 0;   /* uniform in y */
+                if (!moves) {
+                    for (int k = 0; k < 3; ++k) {
+                        e[v][k] = src[LIDX(0, v, k) + c];
+                        h[v][k] = src[LIDX(1, v, k) + c];
+                    }
+                    continue;
+                }
+                if (edges == EDGE_XOPEN) sj = (sj + ny) % ny;          /* test harness: periodic in y */
+                int outside = si < 0 || si >= nx || sj < 0 || sj >= ny;
+                if (outside && edges == EDGE_PERIODIC) {
+                    si = (si + nx) % nx;
+                    sj = (sj + ny) % ny;
+                    outside = 0;
+                }
+                if (outside) {
+                    if (lit_c[v][0] == 1) {
+                        double eeq[3], heq[3];
+                        literal_equilibrium(v, 1.0, Einc, Hinc, eeq, heq);
+                        for (int k = 0; k < 3; ++k) { e[v][k] = eeq[k]; h[v][k] = heq[k]; }
+                    } else {
+                        for (int k = 0; k < 3; ++k) {
+                            double eo = src[LIDX(0, v, k) + c], ho = src[LIDX(1, v, k) + c];
+                            if (edges == EDGE_STRIP) {
+                                e[v][k] = 0.0; h[v][k] = 0.0;
+                            } else if (lit_c[v][0] == -1) {
+                                e[v][k] = (1.0 - OPEN_DELTA) * eo;
+                                h[v][k] = (1.0 - OPEN_DELTA) * ho;
+                            } else {
+                                size_t sc = (((size_t)0 * 7 + v) * 3 + k) * splane + i;
+                                size_t sh = (((size_t)1 * 7 + v) * 3 + k) * splane + i;
+                                e[v][k] = (1.0 - OPEN_DELTA) * eo + OPEN_DELTA * strip[sc];
+                                h[v][k] = (1.0 - OPEN_DELTA) * ho + OPEN_DELTA * strip[sh];
+                            }
+                        }
+                    }
+                    continue;
+                }
+                size_t s = (size_t)sj * nx + si;
+                if (mat && mat[s] == MAT_PEC) {
+                    /* wall normal along the link axis */
+                    int axis = lit_c[v][0] != 0 ? 0 : 1;
+                    int o = lit_opp[v];
+                    for (int k = 0; k < 3; ++k) {
+                        double se = (k == axis) ? 1.0 : -1.0;   /* E: tangential flips */
+                        double sh = (k == axis) ? -1.0 : 1.0;   /* H: normal flips */
+                        e[v][k] = se * src[LIDX(0, o, k) + c];
+                        h[v][k] = sh * src[LIDX(1, o, k) + c];
+                    }
+                } else {
+                    for (int k = 0; k < 3; ++k) {
+                        e[v][k] = src[LIDX(0, v, k) + s];
+                        h[v][k] = src[LIDX(1, v, k) + s];
+                    }
+                }
+            }
+            double eps = mat ? eps_of(p, mat[c]) : 1.0;
+            double E[3] = {0, 0, 0}, H[3] = {0, 0, 0};
+            for (int v = 0; v < 7; ++v)
+                for (int k = 0; k < 3; ++k) { E[k] += e[v][k]; H[k] += h[v][k]; }
+            for (int k = 0; k < 3; ++k) { E[k] /= eps; H[k] /= 1.0; }
+            for (int v = 0; v < 7; ++v) {
+                double eeq[3], heq[3];
+                literal_equilibrium(v, eps, E, H, eeq, heq);
+                for (int k = 0; k < 3; ++k) {
+                    dst[LIDX(0, v, k) + c] = 2.0 * eeq[k] - e[v][k];
+                    dst[LIDX(1, v, k) + c] = 2.0 * heq[k] - h[v][k];
+                }
+            }
+            ez[c] = E[2]; hx[c] = H[0]; hy[c] = H[1];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Full solve                                                                */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * orc_run: mask (or the caller's material map) -> zero state (or the caller's
+ * reduced state) -> time loop -> contour average -> forces.
+ *   mat_in       optional [ny][nx] material ids; NULL builds the mask
+ *   state_io     optional post-collision state, reduced [11][ny][nx] or
+ *                literal [2][7][3][ny][nx]: read as the state at time 0,
+ *                overwritten with the final one
+ *   ez, hx, hy   optional [ny][nx] outputs, fields after the last step
+ *   energy       optional [steps] output, W(n+1) after each step
+ *   acc          optional [N_c][4] output, time sums of Ez^2, Hx^2, Hy^2, HxHy
+ */
+int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
+            double *ez_out, double *hx_out, double *hy_out, double *energy,
+            double *acc_out, orc_result *res)
+{
+    if (!p || !res || p->nx < 1 || p->ny < 1 || p->steps < 0 || p->wavelength <= 0.0) return ORC_E_ARG;
+    const int nx = p->nx, ny = p->ny;
+    const size_t plane = (size_t)nx * ny;
+    const size_t nstate = (p->literal ? 42 : NPOP) * plane;
+    memset(res, 0, sizeof(*res));
+
+    uint8_t *mat = malloc(plane);
+    double *a = calloc(nstate, sizeof(double));
+    double *b = calloc(nstate, sizeof(double));
+    const size_t nstrip = (size_t)(p->literal ? 42 : NPOP) * nx;
+    double *sa = calloc(nstrip, sizeof(double));   /* incident-wave companion row */
+    double *sb = calloc(nstrip, sizeof(double));
+    double *sf = calloc((size_t)3 * nx, sizeof(double));
+    double *ez = calloc(plane, sizeof(double));
+    double *hx = calloc(plane, sizeof(double));
+    double *hy = calloc(plane, sizeof(double));
+    contour_t con = {0};
+    int rc = ORC_OK;
+    if (!mat || !a || !b || !ez || !hx || !hy || !sa || !sb || !sf) { rc = ORC_E_OOM; goto done; }
+    if (mat_in) memcpy(mat, mat_in, plane);
+    else orc_mask(p, mat);
+    if (state_io) memcpy(a, state_io, nstate * sizeof(double));
+
+    int64_t period = (int64_t)llround(3.0 * p->wavelength);
+    int64_t window = (int64_t)p->avg_periods * period;
+    int do_contour = p->boundary == 0 && window > 0;
+    double *acc = NULL;
+    if (do_contour) {
+        rc = contour_build(p, &con);
+        if (rc != ORC_OK) goto done;
+        acc = calloc((size_t)con.n * 4, sizeof(double));
+        if (!acc) { rc = ORC_E_OOM; goto done; }
+    }
+
+    for (int64_t n = 0; n < p->steps; ++n) {
+        double einc = p->boundary != 1 ? incident_ez(p, n) : 0.0;
+        int edges = p->boundary == 0 ? EDGE_OPEN : p->boundary == 1 ? EDGE_PERIODIC : EDGE_XOPEN;
+        if (p->literal) literal_step(p, edges, nx, ny, mat, a, b, sa, ez, hx, hy, einc);
+        else reduced_step(p, edges, nx, ny, mat, a, b, sa, ez, hx, hy, einc);
+        if (edges == EDGE_OPEN) {
+            double *sez = sf, *shx = sf + nx, *shy = sf + 2 * (size_t)nx;
+            if (p->literal) literal_step(p, EDGE_STRIP, nx, 1, NULL, sa, sb, NULL, sez, shx, shy, einc);
+            else reduced_step(p, EDGE_STRIP, nx, 1, NULL, sa, sb, NULL, sez, shx, shy, einc);
+            double *u = sa; sa = sb; sb = u;
+        }
+        double *t = a; a = b; b = t;
+        if (do_contour && n + 1 > p->steps - window) {
+            for (int k = 0; k < con.n; ++k) {
+                double e = bilinear(ez, nx, con.px[k], con.py[k]);
+                double u = bilinear(hx, nx, con.px[k], con.py[k]);
+                double v = bilinear(hy, nx, con.px[k], con.py[k]);
+                acc[4 * k + 0] += e * e;
+                acc[4 * k + 1] += u * u;
+                acc[4 * k + 2] += v * v;
+                acc[4 * k + 3] += u * v;
+            }
+            res->window_steps += 1;
+        }
+        if (energy) {
+            double w = 0.0;
+            for (size_t c = 0; c < plane; ++c)
+                w += 0.5 * (eps_of(p, mat[c]) * ez[c] * ez[c] + hx[c] * hx[c] + hy[c] * hy[c]);
+            energy[n] = w;
+        }
+    }
+
+    {
+        double w = 0.0;
+        for (size_t c = 0; c < plane; ++c)
+            w += 0.5 * (eps_of(p, mat[c]) * ez[c] * ez[c] + hx[c] * hx[c] + hy[c] * hy[c]);
+        res->energy_final = w;
+    }
+
+    if (do_contour && res->window_steps > 0) {
+        /* time-averaged stress T = E E + H H - (|E|^2 + |H|^2) I / 2 for
+         * E = Ez z, H = (Hx, Hy, 0); in-plane force F = sum w T.n,
+         * torque M_z = sum w (r x T.n)_z with r = R_c n. */
+        double inv = 1.0 / (double)res->window_steps;
+        double w = 2.0 * M_PI * con.rc / con.n;
+        double fx = 0.0, fy = 0.0, tz = 0.0;
+        for (int k = 0; k < con.n; ++k) {
+            double e2 = acc[4 * k + 0] * inv, x2 = acc[4 * k + 1] * inv;
+            double y2 = acc[4 * k + 2] * inv, xy = acc[4 * k + 3] * inv;
+            double txx = 0.5 * (x2 - y2 - e2);
+            double tyy = 0.5 * (y2 - x2 - e2);
+            double txy = xy;
+            double nxk = con.nxv[k], nyk = con.nyv[k];
+            double tx = txx * nxk + txy * nyk;
+            double ty = txy * nxk + tyy * nyk;
+            fx += w * tx;
+            fy += w * ty;
+            tz += w * con.rc * (nxk * ty - nyk * tx);
+        }
+        double f0 = M_PI * p->radius * p->e0 * p->e0 / 4.0;
+        double m0 = 2.0 * f0 * p->radius;
+        res->fx_raw = fx; res->fy_raw = fy; res->tz_raw = tz;
+        res->fx = fx / f0; res->fy = fy / f0; res->tz = tz / m0;
+        res->contour_points = con.n;
+        if (acc_out) memcpy(acc_out, acc, sizeof(double) * 4 * con.n);
+    }
+    if (ez_out) memcpy(ez_out, ez, plane * sizeof(double));
+    if (hx_out) memcpy(hx_out, hx, plane * sizeof(double));
+    if (hy_out) memcpy(hy_out, hy, plane * sizeof(double));
+    if (state_io) memcpy(state_io, a, nstate * sizeof(double));
+    free(acc);
+
+done:
+    contour_free(&con);
+    free(mat); free(a); free(b); free(ez); free(hx); free(hy); free(sa); free(sb); free(sf);
+    return rc;
+}
+
+/* Number of contour samples the oracle uses for these parameters. */
+int orc_contour_points(const orc_params *p)
+{
+    double rc = p->radius + p->contour_offset;
+    return p->contour_points > 0 ? p->contour_points : 8 * (int)ceil(2.0 * M_PI * rc / 8.0);
+}
