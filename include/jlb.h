@@ -1,0 +1,227 @@
+/*
+ * jlb.h -- C ABI of the MI355X (gfx950) library for the electromagnetic
+ * lattice Boltzmann solve of TM^z plane-wave scattering off a circular Janus
+ * cylinder and the radiation force and torque that follow from it.
+ *
+ * Method (arXiv 2509.22308):
+ *   Sec. II, Fig. (schematic)   cylinder of radius a at the domain centre,
+ *                               split by a diameter into region II (eps_r1)
+ *                               and region III (PEC or eps_r2), vacuum outside;
+ *                               plane wave entering from the left, interface
+ *                               angle phi0.
+ *   Sec. III, Eqs. (LBGK equation), (equilibrium distribution functions)
+ *                               D3Q7 electric and magnetic populations,
+ *                               tau = 1/2 update f -> 2 f^eq - f, fields as
+ *                               moments, per-cell permittivity, mu_r = 1.
+ *   Sec. II.B, Eqs. (stress tensor average), (force), (torque)
+ *                               time-averaged Maxwell stress on a closed
+ *                               contour around the body -> F_x, F_y, M_z,
+ *                               normalised by F0 = pi a eps0 E0^2 / 4 and
+ *                               M0 = 2 F0 a.
+ *
+ * Lattice units: dx = dt = 1, eps0 = mu0 = 1.  The model's vacuum wave speed
+ * is 1/3 cell per step, so the angular frequency is omega = 2 pi / (3 lambda)
+ * and the period is T = 3 lambda steps; 3 lambda must be an integer.
+ *
+ * Conventions shared by every call:
+ *   - every function returns int: JLB_OK (0) or a negative JLB_E_* code; the
+ *     calling thread's jlb_last_error() then describes the failure;
+ *   - no C++ exception crosses this boundary;
+ *   - 2-D arrays are row-major [ny][nx] with x (the direction of incidence)
+ *     fastest;
+ *   - "device" pointers are HIP device allocations on the current device,
+ *     "host" pointers ordinary host memory;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *     calls order their work after prior work on it and return only when
+ *     their results are complete (the solve is synchronous for the host).
+ */
+#ifndef JLB_H
+#define JLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JLB_OK 0
+#define JLB_E_ARG -1          /* a parameter is out of range or a pointer is missing          */
+#define JLB_E_GEOMETRY -2     /* disk + contour + margin do not fit inside the domain         */
+#define JLB_E_RESOLUTION -3   /* lambda / sqrt(eps_max) < 10 (Sec. III) without the override  */
+#define JLB_E_WINDOW -4       /* steps < (avg_periods + ramp_periods) * T                      */
+#define JLB_E_OOM -5          /* workspace too small or device allocation failed              */
+#define JLB_E_DEVICE -6       /* a HIP runtime call failed                                     */
+#define JLB_E_NONFINITE -7    /* the forces came out NaN or infinite                           */
+#define JLB_E_ADMISSION -8    /* engine: the request can never fit the engine's memory budget */
+#define JLB_E_STATE -9        /* engine: unknown ticket or call out of order                   */
+
+/* Sec. II: body kinds. */
+typedef enum {
+    JLB_HOMOGENEOUS = 0,              /* whole disk eps1                                  */
+    JLB_DIELECTRIC_JANUS = 1,         /* region II eps1, region III eps2                  */
+    JLB_METALLO_DIELECTRIC_JANUS = 2  /* region II eps1, region III perfect conductor     */
+} jlb_kind;
+
+/* Storage and arithmetic of the populations. */
+typedef enum {
+    JLB_FP64 = 0,  /* 11 populations per cell in FP64, FP64 arithmetic            */
+    JLB_FP32 = 1,  /* fields (Ez, Hx, Hy) in FP32 + 8 moving-population deviations
+                      from equilibrium in FP32; FP32 arithmetic                    */
+    JLB_BF16 = 2   /* as JLB_FP32 but the 8 deviations stored in bfloat16         */
+} jlb_precision;
+
+/* jlb_problem.flags */
+#define JLB_F_ALLOW_UNDERRESOLVED 1u  /* skip the lambda / sqrt(eps_max) >= 10 check         */
+#define JLB_F_NO_GRAPH 2u             /* launch every step directly instead of replaying a
+                                         captured hipGraph of whole periods                  */
+
+/*
+ * One scattering problem (Sec. II; Sec. III for the domain and the source).
+ * The cylinder centre is ((nx-1)/2, (ny-1)/2) in node coordinates.  A node
+ * (i, j) with d = (i - cx, j - cy) is inside when |d|^2 <= a^2; inside nodes
+ * with d . (-sin phi0, -cos phi0) > 1e-9 are region II, the rest region III.
+ * With this lab frame phi0 = pi/2 puts region II towards the incoming wave
+ * and phi0 = 0 puts region III on the +y side, as in Sec. IV.A and App. A.
+ */
+typedef struct {
+    int32_t nx, ny;          /* grid nodes, each >= 16                                    */
+    int32_t kind;            /* jlb_kind                                                  */
+    int32_t precision;       /* jlb_precision                                             */
+    double radius;           /* a, cells, > 0                                             */
+    double eps1, eps2;       /* relative permittivities of regions II and III, >= 1      */
+    double phi0;             /* interface angle, radians                                  */
+    double wavelength;       /* lambda, cells; 3 * lambda integer                         */
+    double e0;               /* incident amplitude E0 (> 0)                               */
+    int64_t steps;           /* lattice time steps                                        */
+    int32_t avg_periods;     /* average the stress over the last avg_periods * T steps    */
+    int32_t ramp_periods;    /* raised-cosine source ramp length in periods (>= 0)        */
+    double contour_offset;   /* contour radius R_c = radius + contour_offset (> 0)        */
+    int32_t contour_points;  /* samples on the contour; 0 selects 8 * ceil(2 pi R_c / 8)  */
+    uint32_t flags;          /* JLB_F_*                                                   */
+} jlb_problem;
+
+/* Outcome of one solve (host struct, written by the library). */
+typedef struct {
+    double fx, fy, tz;              /* F~x, F~y, M~z (Sec. II.B normalisation)                */
+    double fx_raw, fy_raw, tz_raw;  /* per unit length in lattice units                       */
+    double loop_ms;                 /* HIP-event time of the time-stepping loop on the device */
+    double total_ms;                /* host wall time of the whole call                       */
+    int64_t steps_done;
+    int64_t window_steps;           /* time samples in the stress average                     */
+    int32_t contour_points;
+    int32_t graph_used;             /* 1 when whole periods were replayed from a hipGraph     */
+    int64_t bytes_per_step;         /* algorithmic HBM bytes of one lattice step              */
+} jlb_result;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int jlb_version(void);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *jlb_last_error(void);
+
+/*
+ * Checks a problem without touching the device: argument ranges, geometry
+ * (disk, contour and a 4-cell margin inside the grid, contour outside the
+ * disk), resolution (Sec. III: lambda / sqrt(eps_max) >= 10 unless
+ * JLB_F_ALLOW_UNDERRESOLVED) and the averaging window.  Returns JLB_OK or the
+ * JLB_E_* code of the first violation.
+ */
+int jlb_validate(const jlb_problem *prob);
+
+/*
+ * Device workspace one solve of `prob` needs, in bytes (host out-pointer).
+ * The grid carries one extra row for the incident-wave companion lattice and
+ * pads rows to a multiple of 64 nodes.
+ */
+int jlb_workspace_size(const jlb_problem *prob, size_t *bytes);
+
+/*
+ * Material map of `prob` (Sec. II geometry; staircase on the nodes) into the
+ * caller's host array mat[ny][nx]: 0 vacuum, 1 region II, 2 region III
+ * dielectric, 3 perfect conductor.
+ */
+int jlb_material_map(const jlb_problem *prob, uint8_t *mat);
+
+/*
+ * Runs one solve on the device (Sec. III time stepping, Sec. II.B stress
+ * average and contour integral) and writes the forces to *res (host).
+ *   workspace        device buffer of at least jlb_workspace_size() bytes,
+ *                    owned by the caller and not used by others during the
+ *                    call; NULL makes the library allocate and free its own
+ *   ez, hx, hy       optional device arrays [ny][nx] of double: the fields
+ *                    after the last step (zero on conductor nodes), written
+ *                    in FP64 whatever the storage precision; NULL to skip
+ *   energy           optional device array [steps] of double: the field
+ *                    energy sum (eps Ez^2 + Hx^2 + Hy^2)/2 after each step;
+ *                    NULL to skip (tracing slows the solve)
+ * Errors: any code of jlb_validate, JLB_E_OOM, JLB_E_DEVICE, and
+ * JLB_E_NONFINITE when the forces are not finite (e.g. an unstable setup).
+ */
+int jlb_solve(const jlb_problem *prob, void *workspace, size_t workspace_bytes, jlb_result *res,
+              double *ez, double *hx, double *hy, double *energy, void *stream);
+
+/*
+ * Times `launches` back-to-back launches of the fused lattice-step kernel
+ * of `prob` (no contour work), on `stream`, between two HIP events, after
+ * `warmup` untimed launches; *ms_per_launch (host) receives the mean.  The
+ * workspace is as for jlb_solve (NULL allocates).  The state starts at zero
+ * and the source is on, so the kernel takes the same paths as in a solve.
+ */
+int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
+                         int32_t launches, double *ms_per_launch, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched engine: many independent solves resident on one device, stepped  */
+/* together by one launch per lattice step over a work list of tiles drawn   */
+/* from every admitted solve (Sec. IV design maps are sweeps of independent  */
+/* solves).  Requests are admitted while their device footprint fits the    */
+/* engine's byte budget; finished solves release their memory, which admits  */
+/* waiting requests at the next step boundary (continuous batching).         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct jlb_engine jlb_engine;
+
+/* Request status reported by jlb_engine_poll. */
+#define JLB_REQ_QUEUED 0
+#define JLB_REQ_RUNNING 1
+#define JLB_REQ_DONE 2
+#define JLB_REQ_FAILED 3
+#define JLB_REQ_CANCELLED 4
+
+/*
+ * Creates an engine on the current device.
+ *   budget_bytes  device bytes the engine may hold for admitted solves
+ *   max_slots     most solves resident at once (>= 1)
+ *   stream        stream the engine launches on (NULL = a private one)
+ * *out receives the handle (host pointer).
+ */
+int jlb_engine_create(size_t budget_bytes, int32_t max_slots, void *stream, jlb_engine **out);
+
+/* Queues a problem (validated now; JLB_E_ADMISSION if it can never fit the
+ * budget); *ticket (host) receives its id.  Never blocks on the device. */
+int jlb_engine_submit(jlb_engine *eng, const jlb_problem *prob, uint64_t *ticket);
+
+/* Admits queued requests that fit, then advances every resident solve by up to
+ * `steps` lattice steps (one batched launch per step), retiring solves that
+ * finish.  *active (host, optional) receives the resident count afterwards. */
+int jlb_engine_run(jlb_engine *eng, int64_t steps, int32_t *active);
+
+/* Status of a ticket: *status one of JLB_REQ_*; when DONE, *res holds the
+ * outcome (res may be NULL). */
+int jlb_engine_poll(jlb_engine *eng, uint64_t ticket, int32_t *status, jlb_result *res);
+
+/* Cancels a queued or resident request and frees its memory. */
+int jlb_engine_cancel(jlb_engine *eng, uint64_t ticket);
+
+/* Counts of queued, resident and finished requests and device bytes in use. */
+int jlb_engine_stats(jlb_engine *eng, int32_t *queued, int32_t *resident, int32_t *finished, size_t *bytes_in_use);
+
+/* Releases every resource of the engine. */
+int jlb_engine_destroy(jlb_engine *eng);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JLB_H */

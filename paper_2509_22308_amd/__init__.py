@@ -1,0 +1,236 @@
+"""Python binding of libjlb, the gfx950 library for the Janus-cylinder
+electromagnetic lattice Boltzmann solve (arXiv 2509.22308).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libjlb.so``.  The functions keep the C names of
+``include/jlb.h``; PyTorch provides device memory (workspace, field arrays)
+and the stream.  Importing this module never loads the library; the first
+call does, and raises if it has not been built (``python
+paper_2509_22308_amd/build.py``).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjlb.so")
+
+JLB_OK = 0
+ERRORS = {-1: "JLB_E_ARG", -2: "JLB_E_GEOMETRY", -3: "JLB_E_RESOLUTION", -4: "JLB_E_WINDOW", -5: "JLB_E_OOM",
+          -6: "JLB_E_DEVICE", -7: "JLB_E_NONFINITE", -8: "JLB_E_ADMISSION", -9: "JLB_E_STATE"}
+KINDS = {"homogeneous": 0, "dielectric_janus": 1, "metallo_dielectric_janus": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+JLB_F_ALLOW_UNDERRESOLVED = 1
+JLB_F_NO_GRAPH = 2
+REQ_STATUS = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
+
+
+class jlb_problem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("kind", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("radius", ctypes.c_double), ("eps1", ctypes.c_double), ("eps2", ctypes.c_double),
+        ("phi0", ctypes.c_double), ("wavelength", ctypes.c_double), ("e0", ctypes.c_double),
+        ("steps", ctypes.c_int64), ("avg_periods", ctypes.c_int32), ("ramp_periods", ctypes.c_int32),
+        ("contour_offset", ctypes.c_double), ("contour_points", ctypes.c_int32), ("flags", ctypes.c_uint32),
+    ]
+
+
+class jlb_result(ctypes.Structure):
+    _fields_ = [
+        ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("tz", ctypes.c_double),
+        ("fx_raw", ctypes.c_double), ("fy_raw", ctypes.c_double), ("tz_raw", ctypes.c_double),
+        ("loop_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+        ("steps_done", ctypes.c_int64), ("window_steps", ctypes.c_int64),
+        ("contour_points", ctypes.c_int32), ("graph_used", ctypes.c_int32),
+        ("bytes_per_step", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class JlbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+
+
+def load():
+    """Load libjlb.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run python paper_2509_22308_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "jlb_version": ([], ctypes.c_int),
+            "jlb_last_error": ([], ctypes.c_char_p),
+            "jlb_validate": ([_P(jlb_problem)], ctypes.c_int),
+            "jlb_workspace_size": ([_P(jlb_problem), _P(ctypes.c_size_t)], ctypes.c_int),
+            "jlb_material_map": ([_P(jlb_problem), _vp], ctypes.c_int),
+            "jlb_solve": ([_P(jlb_problem), _vp, ctypes.c_size_t, _P(jlb_result), _vp, _vp, _vp, _vp, _vp],
+                          ctypes.c_int),
+            "jlb_time_step_kernel": ([_P(jlb_problem), _vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                      _P(ctypes.c_double), _vp], ctypes.c_int),
+            "jlb_engine_create": ([ctypes.c_size_t, ctypes.c_int32, _vp, _P(_vp)], ctypes.c_int),
+            "jlb_engine_submit": ([_vp, _P(jlb_problem), _P(ctypes.c_uint64)], ctypes.c_int),
+            "jlb_engine_run": ([_vp, ctypes.c_int64, _P(ctypes.c_int32)], ctypes.c_int),
+            "jlb_engine_poll": ([_vp, ctypes.c_uint64, _P(ctypes.c_int32), _P(jlb_result)], ctypes.c_int),
+            "jlb_engine_cancel": ([_vp, ctypes.c_uint64], ctypes.c_int),
+            "jlb_engine_stats": ([_vp, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                  _P(ctypes.c_size_t)], ctypes.c_int),
+            "jlb_engine_destroy": ([_vp], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != JLB_OK:
+        raise JlbError(rc, load().jlb_last_error().decode())
+
+
+def make_problem(d: dict, precision: str | int | None = None, flags: int = 0) -> jlb_problem:
+    """jlb_problem from a problem dict (keys as in the seeded workloads)."""
+    kind = d.get("kind", "homogeneous")
+    prec = precision if precision is not None else d.get("precision", "fp64")
+    phi0 = d.get("phi0")
+    if phi0 is None:
+        phi0 = math.radians(d.get("phi0_deg", 0.0))
+    return jlb_problem(
+        nx=int(d["nx"]), ny=int(d.get("ny", d["nx"])), kind=KINDS[kind] if isinstance(kind, str) else int(kind),
+        precision=PRECISIONS[prec] if isinstance(prec, str) else int(prec), radius=float(d["radius"]),
+        eps1=float(d.get("eps1", 1.0)), eps2=float(d.get("eps2", 1.0)), phi0=float(phi0),
+        wavelength=float(d["wavelength"]), e0=float(d.get("e0", 1.0)), steps=int(d["steps"]),
+        avg_periods=int(d.get("avg_periods", 5)), ramp_periods=int(d.get("ramp_periods", 1)),
+        contour_offset=float(d.get("contour_offset", 3.0)), contour_points=int(d.get("contour_points", 0)),
+        flags=int(flags | d.get("flags", 0)),
+    )
+
+
+def jlb_version() -> int:
+    return load().jlb_version()
+
+
+def jlb_validate(prob: jlb_problem) -> int:
+    """Return code of the library's problem check (0 = valid)."""
+    return load().jlb_validate(ctypes.byref(prob))
+
+
+def jlb_last_error() -> str:
+    return load().jlb_last_error().decode()
+
+
+def jlb_workspace_size(prob: jlb_problem) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().jlb_workspace_size(ctypes.byref(prob), ctypes.byref(n)))
+    return n.value
+
+
+def jlb_material_map(prob: jlb_problem) -> np.ndarray:
+    out = np.zeros((prob.ny, prob.nx), dtype=np.uint8)
+    _check(load().jlb_material_map(ctypes.byref(prob), out.ctypes.data_as(_vp)))
+    return out
+
+
+def _dptr(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+def jlb_solve(prob: jlb_problem, workspace=None, ez=None, hx=None, hy=None, energy=None, stream=None) -> jlb_result:
+    """One solve; workspace/fields/energy are CUDA tensors (or None)."""
+    res = jlb_result()
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(load().jlb_solve(ctypes.byref(prob), _dptr(workspace), nbytes, ctypes.byref(res), _dptr(ez), _dptr(hx),
+                            _dptr(hy), _dptr(energy), _stream(stream)))
+    return res
+
+
+def jlb_time_step_kernel(prob: jlb_problem, warmup: int, launches: int, workspace=None, stream=None) -> float:
+    ms = ctypes.c_double(0.0)
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(load().jlb_time_step_kernel(ctypes.byref(prob), _dptr(workspace), nbytes, int(warmup), int(launches),
+                                       ctypes.byref(ms), _stream(stream)))
+    return ms.value
+
+
+def solve(d: dict, precision: str = "fp64", fields: bool = False, energy: bool = False, flags: int = 0,
+          device: str = "cuda") -> dict:
+    """Convenience wrapper: torch-allocated workspace and outputs; returns numpy arrays."""
+    import torch
+    prob = make_problem(d, precision, flags)
+    ws = torch.empty(jlb_workspace_size(prob), dtype=torch.uint8, device=device)
+    f = [torch.empty((prob.ny, prob.nx), dtype=torch.float64, device=device) for _ in range(3)] if fields else [None] * 3
+    en = torch.empty(prob.steps, dtype=torch.float64, device=device) if energy else None
+    res = jlb_solve(prob, ws, *f, en)
+    out = res.as_dict()
+    if fields:
+        out.update(ez=f[0].cpu().numpy(), hx=f[1].cpu().numpy(), hy=f[2].cpu().numpy())
+    if energy:
+        out["energy"] = en.cpu().numpy()
+    return out
+
+
+class Engine:
+    """Batched solves resident on one device (see jlb_engine_* in include/jlb.h)."""
+
+    def __init__(self, budget_bytes: int, max_slots: int, stream=None):
+        self._h = _vp()
+        s = None if stream is None else _vp(stream.cuda_stream)
+        _check(load().jlb_engine_create(int(budget_bytes), int(max_slots), s, ctypes.byref(self._h)))
+
+    def submit(self, prob: jlb_problem) -> int:
+        t = ctypes.c_uint64(0)
+        _check(load().jlb_engine_submit(self._h, ctypes.byref(prob), ctypes.byref(t)))
+        return t.value
+
+    def run(self, steps: int) -> int:
+        a = ctypes.c_int32(0)
+        _check(load().jlb_engine_run(self._h, int(steps), ctypes.byref(a)))
+        return a.value
+
+    def poll(self, ticket: int):
+        st = ctypes.c_int32(0)
+        res = jlb_result()
+        _check(load().jlb_engine_poll(self._h, int(ticket), ctypes.byref(st), ctypes.byref(res)))
+        return REQ_STATUS[st.value], res
+
+    def cancel(self, ticket: int):
+        _check(load().jlb_engine_cancel(self._h, int(ticket)))
+
+    def stats(self) -> dict:
+        q, r, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        b = ctypes.c_size_t()
+        _check(load().jlb_engine_stats(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(f), ctypes.byref(b)))
+        return {"queued": q.value, "resident": r.value, "finished": f.value, "bytes_in_use": b.value}
+
+    def close(self):
+        if self._h:
+            _check(load().jlb_engine_destroy(self._h))
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,580 @@
+// Host side of the Janus-cylinder EM lattice Boltzmann library: problem
+// checks, staircase geometry, contour table, workspace layout and the
+// time-stepping driver behind the C ABI of include/jlb.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/jlb.h"
+#include "jlb_host_internal.h"
+#include "jlb_internal.h"
+
+namespace jlb {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+void clear_error() { g_last_error.clear(); }
+const char *last_error() { return g_last_error.c_str(); }
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(JLB_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Problem plan: every derived quantity of one solve
+// ---------------------------------------------------------------------------
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int make_plan(const jlb_problem *p, Plan *pl)
+{
+    if (!p || !pl) return fail(JLB_E_ARG, "null problem or plan");
+    if (p->nx < 16 || p->ny < 16) return fail(JLB_E_ARG, "grid %dx%d smaller than 16x16", p->nx, p->ny);
+    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(JLB_E_ARG, "grid too large");
+    if (p->kind < 0 || p->kind > 2) return fail(JLB_E_ARG, "unknown kind %d", p->kind);
+    if (p->precision < 0 || p->precision > 2) return fail(JLB_E_ARG, "unknown precision %d", p->precision);
+    if (!(p->radius > 0.0)) return fail(JLB_E_ARG, "radius must be > 0");
+    if (!(p->eps1 >= 1.0) || !std::isfinite(p->eps1)) return fail(JLB_E_ARG, "eps1 must be >= 1");
+    if (p->kind == JLB_DIELECTRIC_JANUS && (!(p->eps2 >= 1.0) || !std::isfinite(p->eps2)))
+        return fail(JLB_E_ARG, "eps2 must be >= 1");
+    if (!std::isfinite(p->phi0)) return fail(JLB_E_ARG, "phi0 not finite");
+    if (!(p->wavelength > 0.0) || !std::isfinite(p->wavelength)) return fail(JLB_E_ARG, "wavelength must be > 0");
+    const double period = 3.0 * p->wavelength;
+    const int64_t T = (int64_t)std::llround(period);
+    if (std::fabs(period - (double)T) > 1e-9 || T < 4) return fail(JLB_E_ARG, "3*wavelength must be an integer >= 4");
+    if (!(p->e0 > 0.0) || !std::isfinite(p->e0)) return fail(JLB_E_ARG, "e0 must be > 0");
+    if (p->steps < 1) return fail(JLB_E_ARG, "steps must be >= 1");
+    if (p->avg_periods < 1 || p->ramp_periods < 0) return fail(JLB_E_ARG, "avg_periods >= 1 and ramp_periods >= 0");
+    if (!(p->contour_offset > 1.5)) return fail(JLB_E_GEOMETRY, "contour_offset must exceed 1.5 cells");
+    if (p->contour_points < 0) return fail(JLB_E_ARG, "contour_points must be >= 0");
+
+    Plan &q = *pl;
+    q.prob = *p;
+    q.nx = p->nx;
+    q.ny = p->ny;
+    q.pitch = (int)align_up((size_t)p->nx, ROW_ALIGN);
+    q.plane = (size_t)(p->ny + 1) * q.pitch;
+    q.period = period;
+    q.T = T;
+    q.omega = 2.0 * M_PI / period;
+    q.ramp_steps = (double)p->ramp_periods * period;
+    q.window = (int64_t)p->avg_periods * T;
+    q.cx = 0.5 * (p->nx - 1);
+    q.cy = 0.5 * (p->ny - 1);
+    q.rc = p->radius + p->contour_offset;
+    q.nc = p->contour_points > 0 ? p->contour_points : 8 * (int)std::ceil(2.0 * M_PI * q.rc / 8.0);
+    // disk, contour and a 4-cell margin inside the grid
+    const double reach = q.rc + 4.0;
+    if (q.cx - reach < 0.0 || q.cy - reach < 0.0 || q.cx + reach > p->nx - 1 || q.cy + reach > p->ny - 1)
+        return fail(JLB_E_GEOMETRY, "disk radius %.3g + contour offset %.3g + 4 does not fit a %dx%d grid", p->radius,
+                    p->contour_offset, p->nx, p->ny);
+    double eps_max = p->eps1;
+    if (p->kind == JLB_DIELECTRIC_JANUS) eps_max = std::max(eps_max, p->eps2);
+    if (!(p->flags & JLB_F_ALLOW_UNDERRESOLVED) && p->wavelength / std::sqrt(eps_max) < 10.0)
+        return fail(JLB_E_RESOLUTION, "lambda/sqrt(eps_max) = %.3g < 10", p->wavelength / std::sqrt(eps_max));
+    if (p->steps < (int64_t)(p->avg_periods + p->ramp_periods) * T)
+        return fail(JLB_E_WINDOW, "steps %lld < (avg_periods + ramp_periods) * T = %lld", (long long)p->steps,
+                    (long long)(p->avg_periods + p->ramp_periods) * T);
+
+    q.eps[MAT_VACUUM] = 1.0;
+    q.eps[MAT_REGION2] = p->eps1;
+    q.eps[MAT_REGION3] = p->kind == JLB_DIELECTRIC_JANUS ? p->eps2 : (p->kind == JLB_HOMOGENEOUS ? p->eps1 : 1.0);
+    q.eps[MAT_PEC] = 1.0;
+
+    // workspace layout (each region 256-byte aligned)
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    if (p->precision == JLB_FP64) {
+        q.state_bytes = 11 * q.plane * sizeof(double);
+        q.bytes_per_lup = 11 * 2 * sizeof(double) + 1;
+    } else {
+        const size_t nb = p->precision == JLB_FP32 ? 4 : 2;
+        q.state_bytes = 3 * q.plane * sizeof(float) + 8 * q.plane * nb;
+        q.bytes_per_lup = (3 * 4 + 8 * nb) * 2 + 1;
+    }
+    q.off_state[0] = take(q.state_bytes);
+    q.off_state[1] = take(q.state_bytes);
+    q.off_fields = p->precision == JLB_FP64 ? take(3 * q.plane * sizeof(double)) : 0;
+    q.off_mask = take((size_t)q.ny * q.pitch);
+    q.off_i0 = take(q.nc * sizeof(int));
+    q.off_j0 = take(q.nc * sizeof(int));
+    q.off_wx = take(q.nc * sizeof(double));
+    q.off_wy = take(q.nc * sizeof(double));
+    q.off_nxk = take(q.nc * sizeof(double));
+    q.off_nyk = take(q.nc * sizeof(double));
+    q.off_acc = take(4 * q.nc * sizeof(double));
+    q.off_out = take(8 * sizeof(double));
+    Lattice tmp{};
+    tmp.nx = q.nx;
+    tmp.ny = q.ny;
+    q.nparts = energy_partials(tmp);
+    q.off_parts = take(q.nparts * sizeof(double));
+    q.ws_bytes = off;
+    return JLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry (Sec. II, Fig. schematic): staircase material map on the nodes
+// ---------------------------------------------------------------------------
+
+void material_map(const Plan &q, uint8_t *mat, size_t row_stride)
+{
+    const jlb_problem &p = q.prob;
+    const double sp = std::sin(p.phi0), cp = std::cos(p.phi0);
+    for (int j = 0; j < q.ny; ++j) {
+        for (int i = 0; i < q.nx; ++i) {
+            const double dx = i - q.cx, dy = j - q.cy;
+            uint8_t m = MAT_VACUUM;
+            if (dx * dx + dy * dy <= p.radius * p.radius) {
+                if (p.kind == JLB_HOMOGENEOUS) {
+                    m = MAT_REGION2;
+                } else {
+                    // side of the interface diameter: region II towards (-sin phi0, -cos phi0)
+                    const double s = -dx * sp - dy * cp;
+                    m = s > 1e-9 ? MAT_REGION2 : (p.kind == JLB_DIELECTRIC_JANUS ? MAT_REGION3 : MAT_PEC);
+                }
+            }
+            mat[(size_t)j * row_stride + i] = m;
+        }
+    }
+}
+
+// Mask bytes: material id plus conductor-neighbour bits.
+void build_mask(const Plan &q, std::vector<uint8_t> &mask)
+{
+    mask.assign((size_t)q.ny * q.pitch, 0);
+    material_map(q, mask.data(), q.pitch);
+    auto pec = [&](int i, int j) {
+        return i >= 0 && j >= 0 && i < q.nx && j < q.ny && (mask[(size_t)j * q.pitch + i] & 3) == MAT_PEC;
+    };
+    for (int j = 0; j < q.ny; ++j)
+        for (int i = 0; i < q.nx; ++i) {
+            uint8_t &m = mask[(size_t)j * q.pitch + i];
+            if (pec(i - 1, j)) m |= NB_PEC_XM;
+            if (pec(i + 1, j)) m |= NB_PEC_XP;
+            if (pec(i, j - 1)) m |= NB_PEC_YM;
+            if (pec(i, j + 1)) m |= NB_PEC_YP;
+        }
+}
+
+// Contour (Sec. II.B): N_c midpoint samples on the circle of radius R_c.
+void build_contour(const Plan &q, ContourHost &c)
+{
+    c.i0.resize(q.nc);
+    c.j0.resize(q.nc);
+    c.wx.resize(q.nc);
+    c.wy.resize(q.nc);
+    c.nxk.resize(q.nc);
+    c.nyk.resize(q.nc);
+    for (int k = 0; k < q.nc; ++k) {
+        const double th = 2.0 * M_PI * (k + 0.5) / q.nc;
+        c.nxk[k] = std::cos(th);
+        c.nyk[k] = std::sin(th);
+        const double px = q.cx + q.rc * c.nxk[k];
+        const double py = q.cy + q.rc * c.nyk[k];
+        c.i0[k] = (int)std::floor(px);
+        c.j0[k] = (int)std::floor(py);
+        c.wx[k] = px - c.i0[k];
+        c.wy[k] = py - c.j0[k];
+    }
+}
+
+// Incident wave at the left edge (Sec. III): E_inc(n) = E0 r(n) cos(omega n),
+// raised-cosine ramp r over the first ramp_periods periods.  The phase is
+// taken as omega (n mod T), which repeats exactly with the period, so the
+// source values captured in a graph of whole periods equal those of direct
+// launches at every replay.
+double incident(const Plan &q, int64_t n)
+{
+    double ramp = 1.0;
+    if (q.prob.ramp_periods > 0 && (double)n < q.ramp_steps) ramp = 0.5 * (1.0 - std::cos(M_PI * (double)n / q.ramp_steps));
+    return q.prob.e0 * ramp * std::cos(q.omega * (double)(n % q.T));
+}
+
+// ---------------------------------------------------------------------------
+// Streams
+// ---------------------------------------------------------------------------
+
+hipStream_t own_stream()
+{
+    static thread_local hipStream_t s = nullptr;
+    static thread_local int dev = -1;
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) return nullptr;
+    if (!s || dev != d) {
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        dev = d;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// One solve on prepared device memory
+// ---------------------------------------------------------------------------
+
+Lattice lattice_of(const Plan &q, const uint8_t *dmask)
+{
+    Lattice L{};
+    L.nx = q.nx;
+    L.ny = q.ny;
+    L.pitch = q.pitch;
+    L.plane = q.plane;
+    L.mask = dmask;
+    for (int k = 0; k < 4; ++k) {
+        L.eps[k] = q.eps[k];
+        L.eps_rest[k] = q.eps[k] - 2.0 / 3.0;
+    }
+    return L;
+}
+
+ContourDev contour_of(const Plan &q, char *ws)
+{
+    ContourDev C{};
+    C.n = q.nc;
+    C.rc = q.rc;
+    C.i0 = (const int *)(ws + q.off_i0);
+    C.j0 = (const int *)(ws + q.off_j0);
+    C.wx = (const double *)(ws + q.off_wx);
+    C.wy = (const double *)(ws + q.off_wy);
+    C.nxk = (const double *)(ws + q.off_nxk);
+    C.nyk = (const double *)(ws + q.off_nyk);
+    C.acc = (double *)(ws + q.off_acc);
+    return C;
+}
+
+int upload_setup(const Plan &q, char *ws, hipStream_t s)
+{
+    std::vector<uint8_t> mask;
+    build_mask(q, mask);
+    ContourHost ch;
+    build_contour(q, ch);
+    HIP_TRY(hipMemcpyAsync(ws + q.off_mask, mask.data(), mask.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws + q.off_i0, ch.i0.data(), q.nc * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws + q.off_j0, ch.j0.data(), q.nc * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws + q.off_wx, ch.wx.data(), q.nc * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws + q.off_wy, ch.wy.data(), q.nc * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws + q.off_nxk, ch.nxk.data(), q.nc * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws + q.off_nyk, ch.nyk.data(), q.nc * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(ws + q.off_state[0], 0, q.state_bytes, s));
+    HIP_TRY(hipMemsetAsync(ws + q.off_state[1], 0, q.state_bytes, s));
+    if (q.prob.precision == JLB_FP64) HIP_TRY(hipMemsetAsync(ws + q.off_fields, 0, 3 * q.plane * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(ws + q.off_acc, 0, 4 * q.nc * sizeof(double), s));
+    // the host vectors are released on return: finish the copies first
+    HIP_TRY(hipStreamSynchronize(s));
+    return JLB_OK;
+}
+
+// Launches lattice step n (state at n in buffer n % 2), plus the contour
+// accumulation when n + 1 is inside the averaging window.
+static int launch_one_step(const Plan &q, char *ws, const Lattice &L, const ContourDev &C, int64_t n, bool want_fields,
+                           double einc, hipStream_t s)
+{
+    const int prec = q.prob.precision;
+    void *src = ws + q.off_state[n & 1];
+    void *dst = ws + q.off_state[(n + 1) & 1];
+    const bool in_window = n + 1 > q.prob.steps - q.window;
+    hipError_t e;
+    if (prec == JLB_FP64) {
+        double *fields = (in_window || want_fields) ? (double *)(ws + q.off_fields) : nullptr;
+        e = launch_step_f64(L, (const double *)src, (double *)dst, fields, einc, s);
+        if (e == hipSuccess && in_window) e = launch_contour(prec, L, ws + q.off_fields, C, s);
+    } else {
+        e = launch_step_neq(prec, L, src, dst, einc, s);
+        if (e == hipSuccess && in_window) e = launch_contour(prec, L, dst, C, s);
+    }
+    if (e != hipSuccess) return fail(JLB_E_DEVICE, "launch of step %lld failed: %s", (long long)n, hipGetErrorString(e));
+    return JLB_OK;
+}
+
+const void *fields_ptr(const Plan &q, char *ws, int64_t n_done)
+{
+    if (q.prob.precision == JLB_FP64) return ws + q.off_fields;
+    return ws + q.off_state[n_done & 1];
+}
+
+int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, double *hy, double *energy,
+              hipStream_t s)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    memset(res, 0, sizeof(*res));
+    int rc = upload_setup(q, ws, s);
+    if (rc) return rc;
+    const Lattice L = lattice_of(q, (const uint8_t *)(ws + q.off_mask));
+    const ContourDev C = contour_of(q, ws);
+    const int64_t steps = q.prob.steps;
+    const int64_t wstart = steps - q.window;  // first n whose result enters the average
+    const bool use_graph = !(q.prob.flags & JLB_F_NO_GRAPH) && !energy;
+    const int64_t chunk = (q.T % 2 == 0) ? q.T : 2 * q.T;  // whole periods, even step count
+    const int64_t ramp_end = (int64_t)std::ceil(q.ramp_steps);
+
+    hipEvent_t ev0, ev1;
+    HIP_TRY(hipEventCreate(&ev0));
+    HIP_TRY(hipEventCreate(&ev1));
+    HIP_TRY(hipEventRecord(ev0, s));
+
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] outside the window, [1] inside
+    int64_t gstart[2] = {-1, -1};
+    auto capture = [&](int which, int64_t n0) -> int {
+        hipGraph_t g;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int64_t k = 0; k < chunk; ++k) {
+            int r = launch_one_step(q, ws, L, C, n0 + k, false, incident(q, n0 + k), s);
+            if (r) {
+                hipGraph_t dummy;
+                (void)hipStreamEndCapture(s, &dummy);
+                return r;
+            }
+        }
+        HIP_TRY(hipStreamEndCapture(s, &g));
+        HIP_TRY(hipGraphInstantiate(&gexec[which], g, nullptr, nullptr, 0));
+        HIP_TRY(hipGraphDestroy(g));
+        gstart[which] = n0;
+        return JLB_OK;
+    };
+
+    int64_t n = 0;
+    int graph_used = 0;
+    while (n < steps && rc == JLB_OK) {
+        const bool in_window = n >= wstart;
+        const int64_t seg_end = in_window ? steps : wstart;  // chunk must not straddle the window start
+        if (use_graph && n >= ramp_end && n + chunk <= seg_end) {
+            const int which = in_window ? 1 : 0;
+            if (!gexec[which]) {
+                rc = capture(which, n);
+                if (rc) break;
+            }
+            // the captured source values repeat with the period after the ramp
+            if ((n - gstart[which]) % chunk != 0) {
+                rc = fail(JLB_E_DEVICE, "internal: graph phase mismatch");
+                break;
+            }
+            hipError_t e = hipGraphLaunch(gexec[which], s);
+            if (e != hipSuccess) {
+                rc = fail(JLB_E_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+                break;
+            }
+            graph_used = 1;
+            n += chunk;
+            continue;
+        }
+        rc = launch_one_step(q, ws, L, C, n, energy != nullptr || n == steps - 1, incident(q, n), s);
+        if (rc) break;
+        if (energy) {
+            hipError_t e = launch_energy(q.prob.precision, L, fields_ptr(q, ws, n + 1), (double *)(ws + q.off_parts),
+                                         q.nparts, energy + n, s);
+            if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "energy launch: %s", hipGetErrorString(e));
+        }
+        ++n;
+    }
+    if (rc == JLB_OK) {
+        hipError_t e = hipEventRecord(ev1, s);
+        if (e == hipSuccess) e = launch_reduce(C, 1.0 / (double)q.window, M_PI * q.prob.radius * q.prob.e0 * q.prob.e0 / 4.0,
+                                               2.0 * (M_PI * q.prob.radius * q.prob.e0 * q.prob.e0 / 4.0) * q.prob.radius,
+                                               (double *)(ws + q.off_out), s);
+        if (e == hipSuccess && ez && hx && hy)
+            e = launch_fields_out(q.prob.precision, L, fields_ptr(q, ws, steps), ez, hx, hy, s);
+        double out[8] = {0};
+        if (e == hipSuccess) e = hipMemcpyAsync(out, ws + q.off_out, 6 * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "finishing the solve: %s", hipGetErrorString(e));
+        if (rc == JLB_OK) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ev0, ev1);
+            res->fx = out[0];
+            res->fy = out[1];
+            res->tz = out[2];
+            res->fx_raw = out[3];
+            res->fy_raw = out[4];
+            res->tz_raw = out[5];
+            res->loop_ms = ms;
+            res->steps_done = steps;
+            res->window_steps = q.window;
+            res->contour_points = q.nc;
+            res->graph_used = graph_used;
+            res->bytes_per_step = (int64_t)q.bytes_per_lup * q.nx * q.ny;
+            for (int k = 0; k < 6; ++k)
+                if (!std::isfinite(out[k])) rc = fail(JLB_E_NONFINITE, "forces are not finite");
+        }
+    } else {
+        (void)hipStreamSynchronize(s);
+    }
+    for (auto &g : gexec)
+        if (g) (void)hipGraphExecDestroy(g);
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    res->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+// Orders work on the library's stream after the caller's stream, and back.
+struct StreamJoin {
+    hipStream_t caller, own;
+    hipEvent_t ev = nullptr;
+    int begin()
+    {
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(ev, caller));
+        HIP_TRY(hipStreamWaitEvent(own, ev, 0));
+        return JLB_OK;
+    }
+    int end()
+    {
+        HIP_TRY(hipEventRecord(ev, own));
+        HIP_TRY(hipStreamWaitEvent(caller, ev, 0));
+        return JLB_OK;
+    }
+    ~StreamJoin()
+    {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+
+}  // namespace jlb
+
+using namespace jlb;
+
+extern "C" {
+
+int jlb_version(void) { return 10000; }
+
+const char *jlb_last_error(void) { return jlb::last_error(); }
+
+int jlb_validate(const jlb_problem *prob)
+{
+    clear_error();
+    Plan q;
+    return make_plan(prob, &q);
+}
+
+int jlb_workspace_size(const jlb_problem *prob, size_t *bytes)
+{
+    clear_error();
+    if (!bytes) return fail(JLB_E_ARG, "null bytes");
+    Plan q;
+    int rc = make_plan(prob, &q);
+    if (rc) return rc;
+    *bytes = q.ws_bytes;
+    return JLB_OK;
+}
+
+int jlb_material_map(const jlb_problem *prob, uint8_t *mat)
+{
+    clear_error();
+    if (!mat) return fail(JLB_E_ARG, "null mat");
+    Plan q;
+    int rc = make_plan(prob, &q);
+    if (rc) return rc;
+    material_map(q, mat, (size_t)q.nx);
+    return JLB_OK;
+}
+
+int jlb_solve(const jlb_problem *prob, void *workspace, size_t workspace_bytes, jlb_result *res, double *ez,
+              double *hx, double *hy, double *energy, void *stream)
+{
+    clear_error();
+    if (!res) return fail(JLB_E_ARG, "null result");
+    Plan q;
+    int rc = make_plan(prob, &q);
+    if (rc) return rc;
+    if ((ez || hx || hy) && !(ez && hx && hy)) return fail(JLB_E_ARG, "ez, hx, hy must all be given or all NULL");
+    if (workspace && workspace_bytes < q.ws_bytes)
+        return fail(JLB_E_OOM, "workspace %zu bytes < %zu needed", workspace_bytes, q.ws_bytes);
+    hipStream_t own = own_stream();
+    if (!own) return fail(JLB_E_DEVICE, "cannot create a stream");
+    StreamJoin join{(hipStream_t)stream, own};
+    rc = join.begin();
+    if (rc) return rc;
+    char *ws = (char *)workspace;
+    bool owned = false;
+    if (!ws) {
+        hipError_t e = hipMalloc((void **)&ws, q.ws_bytes);
+        if (e != hipSuccess) return fail(JLB_E_OOM, "hipMalloc(%zu): %s", q.ws_bytes, hipGetErrorString(e));
+        owned = true;
+    }
+    rc = run_solve(q, ws, res, ez, hx, hy, energy, own);
+    int rc2 = join.end();
+    if (owned) {
+        (void)hipStreamSynchronize(own);
+        (void)hipFree(ws);
+    }
+    return rc ? rc : rc2;
+}
+
+int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
+                         int32_t launches, double *ms_per_launch, void *stream)
+{
+    clear_error();
+    if (!ms_per_launch || launches < 1 || warmup < 0) return fail(JLB_E_ARG, "bad launch counts");
+    Plan q;
+    int rc = make_plan(prob, &q);
+    if (rc) return rc;
+    if (workspace && workspace_bytes < q.ws_bytes) return fail(JLB_E_OOM, "workspace too small");
+    hipStream_t own = own_stream();
+    if (!own) return fail(JLB_E_DEVICE, "cannot create a stream");
+    StreamJoin join{(hipStream_t)stream, own};
+    rc = join.begin();
+    if (rc) return rc;
+    char *ws = (char *)workspace;
+    bool owned = false;
+    if (!ws) {
+        if (hipMalloc((void **)&ws, q.ws_bytes) != hipSuccess) return fail(JLB_E_OOM, "hipMalloc failed");
+        owned = true;
+    }
+    rc = upload_setup(q, ws, own);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == JLB_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(JLB_E_DEVICE, "event create");
+    const Lattice L = lattice_of(q, (const uint8_t *)(ws + q.off_mask));
+    for (int64_t n = 0; rc == JLB_OK && n < (int64_t)warmup + launches; ++n) {
+        if (n == warmup && hipEventRecord(e0, own) != hipSuccess) rc = fail(JLB_E_DEVICE, "event record");
+        void *src = ws + q.off_state[n & 1];
+        void *dst = ws + q.off_state[(n + 1) & 1];
+        hipError_t e = q.prob.precision == JLB_FP64
+                           ? launch_step_f64(L, (const double *)src, (double *)dst, nullptr, incident(q, n), own)
+                           : launch_step_neq(q.prob.precision, L, src, dst, incident(q, n), own);
+        if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "step launch: %s", hipGetErrorString(e));
+    }
+    if (rc == JLB_OK) {
+        float ms = 0.0f;
+        if (hipEventRecord(e1, own) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            rc = fail(JLB_E_DEVICE, "event timing");
+        *ms_per_launch = (double)ms / launches;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    int rc2 = join.end();
+    (void)hipStreamSynchronize(own);
+    if (owned) (void)hipFree(ws);
+    return rc ? rc : rc2;
+}
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+// Host-side helpers shared by the single-solve driver and the batched engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <vector>
+
+#include "../../include/jlb.h"
+#include "jlb_internal.h"
+
+namespace jlb {
+
+// Every derived quantity of one solve, including its device workspace layout.
+struct Plan {
+    jlb_problem prob;
+    int nx, ny, pitch;
+    size_t plane;           // elements per population plane ((ny + 1) * pitch)
+    double period;          // 3 lambda
+    int64_t T;              // period in whole steps
+    double omega;           // 2 pi / period
+    double ramp_steps;      // ramp_periods * period
+    int64_t window;         // avg_periods * T
+    double cx, cy, rc;      // centre and contour radius
+    int nc;                 // contour samples
+    double eps[4];          // permittivity per material id
+    size_t state_bytes;     // one state buffer
+    int bytes_per_lup;      // algorithmic HBM bytes per lattice update
+    size_t off_state[2], off_fields, off_mask, off_i0, off_j0, off_wx, off_wy, off_nxk, off_nyk, off_acc, off_out,
+        off_parts;
+    int nparts;
+    size_t ws_bytes;
+};
+
+struct ContourHost {
+    std::vector<int> i0, j0;
+    std::vector<double> wx, wy, nxk, nyk;
+};
+
+int fail(int code, const char *fmt, ...);
+void clear_error();
+const char *last_error();
+
+int make_plan(const jlb_problem *p, Plan *pl);
+void material_map(const Plan &q, uint8_t *mat, size_t row_stride);
+void build_mask(const Plan &q, std::vector<uint8_t> &mask);
+void build_contour(const Plan &q, ContourHost &c);
+double incident(const Plan &q, int64_t n);
+hipStream_t own_stream();
+Lattice lattice_of(const Plan &q, const uint8_t *dmask);
+ContourDev contour_of(const Plan &q, char *ws);
+int upload_setup(const Plan &q, char *ws, hipStream_t s);
+int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, double *hy, double *energy,
+              hipStream_t s);
+
+}  // namespace jlb

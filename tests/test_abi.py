@@ -1,0 +1,67 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared
+entry point, and its host logic (problem checks, staircase geometry) agrees
+with the oracle."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2509_22308_amd as J
+import workloads as W
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "jlb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(jlb_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 14
+    lib = J.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert J.jlb_version() >= 10000
+
+
+@pytest.mark.parametrize("prob", [W.config1(), W.config2(), W.config3(4.0, 45.0), W.small_mdjc(8.0, 135.0),
+                                  W.problem(nx=101, ny=77, radius=17.3, kind="dielectric_janus", eps1=3.0, eps2=1.5,
+                                            phi0_deg=225.0, wavelength=40.0, steps=2000)],
+                         ids=["c1", "c2", "c3", "mdjc", "ragged"])
+def test_material_map_matches_oracle_bit_for_bit(prob):
+    assert np.array_equal(J.jlb_material_map(J.make_problem(prob)), O.mask(prob))
+
+
+def test_problem_checks_return_the_documented_codes():
+    ok = W.config1()
+    assert J.jlb_validate(J.make_problem(ok)) == 0
+    assert J.jlb_validate(J.make_problem(dict(ok, nx=8))) == -1                       # JLB_E_ARG
+    assert J.jlb_validate(J.make_problem(dict(ok, wavelength=40.1))) == -1            # 3 lambda not integer
+    assert J.jlb_validate(J.make_problem(dict(ok, radius=60.0))) == -2                # JLB_E_GEOMETRY
+    assert J.jlb_validate(J.make_problem(dict(ok, eps1=30.0))) == -3                  # JLB_E_RESOLUTION
+    assert J.jlb_validate(J.make_problem(dict(ok, eps1=30.0), flags=J.JLB_F_ALLOW_UNDERRESOLVED)) == 0
+    assert J.jlb_validate(J.make_problem(dict(ok, steps=500))) == -4                  # JLB_E_WINDOW
+    assert J.jlb_validate(J.make_problem(dict(ok, eps1=0.5))) == -1
+    assert "eps1" in J.jlb_last_error()
+
+
+def test_workspace_grows_with_precision_and_grid():
+    p = W.config2()
+    sizes = [J.jlb_workspace_size(J.make_problem(p, prec)) for prec in ("bf16", "fp32", "fp64")]
+    assert sizes[0] < sizes[1] < sizes[2]
+    # FP64: two 11-population states plus FP64 field planes, rows padded to 64 nodes, one companion row
+    plane = (1024 + 1) * 1024
+    assert sizes[2] >= 2 * 11 * plane * 8 + 3 * plane * 8
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    monkeypatch.setattr(J, "_lib", None)
+    monkeypatch.setattr(J, "LIB_PATH", "/nonexistent/libjlb.so")
+    with pytest.raises(RuntimeError):
+        J.load()
