@@ -171,6 +171,38 @@ int jlb_solve(const jlb_problem *prob, void *workspace, size_t workspace_bytes, 
 int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
                          int32_t launches, double *ms_per_launch, void *stream);
 
+/*
+ * The FP32 / BF16 lattice step has JLB_STEP_VARIANTS kernel variants with
+ * identical results and different thread-to-node mappings:
+ *   0     one node per thread, 64 x 4 node blocks;
+ *   1-3   one column per thread sweeping 8 / 16 / 32 rows (256 columns per block);
+ *   4-6   two adjacent nodes per thread (two-wide loads and stores), 4 / 8 / 16 rows;
+ *   7-9   four adjacent nodes per thread (four-wide loads and stores), 4 / 8 / 16 rows.
+ * The choice is process-wide per precision (default 5).
+ *
+ * jlb_autotune times every variant of prob->precision on prob's grid
+ * (`launches` timed launches each, after 2 warm-up launches; workspace as for
+ * jlb_solve), makes the fastest the current choice and writes it to
+ * *best_variant; ms_per_variant (host, optional) receives JLB_STEP_VARIANTS
+ * mean launch times in ms.  For JLB_FP64 there is one variant (0).
+ */
+#define JLB_STEP_VARIANTS 10
+int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t launches,
+                 int32_t *best_variant, double *ms_per_variant, void *stream);
+
+/* Forces (set) or reports (get) the current FP32 / BF16 step variant. */
+int jlb_set_step_variant(int32_t precision, int32_t variant);
+int jlb_get_step_variant(int32_t precision, int32_t *variant);
+
+/*
+ * Reference bandwidth: times `launches` runs of a plain device copy of
+ * `bytes` bytes (16 bytes per lane, grid-stride) between two device buffers
+ * the call allocates, after one warm-up run; *ms_per_launch (host) receives
+ * the mean.  Used as the practical peak next to the lattice step and as the
+ * known-size kernel that calibrates memory-traffic counters.
+ */
+int jlb_copy_bandwidth(size_t bytes, int32_t launches, double *ms_per_launch, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched engine: many independent solves resident on one device, stepped  */
 /* together by one launch per lattice step over a work list of tiles drawn   */

@@ -81,6 +81,11 @@ def load():
                           ctypes.c_int),
             "jlb_time_step_kernel": ([_P(jlb_problem), _vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
                                       _P(ctypes.c_double), _vp], ctypes.c_int),
+            "jlb_autotune": ([_P(jlb_problem), _vp, ctypes.c_size_t, ctypes.c_int32, _P(ctypes.c_int32),
+                              _P(ctypes.c_double), _vp], ctypes.c_int),
+            "jlb_set_step_variant": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+            "jlb_get_step_variant": ([ctypes.c_int32, _P(ctypes.c_int32)], ctypes.c_int),
+            "jlb_copy_bandwidth": ([ctypes.c_size_t, ctypes.c_int32, _P(ctypes.c_double), _vp], ctypes.c_int),
             "jlb_engine_create": ([ctypes.c_size_t, ctypes.c_int32, _vp, _P(_vp)], ctypes.c_int),
             "jlb_engine_submit": ([_vp, _P(jlb_problem), _P(ctypes.c_uint64)], ctypes.c_int),
             "jlb_engine_run": ([_vp, ctypes.c_int64, _P(ctypes.c_int32)], ctypes.c_int),
@@ -172,6 +177,38 @@ def jlb_time_step_kernel(prob: jlb_problem, warmup: int, launches: int, workspac
     _check(load().jlb_time_step_kernel(ctypes.byref(prob), _dptr(workspace), nbytes, int(warmup), int(launches),
                                        ctypes.byref(ms), _stream(stream)))
     return ms.value
+
+
+STEP_VARIANTS = {0: "direct 64x4", 1: "sweep 8 rows", 2: "sweep 16 rows", 3: "sweep 32 rows",
+                 4: "2-wide sweep 4 rows", 5: "2-wide sweep 8 rows", 6: "2-wide sweep 16 rows",
+                 7: "4-wide sweep 4 rows", 8: "4-wide sweep 8 rows", 9: "4-wide sweep 16 rows"}
+
+
+def jlb_autotune(prob: jlb_problem, launches: int = 20, workspace=None, stream=None):
+    """Times every step variant of prob's precision; returns (best, [ms per variant])."""
+    best = ctypes.c_int32(0)
+    ms = (ctypes.c_double * len(STEP_VARIANTS))()
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(load().jlb_autotune(ctypes.byref(prob), _dptr(workspace), nbytes, int(launches), ctypes.byref(best), ms,
+                               _stream(stream)))
+    return best.value, list(ms)
+
+
+def jlb_copy_bandwidth(nbytes: int, launches: int = 10, stream=None) -> float:
+    """Mean ms of a plain device copy of nbytes (reference kernel)."""
+    ms = ctypes.c_double(0.0)
+    _check(load().jlb_copy_bandwidth(int(nbytes), int(launches), ctypes.byref(ms), _stream(stream)))
+    return ms.value
+
+
+def jlb_set_step_variant(precision: int, variant: int):
+    _check(load().jlb_set_step_variant(int(precision), int(variant)))
+
+
+def jlb_get_step_variant(precision: int) -> int:
+    v = ctypes.c_int32(0)
+    _check(load().jlb_get_step_variant(int(precision), ctypes.byref(v)))
+    return v.value
 
 
 def solve(d: dict, precision: str = "fp64", fields: bool = False, energy: bool = False, flags: int = 0,

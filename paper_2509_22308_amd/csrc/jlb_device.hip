@@ -37,11 +37,27 @@
 // No MFMA: the step is a stencil with about 0.3 flop per byte.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "jlb_internal.h"
 
 namespace jlb {
 
 namespace {
+
+// Stores of the next state are written once and read only in the next step:
+// with JLB_STREAM_STORES they bypass the caches (non-temporal).
+#ifndef JLB_STREAM_STORES
+#define JLB_STREAM_STORES 1
+#endif
+template <typename T> __device__ __forceinline__ void put(T *p, T v)
+{
+#if JLB_STREAM_STORES
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
 
 constexpr int BX = 64;  // one wavefront per row segment
 constexpr int BY = 4;   // four rows per block
@@ -54,14 +70,10 @@ __device__ __forceinline__ size_t node(const Lattice &L, int i, int j) { return 
 // contraction.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(BX *BY) void k_step_f64(Lattice L, const double *__restrict__ src,
-                                                      double *__restrict__ dst, double *__restrict__ fields,
-                                                      double einc)
+__device__ __forceinline__ void f64_node(const Lattice &L, const double *__restrict__ src, double *__restrict__ dst,
+                                         double *__restrict__ fields, double einc, int i, int j)
 {
 #pragma clang fp contract(off)
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    if (i >= L.nx || j > L.ny) return;
     const size_t P = L.plane;
     const size_t c = node(L, i, j);
     const double keep = 1.0 - OPEN_DELTA;
@@ -127,12 +139,22 @@ __global__ __launch_bounds__(BX *BY) void k_step_f64(Lattice L, const double *__
     q[9] = hy / 6.0;
     q[10] = hy / 6.0;
 #pragma unroll
-    for (int k = 0; k < 11; ++k) dst[k * P + c] = 2.0 * q[k] - f[k];
+    for (int k = 0; k < 11; ++k) put(&dst[k * P + c], 2.0 * q[k] - f[k]);
     if (fields && j < L.ny) {
         fields[0 * P + c] = ez;
         fields[1 * P + c] = hx;
         fields[2 * P + c] = hy;
     }
+}
+
+__global__ __launch_bounds__(BX *BY) void k_step_f64(Lattice L, const double *__restrict__ src,
+                                                      double *__restrict__ dst, double *__restrict__ fields,
+                                                      double einc)
+{
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    if (i >= L.nx || j > L.ny) return;
+    f64_node(L, src, dst, fields, einc, i, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -144,21 +166,241 @@ __global__ __launch_bounds__(BX *BY) void k_step_f64(Lattice L, const double *__
 enum { N_EPX = 0, N_EMX, N_EPY, N_EMY, N_HXPX, N_HXMX, N_HYPY, N_HYMY };
 
 template <typename T> __device__ __forceinline__ float ld(const T *p) { return (float)*p; }
-template <typename T> __device__ __forceinline__ void st(T *p, float v) { *p = (T)v; }
+template <typename T> __device__ __forceinline__ void st(T *p, float v) { put(p, (T)v); }
 
-template <typename NeqT>
-struct NeqState {
-    float *F;     // [3][plane]
-    NeqT *N;      // [8][plane]
+constexpr float SIXTH = 1.0f / 6.0f;
+constexpr float THIRD = 1.0f / 3.0f;
+
+// Fields and deviations of one node at time n.
+struct NodeData {
+    float ez, hx, hy;
+    float n[8];
+};
+
+// What a neighbour contributes to a pull: its fields and the two deviations
+// of the populations that stream from it towards the node.
+struct Side {
+    float ez, hx, hy, na, nb;
 };
 
 template <typename NeqT>
-__device__ __forceinline__ NeqState<NeqT> neq_view(void *base, size_t plane)
+__device__ __forceinline__ NodeData load_node(const float *F, const NeqT *N, size_t P, size_t c)
 {
-    NeqState<NeqT> s;
-    s.F = reinterpret_cast<float *>(base);
-    s.N = reinterpret_cast<NeqT *>(s.F + 3 * plane);
+    NodeData d;
+    d.ez = F[c];
+    d.hx = F[P + c];
+    d.hy = F[2 * P + c];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) d.n[k] = ld(&N[k * P + c]);
+    return d;
+}
+
+template <typename NeqT>
+__device__ __forceinline__ Side load_side(const float *F, const NeqT *N, size_t P, size_t c, int qa, int qb)
+{
+    Side s;
+    s.ez = F[c];
+    s.hx = F[P + c];
+    s.hy = F[2 * P + c];
+    s.na = ld(&N[qa * P + c]);
+    s.nb = ld(&N[qb * P + c]);
     return s;
+}
+
+// One node's update from its own data and the four sides.  Sides are read
+// only where the pull crosses an interior, non-conductor link.  `inc_lo` /
+// `inc_hi` hold the incident-wave companion node of the same column
+// (fields + N_{e+y}, N_{hy+y} / N_{e-y}, N_{hy-y}) for the bottom / top rows.
+template <bool STRIP>
+__device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t m, float eps, float eps_rest,
+                                         const NodeData &o, const Side &l, const Side &r, const Side &b, const Side &t,
+                                         const Side &inc_lo, const Side &inc_hi, float einc, NodeData &out)
+{
+    // no FMA contraction: every kernel variant that inlines this core must
+    // round the same operations the same way
+#pragma clang fp contract(off)
+    const float keep = (float)(1.0 - OPEN_DELTA);
+    const float delta = (float)OPEN_DELTA;
+    // own post-collision moving populations (edges and conductor links use them)
+    const float s_epx = (o.ez - o.hy) * SIXTH - o.n[N_EPX];
+    const float s_emx = (o.ez + o.hy) * SIXTH - o.n[N_EMX];
+    const float s_epy = (o.ez + o.hx) * SIXTH - o.n[N_EPY];
+    const float s_emy = (o.ez - o.hx) * SIXTH - o.n[N_EMY];
+    const float s_hxpx = o.hx * SIXTH - o.n[N_HXPX];
+    const float s_hxmx = o.hx * SIXTH - o.n[N_HXMX];
+    const float s_hypy = o.hy * SIXTH - o.n[N_HYPY];
+    const float s_hymy = o.hy * SIXTH - o.n[N_HYMY];
+    // rest populations stream in place: f*_r = f_r^eq - N_r with the sum rules
+    const float r_e = eps_rest * o.ez + (o.n[N_EPX] + o.n[N_EMX] + o.n[N_EPY] + o.n[N_EMY]);
+    const float r_hx = o.hx * THIRD + (o.n[N_HXPX] + o.n[N_HXMX] + o.n[N_EPY] - o.n[N_EMY]);
+    const float r_hy = o.hy * THIRD + (o.n[N_HYPY] + o.n[N_HYMY] - o.n[N_EPX] + o.n[N_EMX]);
+
+    float e_px, hx_px, e_mx, hx_mx, e_py, hy_py, e_my, hy_my;
+    // +x from (i-1, j)
+    if (i == 0) { e_px = einc * THIRD; hx_px = 0.0f; }
+    else if (m & NB_PEC_XM) { e_px = -s_emx; hx_px = -s_hxmx; }
+    else { e_px = (l.ez - l.hy) * SIXTH - l.na; hx_px = l.hx * SIXTH - l.nb; }
+    // -x from (i+1, j)
+    if (i == L.nx - 1) {
+        if (STRIP) { e_mx = 0.0f; hx_mx = 0.0f; }
+        else { e_mx = keep * s_emx; hx_mx = keep * s_hxmx; }
+    } else if (m & NB_PEC_XP) { e_mx = -s_epx; hx_mx = -s_hxpx; }
+    else { e_mx = (r.ez + r.hy) * SIXTH - r.na; hx_mx = r.hx * SIXTH - r.nb; }
+    if (STRIP) {
+        // uniform in y: the +-y populations stay in their node
+        e_py = s_epy; hy_py = s_hypy; e_my = s_emy; hy_my = s_hymy;
+    } else {
+        // +y from (i, j-1)
+        if (j == 0) {
+            e_py = keep * s_epy + delta * ((inc_lo.ez + inc_lo.hx) * SIXTH - inc_lo.na);
+            hy_py = keep * s_hypy + delta * (inc_lo.hy * SIXTH - inc_lo.nb);
+        } else if (m & NB_PEC_YM) { e_py = -s_emy; hy_py = -s_hymy; }
+        else { e_py = (b.ez + b.hx) * SIXTH - b.na; hy_py = b.hy * SIXTH - b.nb; }
+        // -y from (i, j+1)
+        if (j == L.ny - 1) {
+            e_my = keep * s_emy + delta * ((inc_hi.ez - inc_hi.hx) * SIXTH - inc_hi.na);
+            hy_my = keep * s_hymy + delta * (inc_hi.hy * SIXTH - inc_hi.nb);
+        } else if (m & NB_PEC_YP) { e_my = -s_epy; hy_my = -s_hypy; }
+        else { e_my = (t.ez - t.hx) * SIXTH - t.na; hy_my = t.hy * SIXTH - t.nb; }
+    }
+
+    const float dz = r_e + e_px + e_mx + (e_py + e_my);
+    const float ez = dz / eps;
+    const float hx = r_hx + hx_px + hx_mx + (e_py - e_my);
+    const float hy = r_hy + (hy_py + hy_my) + (e_mx - e_px);
+    out.ez = ez;
+    out.hx = hx;
+    out.hy = hy;
+    out.n[N_EPX] = e_px - (ez - hy) * SIXTH;
+    out.n[N_EMX] = e_mx - (ez + hy) * SIXTH;
+    out.n[N_EPY] = e_py - (ez + hx) * SIXTH;
+    out.n[N_EMY] = e_my - (ez - hx) * SIXTH;
+    out.n[N_HXPX] = hx_px - hx * SIXTH;
+    out.n[N_HXMX] = hx_mx - hx * SIXTH;
+    out.n[N_HYPY] = hy_py - hy * SIXTH;
+    out.n[N_HYMY] = hy_my - hy * SIXTH;
+}
+
+template <typename NeqT>
+__device__ __forceinline__ void store_node(float *F, NeqT *N, size_t P, size_t c, const NodeData &d)
+{
+    put(&F[c], d.ez);
+    put(&F[P + c], d.hx);
+    put(&F[2 * P + c], d.hy);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) st(&N[k * P + c], d.n[k]);
+}
+
+// Sides along x of node (i, j) and the material parameters; false for a conductor node.
+template <typename NeqT>
+__device__ __forceinline__ bool node_setup(const Lattice &L, const float *F, const NeqT *N, int i, int j, size_t c,
+                                           uint8_t &m, float &eps, float &eps_rest, Side &l, Side &r)
+{
+    const size_t P = L.plane;
+    m = 0;
+    eps = 1.0f;
+    eps_rest = (float)(1.0 - 2.0 / 3.0);
+    if (j < L.ny) {
+        m = L.mask[c];
+        const int mat = m & 3;
+        if (mat == MAT_PEC) return false;
+        eps = (float)L.eps[mat];
+        eps_rest = (float)L.eps_rest[mat];
+    }
+    if (i > 0 && !(m & NB_PEC_XM)) l = load_side(F, N, P, c - 1, N_EPX, N_HXPX);
+    if (i < L.nx - 1 && !(m & NB_PEC_XP)) r = load_side(F, N, P, c + 1, N_EMX, N_HXMX);
+    return true;
+}
+
+template <typename NeqT>
+__device__ __forceinline__ void load_incident_sides(const Lattice &L, const float *F, const NeqT *N, int i, int j,
+                                                    Side &inc_lo, Side &inc_hi)
+{
+    const size_t P = L.plane;
+    const size_t sc = node(L, i, L.ny);
+    if (j == 0) inc_lo = load_side(F, N, P, sc, N_EPY, N_HYPY);
+    if (j == L.ny - 1) inc_hi = load_side(F, N, P, sc, N_EMY, N_HYMY);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 / BF16 kernels.  State planes: F = {Ez, Hx, Hy} (float), N = 8 moving
+// deviations in the order {e+x, e-x, e+y, e-y, hx+x, hx-x, hy+y, hy-y}.
+// Variant "direct": one node per thread, every side read from memory.
+// Variant "sweep": one column per thread over TY rows; the rows above and
+// below stay in registers, so each node's data is fetched once per sweep.
+// Both call neq_core with the same operands and give identical results.
+// ---------------------------------------------------------------------------
+
+template <typename NeqT>
+__device__ __forceinline__ void neq_direct_node(const Lattice &L, const void *__restrict__ srcv,
+                                                void *__restrict__ dstv, float einc, int i, int j)
+{
+    const size_t P = L.plane;
+    const float *F = reinterpret_cast<const float *>(srcv);
+    const NeqT *N = reinterpret_cast<const NeqT *>(F + 3 * P);
+    float *DF = reinterpret_cast<float *>(dstv);
+    NeqT *DN = reinterpret_cast<NeqT *>(DF + 3 * P);
+    const size_t c = node(L, i, j);
+    uint8_t m;
+    float eps, eps_rest;
+    Side l{}, r{}, b{}, t{}, lo{}, hi{};
+    if (!node_setup(L, F, N, i, j, c, m, eps, eps_rest, l, r)) return;
+    const NodeData o = load_node(F, N, P, c);
+    NodeData out;
+    if (j == L.ny) {
+        neq_core<true>(L, i, j, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
+    } else {
+        if (j > 0 && !(m & NB_PEC_YM)) b = load_side(F, N, P, c - L.pitch, N_EPY, N_HYPY);
+        if (j < L.ny - 1 && !(m & NB_PEC_YP)) t = load_side(F, N, P, c + L.pitch, N_EMY, N_HYMY);
+        load_incident_sides(L, F, N, i, j, lo, hi);
+        neq_core<false>(L, i, j, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
+    }
+    store_node(DF, DN, P, c, out);
+}
+
+// Column i over rows [j0, j0 + TY) of the domain, or the companion row when j0 >= ny.
+template <typename NeqT, int TY>
+__device__ __forceinline__ void neq_sweep_column(const Lattice &L, const void *__restrict__ srcv,
+                                                 void *__restrict__ dstv, float einc, int i, int j0)
+{
+    const size_t P = L.plane;
+    const float *F = reinterpret_cast<const float *>(srcv);
+    const NeqT *N = reinterpret_cast<const NeqT *>(F + 3 * P);
+    float *DF = reinterpret_cast<float *>(dstv);
+    NeqT *DN = reinterpret_cast<NeqT *>(DF + 3 * P);
+    if (j0 >= L.ny) {
+        const size_t c = node(L, i, L.ny);
+        uint8_t m;
+        float eps, eps_rest;
+        Side l{}, r{}, b{}, t{}, lo{}, hi{};
+        node_setup(L, F, N, i, L.ny, c, m, eps, eps_rest, l, r);
+        const NodeData o = load_node(F, N, P, c);
+        NodeData out;
+        neq_core<true>(L, i, L.ny, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
+        store_node(DF, DN, P, c, out);
+        return;
+    }
+    const int j1 = min(j0 + TY, L.ny);
+    Side below{};
+    if (j0 > 0) below = load_side(F, N, P, node(L, i, j0 - 1), N_EPY, N_HYPY);
+    NodeData cur = load_node(F, N, P, node(L, i, j0));
+    for (int j = j0; j < j1; ++j) {
+        const size_t c = node(L, i, j);
+        NodeData nxt{};
+        if (j + 1 < L.ny) nxt = load_node(F, N, P, c + L.pitch);
+        const Side above{nxt.ez, nxt.hx, nxt.hy, nxt.n[N_EMY], nxt.n[N_HYMY]};
+        uint8_t m;
+        float eps, eps_rest;
+        Side l{}, r{}, lo{}, hi{};
+        if (node_setup(L, F, N, i, j, c, m, eps, eps_rest, l, r)) {
+            load_incident_sides(L, F, N, i, j, lo, hi);
+            NodeData out;
+            neq_core<false>(L, i, j, m, eps, eps_rest, cur, l, r, below, above, lo, hi, einc, out);
+            store_node(DF, DN, P, c, out);
+        }
+        below = Side{cur.ez, cur.hx, cur.hy, cur.n[N_EPY], cur.n[N_HYPY]};
+        cur = nxt;
+    }
 }
 
 template <typename NeqT>
@@ -168,113 +410,241 @@ __global__ __launch_bounds__(BX *BY) void k_step_neq(Lattice L, const void *__re
     const int i = blockIdx.x * BX + threadIdx.x;
     const int j = blockIdx.y * BY + threadIdx.y;
     if (i >= L.nx || j > L.ny) return;
-    const size_t P = L.plane;
-    const NeqState<NeqT> S = neq_view<NeqT>(const_cast<void *>(srcv), P);
-    const NeqState<NeqT> D = neq_view<NeqT>(dstv, P);
-    const size_t c = node(L, i, j);
-    const float keep = (float)(1.0 - OPEN_DELTA);
-    const float delta = (float)OPEN_DELTA;
-    const float sixth = 1.0f / 6.0f, third = 1.0f / 3.0f;
+    neq_direct_node<NeqT>(L, srcv, dstv, einc, i, j);
+}
 
-    uint8_t m = 0;
-    float eps = 1.0f, eps_rest = (float)(1.0 - 2.0 / 3.0);
-    const bool strip_row = (j == L.ny);
-    if (!strip_row) {
-        m = L.mask[c];
-        const int mat = m & 3;
-        if (mat == MAT_PEC) return;
-        eps = (float)L.eps[mat];
-        eps_rest = (float)L.eps_rest[mat];
-    }
+constexpr int SWEEP_THREADS = 256;
 
-    // own fields and deviations at time n
-    const float ez0 = S.F[0 * P + c], hx0 = S.F[1 * P + c], hy0 = S.F[2 * P + c];
-    float n0[8];
+template <typename NeqT, int TY>
+__global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_sweep(Lattice L, const void *__restrict__ srcv,
+                                                                   void *__restrict__ dstv, float einc)
+{
+    const int i = blockIdx.x * SWEEP_THREADS + threadIdx.x;
+    if (i >= L.nx) return;
+    neq_sweep_column<NeqT, TY>(L, srcv, dstv, einc, i, blockIdx.y * TY);
+}
+
+// ---------------------------------------------------------------------------
+// Variant "vector sweep": each thread owns V adjacent nodes of a row, moves
+// every plane with one V-wide load or store, exchanges the x-neighbours with
+// the adjacent lanes (the wavefront's two edge lanes read theirs from
+// memory) and sweeps TY rows keeping the rows above and below in registers.
+// Conductor and padding nodes store zeros, which is what they hold.
+// ---------------------------------------------------------------------------
+
+template <typename T, int V> struct VecOf;
+template <> struct VecOf<float, 2> { typedef float __attribute__((ext_vector_type(2))) type; };
+template <> struct VecOf<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
+template <> struct VecOf<__bf16, 2> { typedef __bf16 __attribute__((ext_vector_type(2))) type; };
+template <> struct VecOf<__bf16, 4> { typedef __bf16 __attribute__((ext_vector_type(4))) type; };
+template <int V> struct MaskVec;
+template <> struct MaskVec<2> { typedef unsigned short type; };
+template <> struct MaskVec<4> { typedef unsigned int type; };
+
+template <typename T, int V>
+__device__ __forceinline__ void vload(const T *p, float (&out)[V])
+{
+    const typename VecOf<T, V>::type v = *reinterpret_cast<const typename VecOf<T, V>::type *>(p);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) n0[k] = ld(&S.N[k * P + c]);
-    // own post-collision moving populations (used by edges and conductor links)
-    const float s_epx = (ez0 - hy0) * sixth - n0[N_EPX];
-    const float s_emx = (ez0 + hy0) * sixth - n0[N_EMX];
-    const float s_epy = (ez0 + hx0) * sixth - n0[N_EPY];
-    const float s_emy = (ez0 - hx0) * sixth - n0[N_EMY];
-    const float s_hxpx = hx0 * sixth - n0[N_HXPX];
-    const float s_hxmx = hx0 * sixth - n0[N_HXMX];
-    const float s_hypy = hy0 * sixth - n0[N_HYPY];
-    const float s_hymy = hy0 * sixth - n0[N_HYMY];
-    // rest populations stream in place: f*_r = f_r^eq - N_r with the sum rules
-    const float r_e = eps_rest * ez0 + (n0[N_EPX] + n0[N_EMX] + n0[N_EPY] + n0[N_EMY]);
-    const float r_hx = hx0 * third + (n0[N_HXPX] + n0[N_HXMX] + n0[N_EPY] - n0[N_EMY]);
-    const float r_hy = hy0 * third + (n0[N_HYPY] + n0[N_HYMY] - n0[N_EPX] + n0[N_EMX]);
+    for (int k = 0; k < V; ++k) out[k] = (float)v[k];
+}
 
-    float e_px, hx_px, e_mx, hx_mx, e_py, hy_py, e_my, hy_my;
-    // +x from (i-1, j)
-    if (i == 0) { e_px = einc * third; hx_px = 0.0f; }
-    else if (m & NB_PEC_XM) { e_px = -s_emx; hx_px = -s_hxmx; }
-    else {
-        const size_t s = c - 1;
-        const float ez = S.F[0 * P + s], hx = S.F[1 * P + s], hy = S.F[2 * P + s];
-        e_px = (ez - hy) * sixth - ld(&S.N[N_EPX * P + s]);
-        hx_px = hx * sixth - ld(&S.N[N_HXPX * P + s]);
-    }
-    // -x from (i+1, j)
-    if (i == L.nx - 1) {
-        if (strip_row) { e_mx = 0.0f; hx_mx = 0.0f; }
-        else { e_mx = keep * s_emx; hx_mx = keep * s_hxmx; }
-    } else if (m & NB_PEC_XP) { e_mx = -s_epx; hx_mx = -s_hxpx; }
-    else {
-        const size_t s = c + 1;
-        const float ez = S.F[0 * P + s], hx = S.F[1 * P + s], hy = S.F[2 * P + s];
-        e_mx = (ez + hy) * sixth - ld(&S.N[N_EMX * P + s]);
-        hx_mx = hx * sixth - ld(&S.N[N_HXMX * P + s]);
-    }
-    if (strip_row) {
-        // uniform in y: the +-y populations stay in their node
-        e_py = s_epy; hy_py = s_hypy; e_my = s_emy; hy_my = s_hymy;
-    } else {
-        const size_t strip = node(L, i, L.ny);
-        float i_epy = 0.0f, i_hypy = 0.0f, i_emy = 0.0f, i_hymy = 0.0f;
-        if (j == 0 || j == L.ny - 1) {
-            const float ez = S.F[0 * P + strip], hx = S.F[1 * P + strip], hy = S.F[2 * P + strip];
-            i_epy = (ez + hx) * sixth - ld(&S.N[N_EPY * P + strip]);
-            i_hypy = hy * sixth - ld(&S.N[N_HYPY * P + strip]);
-            i_emy = (ez - hx) * sixth - ld(&S.N[N_EMY * P + strip]);
-            i_hymy = hy * sixth - ld(&S.N[N_HYMY * P + strip]);
-        }
-        // +y from (i, j-1)
-        if (j == 0) { e_py = keep * s_epy + delta * i_epy; hy_py = keep * s_hypy + delta * i_hypy; }
-        else if (m & NB_PEC_YM) { e_py = -s_emy; hy_py = -s_hymy; }
-        else {
-            const size_t s = c - L.pitch;
-            const float ez = S.F[0 * P + s], hx = S.F[1 * P + s];
-            e_py = (ez + hx) * sixth - ld(&S.N[N_EPY * P + s]);
-            hy_py = S.F[2 * P + s] * sixth - ld(&S.N[N_HYPY * P + s]);
-        }
-        // -y from (i, j+1)
-        if (j == L.ny - 1) { e_my = keep * s_emy + delta * i_emy; hy_my = keep * s_hymy + delta * i_hymy; }
-        else if (m & NB_PEC_YP) { e_my = -s_epy; hy_my = -s_hypy; }
-        else {
-            const size_t s = c + L.pitch;
-            const float ez = S.F[0 * P + s], hx = S.F[1 * P + s];
-            e_my = (ez - hx) * sixth - ld(&S.N[N_EMY * P + s]);
-            hy_my = S.F[2 * P + s] * sixth - ld(&S.N[N_HYMY * P + s]);
-        }
-    }
+template <typename T, int V>
+__device__ __forceinline__ void vstore(T *p, const float (&in)[V])
+{
+    typename VecOf<T, V>::type v;
+#pragma unroll
+    for (int k = 0; k < V; ++k) v[k] = (T)in[k];
+    put(reinterpret_cast<typename VecOf<T, V>::type *>(p), v);
+}
 
-    const float dz = r_e + e_px + e_mx + (e_py + e_my);
-    const float ez = dz / eps;
-    const float hx = r_hx + hx_px + hx_mx + (e_py - e_my);
-    const float hy = r_hy + (hy_py + hy_my) + (e_mx - e_px);
-    D.F[0 * P + c] = ez;
-    D.F[1 * P + c] = hx;
-    D.F[2 * P + c] = hy;
-    st(&D.N[N_EPX * P + c], e_px - (ez - hy) * sixth);
-    st(&D.N[N_EMX * P + c], e_mx - (ez + hy) * sixth);
-    st(&D.N[N_EPY * P + c], e_py - (ez + hx) * sixth);
-    st(&D.N[N_EMY * P + c], e_my - (ez - hx) * sixth);
-    st(&D.N[N_HXPX * P + c], hx_px - hx * sixth);
-    st(&D.N[N_HXMX * P + c], hx_mx - hx * sixth);
-    st(&D.N[N_HYPY * P + c], hy_py - hy * sixth);
-    st(&D.N[N_HYMY * P + c], hy_my - hy * sixth);
+template <int V>
+struct RowData {
+    float ez[V], hx[V], hy[V];
+    float n[8][V];
+};
+
+template <typename NeqT, int V>
+__device__ __forceinline__ void load_row(const float *F, const NeqT *N, size_t P, size_t c, RowData<V> &r)
+{
+    vload<float, V>(F + c, r.ez);
+    vload<float, V>(F + P + c, r.hx);
+    vload<float, V>(F + 2 * P + c, r.hy);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) vload<NeqT, V>(N + q * P + c, r.n[q]);
+}
+
+template <int V>
+__device__ __forceinline__ void zero_row(RowData<V> &r)
+{
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        r.ez[k] = r.hx[k] = r.hy[k] = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r.n[q][k] = 0.0f;
+    }
+}
+
+template <typename NeqT, int V, int TY>
+__device__ __forceinline__ void neq_vsweep_column(const Lattice &L, const void *__restrict__ srcv,
+                                                  void *__restrict__ dstv, float einc, int col, int j0)
+{
+    const size_t P = L.plane;
+    const float *F = reinterpret_cast<const float *>(srcv);
+    const NeqT *N = reinterpret_cast<const NeqT *>(F + 3 * P);
+    float *DF = reinterpret_cast<float *>(dstv);
+    NeqT *DN = reinterpret_cast<NeqT *>(DF + 3 * P);
+    const int i0 = col * V;
+    const int lane = threadIdx.x & 63;
+    const bool active = i0 < L.nx;
+    if (j0 >= L.ny) {
+        // companion row: per node, as in the other variants
+        if (active)
+            for (int v = 0; v < V; ++v)
+                if (i0 + v < L.nx) neq_direct_node<NeqT>(L, srcv, dstv, einc, i0 + v, L.ny);
+        return;
+    }
+    const int j1 = min(j0 + TY, L.ny);
+    RowData<V> below, cur, nxt;
+    zero_row(below);
+    zero_row(cur);
+    if (active && j0 > 0) load_row<NeqT, V>(F, N, P, node(L, i0, j0 - 1), below);
+    if (active) load_row<NeqT, V>(F, N, P, node(L, i0, j0), cur);
+    for (int j = j0; j < j1; ++j) {
+        const size_t c = node(L, i0, j);
+        zero_row(nxt);
+        if (active && j + 1 < L.ny) load_row<NeqT, V>(F, N, P, c + L.pitch, nxt);
+        // x-neighbours across lanes (all lanes take part in the exchange)
+        Side xl, xr;
+        xl.ez = __shfl_up(cur.ez[V - 1], 1, 64);
+        xl.hx = __shfl_up(cur.hx[V - 1], 1, 64);
+        xl.hy = __shfl_up(cur.hy[V - 1], 1, 64);
+        xl.na = __shfl_up(cur.n[N_EPX][V - 1], 1, 64);
+        xl.nb = __shfl_up(cur.n[N_HXPX][V - 1], 1, 64);
+        xr.ez = __shfl_down(cur.ez[0], 1, 64);
+        xr.hx = __shfl_down(cur.hx[0], 1, 64);
+        xr.hy = __shfl_down(cur.hy[0], 1, 64);
+        xr.na = __shfl_down(cur.n[N_EMX][0], 1, 64);
+        xr.nb = __shfl_down(cur.n[N_HXMX][0], 1, 64);
+        if (!active) continue;
+        if (lane == 0 && i0 > 0) xl = load_side(F, N, P, c - 1, N_EPX, N_HXPX);
+        if (lane == 63 && i0 + V < L.nx) xr = load_side(F, N, P, c + V, N_EMX, N_HXMX);
+        const typename MaskVec<V>::type mv = *reinterpret_cast<const typename MaskVec<V>::type *>(L.mask + c);
+        RowData<V> out;
+        zero_row(out);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int i = i0 + v;
+            const uint8_t m = (uint8_t)(mv >> (8 * v));
+            const int mat = m & 3;
+            if (i >= L.nx || mat == MAT_PEC) continue;
+            const float eps = (float)L.eps[mat];
+            const float eps_rest = (float)L.eps_rest[mat];
+            NodeData o;
+            o.ez = cur.ez[v];
+            o.hx = cur.hx[v];
+            o.hy = cur.hy[v];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) o.n[q] = cur.n[q][v];
+            const Side l = v == 0 ? xl : Side{cur.ez[v - 1], cur.hx[v - 1], cur.hy[v - 1], cur.n[N_EPX][v - 1], cur.n[N_HXPX][v - 1]};
+            const Side r = v == V - 1 ? xr : Side{cur.ez[v + 1], cur.hx[v + 1], cur.hy[v + 1], cur.n[N_EMX][v + 1], cur.n[N_HXMX][v + 1]};
+            const Side b{below.ez[v], below.hx[v], below.hy[v], below.n[N_EPY][v], below.n[N_HYPY][v]};
+            const Side t{nxt.ez[v], nxt.hx[v], nxt.hy[v], nxt.n[N_EMY][v], nxt.n[N_HYMY][v]};
+            Side lo{}, hi{};
+            load_incident_sides(L, F, N, i, j, lo, hi);
+            NodeData res;
+            neq_core<false>(L, i, j, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, res);
+            out.ez[v] = res.ez;
+            out.hx[v] = res.hx;
+            out.hy[v] = res.hy;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) out.n[q][v] = res.n[q];
+        }
+        vstore<float, V>(DF + c, out.ez);
+        vstore<float, V>(DF + P + c, out.hx);
+        vstore<float, V>(DF + 2 * P + c, out.hy);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) vstore<NeqT, V>(DN + q * P + c, out.n[q]);
+        below = cur;
+        cur = nxt;
+    }
+}
+
+template <typename NeqT, int V, int TY>
+__global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_vsweep(Lattice L, const void *__restrict__ srcv,
+                                                                    void *__restrict__ dstv, float einc)
+{
+    neq_vsweep_column<NeqT, V, TY>(L, srcv, dstv, einc, blockIdx.x * SWEEP_THREADS + threadIdx.x, blockIdx.y * TY);
+}
+
+// ---------------------------------------------------------------------------
+// Batched steps: block b works on tiles[b] of solve tiles[b].slot at that
+// solve's own step n (finished solves return at once).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double batch_incident(const SolveDesc &d, int64_t n)
+{
+    return n < d.ramp_end ? d.src_tab[n] : d.src_tab[d.ramp_end + n % d.T];
+}
+
+__global__ __launch_bounds__(BX *BY) void k_step_f64_batch(SolveDesc *__restrict__ D, const Tile *__restrict__ tiles)
+{
+    const Tile t = tiles[blockIdx.x];
+    const SolveDesc &d = D[t.slot];
+    const int64_t n = d.n;
+    if (n >= d.steps) return;
+    const int i = t.tx * BX + threadIdx.x;
+    const int j = t.ty * BY + threadIdx.y;
+    if (i >= d.L.nx || j > d.L.ny) return;
+    const bool in_window = n + 1 > d.steps - d.window;
+    f64_node(d.L, (const double *)d.state[n & 1], (double *)d.state[(n + 1) & 1], in_window ? d.fields : nullptr,
+             batch_incident(d, n), i, j);
+}
+
+template <typename NeqT>
+__global__ __launch_bounds__(BX *BY) void k_step_neq_batch(SolveDesc *__restrict__ D, const Tile *__restrict__ tiles)
+{
+    const Tile t = tiles[blockIdx.x];
+    const SolveDesc &d = D[t.slot];
+    const int64_t n = d.n;
+    if (n >= d.steps) return;
+    const int i = t.tx * BX + threadIdx.x;
+    const int j = t.ty * BY + threadIdx.y;
+    if (i >= d.L.nx || j > d.L.ny) return;
+    neq_direct_node<NeqT>(d.L, d.state[n & 1], d.state[(n + 1) & 1], (float)batch_incident(d, n), i, j);
+}
+
+template <typename NeqT, int TY>
+__global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_sweep_batch(SolveDesc *__restrict__ D,
+                                                                         const Tile *__restrict__ tiles)
+{
+    const Tile t = tiles[blockIdx.x];
+    const SolveDesc &d = D[t.slot];
+    const int64_t n = d.n;
+    if (n >= d.steps) return;
+    const int i = t.tx * SWEEP_THREADS + threadIdx.x;
+    if (i >= d.L.nx) return;
+    neq_sweep_column<NeqT, TY>(d.L, d.state[n & 1], d.state[(n + 1) & 1], (float)batch_incident(d, n), i, t.ty * TY);
+}
+
+template <typename NeqT, int V, int TY>
+__global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_vsweep_batch(SolveDesc *__restrict__ D,
+                                                                          const Tile *__restrict__ tiles)
+{
+    const Tile t = tiles[blockIdx.x];
+    const SolveDesc &d = D[t.slot];
+    const int64_t n = d.n;
+    if (n >= d.steps) return;
+    neq_vsweep_column<NeqT, V, TY>(d.L, d.state[n & 1], d.state[(n + 1) & 1], (float)batch_incident(d, n),
+                                   t.tx * SWEEP_THREADS + threadIdx.x, t.ty * TY);
+}
+
+__global__ void k_advance(SolveDesc *D, int nslots)
+{
+    for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
+        const int64_t n = D[s].n;
+        if (n < D[s].steps) D[s].n = n + 1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -282,11 +652,10 @@ __global__ __launch_bounds__(BX *BY) void k_step_neq(Lattice L, const void *__re
 // Ez^2, Hx^2, Hy^2 and Hx Hy in FP64.  One thread per sample, no atomics.
 // ---------------------------------------------------------------------------
 
-__global__ void k_contour_f64(Lattice L, const double *__restrict__ fld, ContourDev C)
+__device__ __forceinline__ void contour_sample_f64(const Lattice &L, const double *__restrict__ fld,
+                                                   const ContourDev &C, int k)
 {
 #pragma clang fp contract(off)
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= C.n) return;
     const size_t P = L.plane;
     const size_t c00 = node(L, C.i0[k], C.j0[k]);
     const size_t c10 = c00 + L.pitch;
@@ -304,10 +673,10 @@ __global__ void k_contour_f64(Lattice L, const double *__restrict__ fld, Contour
     C.acc[3 * C.n + k] += v[1] * v[2];
 }
 
-__global__ void k_contour_f32(Lattice L, const float *__restrict__ fld, ContourDev C)
+__device__ __forceinline__ void contour_sample_f32(const Lattice &L, const float *__restrict__ fld,
+                                                   const ContourDev &C, int k)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= C.n) return;
+#pragma clang fp contract(off)
     const size_t P = L.plane;
     const size_t c00 = node(L, C.i0[k], C.j0[k]);
     const size_t c10 = c00 + L.pitch;
@@ -323,6 +692,31 @@ __global__ void k_contour_f32(Lattice L, const float *__restrict__ fld, ContourD
     C.acc[1 * C.n + k] += (double)(v[1] * v[1]);
     C.acc[2 * C.n + k] += (double)(v[2] * v[2]);
     C.acc[3 * C.n + k] += (double)(v[1] * v[2]);
+}
+
+__global__ void k_contour_f64(Lattice L, const double *__restrict__ fld, ContourDev C)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < C.n) contour_sample_f64(L, fld, C, k);
+}
+
+__global__ void k_contour_f32(Lattice L, const float *__restrict__ fld, ContourDev C)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < C.n) contour_sample_f32(L, fld, C, k);
+}
+
+// Batched contour accumulation: block row s serves solve s when the step it
+// just took ends inside its averaging window.
+__global__ void k_contour_batch(SolveDesc *__restrict__ D)
+{
+    const SolveDesc &d = D[blockIdx.y];
+    const int64_t n = d.n;
+    if (n >= d.steps || !(n + 1 > d.steps - d.window)) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.C.n) return;
+    if (d.precision == 0) contour_sample_f64(d.L, d.fields, d.C, k);
+    else contour_sample_f32(d.L, reinterpret_cast<const float *>(d.state[(n + 1) & 1]), d.C, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -461,12 +855,33 @@ hipError_t launch_step_f64(const Lattice &L, const double *src, double *dst, dou
     return hipGetLastError();
 }
 
-hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, void *dst, double einc, hipStream_t s)
+hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, void *dst, double einc, hipStream_t s,
+                           int variant)
 {
-    if (precision == 1)
-        hipLaunchKernelGGL(k_step_neq<float>, step_grid(L), dim3(BX, BY), 0, s, L, src, dst, (float)einc);
-    else
-        hipLaunchKernelGGL(k_step_neq<__bf16>, step_grid(L), dim3(BX, BY), 0, s, L, src, dst, (float)einc);
+    const float e = (float)einc;
+    const dim3 sweep_block(SWEEP_THREADS);
+    auto sweep_grid = [&](int v, int ty) {
+        return dim3((L.nx + SWEEP_THREADS * v - 1) / (SWEEP_THREADS * v), (L.ny + ty - 1) / ty + 1);
+    };
+#define JLB_NEQ_LAUNCH(T)                                                                                                    \
+    switch (variant) {                                                                                                       \
+    case NEQ_SWEEP8: hipLaunchKernelGGL((k_step_neq_sweep<T, 8>), sweep_grid(1, 8), sweep_block, 0, s, L, src, dst, e); break;      \
+    case NEQ_SWEEP16: hipLaunchKernelGGL((k_step_neq_sweep<T, 16>), sweep_grid(1, 16), sweep_block, 0, s, L, src, dst, e); break;   \
+    case NEQ_SWEEP32: hipLaunchKernelGGL((k_step_neq_sweep<T, 32>), sweep_grid(1, 32), sweep_block, 0, s, L, src, dst, e); break;   \
+    case NEQ_V2_T4: hipLaunchKernelGGL((k_step_neq_vsweep<T, 2, 4>), sweep_grid(2, 4), sweep_block, 0, s, L, src, dst, e); break;   \
+    case NEQ_V2_T8: hipLaunchKernelGGL((k_step_neq_vsweep<T, 2, 8>), sweep_grid(2, 8), sweep_block, 0, s, L, src, dst, e); break;   \
+    case NEQ_V2_T16: hipLaunchKernelGGL((k_step_neq_vsweep<T, 2, 16>), sweep_grid(2, 16), sweep_block, 0, s, L, src, dst, e); break; \
+    case NEQ_V4_T4: hipLaunchKernelGGL((k_step_neq_vsweep<T, 4, 4>), sweep_grid(4, 4), sweep_block, 0, s, L, src, dst, e); break;   \
+    case NEQ_V4_T8: hipLaunchKernelGGL((k_step_neq_vsweep<T, 4, 8>), sweep_grid(4, 8), sweep_block, 0, s, L, src, dst, e); break;   \
+    case NEQ_V4_T16: hipLaunchKernelGGL((k_step_neq_vsweep<T, 4, 16>), sweep_grid(4, 16), sweep_block, 0, s, L, src, dst, e); break; \
+    default: hipLaunchKernelGGL(k_step_neq<T>, step_grid(L), dim3(BX, BY), 0, s, L, src, dst, e); break;                 \
+    }
+    if (precision == 1) {
+        JLB_NEQ_LAUNCH(float)
+    } else {
+        JLB_NEQ_LAUNCH(__bf16)
+    }
+#undef JLB_NEQ_LAUNCH
     return hipGetLastError();
 }
 
@@ -484,6 +899,80 @@ hipError_t launch_contour(int precision, const Lattice &L, const void *fields, c
 hipError_t launch_reduce(const ContourDev &C, double inv_window, double f0, double m0, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(RED_THREADS), 0, s, C, inv_window, f0, m0, out);
+    return hipGetLastError();
+}
+
+void tile_shape(int precision, int variant, int &cols, int &rows)
+{
+    if (precision == 0 || variant == NEQ_DIRECT || variant < 0 || variant >= NEQ_VARIANTS) {
+        cols = BX;
+        rows = BY;
+        return;
+    }
+    static const int vcols[NEQ_VARIANTS] = {BX, 1, 1, 1, 2, 2, 2, 4, 4, 4};
+    static const int vrows[NEQ_VARIANTS] = {BY, 8, 16, 32, 4, 8, 16, 4, 8, 16};
+    cols = SWEEP_THREADS * vcols[variant];
+    rows = vrows[variant];
+}
+
+hipError_t launch_step_batch(int precision, int variant, SolveDesc *d, const Tile *tiles, int ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (precision == 0) {
+        hipLaunchKernelGGL(k_step_f64_batch, dim3(ntiles), dim3(BX, BY), 0, s, d, tiles);
+        return hipGetLastError();
+    }
+    const dim3 g(ntiles), b(SWEEP_THREADS);
+#define JLB_BATCH_LAUNCH(T)                                                                                         \
+    switch (variant) {                                                                                              \
+    case NEQ_SWEEP8: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 8>), g, b, 0, s, d, tiles); break;              \
+    case NEQ_SWEEP16: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 16>), g, b, 0, s, d, tiles); break;            \
+    case NEQ_SWEEP32: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 32>), g, b, 0, s, d, tiles); break;            \
+    case NEQ_V2_T4: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 4>), g, b, 0, s, d, tiles); break;           \
+    case NEQ_V2_T8: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 8>), g, b, 0, s, d, tiles); break;           \
+    case NEQ_V2_T16: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 16>), g, b, 0, s, d, tiles); break;         \
+    case NEQ_V4_T4: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 4>), g, b, 0, s, d, tiles); break;           \
+    case NEQ_V4_T8: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 8>), g, b, 0, s, d, tiles); break;           \
+    case NEQ_V4_T16: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 16>), g, b, 0, s, d, tiles); break;         \
+    default: hipLaunchKernelGGL(k_step_neq_batch<T>, g, dim3(BX, BY), 0, s, d, tiles); break;                      \
+    }
+    if (precision == 1) {
+        JLB_BATCH_LAUNCH(float)
+    } else {
+        JLB_BATCH_LAUNCH(__bf16)
+    }
+#undef JLB_BATCH_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_contour_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s)
+{
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_contour_batch, dim3((max_nc + 127) / 128, nslots), dim3(128), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(SolveDesc *d, int nslots, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, s, d, nslots);
+    return hipGetLastError();
+}
+
+// Plain copy, 16 bytes per lane: the reference kernel for bandwidth and
+// for calibrating memory-traffic counters.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, size_t n16)
+{
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
+        put(&dst[k], src[k]);
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    const size_t n16 = bytes / 16;
+    const size_t blocks = std::min<size_t>((n16 + 255) / 256, (size_t)256 * 64);
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const u32x4 *)src, (u32x4 *)dst, n16);
     return hipGetLastError();
 }
 

@@ -1,19 +1,419 @@
-// Batched engine entry points (filled in below the single-solve path).
+// Batched engine: many independent solves (the points of a design map, or
+// requests as they arrive) resident on one device and stepped together.
+//
+// Each admitted solve owns a device workspace with the same layout as a
+// single solve plus its table of incident-wave values.  Its descriptor in
+// device memory carries its step counter, which the device advances, so a
+// chunk of K lattice steps -- per step one launch per precision over the
+// tiles of every resident solve, one batched contour launch and one advance
+// launch -- is captured once in a hipGraph and replayed while the set of
+// resident solves is unchanged.  Solves that finish inside a chunk idle
+// (their tiles return at once) until the chunk boundary, where the engine
+// reduces their contour sums, returns their memory and admits waiting
+// requests that fit the byte budget (continuous batching).
+//
+// Every per-node operation is the same device code as in a single solve and
+// the per-solve sums run in the same order, so a solve's result does not
+// depend on what else is resident: it equals the jlb_solve result bit for bit.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <vector>
 
 #include "../../include/jlb.h"
 #include "jlb_host_internal.h"
 
 using namespace jlb;
 
+namespace {
+
+constexpr int64_t CHUNK = 128;  // lattice steps per captured graph
+
+double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    jlb_problem prob;
+    Plan plan;
+    int status = JLB_REQ_QUEUED;
+    jlb_result res{};
+    char *ws = nullptr;       // device: workspace followed by the incident table
+    size_t footprint = 0;
+    int64_t n = 0;            // host mirror of the device step counter
+    int64_t ramp_end = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    double loop_ms_acc = 0;
+};
+
+}  // namespace
+
+struct jlb_engine {
+    size_t budget = 0;
+    int max_slots = 1;
+    hipStream_t s = nullptr;
+    bool own = false;
+    uint64_t next_ticket = 1;
+    std::map<uint64_t, Request> reqs;
+    std::deque<uint64_t> queue;
+    std::vector<uint64_t> resident;
+    size_t in_use = 0;
+    int finished = 0;
+    // device-side batch description
+    SolveDesc *d_desc = nullptr;
+    Tile *d_tiles = nullptr;
+    size_t tiles_cap = 0;
+    int ntiles[3] = {0, 0, 0};
+    int tile_off[3] = {0, 0, 0};
+    int variant[3] = {0, 0, 0};
+    int max_nc = 0;
+    bool dirty = true;
+    hipGraphExec_t graph = nullptr;
+};
+
+namespace {
+
+size_t footprint_of(const Plan &q)
+{
+    const int64_t ramp_end = (int64_t)std::ceil(q.ramp_steps);
+    return q.ws_bytes + (size_t)(ramp_end + q.T) * sizeof(double);
+}
+
+int admit_one(jlb_engine *e, uint64_t t)
+{
+    Request &r = e->reqs[t];
+    const Plan &q = r.plan;
+    hipError_t err = hipMallocAsync((void **)&r.ws, r.footprint, e->s);
+    if (err != hipSuccess) return fail(JLB_E_OOM, "hipMallocAsync(%zu): %s", r.footprint, hipGetErrorString(err));
+    int rc = upload_setup(q, r.ws, e->s);
+    if (rc) return rc;
+    // incident values: the ramp steps one by one, then one period indexed by n mod T
+    r.ramp_end = (int64_t)std::ceil(q.ramp_steps);
+    std::vector<double> tab((size_t)(r.ramp_end + q.T));
+    for (int64_t n = 0; n < r.ramp_end; ++n) tab[n] = incident(q, n);
+    for (int64_t k = 0; k < q.T; ++k) {
+        const int64_t n = r.ramp_end + ((k - r.ramp_end % q.T) + q.T) % q.T;  // first n >= ramp_end with n % T == k
+        tab[r.ramp_end + k] = incident(q, n);
+    }
+    err = hipMemcpyAsync(r.ws + q.ws_bytes, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, e->s);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->s);
+    if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine upload: %s", hipGetErrorString(err));
+    r.status = JLB_REQ_RUNNING;
+    r.n = 0;
+    r.t_admit = now_ms();
+    e->in_use += r.footprint;
+    e->resident.push_back(t);
+    e->dirty = true;
+    return JLB_OK;
+}
+
+// First fit in arrival order: admit every queued request that fits.
+int admit(jlb_engine *e)
+{
+    for (auto it = e->queue.begin(); it != e->queue.end();) {
+        if ((int)e->resident.size() >= e->max_slots) break;
+        Request &r = e->reqs[*it];
+        if (e->in_use + r.footprint <= e->budget) {
+            const uint64_t t = *it;
+            it = e->queue.erase(it);
+            int rc = admit_one(e, t);
+            if (rc) {
+                Request &rr = e->reqs[t];
+                rr.status = JLB_REQ_FAILED;
+                if (rr.ws) (void)hipFreeAsync(rr.ws, e->s);
+                rr.ws = nullptr;
+                return rc;
+            }
+        } else {
+            ++it;
+        }
+    }
+    return JLB_OK;
+}
+
+int rebuild(jlb_engine *e)
+{
+    if (e->graph) {
+        (void)hipGraphExecDestroy(e->graph);
+        e->graph = nullptr;
+    }
+    const int ns = (int)e->resident.size();
+    std::vector<SolveDesc> desc(ns);
+    std::vector<Tile> tiles[3];
+    e->max_nc = 0;
+    for (int p = 0; p < 3; ++p) e->variant[p] = p == 0 ? 0 : jlb::step_variant(p);
+    for (int k = 0; k < ns; ++k) {
+        Request &r = e->reqs[e->resident[k]];
+        const Plan &q = r.plan;
+        SolveDesc &d = desc[k];
+        memset(&d, 0, sizeof(d));
+        d.L = lattice_of(q, (const uint8_t *)(r.ws + q.off_mask));
+        d.state[0] = r.ws + q.off_state[0];
+        d.state[1] = r.ws + q.off_state[1];
+        d.fields = q.prob.precision == JLB_FP64 ? (double *)(r.ws + q.off_fields) : nullptr;
+        d.src_tab = (const double *)(r.ws + q.ws_bytes);
+        d.ramp_end = r.ramp_end;
+        d.T = q.T;
+        d.n = r.n;
+        d.steps = q.prob.steps;
+        d.window = q.window;
+        d.C = contour_of(q, r.ws);
+        d.precision = q.prob.precision;
+        e->max_nc = std::max(e->max_nc, q.nc);
+        const int p = q.prob.precision;
+        int cols, rows;
+        tile_shape(p, e->variant[p], cols, rows);
+        const int tx = (q.nx + cols - 1) / cols;
+        // node tiles cover rows 0..ny (the companion row included); row sweeps
+        // cover the domain rows and give the companion row a tile row of its own
+        const bool sweep = p != JLB_FP64 && e->variant[p] != NEQ_DIRECT;
+        const int ty = sweep ? (q.ny + rows - 1) / rows + 1 : (q.ny + 1 + rows - 1) / rows;
+        for (int y = 0; y < ty; ++y)
+            for (int x = 0; x < tx; ++x) tiles[p].push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
+    }
+    size_t total = 0;
+    for (int p = 0; p < 3; ++p) {
+        e->tile_off[p] = (int)total;
+        e->ntiles[p] = (int)tiles[p].size();
+        total += tiles[p].size();
+    }
+    hipError_t err = hipSuccess;
+    if (!e->d_desc) err = hipMallocAsync((void **)&e->d_desc, sizeof(SolveDesc) * e->max_slots, e->s);
+    if (err == hipSuccess && total > e->tiles_cap) {
+        if (e->d_tiles) (void)hipFreeAsync(e->d_tiles, e->s);
+        e->tiles_cap = std::max(total, 2 * e->tiles_cap);
+        err = hipMallocAsync((void **)&e->d_tiles, sizeof(Tile) * e->tiles_cap, e->s);
+    }
+    if (err == hipSuccess && ns > 0)
+        err = hipMemcpyAsync(e->d_desc, desc.data(), sizeof(SolveDesc) * ns, hipMemcpyHostToDevice, e->s);
+    for (int p = 0; p < 3 && err == hipSuccess; ++p)
+        if (!tiles[p].empty())
+            err = hipMemcpyAsync(e->d_tiles + e->tile_off[p], tiles[p].data(), sizeof(Tile) * tiles[p].size(),
+                                 hipMemcpyHostToDevice, e->s);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->s);  // host vectors go out of scope
+    if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine rebuild: %s", hipGetErrorString(err));
+    e->dirty = false;
+    return JLB_OK;
+}
+
+hipError_t launch_batch_step(jlb_engine *e)
+{
+    const int ns = (int)e->resident.size();
+    hipError_t err = hipSuccess;
+    for (int p = 0; p < 3 && err == hipSuccess; ++p)
+        err = launch_step_batch(p, e->variant[p], e->d_desc, e->d_tiles + e->tile_off[p], e->ntiles[p], e->s);
+    if (err == hipSuccess) err = launch_contour_batch(e->d_desc, ns, e->max_nc, e->s);
+    if (err == hipSuccess) err = launch_advance(e->d_desc, ns, e->s);
+    return err;
+}
+
+int capture(jlb_engine *e)
+{
+    hipGraph_t g;
+    if (hipStreamBeginCapture(e->s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(JLB_E_DEVICE, "engine capture begin");
+    hipError_t err = hipSuccess;
+    for (int64_t k = 0; k < CHUNK && err == hipSuccess; ++k) err = launch_batch_step(e);
+    hipError_t err2 = hipStreamEndCapture(e->s, &g);
+    if (err != hipSuccess || err2 != hipSuccess) return fail(JLB_E_DEVICE, "engine capture failed");
+    err = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine graph instantiate: %s", hipGetErrorString(err));
+    return JLB_OK;
+}
+
+// Reduces and returns every resident solve whose steps are all done.
+int harvest(jlb_engine *e)
+{
+    for (size_t k = 0; k < e->resident.size();) {
+        Request &r = e->reqs[e->resident[k]];
+        const Plan &q = r.plan;
+        if (r.n < q.prob.steps) {
+            ++k;
+            continue;
+        }
+        const ContourDev C = contour_of(q, r.ws);
+        const double f0 = M_PI * q.prob.radius * q.prob.e0 * q.prob.e0 / 4.0;
+        double out[8] = {0};
+        hipError_t err = launch_reduce(C, 1.0 / (double)q.window, f0, 2.0 * f0 * q.prob.radius,
+                                       (double *)(r.ws + q.off_out), e->s);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(out, r.ws + q.off_out, 6 * sizeof(double), hipMemcpyDeviceToHost, e->s);
+        if (err == hipSuccess) err = hipStreamSynchronize(e->s);
+        if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine harvest: %s", hipGetErrorString(err));
+        r.res.fx = out[0];
+        r.res.fy = out[1];
+        r.res.tz = out[2];
+        r.res.fx_raw = out[3];
+        r.res.fy_raw = out[4];
+        r.res.tz_raw = out[5];
+        r.res.steps_done = q.prob.steps;
+        r.res.window_steps = q.window;
+        r.res.contour_points = q.nc;
+        r.res.graph_used = 1;
+        r.res.bytes_per_step = (int64_t)q.bytes_per_lup * q.nx * q.ny;
+        r.t_done = now_ms();
+        r.res.total_ms = r.t_done - r.t_submit;
+        r.res.loop_ms = r.t_done - r.t_admit;
+        bool finite = true;
+        for (int i = 0; i < 6; ++i) finite = finite && std::isfinite(out[i]);
+        r.status = finite ? JLB_REQ_DONE : JLB_REQ_FAILED;
+        (void)hipFreeAsync(r.ws, e->s);
+        r.ws = nullptr;
+        e->in_use -= r.footprint;
+        e->finished += 1;
+        e->resident.erase(e->resident.begin() + (long)k);
+        e->dirty = true;
+    }
+    return JLB_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-int jlb_engine_create(size_t, int32_t, void *, jlb_engine **) { return fail(JLB_E_STATE, "engine not built yet"); }
-int jlb_engine_submit(jlb_engine *, const jlb_problem *, uint64_t *) { return fail(JLB_E_STATE, "engine not built yet"); }
-int jlb_engine_run(jlb_engine *, int64_t, int32_t *) { return fail(JLB_E_STATE, "engine not built yet"); }
-int jlb_engine_poll(jlb_engine *, uint64_t, int32_t *, jlb_result *) { return fail(JLB_E_STATE, "engine not built yet"); }
-int jlb_engine_cancel(jlb_engine *, uint64_t) { return fail(JLB_E_STATE, "engine not built yet"); }
-int jlb_engine_stats(jlb_engine *, int32_t *, int32_t *, int32_t *, size_t *) { return fail(JLB_E_STATE, "engine not built yet"); }
-int jlb_engine_destroy(jlb_engine *) { return fail(JLB_E_STATE, "engine not built yet"); }
-
+int jlb_engine_create(size_t budget_bytes, int32_t max_slots, void *stream, jlb_engine **out)
+{
+    clear_error();
+    if (!out || max_slots < 1 || budget_bytes == 0) return fail(JLB_E_ARG, "bad engine arguments");
+    jlb_engine *e = new jlb_engine();
+    e->budget = budget_bytes;
+    e->max_slots = max_slots;
+    if (stream) {
+        e->s = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&e->s, hipStreamNonBlocking) != hipSuccess) {
+            delete e;
+            return fail(JLB_E_DEVICE, "cannot create the engine stream");
+        }
+        e->own = true;
+    }
+    *out = e;
+    return JLB_OK;
 }
+
+int jlb_engine_submit(jlb_engine *e, const jlb_problem *prob, uint64_t *ticket)
+{
+    clear_error();
+    if (!e || !prob || !ticket) return fail(JLB_E_ARG, "null argument");
+    Request r;
+    r.prob = *prob;
+    int rc = make_plan(prob, &r.plan);
+    if (rc) return rc;
+    r.footprint = footprint_of(r.plan);
+    if (r.footprint > e->budget)
+        return fail(JLB_E_ADMISSION, "request needs %zu bytes, budget is %zu", r.footprint, e->budget);
+    r.t_submit = now_ms();
+    const uint64_t t = e->next_ticket++;
+    e->reqs.emplace(t, r);
+    e->queue.push_back(t);
+    *ticket = t;
+    return JLB_OK;
+}
+
+int jlb_engine_run(jlb_engine *e, int64_t steps, int32_t *active)
+{
+    clear_error();
+    if (!e || steps < 0) return fail(JLB_E_ARG, "bad arguments");
+    int rc = admit(e);
+    if (rc) return rc;
+    int64_t done = 0;
+    while (done < steps && !e->resident.empty()) {
+        if (e->dirty) {
+            rc = rebuild(e);
+            if (rc) return rc;
+        }
+        const int64_t k = std::min<int64_t>(CHUNK, steps - done);
+        if (k == CHUNK) {
+            if (!e->graph) {
+                rc = capture(e);
+                if (rc) return rc;
+            }
+            if (hipGraphLaunch(e->graph, e->s) != hipSuccess) return fail(JLB_E_DEVICE, "engine graph launch");
+        } else {
+            for (int64_t i = 0; i < k; ++i)
+                if (launch_batch_step(e) != hipSuccess) return fail(JLB_E_DEVICE, "engine step launch");
+        }
+        for (uint64_t t : e->resident) {
+            Request &r = e->reqs[t];
+            r.n = std::min<int64_t>(r.plan.prob.steps, r.n + k);
+        }
+        done += k;
+        rc = harvest(e);
+        if (rc) return rc;
+        rc = admit(e);
+        if (rc) return rc;
+    }
+    if (hipStreamSynchronize(e->s) != hipSuccess) return fail(JLB_E_DEVICE, "engine sync");
+    if (active) *active = (int32_t)e->resident.size();
+    return JLB_OK;
+}
+
+int jlb_engine_poll(jlb_engine *e, uint64_t ticket, int32_t *status, jlb_result *res)
+{
+    clear_error();
+    if (!e || !status) return fail(JLB_E_ARG, "null argument");
+    auto it = e->reqs.find(ticket);
+    if (it == e->reqs.end()) return fail(JLB_E_STATE, "unknown ticket %llu", (unsigned long long)ticket);
+    *status = it->second.status;
+    if (res) *res = it->second.res;
+    return JLB_OK;
+}
+
+int jlb_engine_cancel(jlb_engine *e, uint64_t ticket)
+{
+    clear_error();
+    if (!e) return fail(JLB_E_ARG, "null engine");
+    auto it = e->reqs.find(ticket);
+    if (it == e->reqs.end()) return fail(JLB_E_STATE, "unknown ticket %llu", (unsigned long long)ticket);
+    Request &r = it->second;
+    if (r.status == JLB_REQ_QUEUED) {
+        e->queue.erase(std::remove(e->queue.begin(), e->queue.end(), ticket), e->queue.end());
+    } else if (r.status == JLB_REQ_RUNNING) {
+        if (hipStreamSynchronize(e->s) != hipSuccess) return fail(JLB_E_DEVICE, "engine sync");
+        (void)hipFreeAsync(r.ws, e->s);
+        r.ws = nullptr;
+        e->in_use -= r.footprint;
+        e->resident.erase(std::remove(e->resident.begin(), e->resident.end(), ticket), e->resident.end());
+        e->dirty = true;
+    } else {
+        return fail(JLB_E_STATE, "ticket %llu already finished", (unsigned long long)ticket);
+    }
+    r.status = JLB_REQ_CANCELLED;
+    return JLB_OK;
+}
+
+int jlb_engine_stats(jlb_engine *e, int32_t *queued, int32_t *resident, int32_t *finished, size_t *bytes_in_use)
+{
+    clear_error();
+    if (!e) return fail(JLB_E_ARG, "null engine");
+    if (queued) *queued = (int32_t)e->queue.size();
+    if (resident) *resident = (int32_t)e->resident.size();
+    if (finished) *finished = e->finished;
+    if (bytes_in_use) *bytes_in_use = e->in_use;
+    return JLB_OK;
+}
+
+int jlb_engine_destroy(jlb_engine *e)
+{
+    clear_error();
+    if (!e) return fail(JLB_E_ARG, "null engine");
+    (void)hipStreamSynchronize(e->s);
+    if (e->graph) (void)hipGraphExecDestroy(e->graph);
+    for (auto &kv : e->reqs)
+        if (kv.second.ws) (void)hipFreeAsync(kv.second.ws, e->s);
+    if (e->d_desc) (void)hipFreeAsync(e->d_desc, e->s);
+    if (e->d_tiles) (void)hipFreeAsync(e->d_tiles, e->s);
+    (void)hipStreamSynchronize(e->s);
+    if (e->own) (void)hipStreamDestroy(e->s);
+    delete e;
+    return JLB_OK;
+}
+
+}  // extern "C"

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -220,6 +222,23 @@ double incident(const Plan &q, int64_t n)
 }
 
 // ---------------------------------------------------------------------------
+// Step-kernel variant per precision (FP32, BF16); set by the autotuner or
+// forced by the caller.  All variants give identical results.
+// ---------------------------------------------------------------------------
+
+static std::atomic<int> g_variant[3] = {{0}, {NEQ_V2_T8}, {NEQ_V2_T8}};
+
+int step_variant(int precision) { return g_variant[precision].load(std::memory_order_relaxed); }
+void set_step_variant(int precision, int v) { g_variant[precision].store(v, std::memory_order_relaxed); }
+
+hipError_t launch_step(const Plan &q, const Lattice &L, void *src, void *dst, double *fields, double einc, hipStream_t s,
+                       int variant)
+{
+    if (q.prob.precision == JLB_FP64) return launch_step_f64(L, (const double *)src, (double *)dst, fields, einc, s);
+    return launch_step_neq(q.prob.precision, L, src, dst, einc, s, variant);
+}
+
+// ---------------------------------------------------------------------------
 // Streams
 // ---------------------------------------------------------------------------
 
@@ -307,7 +326,7 @@ static int launch_one_step(const Plan &q, char *ws, const Lattice &L, const Cont
         e = launch_step_f64(L, (const double *)src, (double *)dst, fields, einc, s);
         if (e == hipSuccess && in_window) e = launch_contour(prec, L, ws + q.off_fields, C, s);
     } else {
-        e = launch_step_neq(prec, L, src, dst, einc, s);
+        e = launch_step_neq(prec, L, src, dst, einc, s, step_variant(prec));
         if (e == hipSuccess && in_window) e = launch_contour(prec, L, dst, C, s);
     }
     if (e != hipSuccess) return fail(JLB_E_DEVICE, "launch of step %lld failed: %s", (long long)n, hipGetErrorString(e));
@@ -528,10 +547,9 @@ int jlb_solve(const jlb_problem *prob, void *workspace, size_t workspace_bytes, 
     return rc ? rc : rc2;
 }
 
-int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
-                         int32_t launches, double *ms_per_launch, void *stream)
+static int time_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
+                            int32_t launches, int variant, double *ms_per_launch, void *stream)
 {
-    clear_error();
     if (!ms_per_launch || launches < 1 || warmup < 0) return fail(JLB_E_ARG, "bad launch counts");
     Plan q;
     int rc = make_plan(prob, &q);
@@ -555,11 +573,8 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
     const Lattice L = lattice_of(q, (const uint8_t *)(ws + q.off_mask));
     for (int64_t n = 0; rc == JLB_OK && n < (int64_t)warmup + launches; ++n) {
         if (n == warmup && hipEventRecord(e0, own) != hipSuccess) rc = fail(JLB_E_DEVICE, "event record");
-        void *src = ws + q.off_state[n & 1];
-        void *dst = ws + q.off_state[(n + 1) & 1];
-        hipError_t e = q.prob.precision == JLB_FP64
-                           ? launch_step_f64(L, (const double *)src, (double *)dst, nullptr, incident(q, n), own)
-                           : launch_step_neq(q.prob.precision, L, src, dst, incident(q, n), own);
+        hipError_t e = launch_step(q, L, ws + q.off_state[n & 1], ws + q.off_state[(n + 1) & 1], nullptr, incident(q, n),
+                                   own, variant);
         if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "step launch: %s", hipGetErrorString(e));
     }
     if (rc == JLB_OK) {
@@ -574,6 +589,98 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
     int rc2 = join.end();
     (void)hipStreamSynchronize(own);
     if (owned) (void)hipFree(ws);
+    return rc ? rc : rc2;
+}
+
+int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
+                         int32_t launches, double *ms_per_launch, void *stream)
+{
+    clear_error();
+    if (!prob) return fail(JLB_E_ARG, "null problem");
+    const int v = prob->precision >= 0 && prob->precision <= 2 ? step_variant(prob->precision) : 0;
+    return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, ms_per_launch, stream);
+}
+
+int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t launches,
+                 int32_t *best_variant, double *ms_per_variant, void *stream)
+{
+    clear_error();
+    if (!prob || !best_variant) return fail(JLB_E_ARG, "null argument");
+    if (launches < 1) return fail(JLB_E_ARG, "launches must be >= 1");
+    if (prob->precision == JLB_FP64) {
+        *best_variant = 0;
+        double ms = 0.0;
+        int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, 0, &ms, stream);
+        if (ms_per_variant) ms_per_variant[0] = ms;
+        return rc;
+    }
+    double best = 1e300;
+    int bv = step_variant(prob->precision);
+    for (int v = 0; v < NEQ_VARIANTS; ++v) {
+        double ms = 0.0;
+        int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, v, &ms, stream);
+        if (rc) return rc;
+        if (ms_per_variant) ms_per_variant[v] = ms;
+        if (ms < best) {
+            best = ms;
+            bv = v;
+        }
+    }
+    set_step_variant(prob->precision, bv);
+    *best_variant = bv;
+    return JLB_OK;
+}
+
+int jlb_set_step_variant(int32_t precision, int32_t variant)
+{
+    clear_error();
+    if (precision < 1 || precision > 2 || variant < 0 || variant >= NEQ_VARIANTS)
+        return fail(JLB_E_ARG, "precision must be 1 or 2 and variant 0..%d", NEQ_VARIANTS - 1);
+    set_step_variant(precision, variant);
+    return JLB_OK;
+}
+
+int jlb_get_step_variant(int32_t precision, int32_t *variant)
+{
+    clear_error();
+    if (precision < 0 || precision > 2 || !variant) return fail(JLB_E_ARG, "bad precision or null variant");
+    *variant = step_variant(precision);
+    return JLB_OK;
+}
+
+int jlb_copy_bandwidth(size_t bytes, int32_t launches, double *ms_per_launch, void *stream)
+{
+    clear_error();
+    if (!ms_per_launch || launches < 1 || bytes < 16) return fail(JLB_E_ARG, "bad copy arguments");
+    bytes &= ~(size_t)15;
+    hipStream_t own = own_stream();
+    if (!own) return fail(JLB_E_DEVICE, "cannot create a stream");
+    StreamJoin join{(hipStream_t)stream, own};
+    int rc = join.begin();
+    if (rc) return rc;
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+        if (a) (void)hipFree(a);
+        return fail(JLB_E_OOM, "copy buffers of %zu bytes", bytes);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMemsetAsync(a, 0, bytes, own);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_copy(a, b, bytes, own);
+    if (e == hipSuccess) e = hipEventRecord(e0, own);
+    for (int k = 0; k < launches && e == hipSuccess; ++k) e = launch_copy(a, b, bytes, own);
+    if (e == hipSuccess) e = hipEventRecord(e1, own);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "copy timing: %s", hipGetErrorString(e));
+    else *ms_per_launch = (double)ms / launches;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    int rc2 = join.end();
     return rc ? rc : rc2;
 }
 

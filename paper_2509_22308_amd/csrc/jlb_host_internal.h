@@ -50,6 +50,7 @@ hipStream_t own_stream();
 Lattice lattice_of(const Plan &q, const uint8_t *dmask);
 ContourDev contour_of(const Plan &q, char *ws);
 int upload_setup(const Plan &q, char *ws, hipStream_t s);
+int step_variant(int precision);
 int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, double *hy, double *energy,
               hipStream_t s);
 

@@ -50,7 +50,23 @@ struct ContourDev {
 // Launchers (return the first HIP error).
 hipError_t launch_step_f64(const Lattice &L, const double *src, double *dst, double *fields, double einc,
                            hipStream_t s);
-hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, void *dst, double einc, hipStream_t s);
+// Kernel variants of the FP32 / BF16 step (identical results, different
+// thread-to-node mappings); chosen per device and grid by the autotuner.
+enum NeqVariant {
+    NEQ_DIRECT = 0,   // one node per thread, 64 x 4 blocks
+    NEQ_SWEEP8 = 1,   // one column per thread, 8 / 16 / 32 rows
+    NEQ_SWEEP16 = 2,
+    NEQ_SWEEP32 = 3,
+    NEQ_V2_T4 = 4,    // two adjacent nodes per thread, 4 / 8 / 16 rows
+    NEQ_V2_T8 = 5,
+    NEQ_V2_T16 = 6,
+    NEQ_V4_T4 = 7,    // four adjacent nodes per thread, 4 / 8 / 16 rows
+    NEQ_V4_T8 = 8,
+    NEQ_V4_T16 = 9,
+    NEQ_VARIANTS = 10
+};
+hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, void *dst, double einc, hipStream_t s,
+                           int variant);
 // Fields: FP64 planes [3][plane] for precision 0, the FP32 field planes of the
 // state for precisions 1 and 2.
 hipError_t launch_contour(int precision, const Lattice &L, const void *fields, const ContourDev &C, hipStream_t s);
@@ -58,7 +74,40 @@ hipError_t launch_reduce(const ContourDev &C, double inv_window, double f0, doub
 hipError_t launch_energy(int precision, const Lattice &L, const void *fields, double *partials, int nparts,
                          double *out, hipStream_t s);
 int energy_partials(const Lattice &L);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_fields_out(int precision, const Lattice &L, const void *fields, double *ez, double *hx, double *hy,
                              hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched engine: per-solve descriptors in device memory.  Each solve keeps
+// its own step counter n on the device; the step kernels read it to pick the
+// source value and the state buffers, the advance kernel increments it, so a
+// captured sequence of steps can be replayed without host involvement.
+// ---------------------------------------------------------------------------
+
+struct SolveDesc {
+    Lattice L;
+    char *state[2];
+    double *fields;          // FP64: field planes written inside the averaging window
+    const double *src_tab;   // incident values: [ramp_end] ramp steps, then [T] by n mod T
+    int64_t ramp_end, T;
+    int64_t n;               // steps done (device-updated)
+    int64_t steps, window;
+    ContourDev C;
+    int precision;
+    int pad;
+};
+
+// One block of work: a tile of one resident solve.
+struct Tile {
+    uint32_t slot;
+    uint16_t tx, ty;
+};
+
+// Tile shape of a precision / variant: columns x rows per block.
+void tile_shape(int precision, int variant, int &cols, int &rows);
+hipError_t launch_step_batch(int precision, int variant, SolveDesc *d, const Tile *tiles, int ntiles, hipStream_t s);
+hipError_t launch_contour_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s);
+hipError_t launch_advance(SolveDesc *d, int nslots, hipStream_t s);
 
 }  // namespace jlb

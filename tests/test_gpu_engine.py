@@ -1,0 +1,121 @@
+"""Batched engine on the GPU: many solves resident and stepped together.
+
+A solve's outcome may not depend on what else is resident: the engine's
+result equals the single-solve result bit for bit, alone or in any mix, in
+every precision.  Admission respects the byte budget, and cancelled or
+oversized requests behave as documented.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def jlb():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2509_22308_amd as J
+    J.load()
+    return J
+
+
+def _mix():
+    """Uneven solves: three kinds, ragged grids, different steps and periods."""
+    return [
+        W.problem(nx=96, ny=90, radius=12.0, kind="metallo_dielectric_janus", eps1=3.0, phi0_deg=40.0,
+                  wavelength=30.0, steps=700, avg_periods=2),
+        W.problem(nx=140, ny=128, radius=16.0, kind="dielectric_janus", eps1=2.0, eps2=5.0, phi0_deg=200.0,
+                  wavelength=40.0, steps=900, avg_periods=2),
+        W.problem(nx=72, ny=80, radius=9.0, kind="homogeneous", eps1=2.5, wavelength=24.0, steps=500,
+                  avg_periods=3),
+        W.problem(nx=200, ny=170, radius=20.0, kind="dielectric_janus", eps1=4.0, eps2=1.5, phi0_deg=75.0,
+                  wavelength=40.0, steps=650, avg_periods=1),
+        W.problem(nx=64, ny=64, radius=8.0, kind="metallo_dielectric_janus", eps1=1.5, phi0_deg=300.0,
+                  wavelength=20.0, steps=420, avg_periods=2),
+    ]
+
+
+def _run_engine(jlb, probs, budget=8 << 30, slots=64, chunk=300):
+    eng = jlb.Engine(budget, slots)
+    tickets = [eng.submit(p) for p in probs]
+    out = {}
+    for _ in range(10000):
+        eng.run(chunk)
+        st = eng.stats()
+        if st["queued"] == 0 and st["resident"] == 0:
+            break
+    for t in tickets:
+        status, res = eng.poll(t)
+        assert status == "done", status
+        out[t] = res.as_dict()
+    eng.close()
+    return [out[t] for t in tickets]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_engine_equals_single_solves_bit_for_bit(jlb, precision):
+    probs = [jlb.make_problem(p, precision) for p in _mix()]
+    single = [jlb.solve(p, precision) for p in _mix()]
+    batched = _run_engine(jlb, probs)
+    for s, b in zip(single, batched):
+        for q in ("fx", "fy", "tz", "fx_raw", "fy_raw", "tz_raw"):
+            assert s[q] == b[q], (precision, q, s[q], b[q])
+
+
+def test_result_alone_equals_result_in_a_mix(jlb):
+    target = _mix()[1]
+    mixed_precisions = ["fp32", "bf16", "fp64", "fp32", "bf16"]
+    alone = _run_engine(jlb, [jlb.make_problem(target, "fp32")])[0]
+    others = [jlb.make_problem(p, pr) for p, pr in zip(_mix(), mixed_precisions)]
+    mixed = _run_engine(jlb, others[:3] + [jlb.make_problem(target, "fp32")] + others[3:], chunk=97)
+    b = mixed[3]
+    for q in ("fx", "fy", "tz"):
+        assert alone[q] == b[q]
+
+
+def test_admission_under_a_small_budget_serialises_requests(jlb):
+    probs = [jlb.make_problem(p, "fp32") for p in _mix()]
+    sizes = [jlb.jlb_workspace_size(p) for p in probs]
+    budget = int(max(sizes) * 1.5)  # the whole mix does not fit at once
+    assert sum(sizes) > budget
+    eng = jlb.Engine(budget, 16)
+    tickets = [eng.submit(p) for p in probs]
+    peak = 0
+    for _ in range(10000):
+        eng.run(200)
+        st = eng.stats()
+        assert st["bytes_in_use"] <= budget
+        peak = max(peak, st["resident"])
+        if st["queued"] == 0 and st["resident"] == 0:
+            break
+    assert all(eng.poll(t)[0] == "done" for t in tickets)
+    assert eng.stats()["finished"] == len(probs)
+    assert 1 <= peak < len(probs)
+    eng.close()
+
+
+def test_cancel_and_oversized_requests(jlb):
+    probs = [jlb.make_problem(p, "bf16") for p in _mix()]
+    eng = jlb.Engine(64 << 20, 2)
+    with pytest.raises(jlb.JlbError) as ei:
+        eng.submit(jlb.make_problem(W.config2(), "fp64"))  # ~400 MB > 64 MB
+    assert ei.value.code == -8
+    tickets = [eng.submit(p) for p in probs]
+    eng.run(50)                     # two resident, three queued
+    st = eng.stats()
+    assert st["resident"] == 2 and st["queued"] == 3
+    eng.cancel(tickets[0])          # running
+    eng.cancel(tickets[4])          # queued
+    for _ in range(1000):
+        eng.run(400)
+        st = eng.stats()
+        if st["queued"] == 0 and st["resident"] == 0:
+            break
+    assert eng.poll(tickets[0])[0] == "cancelled" and eng.poll(tickets[4])[0] == "cancelled"
+    assert all(eng.poll(t)[0] == "done" for t in tickets[1:4])
+    with pytest.raises(jlb.JlbError):
+        eng.cancel(tickets[1])      # already finished
+    eng.close()

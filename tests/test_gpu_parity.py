@@ -156,3 +156,29 @@ def test_config2_full_size_properties(jlb):
         assert _rel(f[q], d[q]) <= 1e-3, (q, f[q], d[q])
     m = jlb.solve(dict(p, phi0=math.pi - p["phi0"]), "fp64")
     assert abs(m["fx"] - d["fx"]) < 1e-10 and abs(m["fy"] + d["fy"]) < 1e-10 and abs(m["tz"] + d["tz"]) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_step_kernel_variants_give_identical_results(jlb, precision):
+    """Every thread-to-node mapping the autotuner may pick computes the same
+    arithmetic: fields and forces agree bit for bit (ragged sizes, conductor
+    links, all four edges)."""
+    prec = jlb.PRECISIONS[precision]
+    before = jlb.jlb_get_step_variant(prec)
+    cases = [W.problem(nx=203, ny=150, radius=20.0, kind="metallo_dielectric_janus", eps1=3.0, phi0_deg=110.0,
+                       wavelength=40.0, steps=700, avg_periods=1),
+             W.problem(nx=130, ny=171, radius=16.0, kind="dielectric_janus", eps1=2.0, eps2=6.0, phi0_deg=45.0,
+                       wavelength=40.0, steps=650, avg_periods=1)]
+    try:
+        for p in cases:
+            outs = []
+            for v in range(len(jlb.STEP_VARIANTS)):
+                jlb.jlb_set_step_variant(prec, v)
+                outs.append(jlb.solve(p, precision, fields=True))
+            for o in outs[1:]:
+                for q in ("fx", "fy", "tz"):
+                    assert o[q] == outs[0][q]
+                for f in ("ez", "hx", "hy"):
+                    assert np.array_equal(o[f], outs[0][f])
+    finally:
+        jlb.jlb_set_step_variant(prec, before)
