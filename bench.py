@@ -1,19 +1,33 @@
 """Benchmark of the Janus-cylinder EM lattice Boltzmann hot path on one MI355X.
 
-A "step" here is one complete solve of the hot path on synthetic input:
-staircase geometry -> zeroed state -> 20000 fused stream-collide-boundary
-lattice steps with the stress accumulation over the last 5 periods -> contour
-reduction to F~x, F~y, M~z.  The workload is the dielectric Janus cylinder
-eps1 = 2.25 / eps2 = 4.0, phi0 = 30 deg, a = 64, 1024 x 1024 grid,
-lambda = 128, 20000 steps.  The value is lattice updates per second
+Default (the contract line): a "step" is one complete solve of the hot path
+on synthetic input -- staircase geometry -> zeroed state -> 20000 fused
+stream-collide-boundary lattice steps with the stress accumulation over the
+last 5 periods -> contour reduction to F~x, F~y, M~z -- for the dielectric
+Janus cylinder eps1 = 2.25 / eps2 = 4.0, phi0 = 30 deg, a = 64 on a
+1024 x 1024 grid, lambda = 128.  value = lattice updates per second
 (nx * ny * steps per solve / wall time per solve, conductor nodes included).
+Prints ONE JSON line.
 
-Prints ONE JSON line (rank 0).  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
+
+Other modes (one JSON line each):
+    --workload designmap [--fraction f]   config 4: 576 dielectric Janus solves
+                                          (a ~ U{32..128}) batched by the engine,
+                                          vs one-at-a-time FP64 solves
+    --workload serve [--requests n]       config 5: Poisson arrivals (20/s),
+                                          byte-budget admission, p50/p99 latency
+    --kernel-only                         the fused step kernel and the copy
+                                          reference alone (for rocprofv3 passes)
+    --summarize DIR --out FILE            turn rocprofv3 CSV output into a
+                                          short text summary under profiles/
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -23,10 +37,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+BYTES_PER_LUP = {"fp64": 177, "fp32": 89, "bf16": 57}
+KERNEL_NAME = {"fp64": "k_step_f64", "fp32": "k_step_neq*<float>", "bf16": "k_step_neq*<__bf16>"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
+DEVICE_SRC = os.path.join(ROOT, "paper_2509_22308_amd", "csrc", "jlb_device.hip")
 
 
-def _kernel_of(precision: str) -> str:
-    return {"fp64": "k_step_f64", "fp32": "k_step_neq<float>", "bf16": "k_step_neq<__bf16>"}[precision]
+def kernel_source_hash() -> str:
+    with open(DEVICE_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _workspace(jlb, prob):
+    import torch
+    return torch.empty(jlb.jlb_workspace_size(prob), dtype=torch.uint8, device="cuda")
+
+
+def measured_traffic(precision: str, variant: int):
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary, or None when it was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    e = t.get("config2", {}).get(precision)
+    if not e or e.get("variant") != variant:
+        return None
+    return e.get("hbm_bytes_per_launch")
 
 
 def gpu_leg(args):
@@ -38,7 +78,9 @@ def gpu_leg(args):
     torch.cuda.set_device(0)
     p = workloads.config2()
     prob = jlb.make_problem(p, args.precision)
-    ws = torch.empty(jlb.jlb_workspace_size(prob), dtype=torch.uint8, device="cuda")
+    ws = _workspace(jlb, prob)
+    # the autotuner picks the step kernel's tile shape for this device and grid
+    variant, tune_ms = jlb.jlb_autotune(prob, 20, ws)
     lups_per_solve = p["nx"] * p["ny"] * p["steps"]
 
     for _ in range(args.warmup):
@@ -53,40 +95,40 @@ def gpu_leg(args):
 
     ms_per_solve = 1e3 * wall / args.steps
     value = lups_per_solve * args.steps / wall
-    # dominant kernel: the fused step; HIP events on the library's stream
-    # bracket the time loop of each solve (step kernels plus the small contour
-    # kernels of the averaging window), so this is an upper bound on the
-    # per-launch duration
+    # dominant kernel: the fused step.  HIP events on the library's stream
+    # bracket each solve's time loop (step kernels plus the small contour
+    # kernels of the averaging window): an upper bound on the launch duration.
     loop_ms = sum(r.loop_ms for r in results) / len(results)
     launch_ms = loop_ms / p["steps"]
     bytes_per_launch = results[0].bytes_per_step
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     r0 = results[0]
-
-    extra = {"forces": {"fx": r0.fx, "fy": r0.fy, "tz": r0.tz},
-             "loop_ms_per_solve": loop_ms, "graph_used": r0.graph_used,
-             "bytes_per_lup": bytes_per_launch / (p["nx"] * p["ny"])}
-    # the same step kernel, timed alone over back-to-back launches
-    extra["step_kernel_ms_alone"] = jlb.jlb_time_step_kernel(prob, 20, 200, ws)
+    extra = {"forces": {"fx": r0.fx, "fy": r0.fy, "tz": r0.tz}, "loop_ms_per_solve": loop_ms,
+             "graph_used": r0.graph_used, "step_variant": jlb.STEP_VARIANTS.get(variant, variant),
+             "autotune_ms_per_variant": [round(m, 5) for m in tune_ms],
+             "step_kernel_ms_alone": jlb.jlb_time_step_kernel(prob, 20, 200, ws)}
     if not args.quick:
+        nb = 4 << 30
+        ms = jlb.jlb_copy_bandwidth(nb, 10)
+        extra["copy_4GiB_GBps"] = 2 * nb / (ms * 1e-3) / 1e9
         # a grid far larger than the 256 MB Infinity Cache: the HBM-bound figure
         big = workloads.problem(nx=4096, ny=4096, radius=256.0, kind="dielectric_janus", eps1=2.25, eps2=4.0,
                                 phi0_deg=30.0, wavelength=512.0, steps=10000)
         for prec in ("fp64", "fp32", "bf16"):
             bp = jlb.make_problem(big, prec)
-            bws = torch.empty(jlb.jlb_workspace_size(bp), dtype=torch.uint8, device="cuda")
+            bws = _workspace(jlb, bp)
+            v, _ = jlb.jlb_autotune(bp, 10, bws)
             ms = jlb.jlb_time_step_kernel(bp, 5, 40, bws)
-            per_lup = {"fp64": 177, "fp32": 89, "bf16": 57}[prec]
-            gbs = 4096 * 4096 * per_lup / (ms * 1e-3) / 1e9
-            extra[f"grid4096_{prec}"] = {"ms_per_step": ms, "glups": 4096 * 4096 / (ms * 1e-3) / 1e9,
-                                        "gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+            gbs = 4096 * 4096 * BYTES_PER_LUP[prec] / (ms * 1e-3) / 1e9
+            extra[f"grid4096_{prec}"] = {"ms_per_step": ms, "glups": 4096 * 4096 / (ms * 1e-3) / 1e9, "gbs": gbs,
+                                        "hbm_frac": gbs / HBM_PEAK_GBS, "variant": jlb.STEP_VARIANTS.get(v, v)}
             del bws
-        # the other precisions on the headline workload (one solve each)
         for prec in ("fp64", "fp32", "bf16"):
             if prec == args.precision:
                 continue
             pp = jlb.make_problem(p, prec)
-            pws = torch.empty(jlb.jlb_workspace_size(pp), dtype=torch.uint8, device="cuda")
+            pws = _workspace(jlb, pp)
+            jlb.jlb_autotune(pp, 10, pws)
             t = time.perf_counter()
             r = jlb.jlb_solve(pp, pws)
             torch.cuda.synchronize()
@@ -94,14 +136,17 @@ def gpu_leg(args):
             extra[f"config2_{prec}"] = {"glups": lups_per_solve / dt / 1e9, "ms_per_solve": 1e3 * dt,
                                         "loop_ms": r.loop_ms, "fx": r.fx, "fy": r.fy, "tz": r.tz}
             del pws
-    roof = {"bound": "hbm", "kernel": _kernel_of(args.precision), "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms}
+    roof = {"bound": "hbm", "kernel": KERNEL_NAME[args.precision], "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(args.precision, variant),
+            "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms,
+            "note": "config 2 (FP32 state 2 x 46 MB) stays in the 256 MB Infinity Cache between steps; "
+                    "the HBM-bound figures are extra.grid4096_*"}
     return p, value, ms_per_solve, roof, extra
 
 
 def cpu_leg(p, budget_s: float = 15.0):
-    """The FP64 oracle as it stands on the host cores, on a bounded sample:
+    """The FP64 oracle as it stands, on the host cores, on a bounded sample:
     the headline workload's first n steps (n sized to about budget_s)."""
     from oracle import oracle
 
@@ -115,10 +160,145 @@ def cpu_leg(p, budget_s: float = 15.0):
     t = time.perf_counter()
     oracle.solve(sample, fields=False, threads=threads)
     dt = time.perf_counter() - t
-    lups = p["nx"] * p["ny"] * n / dt
-    return {"value": lups, "unit": "LUPS", "cores": threads, "kind": "oracle",
+    return {"value": p["nx"] * p["ny"] * n / dt, "unit": "LUPS", "cores": threads, "kind": "oracle",
             "sample": f"{p['nx']}x{p['ny']} dielectric Janus, first {n} of {p['steps']} steps, "
                       f"reduced 11-population FP64, {dt:.1f} s"}
+
+
+def base_line(args, metric_value, ms, config, roof=None, cpu=None, extra=None, dtype=None):
+    return {
+        "metric": "lattice updates/s and % HBM roofline; design-map solves/hour, p50/p99 latency",
+        "value": metric_value, "unit": "LUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype or {"fp64": "f64", "fp32": "f32", "bf16": "bf16-storage/f32"}[args.precision],
+        "data": "synthetic (parameter-defined scattering problems; no dataset)",
+        "config": config, "roofline": roof, "cpu_baseline": cpu, "extra": extra or {},
+    }
+
+
+def run_default(args):
+    p, value, ms, roof, extra = gpu_leg(args)
+    cpu = None if args.no_cpu else cpu_leg(p)
+    config = {"workload": "dielectric Janus cylinder eps 2.25/4.0, phi0 30 deg, a=64, 1024x1024, lambda=128, "
+                          "20000 steps, 5-period stress average (one full solve per step)",
+              "nx": p["nx"], "ny": p["ny"], "steps_per_solve": p["steps"], "precision": args.precision}
+    return base_line(args, value, ms, config, roof, cpu, extra)
+
+
+def run_designmap(args):
+    import torch
+
+    import paper_2509_22308_amd as jlb
+    import workloads
+    from paper_2509_22308_amd.serve import run_design_map
+
+    torch.cuda.set_device(0)
+    probs = workloads.config4_sweep()
+    if args.fraction < 1.0:
+        probs = probs[:: max(1, int(round(1.0 / args.fraction)))]
+    jlb.jlb_autotune(jlb.make_problem(probs[0], args.precision), 10)
+    out = run_design_map(probs, args.precision)
+    # baseline: one-at-a-time plain FP64 solves on the same GPU, timed on a
+    # seeded sample stratified by radius, extrapolated by LUP count
+    order = sorted(range(len(probs)), key=lambda k: probs[k]["radius"])
+    sample = [probs[order[int(q * (len(order) - 1))]] for q in (0.0, 0.33, 0.66, 1.0)]
+    t = time.perf_counter()
+    for sp in sample:
+        jlb.solve(sp, "fp64")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    lups_sample = sum(sp["nx"] * sp["ny"] * sp["steps"] for sp in sample)
+    base_lups = lups_sample / dt
+    total = sum(pp["nx"] * pp["ny"] * pp["steps"] for pp in probs)
+    extra = {"solves": len(probs), "wall_s": out["wall_s"], "solves_per_hour": out["solves_per_hour"],
+             "peak_resident": out["peak_resident"],
+             "baseline_fp64_one_at_a_time": {"lups": base_lups, "solves_per_hour_extrapolated":
+                                             len(probs) / (total / base_lups) * 3600.0,
+                                             "sample": "4 solves stratified by radius"},
+             "failed": sum(1 for r in out["results"] if r["status"] != "done")}
+    config = {"workload": f"config 4 design map: {len(probs)} dielectric Janus solves, eps2/eps1 1.1..10 "
+                          f"(16 log-spaced) x 36 orientations, a ~ U{{32..128}}, grid 8a, lambda 2a, 52 periods",
+              "precision": args.precision}
+    return base_line(args, out["lups"], 1e3 * out["wall_s"], config, extra=extra)
+
+
+def run_serve(args):
+    import torch
+
+    import paper_2509_22308_amd as jlb
+    import workloads
+    from paper_2509_22308_amd.serve import serve
+
+    torch.cuda.set_device(0)
+    reqs = workloads.config5_requests(n_req=args.requests, a_min=args.a_min, a_max=args.a_max)
+    jlb.jlb_autotune(jlb.make_problem(reqs[0][1], args.precision), 10)
+    out = serve(reqs, args.precision)
+    extra = {k: out[k] for k in ("requests", "completed", "wall_s", "p50_s", "p99_s", "mean_s", "solves_per_hour",
+                                 "offered_lups", "peak_resident", "budget_bytes")}
+    config = {"workload": f"config 5 serving: {args.requests} Poisson arrivals at 20/s (seed 22308), dielectric "
+                          f"Janus a ~ U{{{args.a_min}..{args.a_max}}}, grid 8a, eps ~ U[1.5,10], lambda 2a, "
+                          "52 periods, byte-budget admission", "precision": args.precision}
+    return base_line(args, out["throughput_lups"], 1e3 * out["wall_s"], config, extra=extra)
+
+
+def run_kernel_only(args):
+    """The fused step kernel of the headline workload and the copy reference,
+    alone: the command the rocprofv3 counter passes profile."""
+    import torch
+
+    import paper_2509_22308_amd as jlb
+    import workloads
+
+    torch.cuda.set_device(0)
+    if args.grid:
+        n = args.grid
+        p = workloads.problem(nx=n, ny=n, radius=n / 16, kind="dielectric_janus", eps1=2.25, eps2=4.0,
+                              phi0_deg=30.0, wavelength=n / 8, steps=10000)
+    else:
+        p = workloads.config2()
+    prob = jlb.make_problem(p, args.precision)
+    ws = _workspace(jlb, prob)
+    variant, _ = jlb.jlb_autotune(prob, 5, ws)
+    ms = jlb.jlb_time_step_kernel(prob, 2, args.launches, ws)
+    copy_bytes = 1 << 30
+    cms = jlb.jlb_copy_bandwidth(copy_bytes, 3)
+    print(json.dumps({"mode": "kernel-only", "grid": [p["nx"], p["ny"]], "precision": args.precision, "variant": variant,
+                      "step_ms": ms, "launches": args.launches, "bytes_per_launch": BYTES_PER_LUP[args.precision]
+                      * p["nx"] * p["ny"], "copy_bytes": copy_bytes, "copy_ms": cms,
+                      "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
+
+
+def summarize(args):
+    """Short text summary of rocprofv3 CSV output (kernel stats or counters)."""
+    lines = [f"# rocprofv3 summary of {args.summarize}", f"command: {args.command}" if args.command else "", ""]
+    stats = glob.glob(os.path.join(args.summarize, "**", "*kernel_stats.csv"), recursive=True)
+    for path in stats:
+        with open(path) as f:
+            rows = list(csv.DictReader(f))
+        lines.append("## kernel stats (" + os.path.basename(path) + ")")
+        lines.append("| kernel | calls | total ms | average us | percent |")
+        lines.append("|---|---|---|---|---|")
+        for r in rows[:15]:
+            name = r.get("Name", "")[:90]
+            lines.append(f"| {name} | {r.get('Calls')} | {float(r.get('TotalDurationNs', 0)) / 1e6:.3f} | "
+                         f"{float(r.get('AverageNs', 0)) / 1e3:.3f} | {float(r.get('Percentage', 0)):.2f} |")
+        lines.append("")
+    ctrs = glob.glob(os.path.join(args.summarize, "**", "*counter_collection.csv"), recursive=True)
+    for path in ctrs:
+        agg = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                key = (r.get("Kernel_Name", "")[:90], r.get("Counter_Name", ""))
+                agg.setdefault(key, []).append(float(r.get("Counter_Value", 0.0)))
+        lines.append("## counters per dispatch (" + os.path.basename(path) + ")")
+        lines.append("| kernel | counter | dispatches | mean | min | max |")
+        lines.append("|---|---|---|---|---|---|")
+        for (k, c), v in sorted(agg.items()):
+            lines.append(f"| {k} | {c} | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} |")
+        lines.append("")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(args.out)
 
 
 def main():
@@ -127,28 +307,31 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--quick", action="store_true", help="skip the extra precision and 4096^2 figures")
+    ap.add_argument("--workload", default="config2", choices=["config2", "designmap", "serve"])
+    ap.add_argument("--fraction", type=float, default=1.0, help="designmap: take every (1/f)-th solve")
+    ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
+    ap.add_argument("--a-min", type=int, default=16)
+    ap.add_argument("--a-max", type=int, default=64)
+    ap.add_argument("--quick", action="store_true", help="skip the extra precision, 4096^2 and copy figures")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--kernel-only", action="store_true")
+    ap.add_argument("--launches", type=int, default=50)
+    ap.add_argument("--grid", type=int, default=0, help="kernel-only: an n x n grid instead of config 2")
+    ap.add_argument("--summarize", default=None)
+    ap.add_argument("--command", default="")
+    ap.add_argument("--out", default=None)
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the solves are independent and this build runs on a single MI355X; "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: this build runs on a single MI355X (independent solves shard with no "
+              "communication; see the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    p, value, ms, roof, extra = gpu_leg(args)
-    cpu = None if args.no_cpu else cpu_leg(p)
-    line = {
-        "metric": "lattice updates/s and % HBM roofline; design-map solves/hour, p50/p99 latency",
-        "value": value, "unit": "LUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-storage/f32"}[args.precision],
-        "data": "synthetic (parameter-defined scattering problem; no dataset)",
-        "config": {"workload": "dielectric Janus cylinder eps 2.25/4.0, phi0 30 deg, a=64, 1024x1024, "
-                               "lambda=128, 20000 steps, 5-period stress average (one full solve per step)",
-                   "nx": p["nx"], "ny": p["ny"], "steps_per_solve": p["steps"], "precision": args.precision},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "extra": extra,
-    }
+    if args.kernel_only:
+        run_kernel_only(args)
+        return
+    line = {"config2": run_default, "designmap": run_designmap, "serve": run_serve}[args.workload](args)
     print(json.dumps(line), flush=True)
 
 

@@ -45,24 +45,49 @@ namespace jlb {
 
 namespace {
 
-// Stores of the next state are written once and read only in the next step:
-// with JLB_STREAM_STORES they bypass the caches (non-temporal).
-#ifndef JLB_STREAM_STORES
-#define JLB_STREAM_STORES 1
-#endif
-template <typename T> __device__ __forceinline__ void put(T *p, T v)
+// Stores of the next state are read only in the next step.  When the state
+// is larger than the 256 MB Infinity Cache they stream past the caches
+// (non-temporal); when it fits, ordinary stores keep it cache-resident for
+// the next step.  The choice is per launch (Lattice::stream_stores).
+template <typename T> __device__ __forceinline__ void put(T *p, T v, bool stream)
 {
-#if JLB_STREAM_STORES
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
+    if (stream) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 constexpr int BX = 64;  // one wavefront per row segment
 constexpr int BY = 4;   // four rows per block
 
 __device__ __forceinline__ size_t node(const Lattice &L, int i, int j) { return (size_t)j * L.pitch + i; }
+
+// Workgroups are handed to the eight XCDs in turn (block b on XCD b mod 8),
+// and each XCD has its own L2.  Renumbering so that XCD x works through one
+// contiguous range of tiles keeps the halo rows that adjacent tiles share
+// inside one L2.  The map is a bijection of [0, nb).
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int x = b % NUM_XCD, k = b / NUM_XCD;
+    const int per = nb / NUM_XCD, rem = nb % NUM_XCD;
+    return x * per + min(x, rem) + k;
+}
+
+// Tile coordinates of this block in a 2-D grid.  A cache-resident state
+// (no streaming stores) gains from XCD-contiguous tiles; a state streamed
+// from HBM runs faster with every XCD on neighbouring rows (the plain order).
+__device__ __forceinline__ void block_tile(const Lattice &L, int &tx, int &ty)
+{
+    const int nb = gridDim.x * gridDim.y;
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    const int t = L.stream_stores ? b : xcd_tile(b, nb);
+    tx = t % gridDim.x;
+    ty = t / gridDim.x;
+}
+
+__device__ __forceinline__ int batch_tile(const SolveDesc *D, int b, int nb, int remap)
+{
+    return remap ? xcd_tile(b, nb) : b;
+}
 
 // ---------------------------------------------------------------------------
 // FP64, 11 populations.  Evaluation order and groupings match the plain
@@ -139,7 +164,7 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
     q[9] = hy / 6.0;
     q[10] = hy / 6.0;
 #pragma unroll
-    for (int k = 0; k < 11; ++k) put(&dst[k * P + c], 2.0 * q[k] - f[k]);
+    for (int k = 0; k < 11; ++k) put(&dst[k * P + c], 2.0 * q[k] - f[k], L.stream_stores);
     if (fields && j < L.ny) {
         fields[0 * P + c] = ez;
         fields[1 * P + c] = hx;
@@ -147,12 +172,14 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
     }
 }
 
-__global__ __launch_bounds__(BX *BY) void k_step_f64(Lattice L, const double *__restrict__ src,
-                                                      double *__restrict__ dst, double *__restrict__ fields,
-                                                      double einc)
+template <int CX, int R>
+__global__ __launch_bounds__(CX *R) void k_step_f64(Lattice L, const double *__restrict__ src,
+                                                     double *__restrict__ dst, double *__restrict__ fields, double einc)
 {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
+    int tx, ty;
+    block_tile(L, tx, ty);
+    const int i = tx * CX + threadIdx.x;
+    const int j = ty * R + threadIdx.y;
     if (i >= L.nx || j > L.ny) return;
     f64_node(L, src, dst, fields, einc, i, j);
 }
@@ -166,7 +193,7 @@ __global__ __launch_bounds__(BX *BY) void k_step_f64(Lattice L, const double *__
 enum { N_EPX = 0, N_EMX, N_EPY, N_EMY, N_HXPX, N_HXMX, N_HYPY, N_HYMY };
 
 template <typename T> __device__ __forceinline__ float ld(const T *p) { return (float)*p; }
-template <typename T> __device__ __forceinline__ void st(T *p, float v) { put(p, (T)v); }
+template <typename T> __device__ __forceinline__ void st(T *p, float v, bool stream) { put(p, (T)v, stream); }
 
 constexpr float SIXTH = 1.0f / 6.0f;
 constexpr float THIRD = 1.0f / 3.0f;
@@ -282,13 +309,13 @@ __device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t
 }
 
 template <typename NeqT>
-__device__ __forceinline__ void store_node(float *F, NeqT *N, size_t P, size_t c, const NodeData &d)
+__device__ __forceinline__ void store_node(float *F, NeqT *N, size_t P, size_t c, const NodeData &d, bool stream)
 {
-    put(&F[c], d.ez);
-    put(&F[P + c], d.hx);
-    put(&F[2 * P + c], d.hy);
+    put(&F[c], d.ez, stream);
+    put(&F[P + c], d.hx, stream);
+    put(&F[2 * P + c], d.hy, stream);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) st(&N[k * P + c], d.n[k]);
+    for (int k = 0; k < 8; ++k) st(&N[k * P + c], d.n[k], stream);
 }
 
 // Sides along x of node (i, j) and the material parameters; false for a conductor node.
@@ -355,7 +382,7 @@ __device__ __forceinline__ void neq_direct_node(const Lattice &L, const void *__
         load_incident_sides(L, F, N, i, j, lo, hi);
         neq_core<false>(L, i, j, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
     }
-    store_node(DF, DN, P, c, out);
+    store_node(DF, DN, P, c, out, L.stream_stores);
 }
 
 // Column i over rows [j0, j0 + TY) of the domain, or the companion row when j0 >= ny.
@@ -377,7 +404,7 @@ __device__ __forceinline__ void neq_sweep_column(const Lattice &L, const void *_
         const NodeData o = load_node(F, N, P, c);
         NodeData out;
         neq_core<true>(L, i, L.ny, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
-        store_node(DF, DN, P, c, out);
+        store_node(DF, DN, P, c, out, L.stream_stores);
         return;
     }
     const int j1 = min(j0 + TY, L.ny);
@@ -396,7 +423,7 @@ __device__ __forceinline__ void neq_sweep_column(const Lattice &L, const void *_
             load_incident_sides(L, F, N, i, j, lo, hi);
             NodeData out;
             neq_core<false>(L, i, j, m, eps, eps_rest, cur, l, r, below, above, lo, hi, einc, out);
-            store_node(DF, DN, P, c, out);
+            store_node(DF, DN, P, c, out, L.stream_stores);
         }
         below = Side{cur.ez, cur.hx, cur.hy, cur.n[N_EPY], cur.n[N_HYPY]};
         cur = nxt;
@@ -407,8 +434,10 @@ template <typename NeqT>
 __global__ __launch_bounds__(BX *BY) void k_step_neq(Lattice L, const void *__restrict__ srcv,
                                                       void *__restrict__ dstv, float einc)
 {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
+    int tx, ty;
+    block_tile(L, tx, ty);
+    const int i = tx * BX + threadIdx.x;
+    const int j = ty * BY + threadIdx.y;
     if (i >= L.nx || j > L.ny) return;
     neq_direct_node<NeqT>(L, srcv, dstv, einc, i, j);
 }
@@ -419,9 +448,11 @@ template <typename NeqT, int TY>
 __global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_sweep(Lattice L, const void *__restrict__ srcv,
                                                                    void *__restrict__ dstv, float einc)
 {
-    const int i = blockIdx.x * SWEEP_THREADS + threadIdx.x;
+    int tx, ty;
+    block_tile(L, tx, ty);
+    const int i = tx * SWEEP_THREADS + threadIdx.x;
     if (i >= L.nx) return;
-    neq_sweep_column<NeqT, TY>(L, srcv, dstv, einc, i, blockIdx.y * TY);
+    neq_sweep_column<NeqT, TY>(L, srcv, dstv, einc, i, ty * TY);
 }
 
 // ---------------------------------------------------------------------------
@@ -450,12 +481,12 @@ __device__ __forceinline__ void vload(const T *p, float (&out)[V])
 }
 
 template <typename T, int V>
-__device__ __forceinline__ void vstore(T *p, const float (&in)[V])
+__device__ __forceinline__ void vstore(T *p, const float (&in)[V], bool stream)
 {
     typename VecOf<T, V>::type v;
 #pragma unroll
     for (int k = 0; k < V; ++k) v[k] = (T)in[k];
-    put(reinterpret_cast<typename VecOf<T, V>::type *>(p), v);
+    put(reinterpret_cast<typename VecOf<T, V>::type *>(p), v, stream);
 }
 
 template <int V>
@@ -560,21 +591,135 @@ __device__ __forceinline__ void neq_vsweep_column(const Lattice &L, const void *
 #pragma unroll
             for (int q = 0; q < 8; ++q) out.n[q][v] = res.n[q];
         }
-        vstore<float, V>(DF + c, out.ez);
-        vstore<float, V>(DF + P + c, out.hx);
-        vstore<float, V>(DF + 2 * P + c, out.hy);
+        vstore<float, V>(DF + c, out.ez, L.stream_stores);
+        vstore<float, V>(DF + P + c, out.hx, L.stream_stores);
+        vstore<float, V>(DF + 2 * P + c, out.hy, L.stream_stores);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) vstore<NeqT, V>(DN + q * P + c, out.n[q]);
+        for (int q = 0; q < 8; ++q) vstore<NeqT, V>(DN + q * P + c, out.n[q], L.stream_stores);
         below = cur;
         cur = nxt;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Variant "vector tile": one shot per thread like the direct variant, but
+// each thread owns V adjacent nodes of one row: every plane moves with one
+// V-wide load or store, the x-neighbours come from the adjacent lanes (the
+// wavefront's edge lanes read theirs from memory) and the rows above and
+// below are read V-wide.  Blocks are 64 lanes x 4 rows.
+// ---------------------------------------------------------------------------
+
+template <typename NeqT, int V>
+__device__ __forceinline__ void neq_vtile_row(const Lattice &L, const void *__restrict__ srcv, void *__restrict__ dstv,
+                                              float einc, int col, int j)
+{
+    const size_t P = L.plane;
+    const float *F = reinterpret_cast<const float *>(srcv);
+    const NeqT *N = reinterpret_cast<const NeqT *>(F + 3 * P);
+    float *DF = reinterpret_cast<float *>(dstv);
+    NeqT *DN = reinterpret_cast<NeqT *>(DF + 3 * P);
+    const int i0 = col * V;
+    const int lane = threadIdx.x & 63;
+    const bool active = i0 < L.nx && j <= L.ny;
+    RowData<V> cur;
+    zero_row(cur);
+    const size_t c = node(L, i0, j);
+    if (active) load_row<NeqT, V>(F, N, P, c, cur);
+    // x-neighbours across lanes (every lane of the wavefront takes part)
+    Side xl, xr;
+    xl.ez = __shfl_up(cur.ez[V - 1], 1, 64);
+    xl.hx = __shfl_up(cur.hx[V - 1], 1, 64);
+    xl.hy = __shfl_up(cur.hy[V - 1], 1, 64);
+    xl.na = __shfl_up(cur.n[N_EPX][V - 1], 1, 64);
+    xl.nb = __shfl_up(cur.n[N_HXPX][V - 1], 1, 64);
+    xr.ez = __shfl_down(cur.ez[0], 1, 64);
+    xr.hx = __shfl_down(cur.hx[0], 1, 64);
+    xr.hy = __shfl_down(cur.hy[0], 1, 64);
+    xr.na = __shfl_down(cur.n[N_EMX][0], 1, 64);
+    xr.nb = __shfl_down(cur.n[N_HXMX][0], 1, 64);
+    if (!active) return;
+    if (j == L.ny) {
+        // companion row: per node, as in the other variants
+        for (int v = 0; v < V; ++v)
+            if (i0 + v < L.nx) neq_direct_node<NeqT>(L, srcv, dstv, einc, i0 + v, L.ny);
+        return;
+    }
+    if (lane == 0 && i0 > 0) xl = load_side(F, N, P, c - 1, N_EPX, N_HXPX);
+    if (lane == 63 && i0 + V < L.nx) xr = load_side(F, N, P, c + V, N_EMX, N_HXMX);
+    // rows below and above, V-wide
+    float bz[V], bhx[V], bhy[V], bna[V], bnb[V], tz[V], thx[V], thy[V], tna[V], tnb[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) bz[v] = bhx[v] = bhy[v] = bna[v] = bnb[v] = tz[v] = thx[v] = thy[v] = tna[v] = tnb[v] = 0.0f;
+    if (j > 0) {
+        const size_t cb = c - L.pitch;
+        vload<float, V>(F + cb, bz);
+        vload<float, V>(F + P + cb, bhx);
+        vload<float, V>(F + 2 * P + cb, bhy);
+        vload<NeqT, V>(N + N_EPY * P + cb, bna);
+        vload<NeqT, V>(N + N_HYPY * P + cb, bnb);
+    }
+    if (j + 1 < L.ny) {
+        const size_t ct = c + L.pitch;
+        vload<float, V>(F + ct, tz);
+        vload<float, V>(F + P + ct, thx);
+        vload<float, V>(F + 2 * P + ct, thy);
+        vload<NeqT, V>(N + N_EMY * P + ct, tna);
+        vload<NeqT, V>(N + N_HYMY * P + ct, tnb);
+    }
+    const typename MaskVec<V>::type mv = *reinterpret_cast<const typename MaskVec<V>::type *>(L.mask + c);
+    RowData<V> out;
+    zero_row(out);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int i = i0 + v;
+        const uint8_t m = (uint8_t)(mv >> (8 * v));
+        const int mat = m & 3;
+        if (i >= L.nx || mat == MAT_PEC) continue;
+        const float eps = (float)L.eps[mat];
+        const float eps_rest = (float)L.eps_rest[mat];
+        NodeData o;
+        o.ez = cur.ez[v];
+        o.hx = cur.hx[v];
+        o.hy = cur.hy[v];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o.n[q] = cur.n[q][v];
+        const Side l = v == 0 ? xl : Side{cur.ez[v - 1], cur.hx[v - 1], cur.hy[v - 1], cur.n[N_EPX][v - 1], cur.n[N_HXPX][v - 1]};
+        const Side r = v == V - 1 ? xr : Side{cur.ez[v + 1], cur.hx[v + 1], cur.hy[v + 1], cur.n[N_EMX][v + 1], cur.n[N_HXMX][v + 1]};
+        const Side b{bz[v], bhx[v], bhy[v], bna[v], bnb[v]};
+        const Side t{tz[v], thx[v], thy[v], tna[v], tnb[v]};
+        Side lo{}, hi{};
+        load_incident_sides(L, F, N, i, j, lo, hi);
+        NodeData res;
+        neq_core<false>(L, i, j, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, res);
+        out.ez[v] = res.ez;
+        out.hx[v] = res.hx;
+        out.hy[v] = res.hy;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) out.n[q][v] = res.n[q];
+    }
+    vstore<float, V>(DF + c, out.ez, L.stream_stores);
+    vstore<float, V>(DF + P + c, out.hx, L.stream_stores);
+    vstore<float, V>(DF + 2 * P + c, out.hy, L.stream_stores);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) vstore<NeqT, V>(DN + q * P + c, out.n[q], L.stream_stores);
+}
+
+template <typename NeqT, int V, int CX, int R>
+__global__ __launch_bounds__(CX *R) void k_step_neq_vtile(Lattice L, const void *__restrict__ srcv,
+                                                           void *__restrict__ dstv, float einc)
+{
+    int tx, ty;
+    block_tile(L, tx, ty);
+    neq_vtile_row<NeqT, V>(L, srcv, dstv, einc, tx * CX + threadIdx.x, ty * R + threadIdx.y);
 }
 
 template <typename NeqT, int V, int TY>
 __global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_vsweep(Lattice L, const void *__restrict__ srcv,
                                                                     void *__restrict__ dstv, float einc)
 {
-    neq_vsweep_column<NeqT, V, TY>(L, srcv, dstv, einc, blockIdx.x * SWEEP_THREADS + threadIdx.x, blockIdx.y * TY);
+    int tx, ty;
+    block_tile(L, tx, ty);
+    neq_vsweep_column<NeqT, V, TY>(L, srcv, dstv, einc, tx * SWEEP_THREADS + threadIdx.x, ty * TY);
 }
 
 // ---------------------------------------------------------------------------
@@ -587,14 +732,16 @@ __device__ __forceinline__ double batch_incident(const SolveDesc &d, int64_t n)
     return n < d.ramp_end ? d.src_tab[n] : d.src_tab[d.ramp_end + n % d.T];
 }
 
-__global__ __launch_bounds__(BX *BY) void k_step_f64_batch(SolveDesc *__restrict__ D, const Tile *__restrict__ tiles)
+template <int CX, int R>
+__global__ __launch_bounds__(CX *R) void k_step_f64_batch(SolveDesc *__restrict__ D, const Tile *__restrict__ tiles,
+                                                           int remap)
 {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[batch_tile(D, blockIdx.x, gridDim.x, remap)];
     const SolveDesc &d = D[t.slot];
     const int64_t n = d.n;
     if (n >= d.steps) return;
-    const int i = t.tx * BX + threadIdx.x;
-    const int j = t.ty * BY + threadIdx.y;
+    const int i = t.tx * CX + threadIdx.x;
+    const int j = t.ty * R + threadIdx.y;
     if (i >= d.L.nx || j > d.L.ny) return;
     const bool in_window = n + 1 > d.steps - d.window;
     f64_node(d.L, (const double *)d.state[n & 1], (double *)d.state[(n + 1) & 1], in_window ? d.fields : nullptr,
@@ -602,9 +749,10 @@ __global__ __launch_bounds__(BX *BY) void k_step_f64_batch(SolveDesc *__restrict
 }
 
 template <typename NeqT>
-__global__ __launch_bounds__(BX *BY) void k_step_neq_batch(SolveDesc *__restrict__ D, const Tile *__restrict__ tiles)
+__global__ __launch_bounds__(BX *BY) void k_step_neq_batch(SolveDesc *__restrict__ D, const Tile *__restrict__ tiles,
+                                                            int remap)
 {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[batch_tile(D, blockIdx.x, gridDim.x, remap)];
     const SolveDesc &d = D[t.slot];
     const int64_t n = d.n;
     if (n >= d.steps) return;
@@ -616,9 +764,9 @@ __global__ __launch_bounds__(BX *BY) void k_step_neq_batch(SolveDesc *__restrict
 
 template <typename NeqT, int TY>
 __global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_sweep_batch(SolveDesc *__restrict__ D,
-                                                                         const Tile *__restrict__ tiles)
+                                                                         const Tile *__restrict__ tiles, int remap)
 {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[batch_tile(D, blockIdx.x, gridDim.x, remap)];
     const SolveDesc &d = D[t.slot];
     const int64_t n = d.n;
     if (n >= d.steps) return;
@@ -629,14 +777,26 @@ __global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_sweep_batch(SolveDes
 
 template <typename NeqT, int V, int TY>
 __global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_vsweep_batch(SolveDesc *__restrict__ D,
-                                                                          const Tile *__restrict__ tiles)
+                                                                          const Tile *__restrict__ tiles, int remap)
 {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[batch_tile(D, blockIdx.x, gridDim.x, remap)];
     const SolveDesc &d = D[t.slot];
     const int64_t n = d.n;
     if (n >= d.steps) return;
     neq_vsweep_column<NeqT, V, TY>(d.L, d.state[n & 1], d.state[(n + 1) & 1], (float)batch_incident(d, n),
                                    t.tx * SWEEP_THREADS + threadIdx.x, t.ty * TY);
+}
+
+template <typename NeqT, int V, int CX, int R>
+__global__ __launch_bounds__(CX *R) void k_step_neq_vtile_batch(SolveDesc *__restrict__ D, const Tile *__restrict__ tiles,
+                                                                 int remap)
+{
+    const Tile t = tiles[batch_tile(D, blockIdx.x, gridDim.x, remap)];
+    const SolveDesc &d = D[t.slot];
+    const int64_t n = d.n;
+    if (n >= d.steps) return;
+    neq_vtile_row<NeqT, V>(d.L, d.state[n & 1], d.state[(n + 1) & 1], (float)batch_incident(d, n),
+                           t.tx * CX + threadIdx.x, t.ty * R + threadIdx.y);
 }
 
 __global__ void k_advance(SolveDesc *D, int nslots)
@@ -849,9 +1009,14 @@ dim3 step_grid(const Lattice &L) { return dim3((L.nx + BX - 1) / BX, (L.ny + 1 +
 }  // namespace
 
 hipError_t launch_step_f64(const Lattice &L, const double *src, double *dst, double *fields, double einc,
-                           hipStream_t s)
+                           hipStream_t s, int variant)
 {
-    hipLaunchKernelGGL(k_step_f64, step_grid(L), dim3(BX, BY), 0, s, L, src, dst, fields, einc);
+    auto grid = [&](int cx, int r) { return dim3((L.nx + cx - 1) / cx, (L.ny + 1 + r - 1) / r); };
+    switch (variant) {
+    case F64_W256_R1: hipLaunchKernelGGL((k_step_f64<256, 1>), grid(256, 1), dim3(256, 1), 0, s, L, src, dst, fields, einc); break;
+    case F64_W256_R2: hipLaunchKernelGGL((k_step_f64<256, 2>), grid(256, 2), dim3(256, 2), 0, s, L, src, dst, fields, einc); break;
+    default: hipLaunchKernelGGL((k_step_f64<BX, 4>), grid(BX, 4), dim3(BX, 4), 0, s, L, src, dst, fields, einc); break;
+    }
     return hipGetLastError();
 }
 
@@ -863,6 +1028,7 @@ hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, voi
     auto sweep_grid = [&](int v, int ty) {
         return dim3((L.nx + SWEEP_THREADS * v - 1) / (SWEEP_THREADS * v), (L.ny + ty - 1) / ty + 1);
     };
+    auto vtile_grid = [&](int v, int cx, int r) { return dim3((L.nx + cx * v - 1) / (cx * v), (L.ny + 1 + r - 1) / r); };
 #define JLB_NEQ_LAUNCH(T)                                                                                                    \
     switch (variant) {                                                                                                       \
     case NEQ_SWEEP8: hipLaunchKernelGGL((k_step_neq_sweep<T, 8>), sweep_grid(1, 8), sweep_block, 0, s, L, src, dst, e); break;      \
@@ -874,6 +1040,12 @@ hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, voi
     case NEQ_V4_T4: hipLaunchKernelGGL((k_step_neq_vsweep<T, 4, 4>), sweep_grid(4, 4), sweep_block, 0, s, L, src, dst, e); break;   \
     case NEQ_V4_T8: hipLaunchKernelGGL((k_step_neq_vsweep<T, 4, 8>), sweep_grid(4, 8), sweep_block, 0, s, L, src, dst, e); break;   \
     case NEQ_V4_T16: hipLaunchKernelGGL((k_step_neq_vsweep<T, 4, 16>), sweep_grid(4, 16), sweep_block, 0, s, L, src, dst, e); break; \
+    case NEQ_TILE_V2: hipLaunchKernelGGL((k_step_neq_vtile<T, 2, 64, 4>), vtile_grid(2, 64, 4), dim3(64, 4), 0, s, L, src, dst, e); break;     \
+    case NEQ_TILE_V4: hipLaunchKernelGGL((k_step_neq_vtile<T, 4, 64, 4>), vtile_grid(4, 64, 4), dim3(64, 4), 0, s, L, src, dst, e); break;     \
+    case NEQ_TILE_V2_W256: hipLaunchKernelGGL((k_step_neq_vtile<T, 2, 256, 1>), vtile_grid(2, 256, 1), dim3(256, 1), 0, s, L, src, dst, e); break; \
+    case NEQ_TILE_V4_W256: hipLaunchKernelGGL((k_step_neq_vtile<T, 4, 256, 1>), vtile_grid(4, 256, 1), dim3(256, 1), 0, s, L, src, dst, e); break; \
+    case NEQ_TILE_V2_W256_R2: hipLaunchKernelGGL((k_step_neq_vtile<T, 2, 256, 2>), vtile_grid(2, 256, 2), dim3(256, 2), 0, s, L, src, dst, e); break; \
+    case NEQ_TILE_V4_W256_R2: hipLaunchKernelGGL((k_step_neq_vtile<T, 4, 256, 2>), vtile_grid(4, 256, 2), dim3(256, 2), 0, s, L, src, dst, e); break; \
     default: hipLaunchKernelGGL(k_step_neq<T>, step_grid(L), dim3(BX, BY), 0, s, L, src, dst, e); break;                 \
     }
     if (precision == 1) {
@@ -904,37 +1076,64 @@ hipError_t launch_reduce(const ContourDev &C, double inv_window, double f0, doub
 
 void tile_shape(int precision, int variant, int &cols, int &rows)
 {
-    if (precision == 0 || variant == NEQ_DIRECT || variant < 0 || variant >= NEQ_VARIANTS) {
+    if (precision == 0) {
+        cols = variant == F64_W256_R1 || variant == F64_W256_R2 ? 256 : BX;
+        rows = variant == F64_W256_R1 ? 1 : variant == F64_W256_R2 ? 2 : 4;
+        return;
+    }
+    if (variant == NEQ_DIRECT || variant < 0 || variant >= NEQ_VARIANTS) {
         cols = BX;
         rows = BY;
         return;
     }
-    static const int vcols[NEQ_VARIANTS] = {BX, 1, 1, 1, 2, 2, 2, 4, 4, 4};
-    static const int vrows[NEQ_VARIANTS] = {BY, 8, 16, 32, 4, 8, 16, 4, 8, 16};
+    if (variant >= NEQ_TILE_V2) {
+        static const int tv[6] = {2, 4, 2, 4, 2, 4}, tc[6] = {64, 64, 256, 256, 256, 256}, tr[6] = {4, 4, 1, 1, 2, 2};
+        cols = tc[variant - NEQ_TILE_V2] * tv[variant - NEQ_TILE_V2];
+        rows = tr[variant - NEQ_TILE_V2];
+        return;
+    }
+    static const int vcols[10] = {BX, 1, 1, 1, 2, 2, 2, 4, 4, 4};
+    static const int vrows[10] = {BY, 8, 16, 32, 4, 8, 16, 4, 8, 16};
     cols = SWEEP_THREADS * vcols[variant];
     rows = vrows[variant];
 }
 
-hipError_t launch_step_batch(int precision, int variant, SolveDesc *d, const Tile *tiles, int ntiles, hipStream_t s)
+bool tile_is_sweep(int precision, int variant)
+{
+    return precision != 0 && variant > NEQ_DIRECT && variant < NEQ_TILE_V2;
+}
+
+hipError_t launch_step_batch(int precision, int variant, SolveDesc *d, const Tile *tiles, int ntiles, int remap,
+                             hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     if (precision == 0) {
-        hipLaunchKernelGGL(k_step_f64_batch, dim3(ntiles), dim3(BX, BY), 0, s, d, tiles);
+        switch (variant) {
+        case F64_W256_R1: hipLaunchKernelGGL((k_step_f64_batch<256, 1>), dim3(ntiles), dim3(256, 1), 0, s, d, tiles, remap); break;
+        case F64_W256_R2: hipLaunchKernelGGL((k_step_f64_batch<256, 2>), dim3(ntiles), dim3(256, 2), 0, s, d, tiles, remap); break;
+        default: hipLaunchKernelGGL((k_step_f64_batch<BX, 4>), dim3(ntiles), dim3(BX, 4), 0, s, d, tiles, remap); break;
+        }
         return hipGetLastError();
     }
     const dim3 g(ntiles), b(SWEEP_THREADS);
 #define JLB_BATCH_LAUNCH(T)                                                                                         \
     switch (variant) {                                                                                              \
-    case NEQ_SWEEP8: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 8>), g, b, 0, s, d, tiles); break;              \
-    case NEQ_SWEEP16: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 16>), g, b, 0, s, d, tiles); break;            \
-    case NEQ_SWEEP32: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 32>), g, b, 0, s, d, tiles); break;            \
-    case NEQ_V2_T4: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 4>), g, b, 0, s, d, tiles); break;           \
-    case NEQ_V2_T8: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 8>), g, b, 0, s, d, tiles); break;           \
-    case NEQ_V2_T16: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 16>), g, b, 0, s, d, tiles); break;         \
-    case NEQ_V4_T4: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 4>), g, b, 0, s, d, tiles); break;           \
-    case NEQ_V4_T8: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 8>), g, b, 0, s, d, tiles); break;           \
-    case NEQ_V4_T16: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 16>), g, b, 0, s, d, tiles); break;         \
-    default: hipLaunchKernelGGL(k_step_neq_batch<T>, g, dim3(BX, BY), 0, s, d, tiles); break;                      \
+    case NEQ_SWEEP8: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 8>), g, b, 0, s, d, tiles, remap); break;              \
+    case NEQ_SWEEP16: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 16>), g, b, 0, s, d, tiles, remap); break;            \
+    case NEQ_SWEEP32: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 32>), g, b, 0, s, d, tiles, remap); break;            \
+    case NEQ_V2_T4: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 4>), g, b, 0, s, d, tiles, remap); break;           \
+    case NEQ_V2_T8: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 8>), g, b, 0, s, d, tiles, remap); break;           \
+    case NEQ_V2_T16: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 16>), g, b, 0, s, d, tiles, remap); break;         \
+    case NEQ_V4_T4: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 4>), g, b, 0, s, d, tiles, remap); break;           \
+    case NEQ_V4_T8: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 8>), g, b, 0, s, d, tiles, remap); break;           \
+    case NEQ_V4_T16: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 16>), g, b, 0, s, d, tiles, remap); break;         \
+    case NEQ_TILE_V2: hipLaunchKernelGGL((k_step_neq_vtile_batch<T, 2, 64, 4>), g, dim3(64, 4), 0, s, d, tiles, remap); break;      \
+    case NEQ_TILE_V4: hipLaunchKernelGGL((k_step_neq_vtile_batch<T, 4, 64, 4>), g, dim3(64, 4), 0, s, d, tiles, remap); break;      \
+    case NEQ_TILE_V2_W256: hipLaunchKernelGGL((k_step_neq_vtile_batch<T, 2, 256, 1>), g, dim3(256, 1), 0, s, d, tiles, remap); break; \
+    case NEQ_TILE_V4_W256: hipLaunchKernelGGL((k_step_neq_vtile_batch<T, 4, 256, 1>), g, dim3(256, 1), 0, s, d, tiles, remap); break; \
+    case NEQ_TILE_V2_W256_R2: hipLaunchKernelGGL((k_step_neq_vtile_batch<T, 2, 256, 2>), g, dim3(256, 2), 0, s, d, tiles, remap); break; \
+    case NEQ_TILE_V4_W256_R2: hipLaunchKernelGGL((k_step_neq_vtile_batch<T, 4, 256, 2>), g, dim3(256, 2), 0, s, d, tiles, remap); break; \
+    default: hipLaunchKernelGGL(k_step_neq_batch<T>, g, dim3(BX, BY), 0, s, d, tiles, remap); break;                      \
     }
     if (precision == 1) {
         JLB_BATCH_LAUNCH(float)
@@ -958,20 +1157,22 @@ hipError_t launch_advance(SolveDesc *d, int nslots, hipStream_t s)
     return hipGetLastError();
 }
 
-// Plain copy, 16 bytes per lane: the reference kernel for bandwidth and
-// for calibrating memory-traffic counters.
+// Plain copy, one 16-byte element per lane over one grid covering the
+// buffer (on this part a one-shot grid outruns grid-stride loops): the
+// reference kernel for bandwidth and for calibrating memory-traffic counters.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, size_t n16)
 {
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += (size_t)gridDim.x * blockDim.x)
-        put(&dst[k], src[k]);
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n16) dst[k] = src[k];
 }
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
 {
     const size_t n16 = bytes / 16;
-    const size_t blocks = std::min<size_t>((n16 + 255) / 256, (size_t)256 * 64);
+    const size_t blocks = (n16 + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const u32x4 *)src, (u32x4 *)dst, n16);
     return hipGetLastError();
 }

@@ -73,6 +73,7 @@ struct jlb_engine {
     int tile_off[3] = {0, 0, 0};
     int variant[3] = {0, 0, 0};
     int max_nc = 0;
+    int remap = 0;
     bool dirty = true;
     hipGraphExec_t graph = nullptr;
 };
@@ -147,13 +148,19 @@ int rebuild(jlb_engine *e)
     std::vector<SolveDesc> desc(ns);
     std::vector<Tile> tiles[3];
     e->max_nc = 0;
-    for (int p = 0; p < 3; ++p) e->variant[p] = p == 0 ? 0 : jlb::step_variant(p);
+    // the resident states together decide whether they stay cache-resident
+    size_t working_set = 0;
+    for (int k = 0; k < ns; ++k) working_set += 2 * e->reqs[e->resident[k]].plan.state_bytes;
+    const int stream_stores = working_set > CACHE_RESIDENT_BYTES ? 1 : 0;
+    e->remap = stream_stores ? 0 : 1;
+    for (int p = 0; p < 3; ++p) e->variant[p] = jlb::step_variant(p);
     for (int k = 0; k < ns; ++k) {
         Request &r = e->reqs[e->resident[k]];
         const Plan &q = r.plan;
         SolveDesc &d = desc[k];
         memset(&d, 0, sizeof(d));
         d.L = lattice_of(q, (const uint8_t *)(r.ws + q.off_mask));
+        d.L.stream_stores = stream_stores;
         d.state[0] = r.ws + q.off_state[0];
         d.state[1] = r.ws + q.off_state[1];
         d.fields = q.prob.precision == JLB_FP64 ? (double *)(r.ws + q.off_fields) : nullptr;
@@ -172,7 +179,7 @@ int rebuild(jlb_engine *e)
         const int tx = (q.nx + cols - 1) / cols;
         // node tiles cover rows 0..ny (the companion row included); row sweeps
         // cover the domain rows and give the companion row a tile row of its own
-        const bool sweep = p != JLB_FP64 && e->variant[p] != NEQ_DIRECT;
+        const bool sweep = tile_is_sweep(p, e->variant[p]);
         const int ty = sweep ? (q.ny + rows - 1) / rows + 1 : (q.ny + 1 + rows - 1) / rows;
         for (int y = 0; y < ty; ++y)
             for (int x = 0; x < tx; ++x) tiles[p].push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
@@ -207,7 +214,7 @@ hipError_t launch_batch_step(jlb_engine *e)
     const int ns = (int)e->resident.size();
     hipError_t err = hipSuccess;
     for (int p = 0; p < 3 && err == hipSuccess; ++p)
-        err = launch_step_batch(p, e->variant[p], e->d_desc, e->d_tiles + e->tile_off[p], e->ntiles[p], e->s);
+        err = launch_step_batch(p, e->variant[p], e->d_desc, e->d_tiles + e->tile_off[p], e->ntiles[p], e->remap, e->s);
     if (err == hipSuccess) err = launch_contour_batch(e->d_desc, ns, e->max_nc, e->s);
     if (err == hipSuccess) err = launch_advance(e->d_desc, ns, e->s);
     return err;

@@ -226,7 +226,7 @@ double incident(const Plan &q, int64_t n)
 // forced by the caller.  All variants give identical results.
 // ---------------------------------------------------------------------------
 
-static std::atomic<int> g_variant[3] = {{0}, {NEQ_V2_T8}, {NEQ_V2_T8}};
+static std::atomic<int> g_variant[3] = {{0}, {NEQ_DIRECT}, {NEQ_DIRECT}};
 
 int step_variant(int precision) { return g_variant[precision].load(std::memory_order_relaxed); }
 void set_step_variant(int precision, int v) { g_variant[precision].store(v, std::memory_order_relaxed); }
@@ -234,7 +234,7 @@ void set_step_variant(int precision, int v) { g_variant[precision].store(v, std:
 hipError_t launch_step(const Plan &q, const Lattice &L, void *src, void *dst, double *fields, double einc, hipStream_t s,
                        int variant)
 {
-    if (q.prob.precision == JLB_FP64) return launch_step_f64(L, (const double *)src, (double *)dst, fields, einc, s);
+    if (q.prob.precision == JLB_FP64) return launch_step_f64(L, (const double *)src, (double *)dst, fields, einc, s, variant);
     return launch_step_neq(q.prob.precision, L, src, dst, einc, s, variant);
 }
 
@@ -271,6 +271,7 @@ Lattice lattice_of(const Plan &q, const uint8_t *dmask)
         L.eps[k] = q.eps[k];
         L.eps_rest[k] = q.eps[k] - 2.0 / 3.0;
     }
+    L.stream_stores = 2 * q.state_bytes > CACHE_RESIDENT_BYTES ? 1 : 0;
     return L;
 }
 
@@ -323,7 +324,7 @@ static int launch_one_step(const Plan &q, char *ws, const Lattice &L, const Cont
     hipError_t e;
     if (prec == JLB_FP64) {
         double *fields = (in_window || want_fields) ? (double *)(ws + q.off_fields) : nullptr;
-        e = launch_step_f64(L, (const double *)src, (double *)dst, fields, einc, s);
+        e = launch_step_f64(L, (const double *)src, (double *)dst, fields, einc, s, step_variant(prec));
         if (e == hipSuccess && in_window) e = launch_contour(prec, L, ws + q.off_fields, C, s);
     } else {
         e = launch_step_neq(prec, L, src, dst, einc, s, step_variant(prec));
@@ -607,16 +608,10 @@ int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_byte
     clear_error();
     if (!prob || !best_variant) return fail(JLB_E_ARG, "null argument");
     if (launches < 1) return fail(JLB_E_ARG, "launches must be >= 1");
-    if (prob->precision == JLB_FP64) {
-        *best_variant = 0;
-        double ms = 0.0;
-        int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, 0, &ms, stream);
-        if (ms_per_variant) ms_per_variant[0] = ms;
-        return rc;
-    }
+    const int nvar = prob->precision == JLB_FP64 ? F64_VARIANTS : NEQ_VARIANTS;
     double best = 1e300;
     int bv = step_variant(prob->precision);
-    for (int v = 0; v < NEQ_VARIANTS; ++v) {
+    for (int v = 0; v < nvar; ++v) {
         double ms = 0.0;
         int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, v, &ms, stream);
         if (rc) return rc;
@@ -634,8 +629,9 @@ int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_byte
 int jlb_set_step_variant(int32_t precision, int32_t variant)
 {
     clear_error();
-    if (precision < 1 || precision > 2 || variant < 0 || variant >= NEQ_VARIANTS)
-        return fail(JLB_E_ARG, "precision must be 1 or 2 and variant 0..%d", NEQ_VARIANTS - 1);
+    const int nvar = precision == JLB_FP64 ? F64_VARIANTS : NEQ_VARIANTS;
+    if (precision < 0 || precision > 2 || variant < 0 || variant >= nvar)
+        return fail(JLB_E_ARG, "precision 0..2 and variant 0..%d", nvar - 1);
     set_step_variant(precision, variant);
     return JLB_OK;
 }

@@ -35,7 +35,13 @@ struct Lattice {
     const uint8_t *mask;  // [ny][pitch]
     double eps[4];        // permittivity per material id (id 3 unused)
     double eps_rest[4];   // eps - 2/3: coefficient of Ez in the rest e-population's equilibrium
+    int stream_stores;    // 1: write the next state past the caches (state larger than the Infinity Cache)
+    int pad;
 };
+
+// Working sets above this many bytes do not stay in the 256 MB Infinity Cache
+// between steps; their state stores stream past the caches.
+constexpr size_t CACHE_RESIDENT_BYTES = (size_t)160 << 20;
 
 // Contour samples (structure of arrays, n entries each).
 struct ContourDev {
@@ -49,7 +55,7 @@ struct ContourDev {
 
 // Launchers (return the first HIP error).
 hipError_t launch_step_f64(const Lattice &L, const double *src, double *dst, double *fields, double einc,
-                           hipStream_t s);
+                           hipStream_t s, int variant);
 // Kernel variants of the FP32 / BF16 step (identical results, different
 // thread-to-node mappings); chosen per device and grid by the autotuner.
 enum NeqVariant {
@@ -63,8 +69,16 @@ enum NeqVariant {
     NEQ_V4_T4 = 7,    // four adjacent nodes per thread, 4 / 8 / 16 rows
     NEQ_V4_T8 = 8,
     NEQ_V4_T16 = 9,
-    NEQ_VARIANTS = 10
+    NEQ_TILE_V2 = 10, // two / four adjacent nodes per thread, one row per thread,
+    NEQ_TILE_V4 = 11, //   64 x 4 thread blocks
+    NEQ_TILE_V2_W256 = 12, // the same with four wavefronts side by side in x
+    NEQ_TILE_V4_W256 = 13, //   (256 x 1 and 256 x 2 thread blocks): the halo
+    NEQ_TILE_V2_W256_R2 = 14, //   between wavefronts stays on one CU
+    NEQ_TILE_V4_W256_R2 = 15,
+    NEQ_VARIANTS = 16
 };
+// FP64 step variants: one node per thread in 64 x 4, 256 x 1 or 256 x 2 thread blocks.
+enum F64Variant { F64_R4 = 0, F64_W256_R1 = 1, F64_W256_R2 = 2, F64_VARIANTS = 3 };
 hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, void *dst, double einc, hipStream_t s,
                            int variant);
 // Fields: FP64 planes [3][plane] for precision 0, the FP32 field planes of the
@@ -106,7 +120,11 @@ struct Tile {
 
 // Tile shape of a precision / variant: columns x rows per block.
 void tile_shape(int precision, int variant, int &cols, int &rows);
-hipError_t launch_step_batch(int precision, int variant, SolveDesc *d, const Tile *tiles, int ntiles, hipStream_t s);
+// Row sweeps give the companion row a tile row of its own.
+bool tile_is_sweep(int precision, int variant);
+// remap = 1 hands XCD-contiguous tiles to the eight XCDs (cache-resident working sets).
+hipError_t launch_step_batch(int precision, int variant, SolveDesc *d, const Tile *tiles, int ntiles, int remap,
+                             hipStream_t s);
 hipError_t launch_contour_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s);
 hipError_t launch_advance(SolveDesc *d, int nslots, hipStream_t s);
 

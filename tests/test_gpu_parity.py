@@ -158,7 +158,7 @@ def test_config2_full_size_properties(jlb):
     assert abs(m["fx"] - d["fx"]) < 1e-10 and abs(m["fy"] + d["fy"]) < 1e-10 and abs(m["tz"] + d["tz"]) < 1e-10
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 def test_step_kernel_variants_give_identical_results(jlb, precision):
     """Every thread-to-node mapping the autotuner may pick computes the same
     arithmetic: fields and forces agree bit for bit (ragged sizes, conductor
@@ -172,7 +172,8 @@ def test_step_kernel_variants_give_identical_results(jlb, precision):
     try:
         for p in cases:
             outs = []
-            for v in range(len(jlb.STEP_VARIANTS)):
+            names = jlb.FP64_STEP_VARIANTS if precision == "fp64" else jlb.STEP_VARIANTS
+            for v in range(len(names)):
                 jlb.jlb_set_step_variant(prec, v)
                 outs.append(jlb.solve(p, precision, fields=True))
             for o in outs[1:]:
