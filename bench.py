@@ -63,10 +63,8 @@ def measured_traffic(precision: str, variant: int):
         return None
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    e = t.get("config2", {}).get(precision)
-    if not e or e.get("variant") != variant:
-        return None
-    return e.get("hbm_bytes_per_launch")
+    e = t.get("config2", {}).get(precision, {}).get(str(variant))
+    return e.get("hbm_bytes_per_launch") if e else None
 
 
 def gpu_leg(args):
@@ -258,7 +256,12 @@ def run_kernel_only(args):
         p = workloads.config2()
     prob = jlb.make_problem(p, args.precision)
     ws = _workspace(jlb, prob)
-    variant, _ = jlb.jlb_autotune(prob, 5, ws)
+    if args.variant >= 0:
+        # counter passes serialise kernels, which would mislead the autotuner
+        jlb.jlb_set_step_variant(jlb.PRECISIONS[args.precision], args.variant)
+        variant = args.variant
+    else:
+        variant, _ = jlb.jlb_autotune(prob, 5, ws)
     ms = jlb.jlb_time_step_kernel(prob, 2, args.launches, ws)
     copy_bytes = 1 << 30
     cms = jlb.jlb_copy_bandwidth(copy_bytes, 3)
@@ -301,6 +304,52 @@ def summarize(args):
     print(args.out)
 
 
+def _counter_means(d: str, counter: str) -> dict:
+    """Mean value of one counter per kernel name over a rocprofv3 CSV output folder."""
+    agg = {}
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") == counter:
+                    agg.setdefault(r.get("Kernel_Name", ""), []).append(float(r.get("Counter_Value", 0.0)))
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def record_traffic(args):
+    """HBM bytes per launch of the step kernel from a FETCH_SIZE and a
+    WRITE_SIZE pass of --kernel-only, each scaled so that the plain copy
+    kernel of the same run reads its known byte count, merged into the
+    traffic file under (workload, precision, variant)."""
+    fetch = _counter_means(args.fetch_dir, "FETCH_SIZE")
+    write = _counter_means(args.write_dir, "WRITE_SIZE")
+    copy_bytes = float(1 << 30)  # --kernel-only copies 1 GiB
+
+    def pick(table, copy):
+        step = [v for k, v in table.items() if "k_step" in k]
+        cp = [v for k, v in table.items() if "k_copy" in k]
+        if len(step) != 1 or len(cp) != 1:
+            raise SystemExit(f"expected one step and one copy kernel, found {list(table)}")
+        return step[0], copy / (cp[0] * 1024.0)
+
+    f_kib, f_scale = pick(fetch, copy_bytes)
+    w_kib, w_scale = pick(write, copy_bytes)
+    entry = {"variant": args.variant, "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
+             "fetch_scale": f_scale, "write_scale": w_scale,
+             "hbm_bytes_per_launch": f_kib * 1024.0 * f_scale + w_kib * 1024.0 * w_scale, "command": args.command}
+    try:
+        with open(args.out) as f:
+            t = json.load(f)
+    except OSError:
+        t = {}
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        t = {}
+    t["kernel_source_sha256_16"] = kernel_source_hash()
+    t.setdefault(args.record_traffic, {}).setdefault(args.precision, {})[str(args.variant)] = entry
+    with open(args.out, "w") as f:
+        json.dump(t, f, indent=1, sort_keys=True)
+    print(json.dumps(entry))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,12 +366,19 @@ def main():
     ap.add_argument("--kernel-only", action="store_true")
     ap.add_argument("--launches", type=int, default=50)
     ap.add_argument("--grid", type=int, default=0, help="kernel-only: an n x n grid instead of config 2")
+    ap.add_argument("--variant", type=int, default=-1, help="kernel-only: this step variant instead of the autotuner's")
     ap.add_argument("--summarize", default=None)
+    ap.add_argument("--record-traffic", default=None, help="workload key (config2, grid4096): merge counter passes")
+    ap.add_argument("--fetch-dir", default=None)
+    ap.add_argument("--write-dir", default=None)
     ap.add_argument("--command", default="")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     if args.summarize:
         summarize(args)
+        return
+    if args.record_traffic:
+        record_traffic(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X (independent solves shard with no "

@@ -124,7 +124,9 @@ int make_plan(const jlb_problem *p, Plan *pl)
     }
     q.off_state[0] = take(q.state_bytes);
     q.off_state[1] = take(q.state_bytes);
-    q.off_fields = p->precision == JLB_FP64 ? take(3 * q.plane * sizeof(double)) : 0;
+    // FP64: field planes for two time levels, by parity (a launch that writes
+    // level n + 1 leaves level n intact)
+    q.off_fields = p->precision == JLB_FP64 ? take(2 * 3 * q.plane * sizeof(double)) : 0;
     q.off_mask = take((size_t)q.ny * q.pitch);
     q.off_i0 = take(q.nc * sizeof(int));
     q.off_j0 = take(q.nc * sizeof(int));
@@ -305,39 +307,40 @@ int upload_setup(const Plan &q, char *ws, hipStream_t s)
     HIP_TRY(hipMemcpyAsync(ws + q.off_nyk, ch.nyk.data(), q.nc * sizeof(double), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(ws + q.off_state[0], 0, q.state_bytes, s));
     HIP_TRY(hipMemsetAsync(ws + q.off_state[1], 0, q.state_bytes, s));
-    if (q.prob.precision == JLB_FP64) HIP_TRY(hipMemsetAsync(ws + q.off_fields, 0, 3 * q.plane * sizeof(double), s));
+    if (q.prob.precision == JLB_FP64) HIP_TRY(hipMemsetAsync(ws + q.off_fields, 0, 2 * 3 * q.plane * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(ws + q.off_acc, 0, 4 * q.nc * sizeof(double), s));
     // the host vectors are released on return: finish the copies first
     HIP_TRY(hipStreamSynchronize(s));
     return JLB_OK;
 }
 
-// Launches lattice step n (state at n in buffer n % 2), plus the contour
-// accumulation when n + 1 is inside the averaging window.
-static int launch_one_step(const Plan &q, char *ws, const Lattice &L, const ContourDev &C, int64_t n, bool want_fields,
-                           double einc, hipStream_t s)
+// Fields at time level t: FP64 keeps them in the field planes of parity t,
+// FP32 / BF16 in the state buffer of parity t.
+const void *fields_ptr(const Plan &q, char *ws, int64_t t)
+{
+    if (q.prob.precision == JLB_FP64) return ws + q.off_fields + (size_t)(t & 1) * 3 * q.plane * sizeof(double);
+    return ws + q.off_state[t & 1];
+}
+
+// Launches lattice step n (state at n in buffer n % 2 -> state at n + 1) and,
+// when `contour` is set, the contour accumulation of time level n + 1.  The
+// averaged levels are the last `window` ones, steps - window + 1 .. steps.
+static int launch_one_step(const Plan &q, char *ws, const Lattice &L, const ContourDev &C, int64_t n, bool contour,
+                           bool want_fields, double einc, hipStream_t s)
 {
     const int prec = q.prob.precision;
     void *src = ws + q.off_state[n & 1];
     void *dst = ws + q.off_state[(n + 1) & 1];
-    const bool in_window = n + 1 > q.prob.steps - q.window;
     hipError_t e;
     if (prec == JLB_FP64) {
-        double *fields = (in_window || want_fields) ? (double *)(ws + q.off_fields) : nullptr;
+        double *fields = (contour || want_fields) ? (double *)fields_ptr(q, ws, n + 1) : nullptr;
         e = launch_step_f64(L, (const double *)src, (double *)dst, fields, einc, s, step_variant(prec));
-        if (e == hipSuccess && in_window) e = launch_contour(prec, L, ws + q.off_fields, C, s);
     } else {
         e = launch_step_neq(prec, L, src, dst, einc, s, step_variant(prec));
-        if (e == hipSuccess && in_window) e = launch_contour(prec, L, dst, C, s);
     }
+    if (e == hipSuccess && contour) e = launch_contour(prec, L, fields_ptr(q, ws, n + 1), C, s);
     if (e != hipSuccess) return fail(JLB_E_DEVICE, "launch of step %lld failed: %s", (long long)n, hipGetErrorString(e));
     return JLB_OK;
-}
-
-const void *fields_ptr(const Plan &q, char *ws, int64_t n_done)
-{
-    if (q.prob.precision == JLB_FP64) return ws + q.off_fields;
-    return ws + q.off_state[n_done & 1];
 }
 
 int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, double *hy, double *energy,
@@ -350,7 +353,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     const Lattice L = lattice_of(q, (const uint8_t *)(ws + q.off_mask));
     const ContourDev C = contour_of(q, ws);
     const int64_t steps = q.prob.steps;
-    const int64_t wstart = steps - q.window;  // first n whose result enters the average
+    const int64_t wstart = steps - q.window;  // launches from here on produce averaged levels
     const bool use_graph = !(q.prob.flags & JLB_F_NO_GRAPH) && !energy;
     const int64_t chunk = (q.T % 2 == 0) ? q.T : 2 * q.T;  // whole periods, even step count
     const int64_t ramp_end = (int64_t)std::ceil(q.ramp_steps);
@@ -366,7 +369,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
         hipGraph_t g;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         for (int64_t k = 0; k < chunk; ++k) {
-            int r = launch_one_step(q, ws, L, C, n0 + k, false, incident(q, n0 + k), s);
+            int r = launch_one_step(q, ws, L, C, n0 + k, which == 1, false, incident(q, n0 + k), s);
             if (r) {
                 hipGraph_t dummy;
                 (void)hipStreamEndCapture(s, &dummy);
@@ -405,7 +408,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             n += chunk;
             continue;
         }
-        rc = launch_one_step(q, ws, L, C, n, energy != nullptr || n == steps - 1, incident(q, n), s);
+        rc = launch_one_step(q, ws, L, C, n, in_window, energy != nullptr || n == steps - 1, incident(q, n), s);
         if (rc) break;
         if (energy) {
             hipError_t e = launch_energy(q.prob.precision, L, fields_ptr(q, ws, n + 1), (double *)(ws + q.off_parts),

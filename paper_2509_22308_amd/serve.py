@@ -13,6 +13,7 @@ submits problems, advances the engine and collects results and timings.
 """
 from __future__ import annotations
 
+import sys
 import time
 
 import numpy as np
@@ -37,12 +38,17 @@ def run_design_map(problems, precision: str = "fp32", budget_bytes: int | None =
     t0 = time.perf_counter()
     tickets = [eng.submit(make_problem(p, precision)) for p in problems]
     peak = 0
+    last = t0
     while True:
         eng.run(steps_per_call)
         st = eng.stats()
         peak = max(peak, st["resident"])
         if st["queued"] == 0 and st["resident"] == 0:
             break
+        if time.perf_counter() - last > 20.0:
+            last = time.perf_counter()
+            print(f"[design map] {st['finished']}/{len(problems)} done, {st['resident']} resident, "
+                  f"{last - t0:.0f} s", file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     results = []
     for t in tickets:
@@ -70,7 +76,12 @@ def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, ma
     k = 0
     peak = 0
     t0 = time.perf_counter()
+    last = t0
     while k < len(reqs) or outstanding:
+        if time.perf_counter() - last > 20.0:
+            last = time.perf_counter()
+            print(f"[serve] {len(done)}/{len(reqs)} done, {len(outstanding)} outstanding, {last - t0:.0f} s",
+                  file=sys.stderr, flush=True)
         now = time.perf_counter() - t0
         while k < len(reqs) and reqs[k][0] * time_scale <= now:
             t = eng.submit(make_problem(reqs[k][1], precision))
