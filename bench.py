@@ -119,7 +119,8 @@ def gpu_leg(args):
             ms = jlb.jlb_time_step_kernel(bp, 5, 40, bws)
             gbs = 4096 * 4096 * BYTES_PER_LUP[prec] / (ms * 1e-3) / 1e9
             extra[f"grid4096_{prec}"] = {"ms_per_step": ms, "glups": 4096 * 4096 / (ms * 1e-3) / 1e9, "gbs": gbs,
-                                        "hbm_frac": gbs / HBM_PEAK_GBS, "variant": jlb.STEP_VARIANTS.get(v, v)}
+                                        "hbm_frac": gbs / HBM_PEAK_GBS,
+                                        "variant": (jlb.FP64_STEP_VARIANTS if prec == "fp64" else jlb.STEP_VARIANTS).get(v, v)}
             del bws
         for prec in ("fp64", "fp32", "bf16"):
             if prec == args.precision:

@@ -175,11 +175,9 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * The lattice step has kernel variants with identical results and different
  * thread-to-node mappings.  FP32 / BF16 (JLB_STEP_VARIANTS of them):
  *   0       one node per thread, 64 x 4 node blocks;
- *   1-3     one column per thread sweeping 8 / 16 / 32 rows (256 columns per block);
- *   4-6     two adjacent nodes per thread (two-wide loads and stores), 4 / 8 / 16 rows;
- *   7-9     four adjacent nodes per thread (four-wide loads and stores), 4 / 8 / 16 rows;
- *   10/11   two / four adjacent nodes per thread, one row, 64 x 4 thread blocks;
- *   12/13   the same with 256 x 1 thread blocks;  14/15  with 256 x 2.
+ *   1/2     two / four adjacent nodes per thread (two- / four-wide loads and
+ *           stores), one row per thread, 64 x 4 thread blocks;
+ *   3/4     the same with 256 x 1 thread blocks;  5/6  with 256 x 2.
  * FP64 (JLB_FP64_STEP_VARIANTS): 0 / 1 / 2 one node per thread in 64 x 4 /
  * 256 x 1 / 256 x 2 thread blocks.
  * The choice is process-wide per precision (default 0 until jlb_autotune or
@@ -191,7 +189,7 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * *best_variant; ms_per_variant (host, optional) receives one mean launch
  * time in ms per variant (JLB_STEP_VARIANTS entries are always enough).
  */
-#define JLB_STEP_VARIANTS 16
+#define JLB_STEP_VARIANTS 7
 #define JLB_FP64_STEP_VARIANTS 3
 int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t launches,
                  int32_t *best_variant, double *ms_per_variant, void *stream);

@@ -179,11 +179,8 @@ def jlb_time_step_kernel(prob: jlb_problem, warmup: int, launches: int, workspac
     return ms.value
 
 
-STEP_VARIANTS = {0: "direct 64x4", 1: "sweep 8 rows", 2: "sweep 16 rows", 3: "sweep 32 rows",
-                 4: "2-wide sweep 4 rows", 5: "2-wide sweep 8 rows", 6: "2-wide sweep 16 rows",
-                 7: "4-wide sweep 4 rows", 8: "4-wide sweep 8 rows", 9: "4-wide sweep 16 rows",
-                 10: "2-wide tile 64x4", 11: "4-wide tile 64x4", 12: "2-wide tile 256x1", 13: "4-wide tile 256x1",
-                 14: "2-wide tile 256x2", 15: "4-wide tile 256x2"}
+STEP_VARIANTS = {0: "direct 64x4", 1: "2-wide tile 64x4", 2: "4-wide tile 64x4", 3: "2-wide tile 256x1",
+                 4: "4-wide tile 256x1", 5: "2-wide tile 256x2", 6: "4-wide tile 256x2"}
 FP64_STEP_VARIANTS = {0: "direct 64x4", 1: "direct 256x1", 2: "direct 256x2"}
 
 

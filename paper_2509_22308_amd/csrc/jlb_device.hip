@@ -58,7 +58,10 @@ template <typename T> __device__ __forceinline__ void put(T *p, T v, bool stream
 constexpr int BX = 64;  // one wavefront per row segment
 constexpr int BY = 4;   // four rows per block
 
+// Mask index of node (i, j).
 __device__ __forceinline__ size_t node(const Lattice &L, int i, int j) { return (size_t)j * L.pitch + i; }
+// Index of node (i, j) in plane 0 of a row-interleaved array with row stride S.
+__device__ __forceinline__ size_t at(int i, int j, size_t S) { return (size_t)j * S + i; }
 
 // Workgroups are handed to the eight XCDs in turn (block b on XCD b mod 8),
 // and each XCD has its own L2.  Renumbering so that XCD x works through one
@@ -100,7 +103,7 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
 {
 #pragma clang fp contract(off)
     const size_t P = L.plane;
-    const size_t c = node(L, i, j);
+    const size_t c = at(i, j, L.sf);
     const double keep = 1.0 - OPEN_DELTA;
     double f[11];
     double eps = 1.0, eps_rest = 1.0 - 2.0 / 3.0;
@@ -119,12 +122,12 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
         if (i == L.nx - 1) { f[2] = 0.0; f[7] = 0.0; }
         else { f[2] = src[2 * P + c + 1]; f[7] = src[7 * P + c + 1]; }
     } else {
-        const uint8_t m = L.mask[c];
+        const uint8_t m = L.mask[node(L, i, j)];
         const int mat = m & 3;
         if (mat == MAT_PEC) return;
         eps = L.eps[mat];
         eps_rest = L.eps_rest[mat];
-        const size_t strip = node(L, i, L.ny);
+        const size_t strip = at(i, L.ny, L.sf);
         // +x populations come from (i-1, j)
         if (i == 0) { f[1] = einc / 3.0; f[6] = 0.0; }
         else if (m & NB_PEC_XM) { f[1] = -src[2 * P + c]; f[6] = -src[7 * P + c]; }
@@ -138,13 +141,13 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
             f[3] = keep * src[3 * P + c] + OPEN_DELTA * src[3 * P + strip];
             f[9] = keep * src[9 * P + c] + OPEN_DELTA * src[9 * P + strip];
         } else if (m & NB_PEC_YM) { f[3] = -src[4 * P + c]; f[9] = -src[10 * P + c]; }
-        else { f[3] = src[3 * P + c - L.pitch]; f[9] = src[9 * P + c - L.pitch]; }
+        else { f[3] = src[3 * P + c - L.sf]; f[9] = src[9 * P + c - L.sf]; }
         // -y populations come from (i, j+1)
         if (j == L.ny - 1) {
             f[4] = keep * src[4 * P + c] + OPEN_DELTA * src[4 * P + strip];
             f[10] = keep * src[10 * P + c] + OPEN_DELTA * src[10 * P + strip];
         } else if (m & NB_PEC_YP) { f[4] = -src[3 * P + c]; f[10] = -src[9 * P + c]; }
-        else { f[4] = src[4 * P + c + L.pitch]; f[10] = src[10 * P + c + L.pitch]; }
+        else { f[4] = src[4 * P + c + L.sf]; f[10] = src[10 * P + c + L.sf]; }
     }
 
     const double dz = f[0] + f[1] + f[2] + (f[3] + f[4]);
@@ -166,9 +169,10 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
 #pragma unroll
     for (int k = 0; k < 11; ++k) put(&dst[k * P + c], 2.0 * q[k] - f[k], L.stream_stores);
     if (fields && j < L.ny) {
-        fields[0 * P + c] = ez;
-        fields[1 * P + c] = hx;
-        fields[2 * P + c] = hy;
+        const size_t cf = at(i, j, L.sfld);
+        fields[0 * P + cf] = ez;
+        fields[1 * P + cf] = hx;
+        fields[2 * P + cf] = hy;
     }
 }
 
@@ -211,26 +215,27 @@ struct Side {
 };
 
 template <typename NeqT>
-__device__ __forceinline__ NodeData load_node(const float *F, const NeqT *N, size_t P, size_t c)
+__device__ __forceinline__ NodeData load_node(const float *F, const NeqT *N, size_t P, size_t cf, size_t cn)
 {
     NodeData d;
-    d.ez = F[c];
-    d.hx = F[P + c];
-    d.hy = F[2 * P + c];
+    d.ez = F[cf];
+    d.hx = F[P + cf];
+    d.hy = F[2 * P + cf];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) d.n[k] = ld(&N[k * P + c]);
+    for (int k = 0; k < 8; ++k) d.n[k] = ld(&N[k * P + cn]);
     return d;
 }
 
 template <typename NeqT>
-__device__ __forceinline__ Side load_side(const float *F, const NeqT *N, size_t P, size_t c, int qa, int qb)
+__device__ __forceinline__ Side load_side(const float *F, const NeqT *N, size_t P, size_t cf, size_t cn, int qa,
+                                          int qb)
 {
     Side s;
-    s.ez = F[c];
-    s.hx = F[P + c];
-    s.hy = F[2 * P + c];
-    s.na = ld(&N[qa * P + c]);
-    s.nb = ld(&N[qb * P + c]);
+    s.ez = F[cf];
+    s.hx = F[P + cf];
+    s.hy = F[2 * P + cf];
+    s.na = ld(&N[qa * P + cn]);
+    s.nb = ld(&N[qb * P + cn]);
     return s;
 }
 
@@ -309,33 +314,34 @@ __device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t
 }
 
 template <typename NeqT>
-__device__ __forceinline__ void store_node(float *F, NeqT *N, size_t P, size_t c, const NodeData &d, bool stream)
+__device__ __forceinline__ void store_node(float *F, NeqT *N, size_t P, size_t cf, size_t cn, const NodeData &d,
+                                           bool stream)
 {
-    put(&F[c], d.ez, stream);
-    put(&F[P + c], d.hx, stream);
-    put(&F[2 * P + c], d.hy, stream);
+    put(&F[cf], d.ez, stream);
+    put(&F[P + cf], d.hx, stream);
+    put(&F[2 * P + cf], d.hy, stream);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) st(&N[k * P + c], d.n[k], stream);
+    for (int k = 0; k < 8; ++k) st(&N[k * P + cn], d.n[k], stream);
 }
 
 // Sides along x of node (i, j) and the material parameters; false for a conductor node.
 template <typename NeqT>
-__device__ __forceinline__ bool node_setup(const Lattice &L, const float *F, const NeqT *N, int i, int j, size_t c,
-                                           uint8_t &m, float &eps, float &eps_rest, Side &l, Side &r)
+__device__ __forceinline__ bool node_setup(const Lattice &L, const float *F, const NeqT *N, int i, int j, size_t cf,
+                                           size_t cn, uint8_t &m, float &eps, float &eps_rest, Side &l, Side &r)
 {
     const size_t P = L.plane;
     m = 0;
     eps = 1.0f;
     eps_rest = (float)(1.0 - 2.0 / 3.0);
     if (j < L.ny) {
-        m = L.mask[c];
+        m = L.mask[node(L, i, j)];
         const int mat = m & 3;
         if (mat == MAT_PEC) return false;
         eps = (float)L.eps[mat];
         eps_rest = (float)L.eps_rest[mat];
     }
-    if (i > 0 && !(m & NB_PEC_XM)) l = load_side(F, N, P, c - 1, N_EPX, N_HXPX);
-    if (i < L.nx - 1 && !(m & NB_PEC_XP)) r = load_side(F, N, P, c + 1, N_EMX, N_HXMX);
+    if (i > 0 && !(m & NB_PEC_XM)) l = load_side(F, N, P, cf - 1, cn - 1, N_EPX, N_HXPX);
+    if (i < L.nx - 1 && !(m & NB_PEC_XP)) r = load_side(F, N, P, cf + 1, cn + 1, N_EMX, N_HXMX);
     return true;
 }
 
@@ -344,18 +350,17 @@ __device__ __forceinline__ void load_incident_sides(const Lattice &L, const floa
                                                     Side &inc_lo, Side &inc_hi)
 {
     const size_t P = L.plane;
-    const size_t sc = node(L, i, L.ny);
-    if (j == 0) inc_lo = load_side(F, N, P, sc, N_EPY, N_HYPY);
-    if (j == L.ny - 1) inc_hi = load_side(F, N, P, sc, N_EMY, N_HYMY);
+    const size_t sf = at(i, L.ny, L.sf), sn = at(i, L.ny, L.sn);
+    if (j == 0) inc_lo = load_side(F, N, P, sf, sn, N_EPY, N_HYPY);
+    if (j == L.ny - 1) inc_hi = load_side(F, N, P, sf, sn, N_EMY, N_HYMY);
 }
 
 // ---------------------------------------------------------------------------
 // FP32 / BF16 kernels.  State planes: F = {Ez, Hx, Hy} (float), N = 8 moving
 // deviations in the order {e+x, e-x, e+y, e-y, hx+x, hx-x, hy+y, hy-y}.
 // Variant "direct": one node per thread, every side read from memory.
-// Variant "sweep": one column per thread over TY rows; the rows above and
-// below stay in registers, so each node's data is fetched once per sweep.
-// Both call neq_core with the same operands and give identical results.
+// Variants "vector tile" (below): V adjacent nodes per thread.  All call
+// neq_core with the same operands and give identical results.
 // ---------------------------------------------------------------------------
 
 template <typename NeqT>
@@ -367,67 +372,22 @@ __device__ __forceinline__ void neq_direct_node(const Lattice &L, const void *__
     const NeqT *N = reinterpret_cast<const NeqT *>(F + 3 * P);
     float *DF = reinterpret_cast<float *>(dstv);
     NeqT *DN = reinterpret_cast<NeqT *>(DF + 3 * P);
-    const size_t c = node(L, i, j);
+    const size_t cf = at(i, j, L.sf), cn = at(i, j, L.sn);
     uint8_t m;
     float eps, eps_rest;
     Side l{}, r{}, b{}, t{}, lo{}, hi{};
-    if (!node_setup(L, F, N, i, j, c, m, eps, eps_rest, l, r)) return;
-    const NodeData o = load_node(F, N, P, c);
+    if (!node_setup(L, F, N, i, j, cf, cn, m, eps, eps_rest, l, r)) return;
+    const NodeData o = load_node(F, N, P, cf, cn);
     NodeData out;
     if (j == L.ny) {
         neq_core<true>(L, i, j, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
     } else {
-        if (j > 0 && !(m & NB_PEC_YM)) b = load_side(F, N, P, c - L.pitch, N_EPY, N_HYPY);
-        if (j < L.ny - 1 && !(m & NB_PEC_YP)) t = load_side(F, N, P, c + L.pitch, N_EMY, N_HYMY);
+        if (j > 0 && !(m & NB_PEC_YM)) b = load_side(F, N, P, cf - L.sf, cn - L.sn, N_EPY, N_HYPY);
+        if (j < L.ny - 1 && !(m & NB_PEC_YP)) t = load_side(F, N, P, cf + L.sf, cn + L.sn, N_EMY, N_HYMY);
         load_incident_sides(L, F, N, i, j, lo, hi);
         neq_core<false>(L, i, j, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
     }
-    store_node(DF, DN, P, c, out, L.stream_stores);
-}
-
-// Column i over rows [j0, j0 + TY) of the domain, or the companion row when j0 >= ny.
-template <typename NeqT, int TY>
-__device__ __forceinline__ void neq_sweep_column(const Lattice &L, const void *__restrict__ srcv,
-                                                 void *__restrict__ dstv, float einc, int i, int j0)
-{
-    const size_t P = L.plane;
-    const float *F = reinterpret_cast<const float *>(srcv);
-    const NeqT *N = reinterpret_cast<const NeqT *>(F + 3 * P);
-    float *DF = reinterpret_cast<float *>(dstv);
-    NeqT *DN = reinterpret_cast<NeqT *>(DF + 3 * P);
-    if (j0 >= L.ny) {
-        const size_t c = node(L, i, L.ny);
-        uint8_t m;
-        float eps, eps_rest;
-        Side l{}, r{}, b{}, t{}, lo{}, hi{};
-        node_setup(L, F, N, i, L.ny, c, m, eps, eps_rest, l, r);
-        const NodeData o = load_node(F, N, P, c);
-        NodeData out;
-        neq_core<true>(L, i, L.ny, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
-        store_node(DF, DN, P, c, out, L.stream_stores);
-        return;
-    }
-    const int j1 = min(j0 + TY, L.ny);
-    Side below{};
-    if (j0 > 0) below = load_side(F, N, P, node(L, i, j0 - 1), N_EPY, N_HYPY);
-    NodeData cur = load_node(F, N, P, node(L, i, j0));
-    for (int j = j0; j < j1; ++j) {
-        const size_t c = node(L, i, j);
-        NodeData nxt{};
-        if (j + 1 < L.ny) nxt = load_node(F, N, P, c + L.pitch);
-        const Side above{nxt.ez, nxt.hx, nxt.hy, nxt.n[N_EMY], nxt.n[N_HYMY]};
-        uint8_t m;
-        float eps, eps_rest;
-        Side l{}, r{}, lo{}, hi{};
-        if (node_setup(L, F, N, i, j, c, m, eps, eps_rest, l, r)) {
-            load_incident_sides(L, F, N, i, j, lo, hi);
-            NodeData out;
-            neq_core<false>(L, i, j, m, eps, eps_rest, cur, l, r, below, above, lo, hi, einc, out);
-            store_node(DF, DN, P, c, out, L.stream_stores);
-        }
-        below = Side{cur.ez, cur.hx, cur.hy, cur.n[N_EPY], cur.n[N_HYPY]};
-        cur = nxt;
-    }
+    store_node(DF, DN, P, cf, cn, out, L.stream_stores);
 }
 
 template <typename NeqT>
@@ -442,25 +402,9 @@ __global__ __launch_bounds__(BX *BY) void k_step_neq(Lattice L, const void *__re
     neq_direct_node<NeqT>(L, srcv, dstv, einc, i, j);
 }
 
-constexpr int SWEEP_THREADS = 256;
-
-template <typename NeqT, int TY>
-__global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_sweep(Lattice L, const void *__restrict__ srcv,
-                                                                   void *__restrict__ dstv, float einc)
-{
-    int tx, ty;
-    block_tile(L, tx, ty);
-    const int i = tx * SWEEP_THREADS + threadIdx.x;
-    if (i >= L.nx) return;
-    neq_sweep_column<NeqT, TY>(L, srcv, dstv, einc, i, ty * TY);
-}
-
 // ---------------------------------------------------------------------------
-// Variant "vector sweep": each thread owns V adjacent nodes of a row, moves
-// every plane with one V-wide load or store, exchanges the x-neighbours with
-// the adjacent lanes (the wavefront's two edge lanes read theirs from
-// memory) and sweeps TY rows keeping the rows above and below in registers.
-// Conductor and padding nodes store zeros, which is what they hold.
+// V-wide row access: each thread of the vector variants owns V adjacent
+// nodes of a row and moves every plane with one V-wide load or store.
 // ---------------------------------------------------------------------------
 
 template <typename T, int V> struct VecOf;
@@ -496,13 +440,13 @@ struct RowData {
 };
 
 template <typename NeqT, int V>
-__device__ __forceinline__ void load_row(const float *F, const NeqT *N, size_t P, size_t c, RowData<V> &r)
+__device__ __forceinline__ void load_row(const float *F, const NeqT *N, size_t P, size_t cf, size_t cn, RowData<V> &r)
 {
-    vload<float, V>(F + c, r.ez);
-    vload<float, V>(F + P + c, r.hx);
-    vload<float, V>(F + 2 * P + c, r.hy);
+    vload<float, V>(F + cf, r.ez);
+    vload<float, V>(F + P + cf, r.hx);
+    vload<float, V>(F + 2 * P + cf, r.hy);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) vload<NeqT, V>(N + q * P + c, r.n[q]);
+    for (int q = 0; q < 8; ++q) vload<NeqT, V>(N + q * P + cn, r.n[q]);
 }
 
 template <int V>
@@ -513,91 +457,6 @@ __device__ __forceinline__ void zero_row(RowData<V> &r)
         r.ez[k] = r.hx[k] = r.hy[k] = 0.0f;
 #pragma unroll
         for (int q = 0; q < 8; ++q) r.n[q][k] = 0.0f;
-    }
-}
-
-template <typename NeqT, int V, int TY>
-__device__ __forceinline__ void neq_vsweep_column(const Lattice &L, const void *__restrict__ srcv,
-                                                  void *__restrict__ dstv, float einc, int col, int j0)
-{
-    const size_t P = L.plane;
-    const float *F = reinterpret_cast<const float *>(srcv);
-    const NeqT *N = reinterpret_cast<const NeqT *>(F + 3 * P);
-    float *DF = reinterpret_cast<float *>(dstv);
-    NeqT *DN = reinterpret_cast<NeqT *>(DF + 3 * P);
-    const int i0 = col * V;
-    const int lane = threadIdx.x & 63;
-    const bool active = i0 < L.nx;
-    if (j0 >= L.ny) {
-        // companion row: per node, as in the other variants
-        if (active)
-            for (int v = 0; v < V; ++v)
-                if (i0 + v < L.nx) neq_direct_node<NeqT>(L, srcv, dstv, einc, i0 + v, L.ny);
-        return;
-    }
-    const int j1 = min(j0 + TY, L.ny);
-    RowData<V> below, cur, nxt;
-    zero_row(below);
-    zero_row(cur);
-    if (active && j0 > 0) load_row<NeqT, V>(F, N, P, node(L, i0, j0 - 1), below);
-    if (active) load_row<NeqT, V>(F, N, P, node(L, i0, j0), cur);
-    for (int j = j0; j < j1; ++j) {
-        const size_t c = node(L, i0, j);
-        zero_row(nxt);
-        if (active && j + 1 < L.ny) load_row<NeqT, V>(F, N, P, c + L.pitch, nxt);
-        // x-neighbours across lanes (all lanes take part in the exchange)
-        Side xl, xr;
-        xl.ez = __shfl_up(cur.ez[V - 1], 1, 64);
-        xl.hx = __shfl_up(cur.hx[V - 1], 1, 64);
-        xl.hy = __shfl_up(cur.hy[V - 1], 1, 64);
-        xl.na = __shfl_up(cur.n[N_EPX][V - 1], 1, 64);
-        xl.nb = __shfl_up(cur.n[N_HXPX][V - 1], 1, 64);
-        xr.ez = __shfl_down(cur.ez[0], 1, 64);
-        xr.hx = __shfl_down(cur.hx[0], 1, 64);
-        xr.hy = __shfl_down(cur.hy[0], 1, 64);
-        xr.na = __shfl_down(cur.n[N_EMX][0], 1, 64);
-        xr.nb = __shfl_down(cur.n[N_HXMX][0], 1, 64);
-        if (!active) continue;
-        if (lane == 0 && i0 > 0) xl = load_side(F, N, P, c - 1, N_EPX, N_HXPX);
-        if (lane == 63 && i0 + V < L.nx) xr = load_side(F, N, P, c + V, N_EMX, N_HXMX);
-        const typename MaskVec<V>::type mv = *reinterpret_cast<const typename MaskVec<V>::type *>(L.mask + c);
-        RowData<V> out;
-        zero_row(out);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const int i = i0 + v;
-            const uint8_t m = (uint8_t)(mv >> (8 * v));
-            const int mat = m & 3;
-            if (i >= L.nx || mat == MAT_PEC) continue;
-            const float eps = (float)L.eps[mat];
-            const float eps_rest = (float)L.eps_rest[mat];
-            NodeData o;
-            o.ez = cur.ez[v];
-            o.hx = cur.hx[v];
-            o.hy = cur.hy[v];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) o.n[q] = cur.n[q][v];
-            const Side l = v == 0 ? xl : Side{cur.ez[v - 1], cur.hx[v - 1], cur.hy[v - 1], cur.n[N_EPX][v - 1], cur.n[N_HXPX][v - 1]};
-            const Side r = v == V - 1 ? xr : Side{cur.ez[v + 1], cur.hx[v + 1], cur.hy[v + 1], cur.n[N_EMX][v + 1], cur.n[N_HXMX][v + 1]};
-            const Side b{below.ez[v], below.hx[v], below.hy[v], below.n[N_EPY][v], below.n[N_HYPY][v]};
-            const Side t{nxt.ez[v], nxt.hx[v], nxt.hy[v], nxt.n[N_EMY][v], nxt.n[N_HYMY][v]};
-            Side lo{}, hi{};
-            load_incident_sides(L, F, N, i, j, lo, hi);
-            NodeData res;
-            neq_core<false>(L, i, j, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, res);
-            out.ez[v] = res.ez;
-            out.hx[v] = res.hx;
-            out.hy[v] = res.hy;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) out.n[q][v] = res.n[q];
-        }
-        vstore<float, V>(DF + c, out.ez, L.stream_stores);
-        vstore<float, V>(DF + P + c, out.hx, L.stream_stores);
-        vstore<float, V>(DF + 2 * P + c, out.hy, L.stream_stores);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) vstore<NeqT, V>(DN + q * P + c, out.n[q], L.stream_stores);
-        below = cur;
-        cur = nxt;
     }
 }
 
@@ -623,8 +482,8 @@ __device__ __forceinline__ void neq_vtile_row(const Lattice &L, const void *__re
     const bool active = i0 < L.nx && j <= L.ny;
     RowData<V> cur;
     zero_row(cur);
-    const size_t c = node(L, i0, j);
-    if (active) load_row<NeqT, V>(F, N, P, c, cur);
+    const size_t cf = at(i0, j, L.sf), cn = at(i0, j, L.sn);
+    if (active) load_row<NeqT, V>(F, N, P, cf, cn, cur);
     // x-neighbours across lanes (every lane of the wavefront takes part)
     Side xl, xr;
     xl.ez = __shfl_up(cur.ez[V - 1], 1, 64);
@@ -644,29 +503,29 @@ __device__ __forceinline__ void neq_vtile_row(const Lattice &L, const void *__re
             if (i0 + v < L.nx) neq_direct_node<NeqT>(L, srcv, dstv, einc, i0 + v, L.ny);
         return;
     }
-    if (lane == 0 && i0 > 0) xl = load_side(F, N, P, c - 1, N_EPX, N_HXPX);
-    if (lane == 63 && i0 + V < L.nx) xr = load_side(F, N, P, c + V, N_EMX, N_HXMX);
+    if (lane == 0 && i0 > 0) xl = load_side(F, N, P, cf - 1, cn - 1, N_EPX, N_HXPX);
+    if (lane == 63 && i0 + V < L.nx) xr = load_side(F, N, P, cf + V, cn + V, N_EMX, N_HXMX);
     // rows below and above, V-wide
     float bz[V], bhx[V], bhy[V], bna[V], bnb[V], tz[V], thx[V], thy[V], tna[V], tnb[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) bz[v] = bhx[v] = bhy[v] = bna[v] = bnb[v] = tz[v] = thx[v] = thy[v] = tna[v] = tnb[v] = 0.0f;
     if (j > 0) {
-        const size_t cb = c - L.pitch;
-        vload<float, V>(F + cb, bz);
-        vload<float, V>(F + P + cb, bhx);
-        vload<float, V>(F + 2 * P + cb, bhy);
-        vload<NeqT, V>(N + N_EPY * P + cb, bna);
-        vload<NeqT, V>(N + N_HYPY * P + cb, bnb);
+        const size_t bf = cf - L.sf, bn = cn - L.sn;
+        vload<float, V>(F + bf, bz);
+        vload<float, V>(F + P + bf, bhx);
+        vload<float, V>(F + 2 * P + bf, bhy);
+        vload<NeqT, V>(N + N_EPY * P + bn, bna);
+        vload<NeqT, V>(N + N_HYPY * P + bn, bnb);
     }
     if (j + 1 < L.ny) {
-        const size_t ct = c + L.pitch;
-        vload<float, V>(F + ct, tz);
-        vload<float, V>(F + P + ct, thx);
-        vload<float, V>(F + 2 * P + ct, thy);
-        vload<NeqT, V>(N + N_EMY * P + ct, tna);
-        vload<NeqT, V>(N + N_HYMY * P + ct, tnb);
+        const size_t tf = cf + L.sf, tn = cn + L.sn;
+        vload<float, V>(F + tf, tz);
+        vload<float, V>(F + P + tf, thx);
+        vload<float, V>(F + 2 * P + tf, thy);
+        vload<NeqT, V>(N + N_EMY * P + tn, tna);
+        vload<NeqT, V>(N + N_HYMY * P + tn, tnb);
     }
-    const typename MaskVec<V>::type mv = *reinterpret_cast<const typename MaskVec<V>::type *>(L.mask + c);
+    const typename MaskVec<V>::type mv = *reinterpret_cast<const typename MaskVec<V>::type *>(L.mask + node(L, i0, j));
     RowData<V> out;
     zero_row(out);
 #pragma unroll
@@ -697,11 +556,11 @@ __device__ __forceinline__ void neq_vtile_row(const Lattice &L, const void *__re
 #pragma unroll
         for (int q = 0; q < 8; ++q) out.n[q][v] = res.n[q];
     }
-    vstore<float, V>(DF + c, out.ez, L.stream_stores);
-    vstore<float, V>(DF + P + c, out.hx, L.stream_stores);
-    vstore<float, V>(DF + 2 * P + c, out.hy, L.stream_stores);
+    vstore<float, V>(DF + cf, out.ez, L.stream_stores);
+    vstore<float, V>(DF + P + cf, out.hx, L.stream_stores);
+    vstore<float, V>(DF + 2 * P + cf, out.hy, L.stream_stores);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) vstore<NeqT, V>(DN + q * P + c, out.n[q], L.stream_stores);
+    for (int q = 0; q < 8; ++q) vstore<NeqT, V>(DN + q * P + cn, out.n[q], L.stream_stores);
 }
 
 template <typename NeqT, int V, int CX, int R>
@@ -711,15 +570,6 @@ __global__ __launch_bounds__(CX *R) void k_step_neq_vtile(Lattice L, const void 
     int tx, ty;
     block_tile(L, tx, ty);
     neq_vtile_row<NeqT, V>(L, srcv, dstv, einc, tx * CX + threadIdx.x, ty * R + threadIdx.y);
-}
-
-template <typename NeqT, int V, int TY>
-__global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_vsweep(Lattice L, const void *__restrict__ srcv,
-                                                                    void *__restrict__ dstv, float einc)
-{
-    int tx, ty;
-    block_tile(L, tx, ty);
-    neq_vsweep_column<NeqT, V, TY>(L, srcv, dstv, einc, tx * SWEEP_THREADS + threadIdx.x, ty * TY);
 }
 
 // ---------------------------------------------------------------------------
@@ -762,31 +612,6 @@ __global__ __launch_bounds__(BX *BY) void k_step_neq_batch(SolveDesc *__restrict
     neq_direct_node<NeqT>(d.L, d.state[n & 1], d.state[(n + 1) & 1], (float)batch_incident(d, n), i, j);
 }
 
-template <typename NeqT, int TY>
-__global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_sweep_batch(SolveDesc *__restrict__ D,
-                                                                         const Tile *__restrict__ tiles, int remap)
-{
-    const Tile t = tiles[batch_tile(D, blockIdx.x, gridDim.x, remap)];
-    const SolveDesc &d = D[t.slot];
-    const int64_t n = d.n;
-    if (n >= d.steps) return;
-    const int i = t.tx * SWEEP_THREADS + threadIdx.x;
-    if (i >= d.L.nx) return;
-    neq_sweep_column<NeqT, TY>(d.L, d.state[n & 1], d.state[(n + 1) & 1], (float)batch_incident(d, n), i, t.ty * TY);
-}
-
-template <typename NeqT, int V, int TY>
-__global__ __launch_bounds__(SWEEP_THREADS) void k_step_neq_vsweep_batch(SolveDesc *__restrict__ D,
-                                                                          const Tile *__restrict__ tiles, int remap)
-{
-    const Tile t = tiles[batch_tile(D, blockIdx.x, gridDim.x, remap)];
-    const SolveDesc &d = D[t.slot];
-    const int64_t n = d.n;
-    if (n >= d.steps) return;
-    neq_vsweep_column<NeqT, V, TY>(d.L, d.state[n & 1], d.state[(n + 1) & 1], (float)batch_incident(d, n),
-                                   t.tx * SWEEP_THREADS + threadIdx.x, t.ty * TY);
-}
-
 template <typename NeqT, int V, int CX, int R>
 __global__ __launch_bounds__(CX *R) void k_step_neq_vtile_batch(SolveDesc *__restrict__ D, const Tile *__restrict__ tiles,
                                                                  int remap)
@@ -817,8 +642,8 @@ __device__ __forceinline__ void contour_sample_f64(const Lattice &L, const doubl
 {
 #pragma clang fp contract(off)
     const size_t P = L.plane;
-    const size_t c00 = node(L, C.i0[k], C.j0[k]);
-    const size_t c10 = c00 + L.pitch;
+    const size_t c00 = at(C.i0[k], C.j0[k], L.sfld);
+    const size_t c10 = c00 + L.sfld;
     const double fx = C.wx[k], fy = C.wy[k];
     const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy), w10 = (1.0 - fx) * fy, w11 = fx * fy;
     double v[3];
@@ -838,8 +663,8 @@ __device__ __forceinline__ void contour_sample_f32(const Lattice &L, const float
 {
 #pragma clang fp contract(off)
     const size_t P = L.plane;
-    const size_t c00 = node(L, C.i0[k], C.j0[k]);
-    const size_t c10 = c00 + L.pitch;
+    const size_t c00 = at(C.i0[k], C.j0[k], L.sfld);
+    const size_t c10 = c00 + L.sfld;
     const float fx = (float)C.wx[k], fy = (float)C.wy[k];
     const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy), w10 = (1.0f - fx) * fy, w11 = fx * fy;
     float v[3];
@@ -957,9 +782,9 @@ __global__ __launch_bounds__(EN_THREADS) void k_energy_partial(Lattice L, const 
         const int j = blockIdx.y * EN_ROWS + r;
         if (j >= L.ny) break;
         for (int i = blockIdx.x * EN_THREADS + t; i < L.nx && i < (int)(blockIdx.x + 1) * EN_THREADS; i += EN_THREADS) {
-            const size_t c = node(L, i, j);
-            const int mat = L.mask[c] & 3;
+            const int mat = L.mask[node(L, i, j)] & 3;
             if (mat == MAT_PEC) continue;
+            const size_t c = at(i, j, L.sfld);
             const double ez = fld[c], hx = fld[P + c], hy = fld[2 * P + c];
             s += 0.5 * (L.eps[mat] * ez * ez + hx * hx + hy * hy);
         }
@@ -997,7 +822,7 @@ __global__ void k_fields_out(Lattice L, const FT *__restrict__ fld, double *ez, 
     const int j = blockIdx.y;
     if (i >= L.nx || j >= L.ny) return;
     const size_t P = L.plane;
-    const size_t c = node(L, i, j);
+    const size_t c = at(i, j, L.sfld);
     const size_t o = (size_t)j * L.nx + i;
     ez[o] = (double)fld[c];
     hx[o] = (double)fld[P + c];
@@ -1024,22 +849,9 @@ hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, voi
                            int variant)
 {
     const float e = (float)einc;
-    const dim3 sweep_block(SWEEP_THREADS);
-    auto sweep_grid = [&](int v, int ty) {
-        return dim3((L.nx + SWEEP_THREADS * v - 1) / (SWEEP_THREADS * v), (L.ny + ty - 1) / ty + 1);
-    };
     auto vtile_grid = [&](int v, int cx, int r) { return dim3((L.nx + cx * v - 1) / (cx * v), (L.ny + 1 + r - 1) / r); };
 #define JLB_NEQ_LAUNCH(T)                                                                                                    \
     switch (variant) {                                                                                                       \
-    case NEQ_SWEEP8: hipLaunchKernelGGL((k_step_neq_sweep<T, 8>), sweep_grid(1, 8), sweep_block, 0, s, L, src, dst, e); break;      \
-    case NEQ_SWEEP16: hipLaunchKernelGGL((k_step_neq_sweep<T, 16>), sweep_grid(1, 16), sweep_block, 0, s, L, src, dst, e); break;   \
-    case NEQ_SWEEP32: hipLaunchKernelGGL((k_step_neq_sweep<T, 32>), sweep_grid(1, 32), sweep_block, 0, s, L, src, dst, e); break;   \
-    case NEQ_V2_T4: hipLaunchKernelGGL((k_step_neq_vsweep<T, 2, 4>), sweep_grid(2, 4), sweep_block, 0, s, L, src, dst, e); break;   \
-    case NEQ_V2_T8: hipLaunchKernelGGL((k_step_neq_vsweep<T, 2, 8>), sweep_grid(2, 8), sweep_block, 0, s, L, src, dst, e); break;   \
-    case NEQ_V2_T16: hipLaunchKernelGGL((k_step_neq_vsweep<T, 2, 16>), sweep_grid(2, 16), sweep_block, 0, s, L, src, dst, e); break; \
-    case NEQ_V4_T4: hipLaunchKernelGGL((k_step_neq_vsweep<T, 4, 4>), sweep_grid(4, 4), sweep_block, 0, s, L, src, dst, e); break;   \
-    case NEQ_V4_T8: hipLaunchKernelGGL((k_step_neq_vsweep<T, 4, 8>), sweep_grid(4, 8), sweep_block, 0, s, L, src, dst, e); break;   \
-    case NEQ_V4_T16: hipLaunchKernelGGL((k_step_neq_vsweep<T, 4, 16>), sweep_grid(4, 16), sweep_block, 0, s, L, src, dst, e); break; \
     case NEQ_TILE_V2: hipLaunchKernelGGL((k_step_neq_vtile<T, 2, 64, 4>), vtile_grid(2, 64, 4), dim3(64, 4), 0, s, L, src, dst, e); break;     \
     case NEQ_TILE_V4: hipLaunchKernelGGL((k_step_neq_vtile<T, 4, 64, 4>), vtile_grid(4, 64, 4), dim3(64, 4), 0, s, L, src, dst, e); break;     \
     case NEQ_TILE_V2_W256: hipLaunchKernelGGL((k_step_neq_vtile<T, 2, 256, 1>), vtile_grid(2, 256, 1), dim3(256, 1), 0, s, L, src, dst, e); break; \
@@ -1086,21 +898,9 @@ void tile_shape(int precision, int variant, int &cols, int &rows)
         rows = BY;
         return;
     }
-    if (variant >= NEQ_TILE_V2) {
-        static const int tv[6] = {2, 4, 2, 4, 2, 4}, tc[6] = {64, 64, 256, 256, 256, 256}, tr[6] = {4, 4, 1, 1, 2, 2};
-        cols = tc[variant - NEQ_TILE_V2] * tv[variant - NEQ_TILE_V2];
-        rows = tr[variant - NEQ_TILE_V2];
-        return;
-    }
-    static const int vcols[10] = {BX, 1, 1, 1, 2, 2, 2, 4, 4, 4};
-    static const int vrows[10] = {BY, 8, 16, 32, 4, 8, 16, 4, 8, 16};
-    cols = SWEEP_THREADS * vcols[variant];
-    rows = vrows[variant];
-}
-
-bool tile_is_sweep(int precision, int variant)
-{
-    return precision != 0 && variant > NEQ_DIRECT && variant < NEQ_TILE_V2;
+    static const int tv[6] = {2, 4, 2, 4, 2, 4}, tc[6] = {64, 64, 256, 256, 256, 256}, tr[6] = {4, 4, 1, 1, 2, 2};
+    cols = tc[variant - NEQ_TILE_V2] * tv[variant - NEQ_TILE_V2];
+    rows = tr[variant - NEQ_TILE_V2];
 }
 
 hipError_t launch_step_batch(int precision, int variant, SolveDesc *d, const Tile *tiles, int ntiles, int remap,
@@ -1115,18 +915,9 @@ hipError_t launch_step_batch(int precision, int variant, SolveDesc *d, const Til
         }
         return hipGetLastError();
     }
-    const dim3 g(ntiles), b(SWEEP_THREADS);
+    const dim3 g(ntiles);
 #define JLB_BATCH_LAUNCH(T)                                                                                         \
     switch (variant) {                                                                                              \
-    case NEQ_SWEEP8: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 8>), g, b, 0, s, d, tiles, remap); break;              \
-    case NEQ_SWEEP16: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 16>), g, b, 0, s, d, tiles, remap); break;            \
-    case NEQ_SWEEP32: hipLaunchKernelGGL((k_step_neq_sweep_batch<T, 32>), g, b, 0, s, d, tiles, remap); break;            \
-    case NEQ_V2_T4: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 4>), g, b, 0, s, d, tiles, remap); break;           \
-    case NEQ_V2_T8: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 8>), g, b, 0, s, d, tiles, remap); break;           \
-    case NEQ_V2_T16: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 2, 16>), g, b, 0, s, d, tiles, remap); break;         \
-    case NEQ_V4_T4: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 4>), g, b, 0, s, d, tiles, remap); break;           \
-    case NEQ_V4_T8: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 8>), g, b, 0, s, d, tiles, remap); break;           \
-    case NEQ_V4_T16: hipLaunchKernelGGL((k_step_neq_vsweep_batch<T, 4, 16>), g, b, 0, s, d, tiles, remap); break;         \
     case NEQ_TILE_V2: hipLaunchKernelGGL((k_step_neq_vtile_batch<T, 2, 64, 4>), g, dim3(64, 4), 0, s, d, tiles, remap); break;      \
     case NEQ_TILE_V4: hipLaunchKernelGGL((k_step_neq_vtile_batch<T, 4, 64, 4>), g, dim3(64, 4), 0, s, d, tiles, remap); break;      \
     case NEQ_TILE_V2_W256: hipLaunchKernelGGL((k_step_neq_vtile_batch<T, 2, 256, 1>), g, dim3(256, 1), 0, s, d, tiles, remap); break; \

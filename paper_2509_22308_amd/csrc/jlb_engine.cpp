@@ -177,10 +177,8 @@ int rebuild(jlb_engine *e)
         int cols, rows;
         tile_shape(p, e->variant[p], cols, rows);
         const int tx = (q.nx + cols - 1) / cols;
-        // node tiles cover rows 0..ny (the companion row included); row sweeps
-        // cover the domain rows and give the companion row a tile row of its own
-        const bool sweep = tile_is_sweep(p, e->variant[p]);
-        const int ty = sweep ? (q.ny + rows - 1) / rows + 1 : (q.ny + 1 + rows - 1) / rows;
+        // tiles cover rows 0..ny (the companion row included)
+        const int ty = (q.ny + 1 + rows - 1) / rows;
         for (int y = 0; y < ty; ++y)
             for (int x = 0; x < tx; ++x) tiles[p].push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
     }

@@ -267,7 +267,18 @@ Lattice lattice_of(const Plan &q, const uint8_t *dmask)
     L.nx = q.nx;
     L.ny = q.ny;
     L.pitch = q.pitch;
-    L.plane = q.plane;
+    // row-interleaved planes: plane offset = pitch inside each row
+    L.plane = (size_t)q.pitch;
+    if (q.prob.precision == JLB_FP64) {
+        L.sf = L.sn = 11 * (size_t)q.pitch;
+        L.sfld = 3 * (size_t)q.pitch;
+    } else {
+        const size_t nb = q.prob.precision == JLB_FP32 ? 4 : 2;
+        const size_t row_bytes = (3 * 4 + 8 * nb) * (size_t)q.pitch;
+        L.sf = row_bytes / 4;
+        L.sn = row_bytes / nb;
+        L.sfld = L.sf;
+    }
     L.mask = dmask;
     for (int k = 0; k < 4; ++k) {
         L.eps[k] = q.eps[k];

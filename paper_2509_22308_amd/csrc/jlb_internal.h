@@ -27,11 +27,25 @@ constexpr double OPEN_DELTA = 1.0 / 20.0;
 constexpr int ROW_ALIGN = 64;
 
 // Lattice of one solve as the kernels see it.  Rows 0..ny-1 are the domain,
-// row ny is the one-row incident-wave companion lattice.  Every population
-// (or field) plane holds (ny + 1) * pitch elements.
+// row ny is the one-row incident-wave companion lattice.
+//
+// Layout: row-interleaved planes.  Row j of the state holds, one after the
+// other, the pitch-long row j of every plane, so element (q, i, j) of an
+// array with row stride S sits at q * plane + j * S + i with plane = pitch.
+// One lattice row is then one contiguous stretch of memory, which keeps the
+// number of DRAM pages a step touches at once small.
+//  * FP64 state: 11 planes of double, S = sf = 11 pitch;
+//  * FP32 / BF16 state: 3 field planes of float, then 8 deviation planes of
+//    float or bfloat16; float elements have row stride sf, deviation
+//    elements sn (both = row bytes / element size);
+//  * fields read by the contour, energy and output kernels: the FP64 field
+//    array (3 planes of double, S = 3 pitch) or the state's field planes
+//    (S = sf); sfld is that stride.
+// The material mask is plain [ny][pitch].
 struct Lattice {
     int nx, ny, pitch;
-    size_t plane;
+    size_t plane;         // offset between planes inside a row: pitch
+    size_t sf, sn, sfld;  // row strides in elements (see above)
     const uint8_t *mask;  // [ny][pitch]
     double eps[4];        // permittivity per material id (id 3 unused)
     double eps_rest[4];   // eps - 2/3: coefficient of Ez in the rest e-population's equilibrium
@@ -59,23 +73,14 @@ hipError_t launch_step_f64(const Lattice &L, const double *src, double *dst, dou
 // Kernel variants of the FP32 / BF16 step (identical results, different
 // thread-to-node mappings); chosen per device and grid by the autotuner.
 enum NeqVariant {
-    NEQ_DIRECT = 0,   // one node per thread, 64 x 4 blocks
-    NEQ_SWEEP8 = 1,   // one column per thread, 8 / 16 / 32 rows
-    NEQ_SWEEP16 = 2,
-    NEQ_SWEEP32 = 3,
-    NEQ_V2_T4 = 4,    // two adjacent nodes per thread, 4 / 8 / 16 rows
-    NEQ_V2_T8 = 5,
-    NEQ_V2_T16 = 6,
-    NEQ_V4_T4 = 7,    // four adjacent nodes per thread, 4 / 8 / 16 rows
-    NEQ_V4_T8 = 8,
-    NEQ_V4_T16 = 9,
-    NEQ_TILE_V2 = 10, // two / four adjacent nodes per thread, one row per thread,
-    NEQ_TILE_V4 = 11, //   64 x 4 thread blocks
-    NEQ_TILE_V2_W256 = 12, // the same with four wavefronts side by side in x
-    NEQ_TILE_V4_W256 = 13, //   (256 x 1 and 256 x 2 thread blocks): the halo
-    NEQ_TILE_V2_W256_R2 = 14, //   between wavefronts stays on one CU
-    NEQ_TILE_V4_W256_R2 = 15,
-    NEQ_VARIANTS = 16
+    NEQ_DIRECT = 0,          // one node per thread, 64 x 4 blocks
+    NEQ_TILE_V2 = 1,         // two / four adjacent nodes per thread, one row
+    NEQ_TILE_V4 = 2,         //   per thread, 64 x 4 thread blocks
+    NEQ_TILE_V2_W256 = 3,    // the same with four wavefronts side by side in x
+    NEQ_TILE_V4_W256 = 4,    //   (256 x 1 and 256 x 2 thread blocks): the halo
+    NEQ_TILE_V2_W256_R2 = 5, //   between wavefronts stays on one CU
+    NEQ_TILE_V4_W256_R2 = 6,
+    NEQ_VARIANTS = 7
 };
 // FP64 step variants: one node per thread in 64 x 4, 256 x 1 or 256 x 2 thread blocks.
 enum F64Variant { F64_R4 = 0, F64_W256_R1 = 1, F64_W256_R2 = 2, F64_VARIANTS = 3 };
@@ -120,8 +125,6 @@ struct Tile {
 
 // Tile shape of a precision / variant: columns x rows per block.
 void tile_shape(int precision, int variant, int &cols, int &rows);
-// Row sweeps give the companion row a tile row of its own.
-bool tile_is_sweep(int precision, int variant);
 // remap = 1 hands XCD-contiguous tiles to the eight XCDs (cache-resident working sets).
 hipError_t launch_step_batch(int precision, int variant, SolveDesc *d, const Tile *tiles, int ntiles, int remap,
                              hipStream_t s);
