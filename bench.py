@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 BYTES_PER_LUP = {"fp64": 177, "fp32": 89, "bf16": 57}
 KERNEL_NAME = {"fp64": "k_step_f64", "fp32": "k_step_neq*<float>", "bf16": "k_step_neq*<__bf16>"}
+TWO_STEP_KERNEL_NAME = {"fp32": "k_step2_neq<float>", "bf16": "k_step2_neq<__bf16>"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 DEVICE_SRC = os.path.join(ROOT, "paper_2509_22308_amd", "csrc", "jlb_device.hip")
 
@@ -67,6 +68,18 @@ def measured_traffic(precision: str, variant: int):
     return e.get("hbm_bytes_per_launch") if e else None
 
 
+def _single_and_two_step(jlb, prob, ws, prec: str, launches: int):
+    """Autotune, then time the chosen kernels: ms per launch of the best
+    single step and (FP32 / BF16, when the autotuner selected one) of the
+    two-step kernel."""
+    best, tune = jlb.jlb_autotune(prob, launches, ws)
+    one = jlb.jlb_time_step_kernel(prob, 5, 4 * launches, ws)
+    two = None
+    if prec != "fp64" and jlb.jlb_get_two_step_variant(jlb.PRECISIONS[prec]) >= 0:
+        two = jlb.jlb_time_two_step_kernel(prob, 5, 2 * launches, ws)
+    return best, tune, one, two
+
+
 def gpu_leg(args):
     import torch
 
@@ -77,8 +90,10 @@ def gpu_leg(args):
     p = workloads.config2()
     prob = jlb.make_problem(p, args.precision)
     ws = _workspace(jlb, prob)
-    # the autotuner picks the step kernel's tile shape for this device and grid
+    # the autotuner picks the step kernels (tile shape, single or two-step)
+    # for this device and grid
     variant, tune_ms = jlb.jlb_autotune(prob, 20, ws)
+    two_variant = jlb.jlb_get_two_step_variant(jlb.PRECISIONS[args.precision]) if args.precision != "fp64" else -1
     lups_per_solve = p["nx"] * p["ny"] * p["steps"]
 
     for _ in range(args.warmup):
@@ -93,18 +108,28 @@ def gpu_leg(args):
 
     ms_per_solve = 1e3 * wall / args.steps
     value = lups_per_solve * args.steps / wall
-    # dominant kernel: the fused step.  HIP events on the library's stream
-    # bracket each solve's time loop (step kernels plus the small contour
-    # kernels of the averaging window): an upper bound on the launch duration.
+    # dominant kernel: the fused step (two steps per launch outside the
+    # averaging window when the autotuner picked a two-step kernel).  HIP
+    # events on the library's stream bracket each solve's time loop; every
+    # step-kernel launch reads and writes the state once (a "pass"), so the
+    # loop's algorithmic bytes are passes x bytes per pass.  The loop also
+    # holds the small contour kernels of the window: a lower bound on the
+    # kernels' own rate.
     loop_ms = sum(r.loop_ms for r in results) / len(results)
-    launch_ms = loop_ms / p["steps"]
-    bytes_per_launch = results[0].bytes_per_step
-    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     r0 = results[0]
+    passes = r0.state_passes
+    launch_ms = loop_ms / passes
+    bytes_per_launch = r0.bytes_per_step
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     extra = {"forces": {"fx": r0.fx, "fy": r0.fy, "tz": r0.tz}, "loop_ms_per_solve": loop_ms,
-             "graph_used": r0.graph_used, "step_variant": jlb.STEP_VARIANTS.get(variant, variant),
-             "autotune_ms_per_variant": [round(m, 5) for m in tune_ms],
+             "state_passes_per_solve": passes, "graph_used": r0.graph_used,
+             "step_variant": jlb.STEP_VARIANTS.get(jlb.jlb_get_step_variant(jlb.PRECISIONS[args.precision]))
+             if args.precision != "fp64" else jlb.FP64_STEP_VARIANTS.get(variant),
+             "two_step_variant": jlb.TWO_STEP_VARIANTS.get(two_variant) if two_variant >= 0 else None,
+             "autotune_ms_per_step": [round(m, 5) for m in tune_ms],
              "step_kernel_ms_alone": jlb.jlb_time_step_kernel(prob, 20, 200, ws)}
+    if two_variant >= 0:
+        extra["two_step_kernel_ms_alone"] = jlb.jlb_time_two_step_kernel(prob, 10, 100, ws)
     if not args.quick:
         nb = 4 << 30
         ms = jlb.jlb_copy_bandwidth(nb, 10)
@@ -112,15 +137,21 @@ def gpu_leg(args):
         # a grid far larger than the 256 MB Infinity Cache: the HBM-bound figure
         big = workloads.problem(nx=4096, ny=4096, radius=256.0, kind="dielectric_janus", eps1=2.25, eps2=4.0,
                                 phi0_deg=30.0, wavelength=512.0, steps=10000)
+        nodes = 4096 * 4096
         for prec in ("fp64", "fp32", "bf16"):
             bp = jlb.make_problem(big, prec)
             bws = _workspace(jlb, bp)
-            v, _ = jlb.jlb_autotune(bp, 10, bws)
-            ms = jlb.jlb_time_step_kernel(bp, 5, 40, bws)
-            gbs = 4096 * 4096 * BYTES_PER_LUP[prec] / (ms * 1e-3) / 1e9
-            extra[f"grid4096_{prec}"] = {"ms_per_step": ms, "glups": 4096 * 4096 / (ms * 1e-3) / 1e9, "gbs": gbs,
-                                        "hbm_frac": gbs / HBM_PEAK_GBS,
-                                        "variant": (jlb.FP64_STEP_VARIANTS if prec == "fp64" else jlb.STEP_VARIANTS).get(v, v)}
+            best, _, one, two = _single_and_two_step(jlb, bp, bws, prec, 10)
+            gbs = nodes * BYTES_PER_LUP[prec] / (one * 1e-3) / 1e9
+            ent = {"single_step": {"variant": (jlb.FP64_STEP_VARIANTS if prec == "fp64" else jlb.STEP_VARIANTS).get(
+                       jlb.jlb_get_step_variant(jlb.PRECISIONS[prec])), "ms_per_launch": one,
+                       "glups": nodes / (one * 1e-3) / 1e9, "gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}}
+            if two is not None:
+                gbs2 = nodes * BYTES_PER_LUP[prec] / (two * 1e-3) / 1e9
+                ent["two_step"] = {"variant": jlb.TWO_STEP_VARIANTS.get(jlb.jlb_get_two_step_variant(
+                    jlb.PRECISIONS[prec])), "ms_per_launch": two, "glups": 2 * nodes / (two * 1e-3) / 1e9,
+                    "gbs": gbs2, "hbm_frac": gbs2 / HBM_PEAK_GBS}
+            extra[f"grid4096_{prec}"] = ent
             del bws
         for prec in ("fp64", "fp32", "bf16"):
             if prec == args.precision:
@@ -135,10 +166,13 @@ def gpu_leg(args):
             extra[f"config2_{prec}"] = {"glups": lups_per_solve / dt / 1e9, "ms_per_solve": 1e3 * dt,
                                         "loop_ms": r.loop_ms, "fx": r.fx, "fy": r.fy, "tz": r.tz}
             del pws
-    roof = {"bound": "hbm", "kernel": KERNEL_NAME[args.precision], "achieved": achieved, "peak": HBM_PEAK_GBS,
+    kname = KERNEL_NAME[args.precision]
+    if two_variant >= 0:
+        kname = TWO_STEP_KERNEL_NAME[args.precision] + " (two steps per launch), " + kname + " (ramp and window)"
+    roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(args.precision, variant),
-            "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms,
+            "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms, "launches_per_solve": passes,
             "note": "config 2 (FP32 state 2 x 46 MB) stays in the 256 MB Infinity Cache between steps; "
                     "the HBM-bound figures are extra.grid4096_*"}
     return p, value, ms_per_solve, roof, extra
@@ -257,13 +291,20 @@ def run_kernel_only(args):
         p = workloads.config2()
     prob = jlb.make_problem(p, args.precision)
     ws = _workspace(jlb, prob)
-    if args.variant >= 0:
-        # counter passes serialise kernels, which would mislead the autotuner
-        jlb.jlb_set_step_variant(jlb.PRECISIONS[args.precision], args.variant)
-        variant = args.variant
+    if args.two_step >= 0:
+        # the two-step kernel alone (counter passes serialise kernels, which
+        # would mislead the autotuner: the variant is given)
+        jlb.jlb_set_two_step_variant(jlb.PRECISIONS[args.precision], args.two_step)
+        variant = len(jlb.STEP_VARIANTS) + args.two_step
+        ms = jlb.jlb_time_two_step_kernel(prob, 2, args.launches, ws)
     else:
-        variant, _ = jlb.jlb_autotune(prob, 5, ws)
-    ms = jlb.jlb_time_step_kernel(prob, 2, args.launches, ws)
+        if args.variant >= 0:
+            jlb.jlb_set_step_variant(jlb.PRECISIONS[args.precision], args.variant)
+            variant = args.variant
+        else:
+            variant, _ = jlb.jlb_autotune(prob, 5, ws)
+            variant = jlb.jlb_get_step_variant(jlb.PRECISIONS[args.precision])
+        ms = jlb.jlb_time_step_kernel(prob, 2, args.launches, ws)
     copy_bytes = 1 << 30
     cms = jlb.jlb_copy_bandwidth(copy_bytes, 3)
     print(json.dumps({"mode": "kernel-only", "grid": [p["nx"], p["ny"]], "precision": args.precision, "variant": variant,
@@ -368,6 +409,7 @@ def main():
     ap.add_argument("--launches", type=int, default=50)
     ap.add_argument("--grid", type=int, default=0, help="kernel-only: an n x n grid instead of config 2")
     ap.add_argument("--variant", type=int, default=-1, help="kernel-only: this step variant instead of the autotuner's")
+    ap.add_argument("--two-step", type=int, default=-1, help="kernel-only: time this two-step variant instead")
     ap.add_argument("--summarize", default=None)
     ap.add_argument("--record-traffic", default=None, help="workload key (config2, grid4096): merge counter passes")
     ap.add_argument("--fetch-dir", default=None)

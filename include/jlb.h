@@ -111,7 +111,8 @@ typedef struct {
     int64_t window_steps;           /* time samples in the stress average                     */
     int32_t contour_points;
     int32_t graph_used;             /* 1 when whole periods were replayed from a hipGraph     */
-    int64_t bytes_per_step;         /* algorithmic HBM bytes of one lattice step              */
+    int64_t bytes_per_step;         /* algorithmic HBM bytes of one pass over the state        */
+    int64_t state_passes;           /* step-kernel launches (a two-step launch is one pass)    */
 } jlb_result;
 
 /* Library version (major * 10000 + minor * 100 + patch). */
@@ -183,19 +184,44 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * The choice is process-wide per precision (default 0 until jlb_autotune or
  * jlb_set_step_variant picks another).
  *
- * jlb_autotune times every variant of prob->precision on prob's grid
- * (`launches` timed launches each, after 2 warm-up launches; workspace as for
- * jlb_solve), makes the fastest the current choice and writes it to
- * *best_variant; ms_per_variant (host, optional) receives one mean launch
- * time in ms per variant (JLB_STEP_VARIANTS entries are always enough).
+ * FP32 / BF16 also have two-step kernels (JLB_TWO_STEP_VARIANTS of them):
+ * one launch takes the state from step n to n + 2, reading and writing it
+ * once (temporal blocking), with results equal to two single steps bit for
+ * bit.  A solve uses the selected two-step variant for the steps outside the
+ * averaging window that run in graph-captured periods, and single steps for
+ * the ramp and the window.  Variants (V adjacent nodes per lane, H rows per
+ * wavefront): 0 V1 H8, 1 V1 H16, 2 V2 H8, 3 V2 H16, 4 V2 H32, 5 V4 H16,
+ * 6 V4 H32.  Default: off (-1).
+ *
+ * jlb_autotune times every single-step variant of prob->precision on prob's
+ * grid (`launches` timed launches each, after 2 warm-up launches; workspace
+ * as for jlb_solve) and makes the fastest the current choice; for FP32 /
+ * BF16 it then times the two-step variants and selects the fastest of them
+ * when its time per lattice step beats the best single step (else turns
+ * two-step kernels off).  *best_variant receives the winner: a single-step
+ * variant index, or JLB_STEP_VARIANTS + the two-step index.  ms_per_variant
+ * (host, optional) receives the mean time per lattice step in ms, single-step
+ * variants first, then the two-step ones (JLB_STEP_VARIANTS +
+ * JLB_TWO_STEP_VARIANTS entries are always enough).
  */
 #define JLB_STEP_VARIANTS 7
 #define JLB_FP64_STEP_VARIANTS 3
+#define JLB_TWO_STEP_VARIANTS 7
 int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t launches,
                  int32_t *best_variant, double *ms_per_variant, void *stream);
 
 /* Forces (set) or reports (get) the current FP32 / BF16 step variant. */
 int jlb_set_step_variant(int32_t precision, int32_t variant);
+/* Forces (set, -1 = off) or reports (get) the current two-step variant. */
+int jlb_set_two_step_variant(int32_t precision, int32_t variant);
+int jlb_get_two_step_variant(int32_t precision, int32_t *variant);
+/*
+ * Mean time of one launch of the current two-step kernel (two lattice
+ * steps), as jlb_time_step_kernel.  JLB_E_ARG for FP64 or when two-step
+ * kernels are off.
+ */
+int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
+                             int32_t launches, double *ms_per_launch, void *stream);
 int jlb_get_step_variant(int32_t precision, int32_t *variant);
 
 /*

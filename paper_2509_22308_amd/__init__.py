@@ -46,7 +46,7 @@ class jlb_result(ctypes.Structure):
         ("loop_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
         ("steps_done", ctypes.c_int64), ("window_steps", ctypes.c_int64),
         ("contour_points", ctypes.c_int32), ("graph_used", ctypes.c_int32),
-        ("bytes_per_step", ctypes.c_int64),
+        ("bytes_per_step", ctypes.c_int64), ("state_passes", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -85,6 +85,10 @@ def load():
                               _P(ctypes.c_double), _vp], ctypes.c_int),
             "jlb_set_step_variant": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
             "jlb_get_step_variant": ([ctypes.c_int32, _P(ctypes.c_int32)], ctypes.c_int),
+            "jlb_set_two_step_variant": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+            "jlb_get_two_step_variant": ([ctypes.c_int32, _P(ctypes.c_int32)], ctypes.c_int),
+            "jlb_time_two_step_kernel": ([_P(jlb_problem), _vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                          _P(ctypes.c_double), _vp], ctypes.c_int),
             "jlb_copy_bandwidth": ([ctypes.c_size_t, ctypes.c_int32, _P(ctypes.c_double), _vp], ctypes.c_int),
             "jlb_engine_create": ([ctypes.c_size_t, ctypes.c_int32, _vp, _P(_vp)], ctypes.c_int),
             "jlb_engine_submit": ([_vp, _P(jlb_problem), _P(ctypes.c_uint64)], ctypes.c_int),
@@ -182,12 +186,25 @@ def jlb_time_step_kernel(prob: jlb_problem, warmup: int, launches: int, workspac
 STEP_VARIANTS = {0: "direct 64x4", 1: "2-wide tile 64x4", 2: "4-wide tile 64x4", 3: "2-wide tile 256x1",
                  4: "4-wide tile 256x1", 5: "2-wide tile 256x2", 6: "4-wide tile 256x2"}
 FP64_STEP_VARIANTS = {0: "direct 64x4", 1: "direct 256x1", 2: "direct 256x2"}
+TWO_STEP_VARIANTS = {0: "two-step V1 H8", 1: "two-step V1 H16", 2: "two-step V2 H8", 3: "two-step V2 H16",
+                     4: "two-step V2 H32", 5: "two-step V4 H16", 6: "two-step V4 H32"}
+
+
+def variant_name(precision, best: int) -> str:
+    """Name of a jlb_autotune winner (single-step index, or len(STEP_VARIANTS) + two-step index)."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if prec == 0:
+        return FP64_STEP_VARIANTS.get(best, str(best))
+    if best >= len(STEP_VARIANTS):
+        return TWO_STEP_VARIANTS.get(best - len(STEP_VARIANTS), str(best))
+    return STEP_VARIANTS.get(best, str(best))
 
 
 def jlb_autotune(prob: jlb_problem, launches: int = 20, workspace=None, stream=None):
-    """Times every step variant of prob's precision; returns (best, [ms per variant])."""
+    """Times every step variant of prob's precision (single steps, then
+    two-step kernels per lattice step); returns (best, [ms per step])."""
     best = ctypes.c_int32(0)
-    ms = (ctypes.c_double * len(STEP_VARIANTS))()
+    ms = (ctypes.c_double * (len(STEP_VARIANTS) + len(TWO_STEP_VARIANTS)))()
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(load().jlb_autotune(ctypes.byref(prob), _dptr(workspace), nbytes, int(launches), ctypes.byref(best), ms,
                                _stream(stream)))
@@ -209,6 +226,25 @@ def jlb_get_step_variant(precision: int) -> int:
     v = ctypes.c_int32(0)
     _check(load().jlb_get_step_variant(int(precision), ctypes.byref(v)))
     return v.value
+
+
+def jlb_set_two_step_variant(precision: int, variant: int):
+    _check(load().jlb_set_two_step_variant(int(precision), int(variant)))
+
+
+def jlb_get_two_step_variant(precision: int) -> int:
+    v = ctypes.c_int32(0)
+    _check(load().jlb_get_two_step_variant(int(precision), ctypes.byref(v)))
+    return v.value
+
+
+def jlb_time_two_step_kernel(prob: jlb_problem, warmup: int, launches: int, workspace=None, stream=None) -> float:
+    """Mean ms of one launch of the current two-step kernel (two lattice steps)."""
+    ms = ctypes.c_double(0.0)
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(load().jlb_time_two_step_kernel(ctypes.byref(prob), _dptr(workspace), nbytes, int(warmup), int(launches),
+                                           ctypes.byref(ms), _stream(stream)))
+    return ms.value
 
 
 def solve(d: dict, precision: str = "fp64", fields: bool = False, energy: bool = False, flags: int = 0,

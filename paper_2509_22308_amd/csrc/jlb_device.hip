@@ -38,6 +38,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "jlb_internal.h"
 
@@ -413,24 +414,33 @@ template <> struct VecOf<float, 4> { typedef float __attribute__((ext_vector_typ
 template <> struct VecOf<__bf16, 2> { typedef __bf16 __attribute__((ext_vector_type(2))) type; };
 template <> struct VecOf<__bf16, 4> { typedef __bf16 __attribute__((ext_vector_type(4))) type; };
 template <int V> struct MaskVec;
+template <> struct MaskVec<1> { typedef unsigned char type; };
 template <> struct MaskVec<2> { typedef unsigned short type; };
 template <> struct MaskVec<4> { typedef unsigned int type; };
 
 template <typename T, int V>
 __device__ __forceinline__ void vload(const T *p, float (&out)[V])
 {
-    const typename VecOf<T, V>::type v = *reinterpret_cast<const typename VecOf<T, V>::type *>(p);
+    if constexpr (V == 1) {
+        out[0] = (float)*p;
+    } else {
+        const typename VecOf<T, V>::type v = *reinterpret_cast<const typename VecOf<T, V>::type *>(p);
 #pragma unroll
-    for (int k = 0; k < V; ++k) out[k] = (float)v[k];
+        for (int k = 0; k < V; ++k) out[k] = (float)v[k];
+    }
 }
 
 template <typename T, int V>
 __device__ __forceinline__ void vstore(T *p, const float (&in)[V], bool stream)
 {
-    typename VecOf<T, V>::type v;
+    if constexpr (V == 1) {
+        put(p, (T)in[0], stream);
+    } else {
+        typename VecOf<T, V>::type v;
 #pragma unroll
-    for (int k = 0; k < V; ++k) v[k] = (T)in[k];
-    put(reinterpret_cast<typename VecOf<T, V>::type *>(p), v, stream);
+        for (int k = 0; k < V; ++k) v[k] = (T)in[k];
+        put(reinterpret_cast<typename VecOf<T, V>::type *>(p), v, stream);
+    }
 }
 
 template <int V>
@@ -570,6 +580,231 @@ __global__ __launch_bounds__(CX *R) void k_step_neq_vtile(Lattice L, const void 
     int tx, ty;
     block_tile(L, tx, ty);
     neq_vtile_row<NeqT, V>(L, srcv, dstv, einc, tx * CX + threadIdx.x, ty * R + threadIdx.y);
+}
+
+
+// ---------------------------------------------------------------------------
+// Two steps per launch (temporal blocking).  The state at n is read once and
+// the state at n + 2 written once, so a launch moves the bytes of one step
+// for two lattice updates.
+//
+// One wavefront is one independent work item: a strip of 64 V columns (V
+// adjacent nodes per lane) and H output rows.  Step n -> n + 1 is taken on
+// the rows j0 - 1 .. j0 + H and on every column of the strip; step
+// n + 1 -> n + 2 on rows j0 .. j0 + H - 1 and on all but HX columns at each
+// side, whose intermediate values lack an x-neighbour.  Strips therefore
+// overlap by 2 HX columns and rows are re-read at segment seams (from L2).
+// The wavefront sweeps up the rows keeping, in registers, three rows at n
+// (one more in flight) and three at n + 1; x-neighbours come from the
+// adjacent lanes.  Both updates call neq_core with the operands the one-step
+// kernels give it, and the intermediate deviations are rounded to the
+// storage type as a store would: results equal two one-step launches bit for
+// bit.  The companion row is stepped alongside where rows 0 or ny - 1 need
+// it; the wavefronts of the bottom segment store it.
+// ---------------------------------------------------------------------------
+
+template <typename NeqT> __device__ __forceinline__ float rt(float x) { return (float)(NeqT)x; }
+
+template <int V>
+struct SideRow {
+    float ez[V], hx[V], hy[V], na[V], nb[V];
+};
+
+template <int V>
+__device__ __forceinline__ SideRow<V> side_of(const RowData<V> &r, int qa, int qb)
+{
+    SideRow<V> s;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        s.ez[v] = r.ez[v];
+        s.hx[v] = r.hx[v];
+        s.hy[v] = r.hy[v];
+        s.na[v] = r.n[qa][v];
+        s.nb[v] = r.n[qb][v];
+    }
+    return s;
+}
+
+// Companion-row values rows 0 and ny - 1 pull from.
+template <int V>
+struct StripSides {
+    SideRow<V> lo, hi;
+};
+
+// One row's update from its own data (row r), the rows below and above (as
+// sides), the x-neighbours across lanes, and the companion row.  Nodes
+// outside the domain, conductors and padding come out zero.  Every lane of
+// the wavefront must call it (the shuffles).
+template <typename NeqT, int V, bool STRIP>
+__device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, bool act,
+                                           typename MaskVec<V>::type mv, const RowData<V> &cur,
+                                           const SideRow<V> &below, const SideRow<V> &above,
+                                           const StripSides<V> &inc, float einc, RowData<V> &out)
+{
+    Side xl, xr;
+    xl.ez = __shfl_up(cur.ez[V - 1], 1, 64);
+    xl.hx = __shfl_up(cur.hx[V - 1], 1, 64);
+    xl.hy = __shfl_up(cur.hy[V - 1], 1, 64);
+    xl.na = __shfl_up(cur.n[N_EPX][V - 1], 1, 64);
+    xl.nb = __shfl_up(cur.n[N_HXPX][V - 1], 1, 64);
+    xr.ez = __shfl_down(cur.ez[0], 1, 64);
+    xr.hx = __shfl_down(cur.hx[0], 1, 64);
+    xr.hy = __shfl_down(cur.hy[0], 1, 64);
+    xr.na = __shfl_down(cur.n[N_EMX][0], 1, 64);
+    xr.nb = __shfl_down(cur.n[N_HXMX][0], 1, 64);
+    zero_row(out);
+    if (!act || r < 0 || r > L.ny || (!STRIP && r == L.ny)) return;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int i = i0 + v;
+        if (i >= L.nx) continue;
+        uint8_t m = 0;
+        float eps = 1.0f, eps_rest = (float)(1.0 - 2.0 / 3.0);
+        if (!STRIP) {
+            m = (uint8_t)(mv >> (8 * v));
+            const int mat = m & 3;
+            if (mat == MAT_PEC) continue;
+            eps = (float)L.eps[mat];
+            eps_rest = (float)L.eps_rest[mat];
+        }
+        NodeData o;
+        o.ez = cur.ez[v];
+        o.hx = cur.hx[v];
+        o.hy = cur.hy[v];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o.n[q] = cur.n[q][v];
+        const Side l = v == 0 ? xl : Side{cur.ez[v - 1], cur.hx[v - 1], cur.hy[v - 1], cur.n[N_EPX][v - 1], cur.n[N_HXPX][v - 1]};
+        const Side rr = v == V - 1 ? xr : Side{cur.ez[v + 1], cur.hx[v + 1], cur.hy[v + 1], cur.n[N_EMX][v + 1], cur.n[N_HXMX][v + 1]};
+        const Side b{below.ez[v], below.hx[v], below.hy[v], below.na[v], below.nb[v]};
+        const Side t{above.ez[v], above.hx[v], above.hy[v], above.na[v], above.nb[v]};
+        const Side lo{inc.lo.ez[v], inc.lo.hx[v], inc.lo.hy[v], inc.lo.na[v], inc.lo.nb[v]};
+        const Side hi{inc.hi.ez[v], inc.hi.hx[v], inc.hi.hy[v], inc.hi.na[v], inc.hi.nb[v]};
+        NodeData res;
+        neq_core<STRIP>(L, i, r, m, eps, eps_rest, o, l, rr, b, t, lo, hi, einc, res);
+        out.ez[v] = res.ez;
+        out.hx[v] = res.hx;
+        out.hy[v] = res.hy;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) out.n[q][v] = res.n[q];
+    }
+}
+
+template <typename NeqT, int V>
+__device__ __forceinline__ void round_row(RowData<V> &r)
+{
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int v = 0; v < V; ++v) r.n[q][v] = rt<NeqT>(r.n[q][v]);
+}
+
+template <typename NeqT, int V>
+__device__ __forceinline__ void store_row(const Lattice &L, float *DF, NeqT *DN, size_t cf, size_t cn,
+                                          const RowData<V> &o)
+{
+    const size_t P = L.plane;
+    vstore<float, V>(DF + cf, o.ez, L.stream_stores);
+    vstore<float, V>(DF + P + cf, o.hx, L.stream_stores);
+    vstore<float, V>(DF + 2 * P + cf, o.hy, L.stream_stores);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) vstore<NeqT, V>(DN + q * P + cn, o.n[q], L.stream_stores);
+}
+
+template <int V> constexpr int two_step_halo() { return V < 2 ? 2 : V; }
+template <int V> constexpr int two_step_width() { return 64 * V - 2 * two_step_halo<V>(); }
+
+constexpr int TWO_STEP_WAVES = 4;  // independent wavefronts per block
+
+template <typename NeqT, int V, int H>
+__global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, const void *__restrict__ srcv,
+                                                                    void *__restrict__ dstv, float einc0, float einc1,
+                                                                    int nsx, int nsy)
+{
+    constexpr int HX = two_step_halo<V>();
+    constexpr int OW = two_step_width<V>();
+    typedef typename MaskVec<V>::type MaskT;
+    const int nb = gridDim.x;
+    const int b = L.stream_stores ? (int)blockIdx.x : xcd_tile(blockIdx.x, nb);
+    const int w = b * TWO_STEP_WAVES + (int)threadIdx.y;
+    if (w >= nsx * nsy) return;  // whole wavefront
+    const int sx = w / nsy, sy = w % nsy;
+    const int x0 = sx * OW, j0 = sy * H;
+    const int lane = threadIdx.x;
+    const int i0 = x0 - HX + V * lane;
+    const bool act = i0 >= 0 && i0 < L.nx;
+    const bool out_lane = act && lane >= HX / V && lane < (HX + OW) / V;
+
+    const size_t P = L.plane;
+    const float *F = reinterpret_cast<const float *>(srcv);
+    const NeqT *N = reinterpret_cast<const NeqT *>(F + 3 * P);
+    float *DF = reinterpret_cast<float *>(dstv);
+    NeqT *DN = reinterpret_cast<NeqT *>(DF + 3 * P);
+    auto load = [&](int r, RowData<V> &d, MaskT &m) {
+        zero_row(d);
+        m = 0;
+        if (act && r >= 0 && r < L.ny) {
+            load_row<NeqT, V>(F, N, P, at(i0, r, L.sf), at(i0, r, L.sn), d);
+            m = *reinterpret_cast<const MaskT *>(L.mask + node(L, i0, r));
+        }
+    };
+
+    // companion row at n and n + 1 where rows 0 or ny - 1 are updated here
+    StripSides<V> s0{}, s1{};
+    if (j0 <= 1 || j0 + H >= L.ny - 1) {
+        RowData<V> c0, c1;
+        zero_row(c0);
+        if (act) load_row<NeqT, V>(F, N, P, at(i0, L.ny, L.sf), at(i0, L.ny, L.sn), c0);
+        row_update<NeqT, V, true>(L, i0, L.ny, act, 0, c0, SideRow<V>{}, SideRow<V>{}, StripSides<V>{}, einc0, c1);
+        round_row<NeqT, V>(c1);
+        s0.lo = side_of(c0, N_EPY, N_HYPY);
+        s0.hi = side_of(c0, N_EMY, N_HYMY);
+        s1.lo = side_of(c1, N_EPY, N_HYPY);
+        s1.hi = side_of(c1, N_EMY, N_HYMY);
+        if (j0 == 0) {
+            RowData<V> c2;
+            row_update<NeqT, V, true>(L, i0, L.ny, act, 0, c1, SideRow<V>{}, SideRow<V>{}, StripSides<V>{}, einc1, c2);
+            if (out_lane) store_row<NeqT, V>(L, DF, DN, at(i0, L.ny, L.sf), at(i0, L.ny, L.sn), c2);
+        }
+    }
+
+    // rows at n: below (side), cur, above, next (in flight); rows at n + 1: below (side), cur
+    RowData<V> a_cur, a_top, tmp;
+    MaskT m_cur, m_top, m_prev = 0, m_dummy;
+    load(j0 - 2, tmp, m_dummy);
+    SideRow<V> a_bot = side_of(tmp, N_EPY, N_HYPY);
+    load(j0 - 1, a_cur, m_cur);
+    load(j0, a_top, m_top);
+    SideRow<V> b_bot{};
+    RowData<V> b_cur;
+    zero_row(b_cur);
+    for (int k = 0; k < H + 2; ++k) {
+        const int r1 = j0 - 1 + k;
+        RowData<V> a_nxt;
+        MaskT m_nxt;
+        if (k <= H) load(r1 + 2, a_nxt, m_nxt);
+        else { zero_row(a_nxt); m_nxt = 0; }
+        // step n -> n + 1 on row r1
+        RowData<V> b_top;
+        row_update<NeqT, V, false>(L, i0, r1, act, m_cur, a_cur, a_bot, side_of(a_top, N_EMY, N_HYMY), s0, einc0,
+                                   b_top);
+        round_row<NeqT, V>(b_top);
+        // step n + 1 -> n + 2 on row r1 - 1
+        if (k >= 2) {
+            const int r2 = r1 - 1;
+            RowData<V> o;
+            row_update<NeqT, V, false>(L, i0, r2, act, m_prev, b_cur, b_bot, side_of(b_top, N_EMY, N_HYMY), s1,
+                                       einc1, o);
+            if (out_lane && r2 < L.ny) store_row<NeqT, V>(L, DF, DN, at(i0, r2, L.sf), at(i0, r2, L.sn), o);
+        }
+        b_bot = side_of(b_cur, N_EPY, N_HYPY);
+        b_cur = b_top;
+        m_prev = m_cur;
+        a_bot = side_of(a_cur, N_EPY, N_HYPY);
+        a_cur = a_top;
+        m_cur = m_top;
+        a_top = a_nxt;
+        m_top = m_nxt;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -866,6 +1101,41 @@ hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, voi
         JLB_NEQ_LAUNCH(__bf16)
     }
 #undef JLB_NEQ_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, void *dst, double einc0, double einc1,
+                            hipStream_t s, int variant)
+{
+    const float e0 = (float)einc0, e1 = (float)einc1;
+    auto go = [&](auto tag, auto vtag, auto htag) {
+        typedef decltype(tag) T;
+        constexpr int V = decltype(vtag)::value, H = decltype(htag)::value;
+        const int nsx = (L.nx + two_step_width<V>() - 1) / two_step_width<V>();
+        const int nsy = (L.ny + H - 1) / H;
+        const int blocks = (nsx * nsy + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
+        hipLaunchKernelGGL((k_step2_neq<T, V, H>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src, dst, e0, e1,
+                           nsx, nsy);
+    };
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I4 = std::integral_constant<int, 4>;
+    using H8 = std::integral_constant<int, 8>;
+    using H16 = std::integral_constant<int, 16>;
+    using H32 = std::integral_constant<int, 32>;
+    auto pick = [&](auto tag) {
+        switch (variant) {
+        case TWO_V1_H8: go(tag, I1{}, H8{}); break;
+        case TWO_V1_H16: go(tag, I1{}, H16{}); break;
+        case TWO_V2_H8: go(tag, I2{}, H8{}); break;
+        case TWO_V2_H16: go(tag, I2{}, H16{}); break;
+        case TWO_V2_H32: go(tag, I2{}, H32{}); break;
+        case TWO_V4_H16: go(tag, I4{}, H16{}); break;
+        default: go(tag, I4{}, H32{}); break;
+        }
+    };
+    if (precision == 1) pick(float{});
+    else pick(__bf16{});
     return hipGetLastError();
 }
 

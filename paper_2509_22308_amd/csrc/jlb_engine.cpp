@@ -263,6 +263,7 @@ int harvest(jlb_engine *e)
         r.res.contour_points = q.nc;
         r.res.graph_used = 1;
         r.res.bytes_per_step = (int64_t)q.bytes_per_lup * q.nx * q.ny;
+        r.res.state_passes = q.prob.steps;
         r.t_done = now_ms();
         r.res.total_ms = r.t_done - r.t_submit;
         r.res.loop_ms = r.t_done - r.t_admit;

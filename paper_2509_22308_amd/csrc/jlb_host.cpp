@@ -20,6 +20,10 @@
 
 namespace jlb {
 
+static_assert(JLB_STEP_VARIANTS == NEQ_VARIANTS, "single-step variant count");
+static_assert(JLB_FP64_STEP_VARIANTS == F64_VARIANTS, "FP64 variant count");
+static_assert(JLB_TWO_STEP_VARIANTS == TWO_STEP_VARIANTS, "two-step variant count");
+
 // ---------------------------------------------------------------------------
 // Errors
 // ---------------------------------------------------------------------------
@@ -229,9 +233,14 @@ double incident(const Plan &q, int64_t n)
 // ---------------------------------------------------------------------------
 
 static std::atomic<int> g_variant[3] = {{0}, {NEQ_DIRECT}, {NEQ_DIRECT}};
+// Two-step kernel variant per precision for the steps outside the averaging
+// window, -1 = off (FP64 has none).
+static std::atomic<int> g_two[3] = {{-1}, {-1}, {-1}};
 
 int step_variant(int precision) { return g_variant[precision].load(std::memory_order_relaxed); }
 void set_step_variant(int precision, int v) { g_variant[precision].store(v, std::memory_order_relaxed); }
+static int two_step_variant(int precision) { return g_two[precision].load(std::memory_order_relaxed); }
+static void set_two_step_variant(int precision, int v) { g_two[precision].store(v, std::memory_order_relaxed); }
 
 hipError_t launch_step(const Plan &q, const Lattice &L, void *src, void *dst, double *fields, double einc, hipStream_t s,
                        int variant)
@@ -366,7 +375,10 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     const int64_t steps = q.prob.steps;
     const int64_t wstart = steps - q.window;  // launches from here on produce averaged levels
     const bool use_graph = !(q.prob.flags & JLB_F_NO_GRAPH) && !energy;
-    const int64_t chunk = (q.T % 2 == 0) ? q.T : 2 * q.T;  // whole periods, even step count
+    // whole periods, a multiple of 4 steps: two-step launches then come in
+    // pairs and a chunk leaves state n in buffer n % 2, as single steps do
+    const int64_t chunk = q.T % 4 == 0 ? q.T : q.T % 2 == 0 ? 2 * q.T : 4 * q.T;
+    const int two = q.prob.precision == JLB_FP64 ? -1 : two_step_variant(q.prob.precision);
     const int64_t ramp_end = (int64_t)std::ceil(q.ramp_steps);
 
     hipEvent_t ev0, ev1;
@@ -379,12 +391,27 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     auto capture = [&](int which, int64_t n0) -> int {
         hipGraph_t g;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int64_t k = 0; k < chunk; ++k) {
-            int r = launch_one_step(q, ws, L, C, n0 + k, which == 1, false, incident(q, n0 + k), s);
-            if (r) {
-                hipGraph_t dummy;
-                (void)hipStreamEndCapture(s, &dummy);
-                return r;
+        if (which == 0 && two >= 0) {
+            // launch m takes state n0 + 2m from buffer (n0 + m) % 2 to the other one
+            for (int64_t m = 0; m < chunk / 2; ++m) {
+                const int64_t n = n0 + 2 * m;
+                hipError_t e = launch_step2_neq(q.prob.precision, L, ws + q.off_state[(n0 + m) & 1],
+                                                ws + q.off_state[(n0 + m + 1) & 1], incident(q, n), incident(q, n + 1),
+                                                s, two);
+                if (e != hipSuccess) {
+                    hipGraph_t dummy;
+                    (void)hipStreamEndCapture(s, &dummy);
+                    return fail(JLB_E_DEVICE, "two-step launch: %s", hipGetErrorString(e));
+                }
+            }
+        } else {
+            for (int64_t k = 0; k < chunk; ++k) {
+                int r = launch_one_step(q, ws, L, C, n0 + k, which == 1, false, incident(q, n0 + k), s);
+                if (r) {
+                    hipGraph_t dummy;
+                    (void)hipStreamEndCapture(s, &dummy);
+                    return r;
+                }
             }
         }
         HIP_TRY(hipStreamEndCapture(s, &g));
@@ -395,6 +422,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     };
 
     int64_t n = 0;
+    int64_t passes = 0;
     int graph_used = 0;
     while (n < steps && rc == JLB_OK) {
         const bool in_window = n >= wstart;
@@ -416,11 +444,13 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
                 break;
             }
             graph_used = 1;
+            passes += which == 0 && two >= 0 ? chunk / 2 : chunk;
             n += chunk;
             continue;
         }
         rc = launch_one_step(q, ws, L, C, n, in_window, energy != nullptr || n == steps - 1, incident(q, n), s);
         if (rc) break;
+        ++passes;
         if (energy) {
             hipError_t e = launch_energy(q.prob.precision, L, fields_ptr(q, ws, n + 1), (double *)(ws + q.off_parts),
                                          q.nparts, energy + n, s);
@@ -454,6 +484,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             res->contour_points = q.nc;
             res->graph_used = graph_used;
             res->bytes_per_step = (int64_t)q.bytes_per_lup * q.nx * q.ny;
+            res->state_passes = passes;
             for (int k = 0; k < 6; ++k)
                 if (!std::isfinite(out[k])) rc = fail(JLB_E_NONFINITE, "forces are not finite");
         }
@@ -563,7 +594,7 @@ int jlb_solve(const jlb_problem *prob, void *workspace, size_t workspace_bytes, 
 }
 
 static int time_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
-                            int32_t launches, int variant, double *ms_per_launch, void *stream)
+                            int32_t launches, int variant, bool two, double *ms_per_launch, void *stream)
 {
     if (!ms_per_launch || launches < 1 || warmup < 0) return fail(JLB_E_ARG, "bad launch counts");
     Plan q;
@@ -588,8 +619,11 @@ static int time_step_kernel(const jlb_problem *prob, void *workspace, size_t wor
     const Lattice L = lattice_of(q, (const uint8_t *)(ws + q.off_mask));
     for (int64_t n = 0; rc == JLB_OK && n < (int64_t)warmup + launches; ++n) {
         if (n == warmup && hipEventRecord(e0, own) != hipSuccess) rc = fail(JLB_E_DEVICE, "event record");
-        hipError_t e = launch_step(q, L, ws + q.off_state[n & 1], ws + q.off_state[(n + 1) & 1], nullptr, incident(q, n),
-                                   own, variant);
+        hipError_t e = two ? launch_step2_neq(q.prob.precision, L, ws + q.off_state[n & 1],
+                                              ws + q.off_state[(n + 1) & 1], incident(q, 2 * n), incident(q, 2 * n + 1),
+                                              own, variant)
+                           : launch_step(q, L, ws + q.off_state[n & 1], ws + q.off_state[(n + 1) & 1], nullptr,
+                                         incident(q, n), own, variant);
         if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "step launch: %s", hipGetErrorString(e));
     }
     if (rc == JLB_OK) {
@@ -613,7 +647,18 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
     clear_error();
     if (!prob) return fail(JLB_E_ARG, "null problem");
     const int v = prob->precision >= 0 && prob->precision <= 2 ? step_variant(prob->precision) : 0;
-    return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, ms_per_launch, stream);
+    return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, false, ms_per_launch, stream);
+}
+
+int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
+                             int32_t launches, double *ms_per_launch, void *stream)
+{
+    clear_error();
+    if (!prob) return fail(JLB_E_ARG, "null problem");
+    if (prob->precision != JLB_FP32 && prob->precision != JLB_BF16) return fail(JLB_E_ARG, "two-step kernels are FP32 / BF16");
+    const int v = two_step_variant(prob->precision);
+    if (v < 0) return fail(JLB_E_ARG, "no two-step variant selected");
+    return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, true, ms_per_launch, stream);
 }
 
 int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t launches,
@@ -627,7 +672,7 @@ int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_byte
     int bv = step_variant(prob->precision);
     for (int v = 0; v < nvar; ++v) {
         double ms = 0.0;
-        int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, v, &ms, stream);
+        int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, v, false, &ms, stream);
         if (rc) return rc;
         if (ms_per_variant) ms_per_variant[v] = ms;
         if (ms < best) {
@@ -637,6 +682,22 @@ int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_byte
     }
     set_step_variant(prob->precision, bv);
     *best_variant = bv;
+    if (prob->precision == JLB_FP64) return JLB_OK;
+    // two-step kernels, compared per lattice step
+    int b2 = -1;
+    for (int v = 0; v < TWO_STEP_VARIANTS; ++v) {
+        double ms = 0.0;
+        int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, v, true, &ms, stream);
+        if (rc) return rc;
+        ms *= 0.5;
+        if (ms_per_variant) ms_per_variant[NEQ_VARIANTS + v] = ms;
+        if (ms < best) {
+            best = ms;
+            b2 = v;
+        }
+    }
+    set_two_step_variant(prob->precision, b2);
+    if (b2 >= 0) *best_variant = NEQ_VARIANTS + b2;
     return JLB_OK;
 }
 
@@ -647,6 +708,24 @@ int jlb_set_step_variant(int32_t precision, int32_t variant)
     if (precision < 0 || precision > 2 || variant < 0 || variant >= nvar)
         return fail(JLB_E_ARG, "precision 0..2 and variant 0..%d", nvar - 1);
     set_step_variant(precision, variant);
+    return JLB_OK;
+}
+
+int jlb_set_two_step_variant(int32_t precision, int32_t variant)
+{
+    clear_error();
+    if (precision < 0 || precision > 2 || variant < -1 || variant >= TWO_STEP_VARIANTS ||
+        (precision == JLB_FP64 && variant != -1))
+        return fail(JLB_E_ARG, "precision 1..2 and variant -1..%d (FP64: -1 only)", TWO_STEP_VARIANTS - 1);
+    set_two_step_variant(precision, variant);
+    return JLB_OK;
+}
+
+int jlb_get_two_step_variant(int32_t precision, int32_t *variant)
+{
+    clear_error();
+    if (precision < 0 || precision > 2 || !variant) return fail(JLB_E_ARG, "bad precision or null variant");
+    *variant = two_step_variant(precision);
     return JLB_OK;
 }
 

@@ -86,6 +86,21 @@ enum NeqVariant {
 enum F64Variant { F64_R4 = 0, F64_W256_R1 = 1, F64_W256_R2 = 2, F64_VARIANTS = 3 };
 hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, void *dst, double einc, hipStream_t s,
                            int variant);
+// Two steps per launch (FP32 / BF16): state n in src -> state n + 2 in dst
+// (src and dst must differ); einc0 / einc1 are the source values of steps n
+// and n + 1.  Variants: V adjacent nodes per lane, H rows per wavefront.
+enum TwoStepVariant {
+    TWO_V1_H8 = 0,
+    TWO_V1_H16 = 1,
+    TWO_V2_H8 = 2,
+    TWO_V2_H16 = 3,
+    TWO_V2_H32 = 4,
+    TWO_V4_H16 = 5,
+    TWO_V4_H32 = 6,
+    TWO_STEP_VARIANTS = 7
+};
+hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, void *dst, double einc0, double einc1,
+                            hipStream_t s, int variant);
 // Fields: FP64 planes [3][plane] for precision 0, the FP32 field planes of the
 // state for precisions 1 and 2.
 hipError_t launch_contour(int precision, const Lattice &L, const void *fields, const ContourDev &C, hipStream_t s);

@@ -183,3 +183,55 @@ def test_step_kernel_variants_give_identical_results(jlb, precision):
                     assert np.array_equal(o[f], outs[0][f])
     finally:
         jlb.jlb_set_step_variant(prec, before)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_two_step_kernels_equal_single_steps(jlb, precision):
+    """A two-step launch (temporal blocking) takes the state from n to n + 2
+    with the single-step arithmetic and the intermediate deviations rounded
+    to the storage type: solves that run their out-of-window periods on any
+    two-step variant equal the single-step solve bit for bit, fields and
+    forces (ragged strips and row segments, conductor links, all edges, the
+    companion row)."""
+    prec = jlb.PRECISIONS[precision]
+    before = jlb.jlb_get_two_step_variant(prec)
+    cases = [W.problem(nx=203, ny=150, radius=20.0, kind="metallo_dielectric_janus", eps1=3.0, phi0_deg=110.0,
+                       wavelength=40.0, steps=700, avg_periods=1),
+             W.problem(nx=130, ny=171, radius=16.0, kind="dielectric_janus", eps1=2.0, eps2=6.0, phi0_deg=45.0,
+                       wavelength=40.0, steps=650, avg_periods=1),
+             W.problem(nx=530, ny=97, radius=20.0, kind="dielectric_janus", eps1=4.0, eps2=1.5, phi0_deg=200.0,
+                       wavelength=40.0, steps=700, avg_periods=1)]
+    try:
+        for p in cases:
+            _print_case(f"two-step {precision}", p)
+            jlb.jlb_set_two_step_variant(prec, -1)
+            ref = jlb.solve(p, precision, fields=True)
+            assert ref["state_passes"] == p["steps"]
+            for v in range(len(jlb.TWO_STEP_VARIANTS)):
+                jlb.jlb_set_two_step_variant(prec, v)
+                o = jlb.solve(p, precision, fields=True)
+                assert o["graph_used"] == 1 and o["state_passes"] < p["steps"], (v, o["state_passes"])
+                for q in ("fx", "fy", "tz"):
+                    assert o[q] == ref[q], (v, q, o[q], ref[q])
+                for f in ("ez", "hx", "hy"):
+                    assert np.array_equal(o[f], ref[f]), (v, f, np.abs(o[f] - ref[f]).max())
+    finally:
+        jlb.jlb_set_two_step_variant(prec, before)
+
+
+def test_two_step_config2_matches_single_steps(jlb):
+    """The headline workload with the autotuner's choice: forces identical to
+    single steps."""
+    p = W.config2()
+    prec = jlb.PRECISIONS["fp32"]
+    before = jlb.jlb_get_two_step_variant(prec)
+    try:
+        jlb.jlb_set_two_step_variant(prec, -1)
+        ref = jlb.solve(p, "fp32")
+        for v in range(len(jlb.TWO_STEP_VARIANTS)):
+            jlb.jlb_set_two_step_variant(prec, v)
+            o = jlb.solve(p, "fp32")
+            for q in ("fx", "fy", "tz"):
+                assert o[q] == ref[q], (v, q, o[q], ref[q])
+    finally:
+        jlb.jlb_set_two_step_variant(prec, before)
