@@ -59,6 +59,30 @@ template <typename T> __device__ __forceinline__ void put(T *p, T v, bool stream
 constexpr int BX = 64;  // one wavefront per row segment
 constexpr int BY = 4;   // four rows per block
 
+// Material parameters by id.  Ids vary per lane; the compiler would turn a
+// select among the uniform values back into an indexed vector load (whose
+// wait also waits for every load issued before it, look-ahead rows
+// included), so the values pass through readfirstlane first.  Id 3
+// (conductor) is never asked for.
+__device__ __forceinline__ float uniform(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+__device__ __forceinline__ double uniform(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <typename R> __device__ __forceinline__ R mat_pick(const double (&v)[4], int mat)
+{
+    const R v0 = uniform((R)v[0]), v1 = uniform((R)v[1]), v2 = uniform((R)v[2]);
+    return mat == 0 ? v0 : mat == 1 ? v1 : v2;
+}
+__device__ __forceinline__ double mat_eps(const Lattice &L, int mat) { return mat_pick<double>(L.eps, mat); }
+__device__ __forceinline__ double mat_eps_rest(const Lattice &L, int mat) { return mat_pick<double>(L.eps_rest, mat); }
+__device__ __forceinline__ float mat_eps_f(const Lattice &L, int mat) { return mat_pick<float>(L.eps, mat); }
+__device__ __forceinline__ float mat_eps_rest_f(const Lattice &L, int mat) { return mat_pick<float>(L.eps_rest, mat); }
+__device__ __forceinline__ float mat_inv_eps_f(const Lattice &L, int mat) { return mat_pick<float>(L.inv_eps, mat); }
+
 // Mask index of node (i, j).
 __device__ __forceinline__ size_t node(const Lattice &L, int i, int j) { return (size_t)j * L.pitch + i; }
 // Index of node (i, j) in plane 0 of a row-interleaved array with row stride S.
@@ -126,8 +150,8 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
         const uint8_t m = L.mask[node(L, i, j)];
         const int mat = m & 3;
         if (mat == MAT_PEC) return;
-        eps = L.eps[mat];
-        eps_rest = L.eps_rest[mat];
+        eps = mat_eps(L, mat);
+        eps_rest = mat_eps_rest(L, mat);
         const size_t strip = at(i, L.ny, L.sf);
         // +x populations come from (i-1, j)
         if (i == 0) { f[1] = einc / 3.0; f[6] = 0.0; }
@@ -245,7 +269,7 @@ __device__ __forceinline__ Side load_side(const float *F, const NeqT *N, size_t 
 // `inc_hi` hold the incident-wave companion node of the same column
 // (fields + N_{e+y}, N_{hy+y} / N_{e-y}, N_{hy-y}) for the bottom / top rows.
 template <bool STRIP>
-__device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t m, float eps, float eps_rest,
+__device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t m, float inv_eps, float eps_rest,
                                          const NodeData &o, const Side &l, const Side &r, const Side &b, const Side &t,
                                          const Side &inc_lo, const Side &inc_hi, float einc, NodeData &out)
 {
@@ -254,51 +278,52 @@ __device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t
 #pragma clang fp contract(off)
     const float keep = (float)(1.0 - OPEN_DELTA);
     const float delta = (float)OPEN_DELTA;
-    // own post-collision moving populations (edges and conductor links use them)
-    const float s_epx = (o.ez - o.hy) * SIXTH - o.n[N_EPX];
-    const float s_emx = (o.ez + o.hy) * SIXTH - o.n[N_EMX];
-    const float s_epy = (o.ez + o.hx) * SIXTH - o.n[N_EPY];
-    const float s_emy = (o.ez - o.hx) * SIXTH - o.n[N_EMY];
-    const float s_hxpx = o.hx * SIXTH - o.n[N_HXPX];
-    const float s_hxmx = o.hx * SIXTH - o.n[N_HXMX];
-    const float s_hypy = o.hy * SIXTH - o.n[N_HYPY];
-    const float s_hymy = o.hy * SIXTH - o.n[N_HYMY];
     // rest populations stream in place: f*_r = f_r^eq - N_r with the sum rules
     const float r_e = eps_rest * o.ez + (o.n[N_EPX] + o.n[N_EMX] + o.n[N_EPY] + o.n[N_EMY]);
     const float r_hx = o.hx * THIRD + (o.n[N_HXPX] + o.n[N_HXMX] + o.n[N_EPY] - o.n[N_EMY]);
     const float r_hy = o.hy * THIRD + (o.n[N_HYPY] + o.n[N_HYMY] - o.n[N_EPX] + o.n[N_EMX]);
 
-    float e_px, hx_px, e_mx, hx_mx, e_py, hy_py, e_my, hy_my;
-    // +x from (i-1, j)
-    if (i == 0) { e_px = einc * THIRD; hx_px = 0.0f; }
-    else if (m & NB_PEC_XM) { e_px = -s_emx; hx_px = -s_hxmx; }
-    else { e_px = (l.ez - l.hy) * SIXTH - l.na; hx_px = l.hx * SIXTH - l.nb; }
-    // -x from (i+1, j)
-    if (i == L.nx - 1) {
-        if (STRIP) { e_mx = 0.0f; hx_mx = 0.0f; }
-        else { e_mx = keep * s_emx; hx_mx = keep * s_hxmx; }
-    } else if (m & NB_PEC_XP) { e_mx = -s_epx; hx_mx = -s_hxpx; }
-    else { e_mx = (r.ez + r.hy) * SIXTH - r.na; hx_mx = r.hx * SIXTH - r.nb; }
-    if (STRIP) {
-        // uniform in y: the +-y populations stay in their node
-        e_py = s_epy; hy_py = s_hypy; e_my = s_emy; hy_my = s_hymy;
-    } else {
-        // +y from (i, j-1)
-        if (j == 0) {
-            e_py = keep * s_epy + delta * ((inc_lo.ez + inc_lo.hx) * SIXTH - inc_lo.na);
-            hy_py = keep * s_hypy + delta * (inc_lo.hy * SIXTH - inc_lo.nb);
-        } else if (m & NB_PEC_YM) { e_py = -s_emy; hy_py = -s_hymy; }
-        else { e_py = (b.ez + b.hx) * SIXTH - b.na; hy_py = b.hy * SIXTH - b.nb; }
-        // -y from (i, j+1)
-        if (j == L.ny - 1) {
-            e_my = keep * s_emy + delta * ((inc_hi.ez - inc_hi.hx) * SIXTH - inc_hi.na);
-            hy_my = keep * s_hymy + delta * (inc_hi.hy * SIXTH - inc_hi.nb);
-        } else if (m & NB_PEC_YP) { e_my = -s_epy; hy_my = -s_hypy; }
-        else { e_my = (t.ez - t.hx) * SIXTH - t.na; hy_my = t.hy * SIXTH - t.nb; }
+    // pulls across interior links: the neighbour's post-collision population
+    float e_px = (l.ez - l.hy) * SIXTH - l.na, hx_px = l.hx * SIXTH - l.nb;  // +x from (i-1, j)
+    float e_mx = (r.ez + r.hy) * SIXTH - r.na, hx_mx = r.hx * SIXTH - r.nb;  // -x from (i+1, j)
+    float e_py = (b.ez + b.hx) * SIXTH - b.na, hy_py = b.hy * SIXTH - b.nb;  // +y from (i, j-1)
+    float e_my = (t.ez - t.hx) * SIXTH - t.na, hy_my = t.hy * SIXTH - t.nb;  // -y from (i, j+1)
+    // edges, conductor links and the companion row replace some of them
+    // (most wavefronts have no such node and skip this block)
+    if (STRIP || i == 0 || i == L.nx - 1 || j == 0 || j == L.ny - 1 ||
+        (m & (NB_PEC_XM | NB_PEC_XP | NB_PEC_YM | NB_PEC_YP))) {
+        // own post-collision moving populations
+        const float s_epx = (o.ez - o.hy) * SIXTH - o.n[N_EPX];
+        const float s_emx = (o.ez + o.hy) * SIXTH - o.n[N_EMX];
+        const float s_epy = (o.ez + o.hx) * SIXTH - o.n[N_EPY];
+        const float s_emy = (o.ez - o.hx) * SIXTH - o.n[N_EMY];
+        const float s_hxpx = o.hx * SIXTH - o.n[N_HXPX];
+        const float s_hxmx = o.hx * SIXTH - o.n[N_HXMX];
+        const float s_hypy = o.hy * SIXTH - o.n[N_HYPY];
+        const float s_hymy = o.hy * SIXTH - o.n[N_HYMY];
+        if (i == 0) { e_px = einc * THIRD; hx_px = 0.0f; }
+        else if (m & NB_PEC_XM) { e_px = -s_emx; hx_px = -s_hxmx; }
+        if (i == L.nx - 1) {
+            if (STRIP) { e_mx = 0.0f; hx_mx = 0.0f; }
+            else { e_mx = keep * s_emx; hx_mx = keep * s_hxmx; }
+        } else if (m & NB_PEC_XP) { e_mx = -s_epx; hx_mx = -s_hxpx; }
+        if (STRIP) {
+            // uniform in y: the +-y populations stay in their node
+            e_py = s_epy; hy_py = s_hypy; e_my = s_emy; hy_my = s_hymy;
+        } else {
+            if (j == 0) {
+                e_py = keep * s_epy + delta * ((inc_lo.ez + inc_lo.hx) * SIXTH - inc_lo.na);
+                hy_py = keep * s_hypy + delta * (inc_lo.hy * SIXTH - inc_lo.nb);
+            } else if (m & NB_PEC_YM) { e_py = -s_emy; hy_py = -s_hymy; }
+            if (j == L.ny - 1) {
+                e_my = keep * s_emy + delta * ((inc_hi.ez - inc_hi.hx) * SIXTH - inc_hi.na);
+                hy_my = keep * s_hymy + delta * (inc_hi.hy * SIXTH - inc_hi.nb);
+            } else if (m & NB_PEC_YP) { e_my = -s_epy; hy_my = -s_hypy; }
+        }
     }
 
     const float dz = r_e + e_px + e_mx + (e_py + e_my);
-    const float ez = dz / eps;
+    const float ez = dz * inv_eps;
     const float hx = r_hx + hx_px + hx_mx + (e_py - e_my);
     const float hy = r_hy + (hy_py + hy_my) + (e_mx - e_px);
     out.ez = ez;
@@ -328,18 +353,18 @@ __device__ __forceinline__ void store_node(float *F, NeqT *N, size_t P, size_t c
 // Sides along x of node (i, j) and the material parameters; false for a conductor node.
 template <typename NeqT>
 __device__ __forceinline__ bool node_setup(const Lattice &L, const float *F, const NeqT *N, int i, int j, size_t cf,
-                                           size_t cn, uint8_t &m, float &eps, float &eps_rest, Side &l, Side &r)
+                                           size_t cn, uint8_t &m, float &inv_eps, float &eps_rest, Side &l, Side &r)
 {
     const size_t P = L.plane;
     m = 0;
-    eps = 1.0f;
+    inv_eps = 1.0f;
     eps_rest = (float)(1.0 - 2.0 / 3.0);
     if (j < L.ny) {
         m = L.mask[node(L, i, j)];
         const int mat = m & 3;
         if (mat == MAT_PEC) return false;
-        eps = (float)L.eps[mat];
-        eps_rest = (float)L.eps_rest[mat];
+        inv_eps = mat_inv_eps_f(L, mat);
+        eps_rest = mat_eps_rest_f(L, mat);
     }
     if (i > 0 && !(m & NB_PEC_XM)) l = load_side(F, N, P, cf - 1, cn - 1, N_EPX, N_HXPX);
     if (i < L.nx - 1 && !(m & NB_PEC_XP)) r = load_side(F, N, P, cf + 1, cn + 1, N_EMX, N_HXMX);
@@ -375,18 +400,18 @@ __device__ __forceinline__ void neq_direct_node(const Lattice &L, const void *__
     NeqT *DN = reinterpret_cast<NeqT *>(DF + 3 * P);
     const size_t cf = at(i, j, L.sf), cn = at(i, j, L.sn);
     uint8_t m;
-    float eps, eps_rest;
+    float inv_eps, eps_rest;
     Side l{}, r{}, b{}, t{}, lo{}, hi{};
-    if (!node_setup(L, F, N, i, j, cf, cn, m, eps, eps_rest, l, r)) return;
+    if (!node_setup(L, F, N, i, j, cf, cn, m, inv_eps, eps_rest, l, r)) return;
     const NodeData o = load_node(F, N, P, cf, cn);
     NodeData out;
     if (j == L.ny) {
-        neq_core<true>(L, i, j, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
+        neq_core<true>(L, i, j, m, inv_eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
     } else {
         if (j > 0 && !(m & NB_PEC_YM)) b = load_side(F, N, P, cf - L.sf, cn - L.sn, N_EPY, N_HYPY);
         if (j < L.ny - 1 && !(m & NB_PEC_YP)) t = load_side(F, N, P, cf + L.sf, cn + L.sn, N_EMY, N_HYMY);
         load_incident_sides(L, F, N, i, j, lo, hi);
-        neq_core<false>(L, i, j, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
+        neq_core<false>(L, i, j, m, inv_eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
     }
     store_node(DF, DN, P, cf, cn, out, L.stream_stores);
 }
@@ -449,6 +474,19 @@ struct RowData {
     float n[8][V];
 };
 
+// x-neighbour exchange across the wavefront with DPP wave shifts (a VALU
+// move, no LDS traffic): lane k receives the value of lane k - 1
+// (from_left) or of lane k + 1 (from_right); the end lanes, which have no
+// such neighbour in the wavefront, receive 0 (callers load or ignore it).
+__device__ __forceinline__ float from_left(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_right(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
 template <typename NeqT, int V>
 __device__ __forceinline__ void load_row(const float *F, const NeqT *N, size_t P, size_t cf, size_t cn, RowData<V> &r)
 {
@@ -457,6 +495,36 @@ __device__ __forceinline__ void load_row(const float *F, const NeqT *N, size_t P
     vload<float, V>(F + 2 * P + cf, r.hy);
 #pragma unroll
     for (int q = 0; q < 8; ++q) vload<NeqT, V>(N + q * P + cn, r.n[q]);
+}
+
+// Row data at columns col .. col + V - 1 of the lattice row that starts at
+// Fr (its field planes, then its deviation planes): a wave-uniform row base
+// plus 32-bit offsets that stay the same from row to row.
+template <typename NeqT> __device__ __forceinline__ unsigned f_off(unsigned P, int q, unsigned col)
+{
+    return (q * P + col) * 4u;
+}
+template <typename NeqT> __device__ __forceinline__ unsigned n_off(unsigned P, int q, unsigned col)
+{
+    return 12u * P + (q * P + col) * (unsigned)sizeof(NeqT);
+}
+template <typename T> __device__ __forceinline__ const T *byte_at(const void *base, unsigned off)
+{
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+template <typename T> __device__ __forceinline__ T *byte_at(void *base, unsigned off)
+{
+    return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off);
+}
+
+template <typename NeqT, int V>
+__device__ __forceinline__ void load_row_at(const float *Fr, unsigned P, unsigned col, RowData<V> &r)
+{
+    vload<float, V>(byte_at<float>(Fr, f_off<NeqT>(P, 0, col)), r.ez);
+    vload<float, V>(byte_at<float>(Fr, f_off<NeqT>(P, 1, col)), r.hx);
+    vload<float, V>(byte_at<float>(Fr, f_off<NeqT>(P, 2, col)), r.hy);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) vload<NeqT, V>(byte_at<NeqT>(Fr, n_off<NeqT>(P, q, col)), r.n[q]);
 }
 
 template <int V>
@@ -496,16 +564,16 @@ __device__ __forceinline__ void neq_vtile_row(const Lattice &L, const void *__re
     if (active) load_row<NeqT, V>(F, N, P, cf, cn, cur);
     // x-neighbours across lanes (every lane of the wavefront takes part)
     Side xl, xr;
-    xl.ez = __shfl_up(cur.ez[V - 1], 1, 64);
-    xl.hx = __shfl_up(cur.hx[V - 1], 1, 64);
-    xl.hy = __shfl_up(cur.hy[V - 1], 1, 64);
-    xl.na = __shfl_up(cur.n[N_EPX][V - 1], 1, 64);
-    xl.nb = __shfl_up(cur.n[N_HXPX][V - 1], 1, 64);
-    xr.ez = __shfl_down(cur.ez[0], 1, 64);
-    xr.hx = __shfl_down(cur.hx[0], 1, 64);
-    xr.hy = __shfl_down(cur.hy[0], 1, 64);
-    xr.na = __shfl_down(cur.n[N_EMX][0], 1, 64);
-    xr.nb = __shfl_down(cur.n[N_HXMX][0], 1, 64);
+    xl.ez = from_left(cur.ez[V - 1]);
+    xl.hx = from_left(cur.hx[V - 1]);
+    xl.hy = from_left(cur.hy[V - 1]);
+    xl.na = from_left(cur.n[N_EPX][V - 1]);
+    xl.nb = from_left(cur.n[N_HXPX][V - 1]);
+    xr.ez = from_right(cur.ez[0]);
+    xr.hx = from_right(cur.hx[0]);
+    xr.hy = from_right(cur.hy[0]);
+    xr.na = from_right(cur.n[N_EMX][0]);
+    xr.nb = from_right(cur.n[N_HXMX][0]);
     if (!active) return;
     if (j == L.ny) {
         // companion row: per node, as in the other variants
@@ -544,8 +612,8 @@ __device__ __forceinline__ void neq_vtile_row(const Lattice &L, const void *__re
         const uint8_t m = (uint8_t)(mv >> (8 * v));
         const int mat = m & 3;
         if (i >= L.nx || mat == MAT_PEC) continue;
-        const float eps = (float)L.eps[mat];
-        const float eps_rest = (float)L.eps_rest[mat];
+        const float inv_eps = mat_inv_eps_f(L, mat);
+        const float eps_rest = mat_eps_rest_f(L, mat);
         NodeData o;
         o.ez = cur.ez[v];
         o.hx = cur.hx[v];
@@ -559,7 +627,7 @@ __device__ __forceinline__ void neq_vtile_row(const Lattice &L, const void *__re
         Side lo{}, hi{};
         load_incident_sides(L, F, N, i, j, lo, hi);
         NodeData res;
-        neq_core<false>(L, i, j, m, eps, eps_rest, o, l, r, b, t, lo, hi, einc, res);
+        neq_core<false>(L, i, j, m, inv_eps, eps_rest, o, l, r, b, t, lo, hi, einc, res);
         out.ez[v] = res.ez;
         out.hx[v] = res.hx;
         out.hy[v] = res.hy;
@@ -632,40 +700,38 @@ struct StripSides {
 };
 
 // One row's update from its own data (row r), the rows below and above (as
-// sides), the x-neighbours across lanes, and the companion row.  Nodes
-// outside the domain, conductors and padding come out zero.  Every lane of
-// the wavefront must call it (the shuffles).
+// sides), the x-neighbours across lanes, and the companion row.  Every node
+// of the row is updated without branching on its kind: for nodes that hold
+// nothing (conductors, padding, rows or columns outside the domain) the
+// result is a finite value that no valid node ever reads -- a valid node
+// next to such a node takes an edge or conductor rule instead -- and
+// store_row_masked writes zeros for them.
 template <typename NeqT, int V, bool STRIP>
-__device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, bool act,
-                                           typename MaskVec<V>::type mv, const RowData<V> &cur,
-                                           const SideRow<V> &below, const SideRow<V> &above,
+__device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, typename MaskVec<V>::type mv,
+                                           const RowData<V> &cur, const SideRow<V> &below, const SideRow<V> &above,
                                            const StripSides<V> &inc, float einc, RowData<V> &out)
 {
     Side xl, xr;
-    xl.ez = __shfl_up(cur.ez[V - 1], 1, 64);
-    xl.hx = __shfl_up(cur.hx[V - 1], 1, 64);
-    xl.hy = __shfl_up(cur.hy[V - 1], 1, 64);
-    xl.na = __shfl_up(cur.n[N_EPX][V - 1], 1, 64);
-    xl.nb = __shfl_up(cur.n[N_HXPX][V - 1], 1, 64);
-    xr.ez = __shfl_down(cur.ez[0], 1, 64);
-    xr.hx = __shfl_down(cur.hx[0], 1, 64);
-    xr.hy = __shfl_down(cur.hy[0], 1, 64);
-    xr.na = __shfl_down(cur.n[N_EMX][0], 1, 64);
-    xr.nb = __shfl_down(cur.n[N_HXMX][0], 1, 64);
-    zero_row(out);
-    if (!act || r < 0 || r > L.ny || (!STRIP && r == L.ny)) return;
+    xl.ez = from_left(cur.ez[V - 1]);
+    xl.hx = from_left(cur.hx[V - 1]);
+    xl.hy = from_left(cur.hy[V - 1]);
+    xl.na = from_left(cur.n[N_EPX][V - 1]);
+    xl.nb = from_left(cur.n[N_HXPX][V - 1]);
+    xr.ez = from_right(cur.ez[0]);
+    xr.hx = from_right(cur.hx[0]);
+    xr.hy = from_right(cur.hy[0]);
+    xr.na = from_right(cur.n[N_EMX][0]);
+    xr.nb = from_right(cur.n[N_HXMX][0]);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const int i = i0 + v;
-        if (i >= L.nx) continue;
         uint8_t m = 0;
-        float eps = 1.0f, eps_rest = (float)(1.0 - 2.0 / 3.0);
+        float inv_eps = 1.0f, eps_rest = (float)(1.0 - 2.0 / 3.0);
         if (!STRIP) {
             m = (uint8_t)(mv >> (8 * v));
             const int mat = m & 3;
-            if (mat == MAT_PEC) continue;
-            eps = (float)L.eps[mat];
-            eps_rest = (float)L.eps_rest[mat];
+            inv_eps = mat_inv_eps_f(L, mat);
+            eps_rest = mat_eps_rest_f(L, mat);
         }
         NodeData o;
         o.ez = cur.ez[v];
@@ -680,7 +746,7 @@ __device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, bool
         const Side lo{inc.lo.ez[v], inc.lo.hx[v], inc.lo.hy[v], inc.lo.na[v], inc.lo.nb[v]};
         const Side hi{inc.hi.ez[v], inc.hi.hx[v], inc.hi.hy[v], inc.hi.na[v], inc.hi.nb[v]};
         NodeData res;
-        neq_core<STRIP>(L, i, r, m, eps, eps_rest, o, l, rr, b, t, lo, hi, einc, res);
+        neq_core<STRIP>(L, i, r, m, inv_eps, eps_rest, o, l, rr, b, t, lo, hi, einc, res);
         out.ez[v] = res.ez;
         out.hx[v] = res.hx;
         out.hy[v] = res.hy;
@@ -698,16 +764,31 @@ __device__ __forceinline__ void round_row(RowData<V> &r)
         for (int v = 0; v < V; ++v) r.n[q][v] = rt<NeqT>(r.n[q][v]);
 }
 
-template <typename NeqT, int V>
-__device__ __forceinline__ void store_row(const Lattice &L, float *DF, NeqT *DN, size_t cf, size_t cn,
-                                          const RowData<V> &o)
+// Zeros for nodes that hold nothing (conductors; padding past nx), as the
+// one-step kernels leave them.
+template <int V>
+__device__ __forceinline__ void mask_row(const Lattice &L, int i0, typename MaskVec<V>::type mv, bool strip,
+                                         RowData<V> &o)
 {
-    const size_t P = L.plane;
-    vstore<float, V>(DF + cf, o.ez, L.stream_stores);
-    vstore<float, V>(DF + P + cf, o.hx, L.stream_stores);
-    vstore<float, V>(DF + 2 * P + cf, o.hy, L.stream_stores);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) vstore<NeqT, V>(DN + q * P + cn, o.n[q], L.stream_stores);
+    for (int v = 0; v < V; ++v) {
+        const bool keep = i0 + v < L.nx && (strip || ((mv >> (8 * v)) & 3) != MAT_PEC);
+        o.ez[v] = keep ? o.ez[v] : 0.0f;
+        o.hx[v] = keep ? o.hx[v] : 0.0f;
+        o.hy[v] = keep ? o.hy[v] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) o.n[q][v] = keep ? o.n[q][v] : 0.0f;
+    }
+}
+
+template <typename NeqT, int V>
+__device__ __forceinline__ void store_row_at(float *Fr, unsigned P, unsigned col, const RowData<V> &o, bool stream)
+{
+    vstore<float, V>(byte_at<float>(Fr, f_off<NeqT>(P, 0, col)), o.ez, stream);
+    vstore<float, V>(byte_at<float>(Fr, f_off<NeqT>(P, 1, col)), o.hx, stream);
+    vstore<float, V>(byte_at<float>(Fr, f_off<NeqT>(P, 2, col)), o.hy, stream);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) vstore<NeqT, V>(byte_at<NeqT>(Fr, n_off<NeqT>(P, q, col)), o.n[q], stream);
 }
 
 template <int V> constexpr int two_step_halo() { return V < 2 ? 2 : V; }
@@ -715,7 +796,7 @@ template <int V> constexpr int two_step_width() { return 64 * V - 2 * two_step_h
 
 constexpr int TWO_STEP_WAVES = 4;  // independent wavefronts per block
 
-template <typename NeqT, int V, int H>
+template <typename NeqT, int V, int H, int D>
 __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, const void *__restrict__ srcv,
                                                                     void *__restrict__ dstv, float einc0, float einc1,
                                                                     int nsx, int nsy)
@@ -725,7 +806,8 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
     typedef typename MaskVec<V>::type MaskT;
     const int nb = gridDim.x;
     const int b = L.stream_stores ? (int)blockIdx.x : xcd_tile(blockIdx.x, nb);
-    const int w = b * TWO_STEP_WAVES + (int)threadIdx.y;
+    // wave-uniform work item (held in scalar registers)
+    const int w = __builtin_amdgcn_readfirstlane(b * TWO_STEP_WAVES + (int)threadIdx.y);
     if (w >= nsx * nsy) return;  // whole wavefront
     const int sx = w / nsy, sy = w % nsy;
     const int x0 = sx * OW, j0 = sy * H;
@@ -739,13 +821,18 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
     const NeqT *N = reinterpret_cast<const NeqT *>(F + 3 * P);
     float *DF = reinterpret_cast<float *>(dstv);
     NeqT *DN = reinterpret_cast<NeqT *>(DF + 3 * P);
+    // Rows are loaded without a branch, from a clamped (always valid)
+    // address, so the look-ahead loads stay in straight-line code ahead of
+    // the arithmetic.  What a lane loads for a row or column outside the
+    // domain is never used: row_update skips such nodes, and domain-edge
+    // nodes take their edge rules instead of the outside neighbour.
+    // Addresses: a wave-uniform row base plus a 32-bit lane offset.
+    const unsigned Pu = (unsigned)P;
+    const unsigned ic = (unsigned)(min(max(i0, 0), L.nx - 1) / V * V);
     auto load = [&](int r, RowData<V> &d, MaskT &m) {
-        zero_row(d);
-        m = 0;
-        if (act && r >= 0 && r < L.ny) {
-            load_row<NeqT, V>(F, N, P, at(i0, r, L.sf), at(i0, r, L.sn), d);
-            m = *reinterpret_cast<const MaskT *>(L.mask + node(L, i0, r));
-        }
+        const int rc = min(max(r, 0), L.ny - 1);
+        load_row_at<NeqT, V>(F + (size_t)rc * L.sf, Pu, ic, d);
+        m = *byte_at<MaskT>(L.mask + (size_t)rc * L.pitch, ic);
     };
 
     // companion row at n and n + 1 where rows 0 or ny - 1 are updated here
@@ -753,8 +840,8 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
     if (j0 <= 1 || j0 + H >= L.ny - 1) {
         RowData<V> c0, c1;
         zero_row(c0);
-        if (act) load_row<NeqT, V>(F, N, P, at(i0, L.ny, L.sf), at(i0, L.ny, L.sn), c0);
-        row_update<NeqT, V, true>(L, i0, L.ny, act, 0, c0, SideRow<V>{}, SideRow<V>{}, StripSides<V>{}, einc0, c1);
+        load_row_at<NeqT, V>(F + (size_t)L.ny * L.sf, Pu, ic, c0);
+        row_update<NeqT, V, true>(L, i0, L.ny, 0, c0, SideRow<V>{}, SideRow<V>{}, StripSides<V>{}, einc0, c1);
         round_row<NeqT, V>(c1);
         s0.lo = side_of(c0, N_EPY, N_HYPY);
         s0.hi = side_of(c0, N_EMY, N_HYMY);
@@ -762,39 +849,47 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
         s1.hi = side_of(c1, N_EMY, N_HYMY);
         if (j0 == 0) {
             RowData<V> c2;
-            row_update<NeqT, V, true>(L, i0, L.ny, act, 0, c1, SideRow<V>{}, SideRow<V>{}, StripSides<V>{}, einc1, c2);
-            if (out_lane) store_row<NeqT, V>(L, DF, DN, at(i0, L.ny, L.sf), at(i0, L.ny, L.sn), c2);
+            row_update<NeqT, V, true>(L, i0, L.ny, 0, c1, SideRow<V>{}, SideRow<V>{}, StripSides<V>{}, einc1, c2);
+            mask_row<V>(L, i0, 0, true, c2);
+            if (out_lane)
+                store_row_at<NeqT, V>(DF + (size_t)L.ny * L.sf, Pu, (unsigned)i0, c2, L.stream_stores);
         }
     }
 
-    // rows at n: below (side), cur, above, next (in flight); rows at n + 1: below (side), cur
-    RowData<V> a_cur, a_top, tmp;
-    MaskT m_cur, m_top, m_prev = 0, m_dummy;
+    // rows at n: below (side), cur, above, and D rows ahead (the newest in
+    // flight); rows at n + 1: below (side), cur
+    RowData<V> a_cur, a_top, tmp, ahead[D];
+    MaskT m_cur, m_top, m_prev = 0, m_dummy, m_ahead[D];
     load(j0 - 2, tmp, m_dummy);
     SideRow<V> a_bot = side_of(tmp, N_EPY, N_HYPY);
     load(j0 - 1, a_cur, m_cur);
     load(j0, a_top, m_top);
+#pragma unroll
+    for (int d = 0; d + 1 < D; ++d) load(j0 + 1 + d, ahead[d], m_ahead[d]);
     SideRow<V> b_bot{};
     RowData<V> b_cur;
     zero_row(b_cur);
+#pragma unroll
     for (int k = 0; k < H + 2; ++k) {
         const int r1 = j0 - 1 + k;
-        RowData<V> a_nxt;
-        MaskT m_nxt;
-        if (k <= H) load(r1 + 2, a_nxt, m_nxt);
-        else { zero_row(a_nxt); m_nxt = 0; }
+        // the last row a step-1 row needs is j0 + H + 1
+        if (k <= H + 1 - D) load(r1 + 1 + D, ahead[D - 1], m_ahead[D - 1]);
+        else { ahead[D - 1] = D > 1 ? ahead[D > 1 ? D - 2 : 0] : a_top; m_ahead[D - 1] = m_top; }
+        // keep the look-ahead loads here, ahead of this row's arithmetic (the
+        // scheduler would otherwise sink them next to their first use)
+        __builtin_amdgcn_sched_barrier(0);
         // step n -> n + 1 on row r1
         RowData<V> b_top;
-        row_update<NeqT, V, false>(L, i0, r1, act, m_cur, a_cur, a_bot, side_of(a_top, N_EMY, N_HYMY), s0, einc0,
-                                   b_top);
+        row_update<NeqT, V, false>(L, i0, r1, m_cur, a_cur, a_bot, side_of(a_top, N_EMY, N_HYMY), s0, einc0, b_top);
         round_row<NeqT, V>(b_top);
         // step n + 1 -> n + 2 on row r1 - 1
         if (k >= 2) {
             const int r2 = r1 - 1;
             RowData<V> o;
-            row_update<NeqT, V, false>(L, i0, r2, act, m_prev, b_cur, b_bot, side_of(b_top, N_EMY, N_HYMY), s1,
-                                       einc1, o);
-            if (out_lane && r2 < L.ny) store_row<NeqT, V>(L, DF, DN, at(i0, r2, L.sf), at(i0, r2, L.sn), o);
+            row_update<NeqT, V, false>(L, i0, r2, m_prev, b_cur, b_bot, side_of(b_top, N_EMY, N_HYMY), s1, einc1, o);
+            mask_row<V>(L, i0, m_prev, false, o);
+            if (out_lane && r2 < L.ny)
+                store_row_at<NeqT, V>(DF + (size_t)r2 * L.sf, Pu, (unsigned)i0, o, L.stream_stores);
         }
         b_bot = side_of(b_cur, N_EPY, N_HYPY);
         b_cur = b_top;
@@ -802,8 +897,13 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
         a_bot = side_of(a_cur, N_EPY, N_HYPY);
         a_cur = a_top;
         m_cur = m_top;
-        a_top = a_nxt;
-        m_top = m_nxt;
+        a_top = ahead[0];
+        m_top = m_ahead[0];
+#pragma unroll
+        for (int d = 0; d + 1 < D; ++d) {
+            ahead[d] = ahead[d + 1];
+            m_ahead[d] = m_ahead[d + 1];
+        }
     }
 }
 
@@ -1021,7 +1121,7 @@ __global__ __launch_bounds__(EN_THREADS) void k_energy_partial(Lattice L, const 
             if (mat == MAT_PEC) continue;
             const size_t c = at(i, j, L.sfld);
             const double ez = fld[c], hx = fld[P + c], hy = fld[2 * P + c];
-            s += 0.5 * (L.eps[mat] * ez * ez + hx * hx + hy * hy);
+            s += 0.5 * (mat_eps(L, mat) * ez * ez + hx * hx + hy * hy);
         }
     }
     s = wave_sum(s);
@@ -1108,30 +1208,30 @@ hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, vo
                             hipStream_t s, int variant)
 {
     const float e0 = (float)einc0, e1 = (float)einc1;
-    auto go = [&](auto tag, auto vtag, auto htag) {
+    auto go = [&](auto tag, auto vtag, auto htag, auto dtag) {
         typedef decltype(tag) T;
-        constexpr int V = decltype(vtag)::value, H = decltype(htag)::value;
+        constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, D = decltype(dtag)::value;
         const int nsx = (L.nx + two_step_width<V>() - 1) / two_step_width<V>();
         const int nsy = (L.ny + H - 1) / H;
         const int blocks = (nsx * nsy + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
-        hipLaunchKernelGGL((k_step2_neq<T, V, H>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src, dst, e0, e1,
-                           nsx, nsy);
+        hipLaunchKernelGGL((k_step2_neq<T, V, H, D>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src, dst, e0,
+                           e1, nsx, nsy);
     };
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
-    using I4 = std::integral_constant<int, 4>;
     using H8 = std::integral_constant<int, 8>;
     using H16 = std::integral_constant<int, 16>;
     using H32 = std::integral_constant<int, 32>;
+    using H64 = std::integral_constant<int, 64>;
     auto pick = [&](auto tag) {
         switch (variant) {
-        case TWO_V1_H8: go(tag, I1{}, H8{}); break;
-        case TWO_V1_H16: go(tag, I1{}, H16{}); break;
-        case TWO_V2_H8: go(tag, I2{}, H8{}); break;
-        case TWO_V2_H16: go(tag, I2{}, H16{}); break;
-        case TWO_V2_H32: go(tag, I2{}, H32{}); break;
-        case TWO_V4_H16: go(tag, I4{}, H16{}); break;
-        default: go(tag, I4{}, H32{}); break;
+        case TWO_V1_H8_D1: go(tag, I1{}, H8{}, I1{}); break;
+        case TWO_V1_H16_D1: go(tag, I1{}, H16{}, I1{}); break;
+        case TWO_V2_H8_D1: go(tag, I2{}, H8{}, I1{}); break;
+        case TWO_V2_H16_D1: go(tag, I2{}, H16{}, I1{}); break;
+        case TWO_V2_H16_D2: go(tag, I2{}, H16{}, I2{}); break;
+        case TWO_V2_H32_D1: go(tag, I2{}, H32{}, I1{}); break;
+        default: go(tag, I2{}, H64{}, I1{}); break;
         }
     };
     if (precision == 1) pick(float{});

@@ -292,6 +292,7 @@ Lattice lattice_of(const Plan &q, const uint8_t *dmask)
     for (int k = 0; k < 4; ++k) {
         L.eps[k] = q.eps[k];
         L.eps_rest[k] = q.eps[k] - 2.0 / 3.0;
+        L.inv_eps[k] = 1.0 / q.eps[k];
     }
     L.stream_stores = 2 * q.state_bytes > CACHE_RESIDENT_BYTES ? 1 : 0;
     return L;

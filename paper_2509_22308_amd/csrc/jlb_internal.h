@@ -49,6 +49,7 @@ struct Lattice {
     const uint8_t *mask;  // [ny][pitch]
     double eps[4];        // permittivity per material id (id 3 unused)
     double eps_rest[4];   // eps - 2/3: coefficient of Ez in the rest e-population's equilibrium
+    double inv_eps[4];    // 1 / eps (the FP32 / BF16 update multiplies by it)
     int stream_stores;    // 1: write the next state past the caches (state larger than the Infinity Cache)
     int pad;
 };
@@ -88,15 +89,16 @@ hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, voi
                            int variant);
 // Two steps per launch (FP32 / BF16): state n in src -> state n + 2 in dst
 // (src and dst must differ); einc0 / einc1 are the source values of steps n
-// and n + 1.  Variants: V adjacent nodes per lane, H rows per wavefront.
+// and n + 1.  Variants: V adjacent nodes per lane, H rows per wavefront, D
+// rows of look-ahead loads in flight.
 enum TwoStepVariant {
-    TWO_V1_H8 = 0,
-    TWO_V1_H16 = 1,
-    TWO_V2_H8 = 2,
-    TWO_V2_H16 = 3,
-    TWO_V2_H32 = 4,
-    TWO_V4_H16 = 5,
-    TWO_V4_H32 = 6,
+    TWO_V1_H8_D1 = 0,
+    TWO_V1_H16_D1 = 1,
+    TWO_V2_H8_D1 = 2,
+    TWO_V2_H16_D1 = 3,
+    TWO_V2_H16_D2 = 4,
+    TWO_V2_H32_D1 = 5,
+    TWO_V2_H64_D1 = 6,
     TWO_STEP_VARIANTS = 7
 };
 hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, void *dst, double einc0, double einc1,
