@@ -190,9 +190,9 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * bit.  A solve uses the selected two-step variant for the steps outside the
  * averaging window that run in graph-captured periods, and single steps for
  * the ramp and the window.  Variants (V adjacent nodes per lane, H rows per
- * wavefront, D rows of loads in flight ahead of the arithmetic): 0 V1 H8 D1,
- * 1 V1 H16 D1, 2 V2 H8 D1, 3 V2 H16 D1, 4 V2 H16 D2, 5 V2 H32 D1,
- * 6 V2 H64 D1.  Default: off (-1).
+ * wavefront, HX halo columns per side; HX 8 keeps output strips 64-byte
+ * aligned): 0 V1 H8 X2, 1 V1 H16 X2, 2 V2 H8 X2, 3 V2 H16 X2, 4 V1 H8 X8,
+ * 5 V2 H16 X8, 6 V2 H32 X8.  Default: off (-1).
  *
  * jlb_autotune times every single-step variant of prob->precision on prob's
  * grid (`launches` timed launches each, after 2 warm-up launches; workspace

@@ -186,9 +186,9 @@ def jlb_time_step_kernel(prob: jlb_problem, warmup: int, launches: int, workspac
 STEP_VARIANTS = {0: "direct 64x4", 1: "2-wide tile 64x4", 2: "4-wide tile 64x4", 3: "2-wide tile 256x1",
                  4: "4-wide tile 256x1", 5: "2-wide tile 256x2", 6: "4-wide tile 256x2"}
 FP64_STEP_VARIANTS = {0: "direct 64x4", 1: "direct 256x1", 2: "direct 256x2"}
-TWO_STEP_VARIANTS = {0: "two-step V1 H8 D1", 1: "two-step V1 H16 D1", 2: "two-step V2 H8 D1",
-                     3: "two-step V2 H16 D1", 4: "two-step V2 H16 D2", 5: "two-step V2 H32 D1",
-                     6: "two-step V2 H64 D1"}
+TWO_STEP_VARIANTS = {0: "two-step V1 H8 X2", 1: "two-step V1 H16 X2", 2: "two-step V2 H8 X2",
+                     3: "two-step V2 H16 X2", 4: "two-step V1 H8 X8", 5: "two-step V2 H16 X8",
+                     6: "two-step V2 H32 X8"}
 
 
 def variant_name(precision, best: int) -> str:

@@ -791,25 +791,34 @@ __device__ __forceinline__ void store_row_at(float *Fr, unsigned P, unsigned col
     for (int q = 0; q < 8; ++q) vstore<NeqT, V>(byte_at<NeqT>(Fr, n_off<NeqT>(P, q, col)), o.n[q], stream);
 }
 
-template <int V> constexpr int two_step_halo() { return V < 2 ? 2 : V; }
-template <int V> constexpr int two_step_width() { return 64 * V - 2 * two_step_halo<V>(); }
+// A wavefront covers 64 V columns: HX halo columns at each side (at least
+// the 2 that two updates need; more keep the output strip aligned to 64
+// bytes, which matters when the state streams to HBM) and 64 V - 2 HX
+// output columns.
+template <int V, int HX> constexpr int two_step_width() { return 64 * V - 2 * HX; }
 
 constexpr int TWO_STEP_WAVES = 4;  // independent wavefronts per block
 
-template <typename NeqT, int V, int H, int D>
+template <typename NeqT, int V, int H, int HX>
 __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, const void *__restrict__ srcv,
                                                                     void *__restrict__ dstv, float einc0, float einc1,
                                                                     int nsx, int nsy)
 {
-    constexpr int HX = two_step_halo<V>();
-    constexpr int OW = two_step_width<V>();
+    constexpr int D = 1;  // rows of look-ahead loads in flight
+    constexpr int OW = two_step_width<V, HX>();
+    static_assert(HX >= 2 && HX % V == 0 && OW > 0, "two-step strip shape");
     typedef typename MaskVec<V>::type MaskT;
+    // Work order.  A cache-resident state: the segments of one strip follow
+    // each other and each XCD takes a contiguous range (the seam rows that
+    // neighbouring segments share stay in one L2).  A state streamed from
+    // HBM: the strips of one band of rows run side by side, so the rows in
+    // flight are whole lattice rows (DRAM page locality).
     const int nb = gridDim.x;
     const int b = L.stream_stores ? (int)blockIdx.x : xcd_tile(blockIdx.x, nb);
     // wave-uniform work item (held in scalar registers)
     const int w = __builtin_amdgcn_readfirstlane(b * TWO_STEP_WAVES + (int)threadIdx.y);
     if (w >= nsx * nsy) return;  // whole wavefront
-    const int sx = w / nsy, sy = w % nsy;
+    const int sx = L.stream_stores ? w % nsx : w / nsy, sy = L.stream_stores ? w / nsx : w % nsy;
     const int x0 = sx * OW, j0 = sy * H;
     const int lane = threadIdx.x;
     const int i0 = x0 - HX + V * lane;
@@ -1208,13 +1217,13 @@ hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, vo
                             hipStream_t s, int variant)
 {
     const float e0 = (float)einc0, e1 = (float)einc1;
-    auto go = [&](auto tag, auto vtag, auto htag, auto dtag) {
+    auto go = [&](auto tag, auto vtag, auto htag, auto xtag) {
         typedef decltype(tag) T;
-        constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, D = decltype(dtag)::value;
-        const int nsx = (L.nx + two_step_width<V>() - 1) / two_step_width<V>();
+        constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
+        const int nsx = (L.nx + two_step_width<V, HX>() - 1) / two_step_width<V, HX>();
         const int nsy = (L.ny + H - 1) / H;
         const int blocks = (nsx * nsy + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
-        hipLaunchKernelGGL((k_step2_neq<T, V, H, D>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src, dst, e0,
+        hipLaunchKernelGGL((k_step2_neq<T, V, H, HX>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src, dst, e0,
                            e1, nsx, nsy);
     };
     using I1 = std::integral_constant<int, 1>;
@@ -1222,16 +1231,17 @@ hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, vo
     using H8 = std::integral_constant<int, 8>;
     using H16 = std::integral_constant<int, 16>;
     using H32 = std::integral_constant<int, 32>;
-    using H64 = std::integral_constant<int, 64>;
+    using X2 = std::integral_constant<int, 2>;
+    using X8 = std::integral_constant<int, 8>;
     auto pick = [&](auto tag) {
         switch (variant) {
-        case TWO_V1_H8_D1: go(tag, I1{}, H8{}, I1{}); break;
-        case TWO_V1_H16_D1: go(tag, I1{}, H16{}, I1{}); break;
-        case TWO_V2_H8_D1: go(tag, I2{}, H8{}, I1{}); break;
-        case TWO_V2_H16_D1: go(tag, I2{}, H16{}, I1{}); break;
-        case TWO_V2_H16_D2: go(tag, I2{}, H16{}, I2{}); break;
-        case TWO_V2_H32_D1: go(tag, I2{}, H32{}, I1{}); break;
-        default: go(tag, I2{}, H64{}, I1{}); break;
+        case TWO_V1_H8_X2: go(tag, I1{}, H8{}, X2{}); break;
+        case TWO_V1_H16_X2: go(tag, I1{}, H16{}, X2{}); break;
+        case TWO_V2_H8_X2: go(tag, I2{}, H8{}, X2{}); break;
+        case TWO_V2_H16_X2: go(tag, I2{}, H16{}, X2{}); break;
+        case TWO_V1_H8_X8: go(tag, I1{}, H8{}, X8{}); break;
+        case TWO_V2_H16_X8: go(tag, I2{}, H16{}, X8{}); break;
+        default: go(tag, I2{}, H32{}, X8{}); break;
         }
     };
     if (precision == 1) pick(float{});

@@ -89,16 +89,17 @@ hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, voi
                            int variant);
 // Two steps per launch (FP32 / BF16): state n in src -> state n + 2 in dst
 // (src and dst must differ); einc0 / einc1 are the source values of steps n
-// and n + 1.  Variants: V adjacent nodes per lane, H rows per wavefront, D
-// rows of look-ahead loads in flight.
+// and n + 1.  Variants: V adjacent nodes per lane, H rows per wavefront, HX
+// halo columns at each side of a wavefront's strip (8 keeps the output
+// strips 64-byte aligned).
 enum TwoStepVariant {
-    TWO_V1_H8_D1 = 0,
-    TWO_V1_H16_D1 = 1,
-    TWO_V2_H8_D1 = 2,
-    TWO_V2_H16_D1 = 3,
-    TWO_V2_H16_D2 = 4,
-    TWO_V2_H32_D1 = 5,
-    TWO_V2_H64_D1 = 6,
+    TWO_V1_H8_X2 = 0,
+    TWO_V1_H16_X2 = 1,
+    TWO_V2_H8_X2 = 2,
+    TWO_V2_H16_X2 = 3,
+    TWO_V1_H8_X8 = 4,
+    TWO_V2_H16_X8 = 5,
+    TWO_V2_H32_X8 = 6,
     TWO_STEP_VARIANTS = 7
 };
 hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, void *dst, double einc0, double einc1,
