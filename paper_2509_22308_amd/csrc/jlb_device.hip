@@ -802,7 +802,7 @@ constexpr int TWO_STEP_WAVES = 4;  // independent wavefronts per block
 template <typename NeqT, int V, int H, int HX>
 __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, const void *__restrict__ srcv,
                                                                     void *__restrict__ dstv, float einc0, float einc1,
-                                                                    int nsx, int nsy)
+                                                                    float *__restrict__ mid, int nsx, int nsy)
 {
     constexpr int D = 1;  // rows of look-ahead loads in flight
     constexpr int OW = two_step_width<V, HX>();
@@ -891,6 +891,17 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
         RowData<V> b_top;
         row_update<NeqT, V, false>(L, i0, r1, m_cur, a_cur, a_bot, side_of(a_top, N_EMY, N_HYMY), s0, einc0, b_top);
         round_row<NeqT, V>(b_top);
+        // fields at n + 1 of the contour-stencil nodes of this strip's rows
+        if (mid && out_lane && r1 >= j0 && r1 < j0 + H && r1 < L.ny) {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if ((m_cur >> (8 * v)) & MASK_CONTOUR) {
+                    float *f = mid + (size_t)r1 * 3 * P + i0 + v;
+                    f[0] = b_top.ez[v];
+                    f[P] = b_top.hx[v];
+                    f[2 * P] = b_top.hy[v];
+                }
+        }
         // step n + 1 -> n + 2 on row r1 - 1
         if (k >= 2) {
             const int r2 = r1 - 1;
@@ -1002,13 +1013,13 @@ __device__ __forceinline__ void contour_sample_f64(const Lattice &L, const doubl
     C.acc[3 * C.n + k] += v[1] * v[2];
 }
 
-__device__ __forceinline__ void contour_sample_f32(const Lattice &L, const float *__restrict__ fld,
+__device__ __forceinline__ void contour_sample_f32(const Lattice &L, const float *__restrict__ fld, size_t stride,
                                                    const ContourDev &C, int k)
 {
 #pragma clang fp contract(off)
     const size_t P = L.plane;
-    const size_t c00 = at(C.i0[k], C.j0[k], L.sfld);
-    const size_t c10 = c00 + L.sfld;
+    const size_t c00 = at(C.i0[k], C.j0[k], stride);
+    const size_t c10 = c00 + stride;
     const float fx = (float)C.wx[k], fy = (float)C.wy[k];
     const float w00 = (1.0f - fx) * (1.0f - fy), w01 = fx * (1.0f - fy), w10 = (1.0f - fx) * fy, w11 = fx * fy;
     float v[3];
@@ -1032,7 +1043,18 @@ __global__ void k_contour_f64(Lattice L, const double *__restrict__ fld, Contour
 __global__ void k_contour_f32(Lattice L, const float *__restrict__ fld, ContourDev C)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < C.n) contour_sample_f32(L, fld, C, k);
+    if (k < C.n) contour_sample_f32(L, fld, L.sfld, C, k);
+}
+
+// Two consecutive levels: the middle level of a two-step launch (fields of
+// the stencil nodes in mid), then the level it ended on (the state).
+__global__ void k_contour2_f32(Lattice L, const float *__restrict__ mid, const float *__restrict__ fld, ContourDev C)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < C.n) {
+        contour_sample_f32(L, mid, 3 * L.plane, C, k);
+        contour_sample_f32(L, fld, L.sfld, C, k);
+    }
 }
 
 // Batched contour accumulation: block row s serves solve s when the step it
@@ -1045,7 +1067,7 @@ __global__ void k_contour_batch(SolveDesc *__restrict__ D)
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.C.n) return;
     if (d.precision == 0) contour_sample_f64(d.L, d.fields, d.C, k);
-    else contour_sample_f32(d.L, reinterpret_cast<const float *>(d.state[(n + 1) & 1]), d.C, k);
+    else contour_sample_f32(d.L, reinterpret_cast<const float *>(d.state[(n + 1) & 1]), d.L.sfld, d.C, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -1214,7 +1236,7 @@ hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, voi
 }
 
 hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, void *dst, double einc0, double einc1,
-                            hipStream_t s, int variant)
+                            float *mid, hipStream_t s, int variant)
 {
     const float e0 = (float)einc0, e1 = (float)einc1;
     auto go = [&](auto tag, auto vtag, auto htag, auto xtag) {
@@ -1224,7 +1246,7 @@ hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, vo
         const int nsy = (L.ny + H - 1) / H;
         const int blocks = (nsx * nsy + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
         hipLaunchKernelGGL((k_step2_neq<T, V, H, HX>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src, dst, e0,
-                           e1, nsx, nsy);
+                           e1, mid, nsx, nsy);
     };
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
@@ -1257,6 +1279,14 @@ hipError_t launch_contour(int precision, const Lattice &L, const void *fields, c
         hipLaunchKernelGGL(k_contour_f64, dim3(blocks), dim3(threads), 0, s, L, (const double *)fields, C);
     else
         hipLaunchKernelGGL(k_contour_f32, dim3(blocks), dim3(threads), 0, s, L, (const float *)fields, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_contour2(const Lattice &L, const float *mid, const void *state, const ContourDev &C, hipStream_t s)
+{
+    const int threads = 128;
+    const int blocks = (C.n + threads - 1) / threads;
+    hipLaunchKernelGGL(k_contour2_f32, dim3(blocks), dim3(threads), 0, s, L, mid, (const float *)state, C);
     return hipGetLastError();
 }
 

@@ -131,6 +131,9 @@ int make_plan(const jlb_problem *p, Plan *pl)
     // FP64: field planes for two time levels, by parity (a launch that writes
     // level n + 1 leaves level n intact)
     q.off_fields = p->precision == JLB_FP64 ? take(2 * 3 * q.plane * sizeof(double)) : 0;
+    // FP32 / BF16: fields at the middle level of a two-step launch, written
+    // only at the contour-stencil nodes
+    q.off_mid = p->precision == JLB_FP64 ? 0 : take((size_t)3 * q.pitch * q.ny * sizeof(float));
     q.off_mask = take((size_t)q.ny * q.pitch);
     q.off_i0 = take(q.nc * sizeof(int));
     q.off_j0 = take(q.nc * sizeof(int));
@@ -319,6 +322,9 @@ int upload_setup(const Plan &q, char *ws, hipStream_t s)
     build_mask(q, mask);
     ContourHost ch;
     build_contour(q, ch);
+    for (int k = 0; k < q.nc; ++k)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) mask[(size_t)(ch.j0[k] + dj) * q.pitch + ch.i0[k] + di] |= MASK_CONTOUR;
     HIP_TRY(hipMemcpyAsync(ws + q.off_mask, mask.data(), mask.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(ws + q.off_i0, ch.i0.data(), q.nc * sizeof(int), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(ws + q.off_j0, ch.j0.data(), q.nc * sizeof(int), hipMemcpyHostToDevice, s));
@@ -392,13 +398,18 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     auto capture = [&](int which, int64_t n0) -> int {
         hipGraph_t g;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        if (which == 0 && two >= 0) {
-            // launch m takes state n0 + 2m from buffer (n0 + m) % 2 to the other one
+        if (two >= 0) {
+            // launch m takes state n0 + 2m from buffer (n0 + m) % 2 to the
+            // other one; inside the window it also leaves the contour-stencil
+            // fields of level n0 + 2m + 1 in mid, and both levels are
+            // accumulated after it
+            float *mid = (float *)(ws + q.off_mid);
             for (int64_t m = 0; m < chunk / 2; ++m) {
                 const int64_t n = n0 + 2 * m;
-                hipError_t e = launch_step2_neq(q.prob.precision, L, ws + q.off_state[(n0 + m) & 1],
-                                                ws + q.off_state[(n0 + m + 1) & 1], incident(q, n), incident(q, n + 1),
-                                                s, two);
+                void *dst = ws + q.off_state[(n0 + m + 1) & 1];
+                hipError_t e = launch_step2_neq(q.prob.precision, L, ws + q.off_state[(n0 + m) & 1], dst,
+                                                incident(q, n), incident(q, n + 1), which == 1 ? mid : nullptr, s, two);
+                if (e == hipSuccess && which == 1) e = launch_contour2(L, mid, dst, C, s);
                 if (e != hipSuccess) {
                     hipGraph_t dummy;
                     (void)hipStreamEndCapture(s, &dummy);
@@ -445,7 +456,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
                 break;
             }
             graph_used = 1;
-            passes += which == 0 && two >= 0 ? chunk / 2 : chunk;
+            passes += two >= 0 ? chunk / 2 : chunk;
             n += chunk;
             continue;
         }
@@ -622,7 +633,7 @@ static int time_step_kernel(const jlb_problem *prob, void *workspace, size_t wor
         if (n == warmup && hipEventRecord(e0, own) != hipSuccess) rc = fail(JLB_E_DEVICE, "event record");
         hipError_t e = two ? launch_step2_neq(q.prob.precision, L, ws + q.off_state[n & 1],
                                               ws + q.off_state[(n + 1) & 1], incident(q, 2 * n), incident(q, 2 * n + 1),
-                                              own, variant)
+                                              nullptr, own, variant)
                            : launch_step(q, L, ws + q.off_state[n & 1], ws + q.off_state[(n + 1) & 1], nullptr,
                                          incident(q, n), own, variant);
         if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "step launch: %s", hipGetErrorString(e));

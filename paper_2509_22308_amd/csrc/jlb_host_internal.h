@@ -26,8 +26,8 @@ struct Plan {
     double eps[4];          // permittivity per material id
     size_t state_bytes;     // one state buffer
     int bytes_per_lup;      // algorithmic HBM bytes per lattice update
-    size_t off_state[2], off_fields, off_mask, off_i0, off_j0, off_wx, off_wy, off_nxk, off_nyk, off_acc, off_out,
-        off_parts;
+    size_t off_state[2], off_fields, off_mid, off_mask, off_i0, off_j0, off_wx, off_wy, off_nxk, off_nyk, off_acc,
+        off_out, off_parts;
     int nparts;
     size_t ws_bytes;
 };

@@ -18,6 +18,8 @@ enum : uint8_t {
     NB_PEC_YM = 1u << 4,  // node (i, j-1): affects the +y populations
     NB_PEC_YP = 1u << 5,  // node (i, j+1): affects the -y populations
 };
+// The node is a corner of some contour sample's bilinear stencil.
+enum : uint8_t { MASK_CONTOUR = 1u << 6 };
 
 // Relaxation of the scattered part of the zero-gradient open-edge
 // extrapolation (the entering population is I_ghost + (1 - delta)(f* - I)).
@@ -102,8 +104,13 @@ enum TwoStepVariant {
     TWO_V2_H32_X8 = 6,
     TWO_STEP_VARIANTS = 7
 };
+// mid (optional): the fields at n + 1 of the contour-stencil nodes are
+// written there (3 float planes, row-interleaved, row stride 3 pitch).
 hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, void *dst, double einc0, double einc1,
-                            hipStream_t s, int variant);
+                            float *mid, hipStream_t s, int variant);
+// Contour accumulation of two consecutive time levels: the fields in mid
+// (as written by a two-step launch), then those of the FP32 / BF16 state.
+hipError_t launch_contour2(const Lattice &L, const float *mid, const void *state, const ContourDev &C, hipStream_t s);
 // Fields: FP64 planes [3][plane] for precision 0, the FP32 field planes of the
 // state for precisions 1 and 2.
 hipError_t launch_contour(int precision, const Lattice &L, const void *fields, const ContourDev &C, hipStream_t s);
