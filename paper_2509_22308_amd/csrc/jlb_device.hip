@@ -804,7 +804,6 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
                                                                     void *__restrict__ dstv, float einc0, float einc1,
                                                                     float *__restrict__ mid, int nsx, int nsy)
 {
-    constexpr int D = 1;  // rows of look-ahead loads in flight
     constexpr int OW = two_step_width<V, HX>();
     static_assert(HX >= 2 && HX % V == 0 && OW > 0, "two-step strip shape");
     typedef typename MaskVec<V>::type MaskT;
@@ -865,66 +864,79 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
         }
     }
 
-    // rows at n: below (side), cur, above, and D rows ahead (the newest in
-    // flight); rows at n + 1: below (side), cur
-    RowData<V> a_cur, a_top, tmp, ahead[D];
-    MaskT m_cur, m_top, m_prev = 0, m_dummy, m_ahead[D];
-    load(j0 - 2, tmp, m_dummy);
-    SideRow<V> a_bot = side_of(tmp, N_EPY, N_HYPY);
-    load(j0 - 1, a_cur, m_cur);
-    load(j0, a_top, m_top);
+    // The sweep.  Consecutive row segments run in opposite directions, so the
+    // two segments next to a seam read its rows at the same moment (both at
+    // the start or both at the end of their sweeps) and the second read hits
+    // in L2.  DIR = +1 walks up the rows, -1 down; "behind" is the row the
+    // sweep came from, "ahead" the row it goes to.
+    auto sweep = [&](auto dir_tag) {
+        constexpr int DIR = decltype(dir_tag)::value;
+        // sides of the rows below / above a node, by the populations they feed
+        constexpr int BQA = DIR > 0 ? N_EPY : N_EMY, BQB = DIR > 0 ? N_HYPY : N_HYMY;  // behind
+        constexpr int AQA = DIR > 0 ? N_EMY : N_EPY, AQB = DIR > 0 ? N_HYMY : N_HYPY;  // ahead
+        const int first = DIR > 0 ? j0 - 1 : j0 + H;  // first row of step n -> n + 1
+        // rows at n: behind (side), cur, ahead (the next one in flight);
+        // rows at n + 1: behind (side), cur
+        RowData<V> a_cur, a_ahead, tmp;
+        MaskT m_cur, m_ahead, m_prev = 0, m_dummy;
+        load(first - DIR, tmp, m_dummy);
+        SideRow<V> a_behind = side_of(tmp, BQA, BQB);
+        load(first, a_cur, m_cur);
+        load(first + DIR, a_ahead, m_ahead);
+        SideRow<V> b_behind{};
+        RowData<V> b_cur;
+        zero_row(b_cur);
 #pragma unroll
-    for (int d = 0; d + 1 < D; ++d) load(j0 + 1 + d, ahead[d], m_ahead[d]);
-    SideRow<V> b_bot{};
-    RowData<V> b_cur;
-    zero_row(b_cur);
+        for (int k = 0; k < H + 2; ++k) {
+            const int r1 = first + DIR * k;
+            RowData<V> a_next;
+            MaskT m_next;
+            // the last row a step-1 row needs lies one past the segment's halo
+            if (k <= H) load(r1 + 2 * DIR, a_next, m_next);
+            else { a_next = a_ahead; m_next = m_ahead; }
+            // keep the look-ahead loads here, ahead of this row's arithmetic
+            // (the scheduler would otherwise sink them next to their first use)
+            __builtin_amdgcn_sched_barrier(0);
+            // step n -> n + 1 on row r1
+            RowData<V> b_new;
+            const SideRow<V> a_side = side_of(a_ahead, AQA, AQB);
+            row_update<NeqT, V, false>(L, i0, r1, m_cur, a_cur, DIR > 0 ? a_behind : a_side,
+                                       DIR > 0 ? a_side : a_behind, s0, einc0, b_new);
+            round_row<NeqT, V>(b_new);
+            // fields at n + 1 of the contour-stencil nodes of this segment's rows
+            if (mid && out_lane && r1 >= j0 && r1 < j0 + H && r1 < L.ny) {
 #pragma unroll
-    for (int k = 0; k < H + 2; ++k) {
-        const int r1 = j0 - 1 + k;
-        // the last row a step-1 row needs is j0 + H + 1
-        if (k <= H + 1 - D) load(r1 + 1 + D, ahead[D - 1], m_ahead[D - 1]);
-        else { ahead[D - 1] = D > 1 ? ahead[D > 1 ? D - 2 : 0] : a_top; m_ahead[D - 1] = m_top; }
-        // keep the look-ahead loads here, ahead of this row's arithmetic (the
-        // scheduler would otherwise sink them next to their first use)
-        __builtin_amdgcn_sched_barrier(0);
-        // step n -> n + 1 on row r1
-        RowData<V> b_top;
-        row_update<NeqT, V, false>(L, i0, r1, m_cur, a_cur, a_bot, side_of(a_top, N_EMY, N_HYMY), s0, einc0, b_top);
-        round_row<NeqT, V>(b_top);
-        // fields at n + 1 of the contour-stencil nodes of this strip's rows
-        if (mid && out_lane && r1 >= j0 && r1 < j0 + H && r1 < L.ny) {
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                if ((m_cur >> (8 * v)) & MASK_CONTOUR) {
-                    float *f = mid + (size_t)r1 * 3 * P + i0 + v;
-                    f[0] = b_top.ez[v];
-                    f[P] = b_top.hx[v];
-                    f[2 * P] = b_top.hy[v];
-                }
+                for (int v = 0; v < V; ++v)
+                    if ((m_cur >> (8 * v)) & MASK_CONTOUR) {
+                        float *f = mid + (size_t)r1 * 3 * P + i0 + v;
+                        f[0] = b_new.ez[v];
+                        f[P] = b_new.hx[v];
+                        f[2 * P] = b_new.hy[v];
+                    }
+            }
+            // step n + 1 -> n + 2 on the row behind r1
+            if (k >= 2) {
+                const int r2 = r1 - DIR;
+                RowData<V> o;
+                const SideRow<V> b_side = side_of(b_new, AQA, AQB);
+                row_update<NeqT, V, false>(L, i0, r2, m_prev, b_cur, DIR > 0 ? b_behind : b_side,
+                                           DIR > 0 ? b_side : b_behind, s1, einc1, o);
+                mask_row<V>(L, i0, m_prev, false, o);
+                if (out_lane && r2 < L.ny)
+                    store_row_at<NeqT, V>(DF + (size_t)r2 * L.sf, Pu, (unsigned)i0, o, L.stream_stores);
+            }
+            b_behind = side_of(b_cur, BQA, BQB);
+            b_cur = b_new;
+            m_prev = m_cur;
+            a_behind = side_of(a_cur, BQA, BQB);
+            a_cur = a_ahead;
+            m_cur = m_ahead;
+            a_ahead = a_next;
+            m_ahead = m_next;
         }
-        // step n + 1 -> n + 2 on row r1 - 1
-        if (k >= 2) {
-            const int r2 = r1 - 1;
-            RowData<V> o;
-            row_update<NeqT, V, false>(L, i0, r2, m_prev, b_cur, b_bot, side_of(b_top, N_EMY, N_HYMY), s1, einc1, o);
-            mask_row<V>(L, i0, m_prev, false, o);
-            if (out_lane && r2 < L.ny)
-                store_row_at<NeqT, V>(DF + (size_t)r2 * L.sf, Pu, (unsigned)i0, o, L.stream_stores);
-        }
-        b_bot = side_of(b_cur, N_EPY, N_HYPY);
-        b_cur = b_top;
-        m_prev = m_cur;
-        a_bot = side_of(a_cur, N_EPY, N_HYPY);
-        a_cur = a_top;
-        m_cur = m_top;
-        a_top = ahead[0];
-        m_top = m_ahead[0];
-#pragma unroll
-        for (int d = 0; d + 1 < D; ++d) {
-            ahead[d] = ahead[d + 1];
-            m_ahead[d] = m_ahead[d + 1];
-        }
-    }
+    };
+    if (sy & 1) sweep(std::integral_constant<int, -1>{});
+    else sweep(std::integral_constant<int, 1>{});
 }
 
 // ---------------------------------------------------------------------------
