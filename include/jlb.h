@@ -266,7 +266,9 @@ int jlb_engine_create(size_t budget_bytes, int32_t max_slots, void *stream, jlb_
 int jlb_engine_submit(jlb_engine *eng, const jlb_problem *prob, uint64_t *ticket);
 
 /* Admits queued requests that fit, then advances every resident solve by up to
- * `steps` lattice steps (one batched launch per step), retiring solves that
+ * `steps` lattice steps (rounded up to an even number: the engine works in
+ * double steps, one two-step launch for FP32 / BF16 solves when a two-step
+ * variant is selected, two single steps otherwise), retiring solves that
  * finish.  *active (host, optional) receives the resident count afterwards. */
 int jlb_engine_run(jlb_engine *eng, int64_t steps, int32_t *active);
 

@@ -799,25 +799,17 @@ template <int V, int HX> constexpr int two_step_width() { return 64 * V - 2 * HX
 
 constexpr int TWO_STEP_WAVES = 4;  // independent wavefronts per block
 
+// One wavefront's share of a two-step launch: strip sx, row segment sy.
+// With `one`, only the first step is taken and its result stored (a solve
+// with a single step left).
 template <typename NeqT, int V, int H, int HX>
-__global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, const void *__restrict__ srcv,
-                                                                    void *__restrict__ dstv, float einc0, float einc1,
-                                                                    float *__restrict__ mid, int nsx, int nsy)
+__device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__restrict__ srcv,
+                                              void *__restrict__ dstv, float einc0, float einc1,
+                                              float *__restrict__ mid, int sx, int sy, bool one)
 {
     constexpr int OW = two_step_width<V, HX>();
     static_assert(HX >= 2 && HX % V == 0 && OW > 0, "two-step strip shape");
     typedef typename MaskVec<V>::type MaskT;
-    // Work order.  A cache-resident state: the segments of one strip follow
-    // each other and each XCD takes a contiguous range (the seam rows that
-    // neighbouring segments share stay in one L2).  A state streamed from
-    // HBM: the strips of one band of rows run side by side, so the rows in
-    // flight are whole lattice rows (DRAM page locality).
-    const int nb = gridDim.x;
-    const int b = L.stream_stores ? (int)blockIdx.x : xcd_tile(blockIdx.x, nb);
-    // wave-uniform work item (held in scalar registers)
-    const int w = __builtin_amdgcn_readfirstlane(b * TWO_STEP_WAVES + (int)threadIdx.y);
-    if (w >= nsx * nsy) return;  // whole wavefront
-    const int sx = L.stream_stores ? w % nsx : w / nsy, sy = L.stream_stores ? w / nsx : w % nsy;
     const int x0 = sx * OW, j0 = sy * H;
     const int lane = threadIdx.x;
     const int i0 = x0 - HX + V * lane;
@@ -851,11 +843,16 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
         load_row_at<NeqT, V>(F + (size_t)L.ny * L.sf, Pu, ic, c0);
         row_update<NeqT, V, true>(L, i0, L.ny, 0, c0, SideRow<V>{}, SideRow<V>{}, StripSides<V>{}, einc0, c1);
         round_row<NeqT, V>(c1);
+        if (one && j0 == 0) {
+            RowData<V> c = c1;
+            mask_row<V>(L, i0, 0, true, c);
+            if (out_lane) store_row_at<NeqT, V>(DF + (size_t)L.ny * L.sf, Pu, (unsigned)i0, c, L.stream_stores);
+        }
         s0.lo = side_of(c0, N_EPY, N_HYPY);
         s0.hi = side_of(c0, N_EMY, N_HYMY);
         s1.lo = side_of(c1, N_EPY, N_HYPY);
         s1.hi = side_of(c1, N_EMY, N_HYMY);
-        if (j0 == 0) {
+        if (!one && j0 == 0) {
             RowData<V> c2;
             row_update<NeqT, V, true>(L, i0, L.ny, 0, c1, SideRow<V>{}, SideRow<V>{}, StripSides<V>{}, einc1, c2);
             mask_row<V>(L, i0, 0, true, c2);
@@ -903,6 +900,14 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
             row_update<NeqT, V, false>(L, i0, r1, m_cur, a_cur, DIR > 0 ? a_behind : a_side,
                                        DIR > 0 ? a_side : a_behind, s0, einc0, b_new);
             round_row<NeqT, V>(b_new);
+            if (one) {
+                // a single step: this row's result is the new state
+                if (out_lane && r1 >= j0 && r1 < j0 + H && r1 < L.ny) {
+                    RowData<V> o = b_new;
+                    mask_row<V>(L, i0, m_cur, false, o);
+                    store_row_at<NeqT, V>(DF + (size_t)r1 * L.sf, Pu, (unsigned)i0, o, L.stream_stores);
+                }
+            }
             // fields at n + 1 of the contour-stencil nodes of this segment's rows
             if (mid && out_lane && r1 >= j0 && r1 < j0 + H && r1 < L.ny) {
 #pragma unroll
@@ -915,7 +920,7 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
                     }
             }
             // step n + 1 -> n + 2 on the row behind r1
-            if (k >= 2) {
+            if (!one && k >= 2) {
                 const int r2 = r1 - DIR;
                 RowData<V> o;
                 const SideRow<V> b_side = side_of(b_new, AQA, AQB);
@@ -939,15 +944,57 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
     else sweep(std::integral_constant<int, 1>{});
 }
 
-// ---------------------------------------------------------------------------
-// Batched steps: block b works on tiles[b] of solve tiles[b].slot at that
-// solve's own step n (finished solves return at once).
-// ---------------------------------------------------------------------------
+template <typename NeqT, int V, int H, int HX>
+__global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, const void *__restrict__ srcv,
+                                                                    void *__restrict__ dstv, float einc0, float einc1,
+                                                                    float *__restrict__ mid, int nsx, int nsy)
+{
+    // Work order.  A cache-resident state: the segments of one strip follow
+    // each other and each XCD takes a contiguous range (the seam rows that
+    // neighbouring segments share stay in one L2).  A state streamed from
+    // HBM: the strips of one band of rows run side by side, so the rows in
+    // flight are whole lattice rows (DRAM page locality).
+    const int nb = gridDim.x;
+    const int b = L.stream_stores ? (int)blockIdx.x : xcd_tile(blockIdx.x, nb);
+    // wave-uniform work item (held in scalar registers)
+    const int w = __builtin_amdgcn_readfirstlane(b * TWO_STEP_WAVES + (int)threadIdx.y);
+    if (w >= nsx * nsy) return;  // whole wavefront
+    const int sx = L.stream_stores ? w % nsx : w / nsy, sy = L.stream_stores ? w / nsx : w % nsy;
+    two_step_wave<NeqT, V, H, HX>(L, srcv, dstv, einc0, einc1, mid, sx, sy, false);
+}
 
+// Source value of a batched solve at its step n (ramp table, then one period).
 __device__ __forceinline__ double batch_incident(const SolveDesc &d, int64_t n)
 {
     return n < d.ramp_end ? d.src_tab[n] : d.src_tab[d.ramp_end + n % d.T];
 }
+
+// Batched two-step launch: wavefront w takes items[w] (slot, strip, row
+// segment) of a resident solve at that solve's own step n.
+template <typename NeqT, int V, int H, int HX>
+__global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq_batch(SolveDesc *__restrict__ D,
+                                                                          const Tile *__restrict__ items, int nitems,
+                                                                          int remap)
+{
+    const int b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(b * TWO_STEP_WAVES + (int)threadIdx.y);
+    if (w >= nitems) return;
+    const Tile t = items[w];
+    const SolveDesc &d = D[t.slot];
+    const int64_t n = d.n;
+    if (n >= d.steps) return;
+    const bool one = d.steps - n == 1;
+    // middle-level fields are needed when level n + 1 is averaged and a
+    // second step follows
+    float *mid = !one && n + 1 > d.steps - d.window ? d.mid : nullptr;
+    two_step_wave<NeqT, V, H, HX>(d.L, d.state[d.cur], d.state[d.cur ^ 1], (float)batch_incident(d, n),
+                                  one ? 0.0f : (float)batch_incident(d, n + 1), mid, t.tx, t.ty, one);
+}
+
+// ---------------------------------------------------------------------------
+// Batched steps: block b works on tiles[b] of solve tiles[b].slot at that
+// solve's own step n (finished solves return at once).
+// ---------------------------------------------------------------------------
 
 template <int CX, int R>
 __global__ __launch_bounds__(CX *R) void k_step_f64_batch(SolveDesc *__restrict__ D, const Tile *__restrict__ tiles,
@@ -961,7 +1008,7 @@ __global__ __launch_bounds__(CX *R) void k_step_f64_batch(SolveDesc *__restrict_
     const int j = t.ty * R + threadIdx.y;
     if (i >= d.L.nx || j > d.L.ny) return;
     const bool in_window = n + 1 > d.steps - d.window;
-    f64_node(d.L, (const double *)d.state[n & 1], (double *)d.state[(n + 1) & 1], in_window ? d.fields : nullptr,
+    f64_node(d.L, (const double *)d.state[d.cur], (double *)d.state[d.cur ^ 1], in_window ? d.fields : nullptr,
              batch_incident(d, n), i, j);
 }
 
@@ -976,7 +1023,7 @@ __global__ __launch_bounds__(BX *BY) void k_step_neq_batch(SolveDesc *__restrict
     const int i = t.tx * BX + threadIdx.x;
     const int j = t.ty * BY + threadIdx.y;
     if (i >= d.L.nx || j > d.L.ny) return;
-    neq_direct_node<NeqT>(d.L, d.state[n & 1], d.state[(n + 1) & 1], (float)batch_incident(d, n), i, j);
+    neq_direct_node<NeqT>(d.L, d.state[d.cur], d.state[d.cur ^ 1], (float)batch_incident(d, n), i, j);
 }
 
 template <typename NeqT, int V, int CX, int R>
@@ -987,15 +1034,18 @@ __global__ __launch_bounds__(CX *R) void k_step_neq_vtile_batch(SolveDesc *__res
     const SolveDesc &d = D[t.slot];
     const int64_t n = d.n;
     if (n >= d.steps) return;
-    neq_vtile_row<NeqT, V>(d.L, d.state[n & 1], d.state[(n + 1) & 1], (float)batch_incident(d, n),
+    neq_vtile_row<NeqT, V>(d.L, d.state[d.cur], d.state[d.cur ^ 1], (float)batch_incident(d, n),
                            t.tx * CX + threadIdx.x, t.ty * R + threadIdx.y);
 }
 
-__global__ void k_advance(SolveDesc *D, int nslots)
+__global__ void k_advance(SolveDesc *D, int nslots, int which)
 {
     for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
-        const int64_t n = D[s].n;
-        if (n < D[s].steps) D[s].n = n + 1;
+        SolveDesc &d = D[s];
+        const int64_t n = d.n;
+        if (d.two != which || n >= d.steps) continue;
+        d.n = which ? min(n + 2, d.steps) : n + 1;
+        d.cur ^= 1;
     }
 }
 
@@ -1075,11 +1125,30 @@ __global__ void k_contour_batch(SolveDesc *__restrict__ D)
 {
     const SolveDesc &d = D[blockIdx.y];
     const int64_t n = d.n;
-    if (n >= d.steps || !(n + 1 > d.steps - d.window)) return;
+    if (d.two || n >= d.steps || !(n + 1 > d.steps - d.window)) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.C.n) return;
     if (d.precision == 0) contour_sample_f64(d.L, d.fields, d.C, k);
-    else contour_sample_f32(d.L, reinterpret_cast<const float *>(d.state[(n + 1) & 1]), d.L.sfld, d.C, k);
+    else contour_sample_f32(d.L, reinterpret_cast<const float *>(d.state[d.cur ^ 1]), d.L.sfld, d.C, k);
+}
+
+// After a batched two-step launch from level n: level n + 1 (the middle
+// fields, or the state when the solve had one step left) and level n + 2,
+// each if it lies in the averaging window, in that order.
+__global__ void k_contour2_batch(SolveDesc *__restrict__ D)
+{
+    const SolveDesc &d = D[blockIdx.y];
+    const int64_t n = d.n;
+    if (!d.two || n >= d.steps) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.C.n) return;
+    const float *next = reinterpret_cast<const float *>(d.state[d.cur ^ 1]);
+    const bool one = d.steps - n == 1;
+    if (n + 1 > d.steps - d.window) {
+        if (one) contour_sample_f32(d.L, next, d.L.sfld, d.C, k);
+        else contour_sample_f32(d.L, d.mid, 3 * d.L.plane, d.C, k);
+    }
+    if (!one && n + 2 > d.steps - d.window) contour_sample_f32(d.L, next, d.L.sfld, d.C, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -1247,19 +1316,9 @@ hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, voi
     return hipGetLastError();
 }
 
-hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, void *dst, double einc0, double einc1,
-                            float *mid, hipStream_t s, int variant)
+// Variant dispatch shared by the single-solve and batched two-step launchers.
+template <typename F> static void two_step_dispatch(int variant, F &&go)
 {
-    const float e0 = (float)einc0, e1 = (float)einc1;
-    auto go = [&](auto tag, auto vtag, auto htag, auto xtag) {
-        typedef decltype(tag) T;
-        constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
-        const int nsx = (L.nx + two_step_width<V, HX>() - 1) / two_step_width<V, HX>();
-        const int nsy = (L.ny + H - 1) / H;
-        const int blocks = (nsx * nsy + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
-        hipLaunchKernelGGL((k_step2_neq<T, V, H, HX>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src, dst, e0,
-                           e1, mid, nsx, nsy);
-    };
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
     using H8 = std::integral_constant<int, 8>;
@@ -1267,19 +1326,61 @@ hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, vo
     using H32 = std::integral_constant<int, 32>;
     using X2 = std::integral_constant<int, 2>;
     using X8 = std::integral_constant<int, 8>;
-    auto pick = [&](auto tag) {
-        switch (variant) {
-        case TWO_V1_H8_X2: go(tag, I1{}, H8{}, X2{}); break;
-        case TWO_V1_H16_X2: go(tag, I1{}, H16{}, X2{}); break;
-        case TWO_V2_H8_X2: go(tag, I2{}, H8{}, X2{}); break;
-        case TWO_V2_H16_X2: go(tag, I2{}, H16{}, X2{}); break;
-        case TWO_V1_H8_X8: go(tag, I1{}, H8{}, X8{}); break;
-        case TWO_V2_H16_X8: go(tag, I2{}, H16{}, X8{}); break;
-        default: go(tag, I2{}, H32{}, X8{}); break;
-        }
+    switch (variant) {
+    case TWO_V1_H8_X2: go(I1{}, H8{}, X2{}); break;
+    case TWO_V1_H16_X2: go(I1{}, H16{}, X2{}); break;
+    case TWO_V2_H8_X2: go(I2{}, H8{}, X2{}); break;
+    case TWO_V2_H16_X2: go(I2{}, H16{}, X2{}); break;
+    case TWO_V1_H8_X8: go(I1{}, H8{}, X8{}); break;
+    case TWO_V2_H16_X8: go(I2{}, H16{}, X8{}); break;
+    default: go(I2{}, H32{}, X8{}); break;
+    }
+}
+
+void two_step_shape(int variant, int nx, int ny, int &nsx, int &nsy)
+{
+    two_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag) {
+        constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
+        nsx = (nx + two_step_width<V, HX>() - 1) / two_step_width<V, HX>();
+        nsy = (ny + H - 1) / H;
+    });
+}
+
+hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, void *dst, double einc0, double einc1,
+                            float *mid, hipStream_t s, int variant)
+{
+    const float e0 = (float)einc0, e1 = (float)einc1;
+    auto run = [&](auto tag) {
+        typedef decltype(tag) T;
+        two_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag) {
+            constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
+            const int nsx = (L.nx + two_step_width<V, HX>() - 1) / two_step_width<V, HX>();
+            const int nsy = (L.ny + H - 1) / H;
+            const int blocks = (nsx * nsy + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
+            hipLaunchKernelGGL((k_step2_neq<T, V, H, HX>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src, dst,
+                               e0, e1, mid, nsx, nsy);
+        });
     };
-    if (precision == 1) pick(float{});
-    else pick(__bf16{});
+    if (precision == 1) run(float{});
+    else run(__bf16{});
+    return hipGetLastError();
+}
+
+hipError_t launch_step2_batch(int precision, int variant, SolveDesc *d, const Tile *items, int nitems, int remap,
+                              hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    const int blocks = (nitems + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
+    auto run = [&](auto tag) {
+        typedef decltype(tag) T;
+        two_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag) {
+            constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
+            hipLaunchKernelGGL((k_step2_neq_batch<T, V, H, HX>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, d,
+                               items, nitems, remap);
+        });
+    };
+    if (precision == 1) run(float{});
+    else run(__bf16{});
     return hipGetLastError();
 }
 
@@ -1364,9 +1465,16 @@ hipError_t launch_contour_batch(SolveDesc *d, int nslots, int max_nc, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_advance(SolveDesc *d, int nslots, hipStream_t s)
+hipError_t launch_contour2_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, s, d, nslots);
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_contour2_batch, dim3((max_nc + 127) / 128, nslots), dim3(128), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(SolveDesc *d, int nslots, int which, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, s, d, nslots, which);
     return hipGetLastError();
 }
 

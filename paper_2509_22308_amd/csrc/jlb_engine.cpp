@@ -3,11 +3,15 @@
 //
 // Each admitted solve owns a device workspace with the same layout as a
 // single solve plus its table of incident-wave values.  Its descriptor in
-// device memory carries its step counter, which the device advances, so a
-// chunk of K lattice steps -- per step one launch per precision over the
-// tiles of every resident solve, one batched contour launch and one advance
-// launch -- is captured once in a hipGraph and replayed while the set of
-// resident solves is unchanged.  Solves that finish inside a chunk idle
+// device memory carries its step counter and the index of the buffer that
+// holds its current state, which the device advances, so a chunk of K
+// lattice steps is captured once in a hipGraph and replayed while the set of
+// resident solves is unchanged.  The chunk is K / 2 double steps; in each,
+// solves on single steps (FP64, or with two-step kernels off) take two
+// rounds of one launch per precision over their tiles, one batched contour
+// launch and one advance launch, and FP32 / BF16 solves take one batched
+// two-step launch over their (strip, row segment) items, one two-level
+// contour launch and one advance-by-two launch.  Solves that finish inside a chunk idle
 // (their tiles return at once) until the chunk boundary, where the engine
 // reduces their contour sums, returns their memory and admits waiting
 // requests that fit the byte budget (continuous batching).
@@ -47,6 +51,7 @@ struct Request {
     char *ws = nullptr;       // device: workspace followed by the incident table
     size_t footprint = 0;
     int64_t n = 0;            // host mirror of the device step counter
+    int cur = 0;              // host mirror of the device buffer index
     int64_t ramp_end = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     double loop_ms_acc = 0;
@@ -72,6 +77,10 @@ struct jlb_engine {
     int ntiles[3] = {0, 0, 0};
     int tile_off[3] = {0, 0, 0};
     int variant[3] = {0, 0, 0};
+    int two[3] = {-1, -1, -1};  // two-step variant per precision (-1: single steps)
+    int nitems[3] = {0, 0, 0};  // two-step work items per precision
+    int item_off[3] = {0, 0, 0};
+    bool any_single = false, any_two = false;
     int max_nc = 0;
     int remap = 0;
     bool dirty = true;
@@ -107,6 +116,7 @@ int admit_one(jlb_engine *e, uint64_t t)
     if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine upload: %s", hipGetErrorString(err));
     r.status = JLB_REQ_RUNNING;
     r.n = 0;
+    r.cur = 0;
     r.t_admit = now_ms();
     e->in_use += r.footprint;
     e->resident.push_back(t);
@@ -146,14 +156,18 @@ int rebuild(jlb_engine *e)
     }
     const int ns = (int)e->resident.size();
     std::vector<SolveDesc> desc(ns);
-    std::vector<Tile> tiles[3];
+    std::vector<Tile> tiles[3], items[3];
     e->max_nc = 0;
     // the resident states together decide whether they stay cache-resident
     size_t working_set = 0;
     for (int k = 0; k < ns; ++k) working_set += 2 * e->reqs[e->resident[k]].plan.state_bytes;
     const int stream_stores = working_set > CACHE_RESIDENT_BYTES ? 1 : 0;
     e->remap = stream_stores ? 0 : 1;
-    for (int p = 0; p < 3; ++p) e->variant[p] = jlb::step_variant(p);
+    for (int p = 0; p < 3; ++p) {
+        e->variant[p] = jlb::step_variant(p);
+        e->two[p] = p == JLB_FP64 ? -1 : jlb::two_step_variant(p);
+    }
+    e->any_single = e->any_two = false;
     for (int k = 0; k < ns; ++k) {
         Request &r = e->reqs[e->resident[k]];
         const Plan &q = r.plan;
@@ -163,7 +177,9 @@ int rebuild(jlb_engine *e)
         d.L.stream_stores = stream_stores;
         d.state[0] = r.ws + q.off_state[0];
         d.state[1] = r.ws + q.off_state[1];
+        d.cur = r.cur;
         d.fields = q.prob.precision == JLB_FP64 ? (double *)(r.ws + q.off_fields) : nullptr;
+        d.mid = q.prob.precision == JLB_FP64 ? nullptr : (float *)(r.ws + q.off_mid);
         d.src_tab = (const double *)(r.ws + q.ws_bytes);
         d.ramp_end = r.ramp_end;
         d.T = q.T;
@@ -174,6 +190,23 @@ int rebuild(jlb_engine *e)
         d.precision = q.prob.precision;
         e->max_nc = std::max(e->max_nc, q.nc);
         const int p = q.prob.precision;
+        d.two = e->two[p] >= 0 ? 1 : 0;
+        if (d.two) {
+            // one wavefront per (strip, row segment), in the order the
+            // single-solve launch uses for this residency
+            e->any_two = true;
+            int nsx, nsy;
+            two_step_shape(e->two[p], q.nx, q.ny, nsx, nsy);
+            if (stream_stores) {
+                for (int y = 0; y < nsy; ++y)
+                    for (int x = 0; x < nsx; ++x) items[p].push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
+            } else {
+                for (int x = 0; x < nsx; ++x)
+                    for (int y = 0; y < nsy; ++y) items[p].push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
+            }
+            continue;
+        }
+        e->any_single = true;
         int cols, rows;
         tile_shape(p, e->variant[p], cols, rows);
         const int tx = (q.nx + cols - 1) / cols;
@@ -188,6 +221,11 @@ int rebuild(jlb_engine *e)
         e->ntiles[p] = (int)tiles[p].size();
         total += tiles[p].size();
     }
+    for (int p = 0; p < 3; ++p) {
+        e->item_off[p] = (int)total;
+        e->nitems[p] = (int)items[p].size();
+        total += items[p].size();
+    }
     hipError_t err = hipSuccess;
     if (!e->d_desc) err = hipMallocAsync((void **)&e->d_desc, sizeof(SolveDesc) * e->max_slots, e->s);
     if (err == hipSuccess && total > e->tiles_cap) {
@@ -197,24 +235,41 @@ int rebuild(jlb_engine *e)
     }
     if (err == hipSuccess && ns > 0)
         err = hipMemcpyAsync(e->d_desc, desc.data(), sizeof(SolveDesc) * ns, hipMemcpyHostToDevice, e->s);
-    for (int p = 0; p < 3 && err == hipSuccess; ++p)
+    for (int p = 0; p < 3 && err == hipSuccess; ++p) {
         if (!tiles[p].empty())
             err = hipMemcpyAsync(e->d_tiles + e->tile_off[p], tiles[p].data(), sizeof(Tile) * tiles[p].size(),
                                  hipMemcpyHostToDevice, e->s);
+        if (err == hipSuccess && !items[p].empty())
+            err = hipMemcpyAsync(e->d_tiles + e->item_off[p], items[p].data(), sizeof(Tile) * items[p].size(),
+                                 hipMemcpyHostToDevice, e->s);
+    }
     if (err == hipSuccess) err = hipStreamSynchronize(e->s);  // host vectors go out of scope
     if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine rebuild: %s", hipGetErrorString(err));
     e->dirty = false;
     return JLB_OK;
 }
 
-hipError_t launch_batch_step(jlb_engine *e)
+// One double step: two single steps of the single-step solves, one two-step
+// launch of the others.
+hipError_t launch_double_step(jlb_engine *e)
 {
     const int ns = (int)e->resident.size();
     hipError_t err = hipSuccess;
-    for (int p = 0; p < 3 && err == hipSuccess; ++p)
-        err = launch_step_batch(p, e->variant[p], e->d_desc, e->d_tiles + e->tile_off[p], e->ntiles[p], e->remap, e->s);
-    if (err == hipSuccess) err = launch_contour_batch(e->d_desc, ns, e->max_nc, e->s);
-    if (err == hipSuccess) err = launch_advance(e->d_desc, ns, e->s);
+    for (int r = 0; r < 2 && e->any_single && err == hipSuccess; ++r) {
+        for (int p = 0; p < 3 && err == hipSuccess; ++p)
+            err = launch_step_batch(p, e->variant[p], e->d_desc, e->d_tiles + e->tile_off[p], e->ntiles[p], e->remap,
+                                    e->s);
+        if (err == hipSuccess) err = launch_contour_batch(e->d_desc, ns, e->max_nc, e->s);
+        if (err == hipSuccess) err = launch_advance(e->d_desc, ns, 0, e->s);
+    }
+    if (e->any_two && err == hipSuccess) {
+        for (int p = 1; p < 3 && err == hipSuccess; ++p)
+            if (e->nitems[p] > 0)
+                err = launch_step2_batch(p, e->two[p], e->d_desc, e->d_tiles + e->item_off[p], e->nitems[p], e->remap,
+                                         e->s);
+        if (err == hipSuccess) err = launch_contour2_batch(e->d_desc, ns, e->max_nc, e->s);
+        if (err == hipSuccess) err = launch_advance(e->d_desc, ns, 1, e->s);
+    }
     return err;
 }
 
@@ -224,7 +279,7 @@ int capture(jlb_engine *e)
     if (hipStreamBeginCapture(e->s, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(JLB_E_DEVICE, "engine capture begin");
     hipError_t err = hipSuccess;
-    for (int64_t k = 0; k < CHUNK && err == hipSuccess; ++k) err = launch_batch_step(e);
+    for (int64_t k = 0; k < CHUNK / 2 && err == hipSuccess; ++k) err = launch_double_step(e);
     hipError_t err2 = hipStreamEndCapture(e->s, &g);
     if (err != hipSuccess || err2 != hipSuccess) return fail(JLB_E_DEVICE, "engine capture failed");
     err = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
@@ -335,7 +390,8 @@ int jlb_engine_run(jlb_engine *e, int64_t steps, int32_t *active)
             rc = rebuild(e);
             if (rc) return rc;
         }
-        const int64_t k = std::min<int64_t>(CHUNK, steps - done);
+        // whole double steps
+        const int64_t k = std::min<int64_t>(CHUNK, (steps - done + 1) / 2 * 2);
         if (k == CHUNK) {
             if (!e->graph) {
                 rc = capture(e);
@@ -343,12 +399,18 @@ int jlb_engine_run(jlb_engine *e, int64_t steps, int32_t *active)
             }
             if (hipGraphLaunch(e->graph, e->s) != hipSuccess) return fail(JLB_E_DEVICE, "engine graph launch");
         } else {
-            for (int64_t i = 0; i < k; ++i)
-                if (launch_batch_step(e) != hipSuccess) return fail(JLB_E_DEVICE, "engine step launch");
+            for (int64_t i = 0; i < k / 2; ++i)
+                if (launch_double_step(e) != hipSuccess) return fail(JLB_E_DEVICE, "engine step launch");
         }
+        // host mirrors of the device counters (the advance kernels' rules)
         for (uint64_t t : e->resident) {
             Request &r = e->reqs[t];
-            r.n = std::min<int64_t>(r.plan.prob.steps, r.n + k);
+            const int64_t total = r.plan.prob.steps;
+            const bool two = e->two[r.plan.prob.precision] >= 0;
+            for (int64_t i = 0; i < (two ? k / 2 : k) && r.n < total; ++i) {
+                r.n = two ? std::min<int64_t>(r.n + 2, total) : r.n + 1;
+                r.cur ^= 1;
+            }
         }
         done += k;
         rc = harvest(e);

@@ -242,7 +242,7 @@ static std::atomic<int> g_two[3] = {{-1}, {-1}, {-1}};
 
 int step_variant(int precision) { return g_variant[precision].load(std::memory_order_relaxed); }
 void set_step_variant(int precision, int v) { g_variant[precision].store(v, std::memory_order_relaxed); }
-static int two_step_variant(int precision) { return g_two[precision].load(std::memory_order_relaxed); }
+int two_step_variant(int precision) { return g_two[precision].load(std::memory_order_relaxed); }
 static void set_two_step_variant(int precision, int v) { g_two[precision].store(v, std::memory_order_relaxed); }
 
 hipError_t launch_step(const Plan &q, const Lattice &L, void *src, void *dst, double *fields, double einc, hipStream_t s,

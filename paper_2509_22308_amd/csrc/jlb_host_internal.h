@@ -51,6 +51,8 @@ Lattice lattice_of(const Plan &q, const uint8_t *dmask);
 ContourDev contour_of(const Plan &q, char *ws);
 int upload_setup(const Plan &q, char *ws, hipStream_t s);
 int step_variant(int precision);
+// Two-step variant of a precision (-1: single steps only; always -1 for FP64).
+int two_step_variant(int precision);
 int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, double *hy, double *energy,
               hipStream_t s);
 

@@ -133,12 +133,15 @@ struct SolveDesc {
     Lattice L;
     char *state[2];
     double *fields;          // FP64: field planes written inside the averaging window
+    float *mid;              // FP32 / BF16 two-step solves: middle-level fields of the contour-stencil nodes
     const double *src_tab;   // incident values: [ramp_end] ramp steps, then [T] by n mod T
     int64_t ramp_end, T;
     int64_t n;               // steps done (device-updated)
     int64_t steps, window;
     ContourDev C;
     int precision;
+    int cur;                 // buffer holding the state at step n (device-updated)
+    int two;                 // 1: advanced by two-step launches
     int pad;
 };
 
@@ -151,9 +154,20 @@ struct Tile {
 // Tile shape of a precision / variant: columns x rows per block.
 void tile_shape(int precision, int variant, int &cols, int &rows);
 // remap = 1 hands XCD-contiguous tiles to the eight XCDs (cache-resident working sets).
+// Single steps: the solves with two == 0.
 hipError_t launch_step_batch(int precision, int variant, SolveDesc *d, const Tile *tiles, int ntiles, int remap,
                              hipStream_t s);
 hipError_t launch_contour_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s);
-hipError_t launch_advance(SolveDesc *d, int nslots, hipStream_t s);
+// Two-step launches over the solves with two == 1 (precision 1 or 2): one
+// wavefront per item (slot, strip tx, row segment ty) of the given variant;
+// a solve with one step left takes only that step.
+hipError_t launch_step2_batch(int precision, int variant, SolveDesc *d, const Tile *items, int nitems, int remap,
+                              hipStream_t s);
+// Strip and segment counts of a two-step variant for an nx x ny lattice.
+void two_step_shape(int variant, int nx, int ny, int &nsx, int &nsy);
+hipError_t launch_contour2_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s);
+// Advances the solves with two == which by one step (which = 0) or by up
+// to two (which = 1) and flips their buffers.
+hipError_t launch_advance(SolveDesc *d, int nslots, int which, hipStream_t s);
 
 }  // namespace jlb

@@ -35,6 +35,9 @@ def _mix():
                   wavelength=40.0, steps=650, avg_periods=1),
         W.problem(nx=64, ny=64, radius=8.0, kind="metallo_dielectric_janus", eps1=1.5, phi0_deg=300.0,
                   wavelength=20.0, steps=420, avg_periods=2),
+        # an odd step count: a two-step engine ends this solve with one step
+        W.problem(nx=110, ny=77, radius=11.0, kind="dielectric_janus", eps1=6.0, eps2=2.0, phi0_deg=135.0,
+                  wavelength=30.0, steps=541, avg_periods=2),
     ]
 
 
@@ -104,18 +107,59 @@ def test_cancel_and_oversized_requests(jlb):
         eng.submit(jlb.make_problem(W.config2(), "fp64"))  # ~400 MB > 64 MB
     assert ei.value.code == -8
     tickets = [eng.submit(p) for p in probs]
-    eng.run(50)                     # two resident, three queued
+    eng.run(50)                     # two resident, the rest queued
     st = eng.stats()
-    assert st["resident"] == 2 and st["queued"] == 3
+    assert st["resident"] == 2 and st["queued"] == len(probs) - 2
     eng.cancel(tickets[0])          # running
-    eng.cancel(tickets[4])          # queued
+    eng.cancel(tickets[-1])         # queued
     for _ in range(1000):
         eng.run(400)
         st = eng.stats()
         if st["queued"] == 0 and st["resident"] == 0:
             break
-    assert eng.poll(tickets[0])[0] == "cancelled" and eng.poll(tickets[4])[0] == "cancelled"
-    assert all(eng.poll(t)[0] == "done" for t in tickets[1:4])
+    assert eng.poll(tickets[0])[0] == "cancelled" and eng.poll(tickets[-1])[0] == "cancelled"
+    assert all(eng.poll(t)[0] == "done" for t in tickets[1:-1])
     with pytest.raises(jlb.JlbError):
         eng.cancel(tickets[1])      # already finished
     eng.close()
+
+
+@pytest.fixture
+def two_step(jlb):
+    """Selects a two-step variant for FP32 and BF16 for the test, then restores."""
+    before = {p: jlb.jlb_get_two_step_variant(jlb.PRECISIONS[p]) for p in ("fp32", "bf16")}
+
+    def select(v):
+        for p in ("fp32", "bf16"):
+            jlb.jlb_set_two_step_variant(jlb.PRECISIONS[p], v)
+    yield select
+    for p, v in before.items():
+        jlb.jlb_set_two_step_variant(jlb.PRECISIONS[p], v)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("variant", [0, 4, 5])
+def test_two_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, precision, variant):
+    """Batched two-step launches (every solve at its own step, ramp and window
+    included, a final single step for an odd count) equal single solves."""
+    two_step(-1)
+    single = [jlb.solve(p, precision) for p in _mix()]
+    two_step(variant)
+    batched = _run_engine(jlb, [jlb.make_problem(p, precision) for p in _mix()], chunk=256)
+    for s, b in zip(single, batched):
+        for q in ("fx", "fy", "tz", "fx_raw", "fy_raw", "tz_raw"):
+            assert s[q] == b[q], (precision, variant, q, s[q], b[q])
+
+
+def test_two_step_and_single_step_solves_share_an_engine(jlb, two_step):
+    """FP64 solves on single steps and FP32 / BF16 solves on two-step launches
+    in one engine, admitted at different times: each equals its single solve."""
+    two_step(5)
+    precs = ["fp64", "fp32", "bf16", "fp32", "bf16", "fp64"]
+    single = [jlb.solve(p, pr) for p, pr in zip(_mix(), precs)]
+    batched = _run_engine(jlb, [jlb.make_problem(p, pr) for p, pr in zip(_mix(), precs)],
+                          budget=sum(jlb.jlb_workspace_size(jlb.make_problem(p, pr)) for p, pr in
+                                     zip(_mix()[:3], precs[:3])) + (1 << 24), chunk=128)
+    for s, b in zip(single, batched):
+        for q in ("fx", "fy", "tz"):
+            assert s[q] == b[q], (q, s[q], b[q])
