@@ -173,8 +173,11 @@ def gpu_leg(args):
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(args.precision, variant),
             "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms, "launches_per_solve": passes,
-            "note": "config 2 (FP32 state 2 x 46 MB) stays in the 256 MB Infinity Cache between steps; "
-                    "the HBM-bound figures are extra.grid4096_*"}
+            "effective_gbs": value * BYTES_PER_LUP[args.precision] / 1e9,
+            "note": "achieved = algorithmic bytes per pass (one read and one write of the state) x passes / loop "
+                    "time; a two-step launch is one pass for two lattice updates, so effective_gbs (LUPS x bytes "
+                    "per single-step update) exceeds it.  Config 2 (FP32 state 2 x 46 MB) stays in the 256 MB "
+                    "Infinity Cache between steps; the HBM-bound figures are extra.grid4096_*"}
     return p, value, ms_per_solve, roof, extra
 
 
