@@ -268,9 +268,10 @@ def run_serve(args):
     torch.cuda.set_device(0)
     reqs = workloads.config5_requests(n_req=args.requests, a_min=args.a_min, a_max=args.a_max)
     jlb.jlb_autotune(jlb.make_problem(reqs[0][1], args.precision), 10)
-    out = serve(reqs, args.precision)
-    extra = {k: out[k] for k in ("requests", "completed", "wall_s", "p50_s", "p99_s", "mean_s", "solves_per_hour",
-                                 "offered_lups", "peak_resident", "budget_bytes")}
+    out = serve(reqs, args.precision, max_slots=args.slots, policy=args.policy)
+    extra = {k: out[k] for k in ("requests", "completed", "wall_s", "p50_s", "p99_s", "mean_s", "queue_p50_s",
+                                 "queue_p99_s", "solves_per_hour", "offered_lups", "peak_resident", "budget_bytes",
+                                 "policy", "max_slots")}
     config = {"workload": f"config 5 serving: {args.requests} Poisson arrivals at 20/s (seed 22308), dielectric "
                           f"Janus a ~ U{{{args.a_min}..{args.a_max}}}, grid 8a, eps ~ U[1.5,10], lambda 2a, "
                           "52 periods, byte-budget admission", "precision": args.precision}
@@ -406,6 +407,8 @@ def main():
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--a-min", type=int, default=16)
     ap.add_argument("--a-max", type=int, default=64)
+    ap.add_argument("--policy", default="fifo", choices=["fifo", "sjf"], help="serve: engine admission order")
+    ap.add_argument("--slots", type=int, default=256, help="serve: most solves resident at once")
     ap.add_argument("--quick", action="store_true", help="skip the extra precision, 4096^2 and copy figures")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--kernel-only", action="store_true")

@@ -282,6 +282,20 @@ int jlb_engine_cancel(jlb_engine *eng, uint64_t ticket);
 /* Counts of queued, resident and finished requests and device bytes in use. */
 int jlb_engine_stats(jlb_engine *eng, int32_t *queued, int32_t *resident, int32_t *finished, size_t *bytes_in_use);
 
+/*
+ * Admission order of queued requests (applied at every chunk boundary, with
+ * the byte budget and the slot count as limits):
+ *   JLB_POLICY_FIFO  first fit in arrival order (the default);
+ *   JLB_POLICY_SJF   smallest work first (cells x steps; ties by arrival) --
+ *                    with a slot count below the offered concurrency this
+ *                    keeps small requests from waiting behind large ones.
+ * max_slots (> 0) replaces the creation-time slot count; 0 keeps it.
+ * JLB_E_ARG for an unknown policy or a negative slot count.
+ */
+#define JLB_POLICY_FIFO 0
+#define JLB_POLICY_SJF 1
+int jlb_engine_set_policy(jlb_engine *eng, int32_t policy, int32_t max_slots);
+
 /* Releases every resource of the engine. */
 int jlb_engine_destroy(jlb_engine *eng);
 

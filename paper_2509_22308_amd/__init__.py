@@ -98,6 +98,7 @@ def load():
             "jlb_engine_stats": ([_vp, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32),
                                   _P(ctypes.c_size_t)], ctypes.c_int),
             "jlb_engine_destroy": ([_vp], ctypes.c_int),
+            "jlb_engine_set_policy": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -291,6 +292,12 @@ class Engine:
 
     def cancel(self, ticket: int):
         _check(load().jlb_engine_cancel(self._h, int(ticket)))
+
+    POLICIES = {"fifo": 0, "sjf": 1}
+
+    def set_policy(self, policy: str = "fifo", max_slots: int = 0):
+        """Admission order ("fifo" or "sjf": smallest work first) and, when > 0, a new slot count."""
+        _check(load().jlb_engine_set_policy(self._h, self.POLICIES[policy], int(max_slots)))
 
     def stats(self) -> dict:
         q, r, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

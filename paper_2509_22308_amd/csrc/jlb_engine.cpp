@@ -62,6 +62,8 @@ struct Request {
 struct jlb_engine {
     size_t budget = 0;
     int max_slots = 1;
+    int slots_cap = 1;          // slots the device descriptors were sized for
+    int policy = JLB_POLICY_FIFO;
     hipStream_t s = nullptr;
     bool own = false;
     uint64_t next_ticket = 1;
@@ -124,25 +126,28 @@ int admit_one(jlb_engine *e, uint64_t t)
     return JLB_OK;
 }
 
-// First fit in arrival order: admit every queued request that fits.
+double work_of(const Request &r) { return (double)r.plan.nx * r.plan.ny * (double)r.plan.prob.steps; }
+
+// Admit every queued request that fits, in the policy's order: first fit in
+// arrival order, or smallest work first.
 int admit(jlb_engine *e)
 {
-    for (auto it = e->queue.begin(); it != e->queue.end();) {
+    std::vector<uint64_t> order(e->queue.begin(), e->queue.end());
+    if (e->policy == JLB_POLICY_SJF)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint64_t a, uint64_t b) { return work_of(e->reqs[a]) < work_of(e->reqs[b]); });
+    for (uint64_t t : order) {
         if ((int)e->resident.size() >= e->max_slots) break;
-        Request &r = e->reqs[*it];
-        if (e->in_use + r.footprint <= e->budget) {
-            const uint64_t t = *it;
-            it = e->queue.erase(it);
-            int rc = admit_one(e, t);
-            if (rc) {
-                Request &rr = e->reqs[t];
-                rr.status = JLB_REQ_FAILED;
-                if (rr.ws) (void)hipFreeAsync(rr.ws, e->s);
-                rr.ws = nullptr;
-                return rc;
-            }
-        } else {
-            ++it;
+        Request &r = e->reqs[t];
+        if (e->in_use + r.footprint > e->budget) continue;
+        e->queue.erase(std::find(e->queue.begin(), e->queue.end(), t));
+        int rc = admit_one(e, t);
+        if (rc) {
+            Request &rr = e->reqs[t];
+            rr.status = JLB_REQ_FAILED;
+            if (rr.ws) (void)hipFreeAsync(rr.ws, e->s);
+            rr.ws = nullptr;
+            return rc;
         }
     }
     return JLB_OK;
@@ -227,7 +232,10 @@ int rebuild(jlb_engine *e)
         total += items[p].size();
     }
     hipError_t err = hipSuccess;
-    if (!e->d_desc) err = hipMallocAsync((void **)&e->d_desc, sizeof(SolveDesc) * e->max_slots, e->s);
+    if (!e->d_desc) {
+        e->slots_cap = e->max_slots;
+        err = hipMallocAsync((void **)&e->d_desc, sizeof(SolveDesc) * e->slots_cap, e->s);
+    }
     if (err == hipSuccess && total > e->tiles_cap) {
         if (e->d_tiles) (void)hipFreeAsync(e->d_tiles, e->s);
         e->tiles_cap = std::max(total, 2 * e->tiles_cap);
@@ -346,6 +354,7 @@ int jlb_engine_create(size_t budget_bytes, int32_t max_slots, void *stream, jlb_
     jlb_engine *e = new jlb_engine();
     e->budget = budget_bytes;
     e->max_slots = max_slots;
+    e->slots_cap = max_slots;
     if (stream) {
         e->s = (hipStream_t)stream;
     } else {
@@ -454,6 +463,20 @@ int jlb_engine_cancel(jlb_engine *e, uint64_t ticket)
         return fail(JLB_E_STATE, "ticket %llu already finished", (unsigned long long)ticket);
     }
     r.status = JLB_REQ_CANCELLED;
+    return JLB_OK;
+}
+
+int jlb_engine_set_policy(jlb_engine *e, int32_t policy, int32_t max_slots)
+{
+    clear_error();
+    if (!e) return fail(JLB_E_ARG, "null engine");
+    if (policy != JLB_POLICY_FIFO && policy != JLB_POLICY_SJF) return fail(JLB_E_ARG, "unknown policy %d", policy);
+    if (max_slots < 0) return fail(JLB_E_ARG, "negative slot count");
+    // the device descriptor array, once allocated, bounds the slot count
+    if (max_slots > 0 && e->d_desc && max_slots > e->slots_cap)
+        return fail(JLB_E_ARG, "slot count %d above the %d the engine was created with", max_slots, e->slots_cap);
+    e->policy = policy;
+    if (max_slots > 0) e->max_slots = max_slots;
     return JLB_OK;
 }
 

@@ -61,16 +61,19 @@ def run_design_map(problems, precision: str = "fp32", budget_bytes: int | None =
 
 
 def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, max_slots: int = 256,
-          steps_per_call: int = 256, time_scale: float = 1.0) -> dict:
+          steps_per_call: int = 256, time_scale: float = 1.0, policy: str = "fifo") -> dict:
     """Replay (arrival_seconds, problem) requests in wall-clock time.
 
     Requests are submitted when their arrival time has passed; the engine
-    admits them as memory and slots free up and steps every resident solve
-    together.  Latency = completion time - arrival time.
+    admits them as memory and slots free up (in arrival order, or smallest
+    work first with policy "sjf") and steps every resident solve together.
+    Latency = completion time - arrival time; queue wait = admission time -
+    arrival time.
     """
     reqs = sorted(requests, key=lambda r: r[0])
     budget = _engine_budget([p for _, p in reqs], precision, budget_bytes)
     eng = Engine(budget, max_slots)
+    eng.set_policy(policy)
     outstanding = {}
     done = []
     k = 0
@@ -99,11 +102,14 @@ def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, ma
             status, res = eng.poll(t)
             if status in ("done", "failed", "cancelled"):
                 idx, arr = outstanding.pop(t)
+                # the engine's own clocks: submit -> done (total_ms), admit -> done (loop_ms)
                 done.append({"index": idx, "status": status, "arrival_s": arr, "done_s": now,
-                             "latency_s": now - arr, "fx": res.fx, "fy": res.fy, "tz": res.tz})
+                             "latency_s": now - arr, "queue_s": max(0.0, (res.total_ms - res.loop_ms) * 1e-3),
+                             "fx": res.fx, "fy": res.fy, "tz": res.tz})
     wall = time.perf_counter() - t0
     eng.close()
     lat = np.array([d["latency_s"] for d in done if d["status"] == "done"])
+    wait = np.array([d["queue_s"] for d in done if d["status"] == "done"])
     lups = float(sum(p["nx"] * p["ny"] * p["steps"] for _, p in reqs))
     span = reqs[-1][0] * time_scale if reqs else 0.0
     return {
@@ -111,6 +117,9 @@ def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, ma
         "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
         "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
         "mean_s": float(lat.mean()) if len(lat) else None,
+        "queue_p50_s": float(np.percentile(wait, 50)) if len(wait) else None,
+        "queue_p99_s": float(np.percentile(wait, 99)) if len(wait) else None,
+        "policy": policy, "max_slots": max_slots,
         "throughput_lups": lups / wall, "solves_per_hour": len(lat) / wall * 3600.0,
         "offered_lups": lups / span if span > 0 else None, "peak_resident": peak, "budget_bytes": budget,
         "done": sorted(done, key=lambda d: d["index"]),

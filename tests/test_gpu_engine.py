@@ -163,3 +163,30 @@ def test_two_step_and_single_step_solves_share_an_engine(jlb, two_step):
     for s, b in zip(single, batched):
         for q in ("fx", "fy", "tz"):
             assert s[q] == b[q], (q, s[q], b[q])
+
+
+def test_smallest_work_first_admission(jlb):
+    """With one slot and policy "sjf", queued requests run in order of work
+    (cells x steps), whatever their arrival order; "fifo" keeps arrival
+    order."""
+    mix = _mix()
+    work = [p["nx"] * p["ny"] * p["steps"] for p in mix]
+    for policy in ("sjf", "fifo"):
+        eng = jlb.Engine(8 << 30, 4)
+        eng.set_policy(policy, 1)
+        tickets = [eng.submit(jlb.make_problem(p, "fp32")) for p in mix]
+        finished = []
+        for _ in range(100000):
+            eng.run(64)
+            for k, t in enumerate(tickets):
+                if k not in finished and eng.poll(t)[0] == "done":
+                    finished.append(k)
+            if len(finished) == len(mix):
+                break
+        eng.close()
+        expect = sorted(range(len(mix)), key=lambda k: (work[k], k)) if policy == "sjf" else list(range(len(mix)))
+        assert finished == expect, (policy, finished, expect)
+    eng = jlb.Engine(1 << 30, 2)
+    with pytest.raises(jlb.JlbError):
+        eng.set_policy("fifo", -1)
+    eng.close()

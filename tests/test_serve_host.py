@@ -39,8 +39,13 @@ class FakeEngine:
 
     def poll(self, t):
         r = self.reqs[t]
-        return r["status"], types.SimpleNamespace(fx=r["fx"], fy=0.0, tz=0.0,
+        return r["status"], types.SimpleNamespace(fx=r["fx"], fy=0.0, tz=0.0, total_ms=0.0, loop_ms=0.0,
                                                   as_dict=lambda: {"fx": r["fx"], "fy": 0.0, "tz": 0.0})
+
+    def set_policy(self, policy="fifo", max_slots=0):
+        self.policy = policy
+        if max_slots:
+            self.slots = max_slots
 
     def close(self):
         pass
