@@ -99,7 +99,21 @@ typedef struct {
     double contour_offset;   /* contour radius R_c = radius + contour_offset (> 0)        */
     int32_t contour_points;  /* samples on the contour; 0 selects 8 * ceil(2 pi R_c / 8)  */
     uint32_t flags;          /* JLB_F_*                                                   */
+    double plateau_tol;      /* > 0: plateau stop (jlb_solve only; see below); 0: off     */
 } jlb_problem;
+
+/*
+ * Plateau stop (Sec. III: convergence is judged by the total field energy
+ * approaching a constant).  With plateau_tol > 0, jlb_solve samples the
+ * energy W = sum over the non-conductor nodes of (eps Ez^2 + Hx^2 + Hy^2)/2
+ * at fixed-phase check points: the end of the ramp (L0 = ramp_periods T) and
+ * every P_c steps after it, P_c = T, 2T or 4T (the shortest whole number of
+ * periods that is a multiple of 4 steps).  At the first check point L >= L0 +
+ * 2 P_c with |W(L) - W(L - P_c)| <= plateau_tol W(L) and L + avg_periods T <=
+ * steps, the solve averages the levels L + 1 .. L + avg_periods T and stops
+ * there (jlb_result.steps_done); without such a point it is the plain solve.
+ * The engine rejects it (JLB_E_ARG): its solves run their full step count.
+ */
 
 /* Outcome of one solve (host struct, written by the library). */
 typedef struct {

@@ -96,6 +96,7 @@ typedef struct {
                                  2 (test harness) open in x with the source, periodic in y */
     int32_t literal;          /* 1 literal 42-scalar populations, 0 reduced 11 */
     int32_t threads;          /* OpenMP threads, <= 0 selects 1 */
+    double plateau_tol;       /* > 0: stop once the field energy has reached a plateau (see orc_run) */
 } orc_params;
 
 typedef struct {
@@ -105,6 +106,7 @@ typedef struct {
     int64_t window_steps;           /* number of time samples in the average */
     int32_t contour_points;
     int32_t pad;
+    int64_t steps_done;             /* steps taken (fewer than steps after a plateau stop) */
 } orc_result;
 
 /* ------------------------------------------------------------------------ */
@@ -463,6 +465,16 @@ static void literal_step(const orc_params *p, int edges, int nx, int ny, const u
  *   ez, hx, hy   optional [ny][nx] outputs, fields after the last step
  *   energy       optional [steps] output, W(n+1) after each step
  *   acc          optional [N_c][4] output, time sums of Ez^2, Hx^2, Hy^2, HxHy
+ *
+ * Plateau stop (plateau_tol > 0).  Sec. III judges convergence by the total
+ * field energy in the domain approaching a constant.  Reading: the energy W
+ * is sampled at fixed-phase check points, the end of the ramp and every P_c
+ * steps after it (P_c = T, 2T or 4T: the shortest whole number of periods
+ * that is a multiple of 4 steps).  At the second and later check points L,
+ * if |W(L) - W(L - P_c)| <= plateau_tol W(L) and L + avg_periods T <= steps,
+ * the run averages the levels L + 1 .. L + avg_periods T and stops there;
+ * otherwise the run is the plain one.  Only the first such check point
+ * counts.
  */
 int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
             double *ez_out, double *hx_out, double *hy_out, double *energy,
@@ -502,7 +514,12 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
         if (!acc) { rc = ORC_E_OOM; goto done; }
     }
 
-    for (int64_t n = 0; n < p->steps; ++n) {
+    int64_t stop = p->steps;
+    const int64_t ramp_end = (int64_t)p->ramp_periods * period;
+    const int64_t pcheck = period % 4 == 0 ? period : period % 2 == 0 ? 2 * period : 4 * period;
+    int plateau = p->plateau_tol > 0.0 && p->boundary == 0;
+    double w_prev = -1.0;
+    for (int64_t n = 0; n < stop; ++n) {
         double einc = p->boundary != 1 ? incident_ez(p, n) : 0.0;
         int edges = p->boundary == 0 ? EDGE_OPEN : p->boundary == 1 ? EDGE_PERIODIC : EDGE_XOPEN;
         if (p->literal) literal_step(p, edges, nx, ny, mat, a, b, sa, ez, hx, hy, einc);
@@ -514,7 +531,17 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
             double *u = sa; sa = sb; sb = u;
         }
         double *t = a; a = b; b = t;
-        if (do_contour && n + 1 > p->steps - window) {
+        if (plateau && n + 1 >= ramp_end + pcheck && (n + 1 - ramp_end) % pcheck == 0) {
+            double w = 0.0;
+            for (size_t c = 0; c < plane; ++c)
+                w += 0.5 * (eps_of(p, mat[c]) * ez[c] * ez[c] + hx[c] * hx[c] + hy[c] * hy[c]);
+            if (w_prev >= 0.0 && fabs(w - w_prev) <= p->plateau_tol * w && n + 1 + window <= p->steps) {
+                stop = n + 1 + window;
+                plateau = 0;
+            }
+            w_prev = w;
+        }
+        if (do_contour && n + 1 > stop - window) {
             for (int k = 0; k < con.n; ++k) {
                 double e = bilinear(ez, nx, con.px[k], con.py[k]);
                 double u = bilinear(hx, nx, con.px[k], con.py[k]);
@@ -539,6 +566,7 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
         for (size_t c = 0; c < plane; ++c)
             w += 0.5 * (eps_of(p, mat[c]) * ez[c] * ez[c] + hx[c] * hx[c] + hy[c] * hy[c]);
         res->energy_final = w;
+        res->steps_done = stop;
     }
 
     if (do_contour && res->window_steps > 0) {

@@ -40,6 +40,7 @@ class _Params(ctypes.Structure):
         ("avg_periods", ctypes.c_int32), ("ramp_periods", ctypes.c_int32),
         ("contour_offset", ctypes.c_double), ("contour_points", ctypes.c_int32),
         ("boundary", ctypes.c_int32), ("literal", ctypes.c_int32), ("threads", ctypes.c_int32),
+        ("plateau_tol", ctypes.c_double),
     ]
 
 
@@ -49,6 +50,7 @@ class _Result(ctypes.Structure):
         ("fx_raw", ctypes.c_double), ("fy_raw", ctypes.c_double), ("tz_raw", ctypes.c_double),
         ("energy_final", ctypes.c_double), ("window_steps", ctypes.c_int64),
         ("contour_points", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("steps_done", ctypes.c_int64),
     ]
 
 
@@ -106,6 +108,7 @@ def _params(prob: dict, boundary: str = "open", literal: bool = False, threads: 
         contour_offset=float(prob.get("contour_offset", 3.0)),
         contour_points=int(prob.get("contour_points", 0)),
         boundary={"open": 0, "periodic": 1, "x_open_y_periodic": 2}[boundary], literal=int(bool(literal)), threads=int(threads),
+        plateau_tol=float(prob.get("plateau_tol", 0.0)),
     )
 
 
@@ -149,7 +152,7 @@ def solve(prob: dict, *, literal: bool = False, boundary: str = "open", mat: np.
     if rc != 0:
         raise ValueError("oracle run failed: %d" % rc)
     out = {k: getattr(res, k) for k in ("fx", "fy", "tz", "fx_raw", "fy_raw", "tz_raw", "energy_final",
-                                         "window_steps", "contour_points")}
+                                         "window_steps", "contour_points", "steps_done")}
     if fields:
         out.update(ez=ez, hx=hx, hy=hy)
     if energy:

@@ -36,6 +36,7 @@ class jlb_problem(ctypes.Structure):
         ("phi0", ctypes.c_double), ("wavelength", ctypes.c_double), ("e0", ctypes.c_double),
         ("steps", ctypes.c_int64), ("avg_periods", ctypes.c_int32), ("ramp_periods", ctypes.c_int32),
         ("contour_offset", ctypes.c_double), ("contour_points", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("plateau_tol", ctypes.c_double),
     ]
 
 
@@ -127,7 +128,7 @@ def make_problem(d: dict, precision: str | int | None = None, flags: int = 0) ->
         wavelength=float(d["wavelength"]), e0=float(d.get("e0", 1.0)), steps=int(d["steps"]),
         avg_periods=int(d.get("avg_periods", 5)), ramp_periods=int(d.get("ramp_periods", 1)),
         contour_offset=float(d.get("contour_offset", 3.0)), contour_points=int(d.get("contour_points", 0)),
-        flags=int(flags | d.get("flags", 0)),
+        flags=int(flags | d.get("flags", 0)), plateau_tol=float(d.get("plateau_tol", 0.0)),
     )
 
 

@@ -372,6 +372,7 @@ int jlb_engine_submit(jlb_engine *e, const jlb_problem *prob, uint64_t *ticket)
 {
     clear_error();
     if (!e || !prob || !ticket) return fail(JLB_E_ARG, "null argument");
+    if (prob->plateau_tol != 0.0) return fail(JLB_E_ARG, "the plateau stop is a single-solve option");
     Request r;
     r.prob = *prob;
     int rc = make_plan(prob, &r.plan);

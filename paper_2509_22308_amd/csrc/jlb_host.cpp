@@ -64,6 +64,7 @@ int make_plan(const jlb_problem *p, Plan *pl)
     if (p->kind < 0 || p->kind > 2) return fail(JLB_E_ARG, "unknown kind %d", p->kind);
     if (p->precision < 0 || p->precision > 2) return fail(JLB_E_ARG, "unknown precision %d", p->precision);
     if (!(p->radius > 0.0)) return fail(JLB_E_ARG, "radius must be > 0");
+    if (!(p->plateau_tol >= 0.0) || !std::isfinite(p->plateau_tol)) return fail(JLB_E_ARG, "plateau_tol must be >= 0");
     if (!(p->eps1 >= 1.0) || !std::isfinite(p->eps1)) return fail(JLB_E_ARG, "eps1 must be >= 1");
     if (p->kind == JLB_DIELECTRIC_JANUS && (!(p->eps2 >= 1.0) || !std::isfinite(p->eps2)))
         return fail(JLB_E_ARG, "eps2 must be >= 1");
@@ -379,14 +380,36 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     if (rc) return rc;
     const Lattice L = lattice_of(q, (const uint8_t *)(ws + q.off_mask));
     const ContourDev C = contour_of(q, ws);
-    const int64_t steps = q.prob.steps;
-    const int64_t wstart = steps - q.window;  // launches from here on produce averaged levels
+    int64_t steps = q.prob.steps;
+    int64_t wstart = steps - q.window;  // launches from here on produce averaged levels
     const bool use_graph = !(q.prob.flags & JLB_F_NO_GRAPH) && !energy;
     // whole periods, a multiple of 4 steps: two-step launches then come in
-    // pairs and a chunk leaves state n in buffer n % 2, as single steps do
+    // pairs and a chunk leaves state n in buffer n % 2, as single steps do;
+    // it is also the spacing of the plateau check points
     const int64_t chunk = q.T % 4 == 0 ? q.T : q.T % 2 == 0 ? 2 * q.T : 4 * q.T;
     const int two = q.prob.precision == JLB_FP64 ? -1 : two_step_variant(q.prob.precision);
     const int64_t ramp_end = (int64_t)std::ceil(q.ramp_steps);
+    bool plateau = q.prob.plateau_tol > 0.0;
+    double w_prev = -1.0;
+    // is level t a plateau check point?
+    auto check_level = [&](int64_t t) { return plateau && t >= ramp_end + chunk && (t - ramp_end) % chunk == 0; };
+    // energy at level t (whose fields are in place); may end the plateau search
+    auto plateau_check = [&](int64_t t) -> int {
+        double *slot = (double *)(ws + q.off_out) + 7;
+        hipError_t e = launch_energy(q.prob.precision, L, fields_ptr(q, ws, t), (double *)(ws + q.off_parts), q.nparts,
+                                     slot, s);
+        double w = 0.0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&w, slot, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail(JLB_E_DEVICE, "plateau check: %s", hipGetErrorString(e));
+        if (w_prev >= 0.0 && std::fabs(w - w_prev) <= q.prob.plateau_tol * w && t + q.window <= q.prob.steps) {
+            steps = t + q.window;
+            wstart = t;
+            plateau = false;
+        }
+        w_prev = w;
+        return JLB_OK;
+    };
 
     hipEvent_t ev0, ev1;
     HIP_TRY(hipEventCreate(&ev0));
@@ -418,7 +441,10 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             }
         } else {
             for (int64_t k = 0; k < chunk; ++k) {
-                int r = launch_one_step(q, ws, L, C, n0 + k, which == 1, false, incident(q, n0 + k), s);
+                // FP64 writes field planes only where they are read: the
+                // window, and the chunk's last level when the plateau is checked
+                int r = launch_one_step(q, ws, L, C, n0 + k, which == 1, plateau && k == chunk - 1,
+                                        incident(q, n0 + k), s);
                 if (r) {
                     hipGraph_t dummy;
                     (void)hipStreamEndCapture(s, &dummy);
@@ -458,11 +484,17 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             graph_used = 1;
             passes += two >= 0 ? chunk / 2 : chunk;
             n += chunk;
+            if (!in_window && check_level(n)) rc = plateau_check(n);
             continue;
         }
-        rc = launch_one_step(q, ws, L, C, n, in_window, energy != nullptr || n == steps - 1, incident(q, n), s);
+        const bool check = !in_window && check_level(n + 1);
+        rc = launch_one_step(q, ws, L, C, n, in_window, energy != nullptr || n == steps - 1 || check, incident(q, n), s);
         if (rc) break;
         ++passes;
+        if (check) {
+            rc = plateau_check(n + 1);
+            if (rc) break;
+        }
         if (energy) {
             hipError_t e = launch_energy(q.prob.precision, L, fields_ptr(q, ws, n + 1), (double *)(ws + q.off_parts),
                                          q.nparts, energy + n, s);

@@ -45,6 +45,7 @@ def test_problem_checks_return_the_documented_codes():
     assert J.jlb_validate(J.make_problem(dict(ok, wavelength=40.1))) == -1            # 3 lambda not integer
     assert J.jlb_validate(J.make_problem(dict(ok, radius=60.0))) == -2                # JLB_E_GEOMETRY
     assert J.jlb_validate(J.make_problem(dict(ok, eps1=30.0))) == -3                  # JLB_E_RESOLUTION
+    assert J.jlb_validate(J.make_problem(dict(ok, plateau_tol=-1e-3))) == -1          # JLB_E_ARG
     assert J.jlb_validate(J.make_problem(dict(ok, eps1=30.0), flags=J.JLB_F_ALLOW_UNDERRESOLVED)) == 0
     assert J.jlb_validate(J.make_problem(dict(ok, steps=500))) == -4                  # JLB_E_WINDOW
     assert J.jlb_validate(J.make_problem(dict(ok, eps1=0.5))) == -1

@@ -190,3 +190,11 @@ def test_smallest_work_first_admission(jlb):
     with pytest.raises(jlb.JlbError):
         eng.set_policy("fifo", -1)
     eng.close()
+
+
+def test_engine_rejects_the_plateau_stop(jlb):
+    eng = jlb.Engine(1 << 30, 2)
+    with pytest.raises(jlb.JlbError) as ei:
+        eng.submit(jlb.make_problem(dict(_mix()[0], plateau_tol=1e-3), "fp32"))
+    assert ei.value.code == -1
+    eng.close()

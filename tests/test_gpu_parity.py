@@ -235,3 +235,26 @@ def test_two_step_config2_matches_single_steps(jlb):
                 assert o[q] == ref[q], (v, q, o[q], ref[q])
     finally:
         jlb.jlb_set_two_step_variant(prec, before)
+
+
+def test_plateau_stop_matches_the_oracle(jlb, oracle):
+    """The plateau stop (Sec. III, energy reaching a constant) decides the same
+    check point on the GPU as in the oracle; FP64 forces then agree to 1e-12,
+    and FP32 with two-step kernels stops at the same step within 1e-3."""
+    p = dict(W.config1(), plateau_tol=1e-3)
+    _print_case("plateau", p)
+    ref = oracle.solve(p)
+    assert ref["steps_done"] < p["steps"]
+    g = jlb.solve(p, "fp64", fields=True)
+    assert g["steps_done"] == ref["steps_done"]
+    _check_fp64(g, ref, "plateau fp64")
+    prec = jlb.PRECISIONS["fp32"]
+    before = jlb.jlb_get_two_step_variant(prec)
+    try:
+        jlb.jlb_set_two_step_variant(prec, 4)
+        f = jlb.solve(p, "fp32")
+    finally:
+        jlb.jlb_set_two_step_variant(prec, before)
+    assert f["steps_done"] == ref["steps_done"]
+    for q in ("fx", "fy", "tz"):
+        assert _rel(f[q], ref[q]) <= 1e-3, (q, f[q], ref[q])
