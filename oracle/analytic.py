@@ -305,3 +305,47 @@ def mdjc_forces_extrapolated(x: float, eps1: float, phi0: float, N: int = 1025, 
         if not (0.5 < p < 3.0):
             p = 4.0 / 3.0
     return tuple(q3 + (q3 - q2) / (2 ** p - 1)), p, (q1, q2, q3)
+
+
+# ----------------------------------------------------------------------------
+# Far field (Sec. II.A): scattering intensity |S(phi)|^2 = k0 r |E^S|^2 / |E^I|^2
+# ----------------------------------------------------------------------------
+
+
+def scattering_coeffs(C, S, x: float, phi0: float):
+    """B_m, D_m of Eq. (scattered field) from the total-field coefficients on
+    r = a: B_m H_m(x) = C_m - incident_m (and likewise D_m with S_m)."""
+    M = len(C) - 1
+    ic, is_, _, _ = incident_coeffs(x, phi0, M)
+    _, inv = _hankel_ratios(x, M)
+    return (np.asarray(C) - ic) * inv, (np.asarray(S) - is_) * inv
+
+
+def far_intensity(B, D, phi):
+    """|S(phi)|^2 at body angles phi for a unit incident amplitude.
+
+    H_m(z) ~ sqrt(2 / (pi z)) exp(j (z - m pi / 2 - pi / 4)) for large z, so
+    k0 r |E^S|^2 -> (2 / pi) |sum_m (-j)^m (B_m cos m phi + D_m sin m phi)|^2.
+    """
+    m = np.arange(len(B))
+    phi = np.atleast_1d(np.asarray(phi, dtype=float))
+    T = np.cos(np.outer(phi, m)) @ ((-1j) ** m * B) + np.sin(np.outer(phi, m)) @ ((-1j) ** m * D)
+    return 2.0 / math.pi * np.abs(T) ** 2
+
+
+def scattered_near_field(B, D, k0: float, R: float, phi):
+    """E_z^S, H_x^S, H_y^S at r = R, body angles phi (Cartesian components in
+    the body frame), time factor exp(-j omega t), eps0 = mu0 = 1, so that
+    curl E = j k0 H: H_x = (dE_z/dy) / (j k0), H_y = -(dE_z/dx) / (j k0)."""
+    m = np.arange(len(B))
+    z = k0 * R
+    h = special.hankel1(m, z)
+    hp = special.h1vp(m, z)
+    phi = np.asarray(phi, dtype=float)
+    cm, sm = np.cos(np.outer(phi, m)), np.sin(np.outer(phi, m))
+    ez = cm @ (B * h) + sm @ (D * h)
+    d_r = k0 * (cm @ (B * hp) + sm @ (D * hp))
+    d_phi = (-sm * m) @ (B * h) + (cm * m) @ (D * h)
+    dx = np.cos(phi) * d_r - np.sin(phi) / R * d_phi
+    dy = np.sin(phi) * d_r + np.cos(phi) / R * d_phi
+    return ez, dy / (1j * k0), -dx / (1j * k0)

@@ -97,6 +97,8 @@ typedef struct {
     int32_t literal;          /* 1 literal 42-scalar populations, 0 reduced 11 */
     int32_t threads;          /* OpenMP threads, <= 0 selects 1 */
     double plateau_tol;       /* > 0: stop once the field energy has reached a plateau (see orc_run) */
+    int32_t far_angles;       /* > 0: far-field intensity at this many angles (see orc_run) */
+    int32_t pad2;
 } orc_params;
 
 typedef struct {
@@ -452,6 +454,48 @@ static void literal_step(const orc_params *p, int edges, int nx, int ny, const u
 }
 
 /* ------------------------------------------------------------------------ */
+/* Near-to-far-field transform (Sec. II.A, Eq. scattering intensity)         */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Far-field scattering intensity from the scattered-field phasors on a closed
+ * contour around the body (time factor exp(-j omega t), lattice units with
+ * eps0 = mu0 = 1 and impedance 1, so curl E = j k0 H).
+ *
+ * Outside the contour the scattered E_z is a radiating solution of the
+ * Helmholtz equation, so Green's second identity with G = (j/4) H_0(k0 |r - r'|)
+ * and the outward normal n gives E_z(r) = int [E_z dG/dn' - G dE_z/dn'] dl'.
+ * With dE_z/dn = -j k0 J_z, J_z = n_x H_y - n_y H_x, and the large-argument
+ * form of H_0, at distance r in direction u = (cos phi, sin phi):
+ *   E_z ~ -(k0/4) sqrt(2 / (pi k0 r)) exp(j (k0 r - pi/4)) I(phi),
+ *   I(phi) = int [J_z - (n.u) E_z] exp(-j k0 u.r') dl',
+ * so |S(phi)|^2 = k0 r |E_z|^2 / |E^I|^2 = k0^2 |I|^2 / (8 pi |E^I|^2).
+ * The contour is given by n samples at positions (rx, ry) relative to the
+ * body centre with outward normals (nx, ny), each of length w.
+ */
+void orc_ntff(int n, const double *rx, const double *ry, const double *nx, const double *ny, double w,
+              const double *ez_re, const double *ez_im, const double *hx_re, const double *hx_im,
+              const double *hy_re, const double *hy_im, double k0, double ei2, int nphi, double *s2)
+{
+    for (int a = 0; a < nphi; ++a) {
+        const double phi = 2.0 * M_PI * a / nphi;
+        const double ux = cos(phi), uy = sin(phi);
+        double ire = 0.0, iim = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double jre = nx[k] * hy_re[k] - ny[k] * hx_re[k];
+            const double jim = nx[k] * hy_im[k] - ny[k] * hx_im[k];
+            const double nu = nx[k] * ux + ny[k] * uy;
+            const double fre = jre - nu * ez_re[k], fim = jim - nu * ez_im[k];
+            const double ph = -k0 * (ux * rx[k] + uy * ry[k]);
+            const double c = cos(ph), sn = sin(ph);
+            ire += w * (fre * c - fim * sn);
+            iim += w * (fre * sn + fim * c);
+        }
+        s2[a] = k0 * k0 * (ire * ire + iim * iim) / (8.0 * M_PI * ei2);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Full solve                                                                */
 /* ------------------------------------------------------------------------ */
 
@@ -465,6 +509,16 @@ static void literal_step(const orc_params *p, int edges, int nx, int ny, const u
  *   ez, hx, hy   optional [ny][nx] outputs, fields after the last step
  *   energy       optional [steps] output, W(n+1) after each step
  *   acc          optional [N_c][4] output, time sums of Ez^2, Hx^2, Hy^2, HxHy
+ *   s2           optional [far_angles] output, far-field intensity |S(phi)|^2
+ *                at lab angles phi = 2 pi a / far_angles (0 = forward)
+ *
+ * Far field (Sec. II.A).  Over the last period of the run the single-bin
+ * phasors F = (2/T) sum_t F(t) exp(j omega t) of Ez, Hx, Hy are accumulated at
+ * the contour samples, and those of the incident wave at the same x from the
+ * companion row (the lattice's own incident wave, uniform in y).  Scattered
+ * = total - incident (Sec. III); the transform is orc_ntff with k0 = 2 pi /
+ * lambda, and |E^I|^2 is the mean incident intensity over the samples (the
+ * incident amplitude in the vicinity of the scatterer).
  *
  * Plateau stop (plateau_tol > 0).  Sec. III judges convergence by the total
  * field energy in the domain approaching a constant.  Reading: the energy W
@@ -478,7 +532,7 @@ static void literal_step(const orc_params *p, int edges, int nx, int ny, const u
  */
 int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
             double *ez_out, double *hx_out, double *hy_out, double *energy,
-            double *acc_out, orc_result *res)
+            double *acc_out, double *s2_out, orc_result *res)
 {
     if (!p || !res || p->nx < 1 || p->ny < 1 || p->steps < 0 || p->wavelength <= 0.0) return ORC_E_ARG;
     const int nx = p->nx, ny = p->ny;
@@ -506,12 +560,17 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
     int64_t period = (int64_t)llround(3.0 * p->wavelength);
     int64_t window = (int64_t)p->avg_periods * period;
     int do_contour = p->boundary == 0 && window > 0;
-    double *acc = NULL;
+    double *acc = NULL, *dft = NULL;
+    int do_far = do_contour && p->far_angles > 0 && s2_out;
     if (do_contour) {
         rc = contour_build(p, &con);
         if (rc != ORC_OK) goto done;
         acc = calloc((size_t)con.n * 4, sizeof(double));
         if (!acc) { rc = ORC_E_OOM; goto done; }
+        if (do_far) {
+            dft = calloc((size_t)con.n * 12, sizeof(double));
+            if (!dft) { rc = ORC_E_OOM; goto done; }
+        }
     }
 
     int64_t stop = p->steps;
@@ -540,6 +599,24 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
                 plateau = 0;
             }
             w_prev = w;
+        }
+        if (do_far && n + 1 > stop - period) {
+            const double ph = 2.0 * M_PI * (double)((n + 1) % period) / (double)period;
+            const double c = cos(ph), sn = sin(ph);
+            const double *sez = sf, *shx = sf + nx, *shy = sf + 2 * (size_t)nx;
+            for (int k = 0; k < con.n; ++k) {
+                const int i0 = (int)floor(con.px[k]);
+                const double fx = con.px[k] - i0;
+                const double g[6] = {bilinear(ez, nx, con.px[k], con.py[k]), bilinear(hx, nx, con.px[k], con.py[k]),
+                                     bilinear(hy, nx, con.px[k], con.py[k]),
+                                     (1.0 - fx) * sez[i0] + fx * sez[i0 + 1],
+                                     (1.0 - fx) * shx[i0] + fx * shx[i0 + 1],
+                                     (1.0 - fx) * shy[i0] + fx * shy[i0 + 1]};
+                for (int q = 0; q < 6; ++q) {
+                    dft[12 * k + 2 * q] += g[q] * c;
+                    dft[12 * k + 2 * q + 1] += g[q] * sn;
+                }
+            }
         }
         if (do_contour && n + 1 > stop - window) {
             for (int k = 0; k < con.n; ++k) {
@@ -596,11 +673,38 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
         res->contour_points = con.n;
         if (acc_out) memcpy(acc_out, acc, sizeof(double) * 4 * con.n);
     }
+    if (do_far) {
+        const double sc = 2.0 / (double)period, k0 = 2.0 * M_PI / p->wavelength;
+        const int nc = con.n;
+        double *buf = calloc((size_t)nc * 8, sizeof(double));
+        if (!buf) { rc = ORC_E_OOM; goto done; }
+        double *rx = buf, *ry = buf + nc, *sre[3], *sim[3];
+        double *tmp = calloc((size_t)nc * 6, sizeof(double));
+        if (!tmp) { free(buf); rc = ORC_E_OOM; goto done; }
+        for (int q = 0; q < 3; ++q) { sre[q] = tmp + (2 * q) * nc; sim[q] = tmp + (2 * q + 1) * nc; }
+        double ei2 = 0.0;
+        for (int k = 0; k < nc; ++k) {
+            rx[k] = con.rc * con.nxv[k];
+            ry[k] = con.rc * con.nyv[k];
+            for (int q = 0; q < 3; ++q) {
+                sre[q][k] = sc * (dft[12 * k + 2 * q] - dft[12 * k + 6 + 2 * q]);
+                sim[q][k] = sc * (dft[12 * k + 2 * q + 1] - dft[12 * k + 7 + 2 * q]);
+            }
+            const double ire = sc * dft[12 * k + 6], iim = sc * dft[12 * k + 7];
+            ei2 += ire * ire + iim * iim;
+        }
+        ei2 /= nc;
+        orc_ntff(nc, rx, ry, con.nxv, con.nyv, 2.0 * M_PI * con.rc / nc, sre[0], sim[0], sre[1], sim[1], sre[2],
+                 sim[2], k0, ei2, p->far_angles, s2_out);
+        free(tmp);
+        free(buf);
+    }
     if (ez_out) memcpy(ez_out, ez, plane * sizeof(double));
     if (hx_out) memcpy(hx_out, hx, plane * sizeof(double));
     if (hy_out) memcpy(hy_out, hy, plane * sizeof(double));
     if (state_io) memcpy(state_io, a, nstate * sizeof(double));
     free(acc);
+    free(dft);
 
 done:
     contour_free(&con);

@@ -40,7 +40,7 @@ class _Params(ctypes.Structure):
         ("avg_periods", ctypes.c_int32), ("ramp_periods", ctypes.c_int32),
         ("contour_offset", ctypes.c_double), ("contour_points", ctypes.c_int32),
         ("boundary", ctypes.c_int32), ("literal", ctypes.c_int32), ("threads", ctypes.c_int32),
-        ("plateau_tol", ctypes.c_double),
+        ("plateau_tol", ctypes.c_double), ("far_angles", ctypes.c_int32), ("pad2", ctypes.c_int32),
     ]
 
 
@@ -78,8 +78,11 @@ def _load():
         lib.orc_mask.restype = ctypes.c_int
         lib.orc_run.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                ctypes.c_void_p, ctypes.POINTER(_Result)]
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Result)]
         lib.orc_run.restype = ctypes.c_int
+        lib.orc_ntff.argtypes = ([ctypes.c_int] + [ctypes.c_void_p] * 4 + [ctypes.c_double] + [ctypes.c_void_p] * 6
+                                 + [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_void_p])
+        lib.orc_ntff.restype = None
         lib.orc_contour_points.argtypes = [ctypes.POINTER(_Params)]
         lib.orc_contour_points.restype = ctypes.c_int
         _lib = lib
@@ -129,9 +132,13 @@ def contour_points(prob: dict) -> int:
 
 def solve(prob: dict, *, literal: bool = False, boundary: str = "open", mat: np.ndarray | None = None,
           state: np.ndarray | None = None, fields: bool = True, energy: bool = False,
-          accumulators: bool = False, threads: int | None = None) -> dict:
-    """Run the oracle.  Returns forces, optional fields, energy trace, final state."""
+          accumulators: bool = False, threads: int | None = None, far_angles: int = 0) -> dict:
+    """Run the oracle.  Returns forces, optional fields, energy trace, final
+    state, and the far-field intensity at far_angles lab angles (key "s2")."""
     p = _params(prob, boundary=boundary, literal=literal, threads=threads)
+    p.far_angles = int(far_angles)
+    if far_angles > 0 and (boundary != "open" or p.avg_periods <= 0):
+        raise ValueError("the far field needs open edges and an averaging window (its last period)")
     shape = (p.ny, p.nx)
     if mat is not None:
         mat = np.ascontiguousarray(mat, dtype=np.uint8)
@@ -146,9 +153,10 @@ def solve(prob: dict, *, literal: bool = False, boundary: str = "open", mat: np.
     en = np.zeros(max(p.steps, 1)) if energy else None
     ncp = _load().orc_contour_points(ctypes.byref(p))
     acc = np.zeros((ncp, 4)) if accumulators else None
+    s2 = np.zeros(far_angles) if far_angles > 0 else None
     res = _Result()
     rc = _load().orc_run(ctypes.byref(p), _ptr(mat), _ptr(st), _ptr(ez), _ptr(hx), _ptr(hy), _ptr(en),
-                         _ptr(acc), ctypes.byref(res))
+                         _ptr(acc), _ptr(s2), ctypes.byref(res))
     if rc != 0:
         raise ValueError("oracle run failed: %d" % rc)
     out = {k: getattr(res, k) for k in ("fx", "fy", "tz", "fx_raw", "fy_raw", "tz_raw", "energy_final",
@@ -159,6 +167,21 @@ def solve(prob: dict, *, literal: bool = False, boundary: str = "open", mat: np.
         out["energy"] = en[: p.steps]
     if accumulators:
         out["acc"] = acc
+    if s2 is not None:
+        out["s2"] = s2
     if st is not None:
         out["state"] = st
+    return out
+
+
+def ntff(rx, ry, nx, ny, w: float, ez, hx, hy, k0: float, ei2: float, nphi: int) -> np.ndarray:
+    """The oracle's near-to-far-field transform on given complex phasors."""
+    arr = [np.ascontiguousarray(a, dtype=np.float64) for a in (rx, ry, nx, ny)]
+    comp = []
+    for f in (ez, hx, hy):
+        f = np.asarray(f, dtype=np.complex128)
+        comp += [np.ascontiguousarray(f.real), np.ascontiguousarray(f.imag)]
+    out = np.zeros(nphi)
+    _load().orc_ntff(ctypes.c_int(len(arr[0])), *[_ptr(a) for a in arr], ctypes.c_double(w), *[_ptr(a) for a in comp],
+                     ctypes.c_double(k0), ctypes.c_double(ei2), ctypes.c_int(nphi), _ptr(out))
     return out

@@ -1,0 +1,110 @@
+"""Pins of the oracle's far field (arXiv 2509.22308, Sec. II.A, Eq. scattering
+intensity) against closed forms and physical laws.  All run on the CPU.
+
+* The near-to-far-field transform, fed the exact near field of a cylindrical
+  wave series, must give that series' asymptotic far field (large-argument
+  Hankel forms) to quadrature accuracy.
+* The lattice far field must match the Mie series of a dielectric cylinder
+  and the paper's analytic Janus solution within the staircase error that
+  the forces also carry.
+* For a lossless body the far field alone fixes the radiation force
+  (momentum balance), independently of the stress integral on the contour.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import analytic as A
+from oracle import oracle as O
+
+
+def _circle(R, n):
+    th = 2 * math.pi * (np.arange(n) + 0.5) / n
+    c, s = np.cos(th), np.sin(th)
+    return th, R * c, R * s, c, s, 2 * math.pi * R / n
+
+
+def test_ntff_reproduces_the_far_field_of_the_mie_series():
+    """Exact scattered near field of a dielectric cylinder (eps_r 2,
+    k0 a = pi / 2) on r = 1.3 a, through the transform, vs (2 / pi) |T|^2."""
+    x, a = math.pi / 2, 10.0
+    k0 = x / a
+    C, S, _, _ = A.mie_coeffs(x, 2.0, 0.0)
+    B, D = A.scattering_coeffs(C, S, x, 0.0)
+    th, rx, ry, nx, ny, w = _circle(13.0, 720)
+    ez, hx, hy = A.scattered_near_field(B, D, k0, 13.0, th)
+    s2 = O.ntff(rx, ry, nx, ny, w, ez, hx, hy, k0, 1.0, 72)
+    ref = A.far_intensity(B, D, 2 * math.pi * np.arange(72) / 72)
+    np.testing.assert_allclose(s2, ref, rtol=0, atol=1e-12 * ref.max())
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_ntff_reproduces_an_asymmetric_radiating_field(seed):
+    """Random B_m, D_m (no mirror symmetry, so a flipped phase sign, normal
+    term sign or angle orientation cannot pass), incident amplitude 2."""
+    rng = np.random.default_rng(seed)
+    M = 10
+    B = (rng.normal(size=M) + 1j * rng.normal(size=M)) / (1.0 + np.arange(M)) ** 2
+    D = (rng.normal(size=M) + 1j * rng.normal(size=M)) / (1.0 + np.arange(M)) ** 2
+    D[0] = 0.0
+    k0, R = 2 * math.pi / 30.0, 17.0
+    th, rx, ry, nx, ny, w = _circle(R, 900)
+    ez, hx, hy = A.scattered_near_field(B, D, k0, R, th)
+    s2 = O.ntff(rx, ry, nx, ny, w, 2 * ez, 2 * hx, 2 * hy, k0, 4.0, 90)
+    ref = A.far_intensity(B, D, 2 * math.pi * np.arange(90) / 90)
+    np.testing.assert_allclose(s2, ref, rtol=0, atol=1e-9 * ref.max())
+    assert np.max(np.abs(s2 - ref[::-1])) > 0.05 * ref.max()
+
+
+def test_lattice_far_field_matches_the_mie_series():
+    """Dielectric cylinder (eps_r 2, a = 10, lambda = 40): within 2 % of the
+    peak intensity; zero lift means a mirror-symmetric pattern."""
+    r = O.solve(W.config1(), fields=False, far_angles=72)
+    x = math.pi / 2
+    C, S, _, _ = A.mie_coeffs(x, 2.0, 0.0)
+    B, D = A.scattering_coeffs(C, S, x, 0.0)
+    phi = 2 * math.pi * np.arange(72) / 72
+    ref = A.far_intensity(B, D, phi + math.pi)  # lab angle 0 = body angle phi0 + pi
+    s2 = r["s2"]
+    assert np.max(np.abs(s2 - ref)) < 0.02 * ref.max(), np.max(np.abs(s2 - ref)) / ref.max()
+    np.testing.assert_allclose(s2[1:], s2[1:][::-1], rtol=1e-12)
+
+
+@pytest.mark.parametrize("eps1,deg", [(4.0, 30.0), (2.0, 0.0)])
+def test_lattice_far_field_matches_the_janus_solution(eps1, deg):
+    """Metallo-dielectric Janus cylinder, a = 24, a / lambda = 0.5, vs the
+    scattered series of Sec. IV.A's integral-equation solution: within 5 % of
+    the peak (the staircase error of the forces); the mirrored pattern is
+    far off, so the lab/body orientation is pinned too."""
+    p = W.small_mdjc(eps1, deg, a=24)
+    r = O.solve(p, fields=False, far_angles=72)
+    x, phi0 = math.pi, math.radians(deg)
+    C, S, _, _ = A.mdjc_coeffs(x, eps1, phi0, 1025)
+    B, D = A.scattering_coeffs(C, S, x, phi0)
+    phi = 2 * math.pi * np.arange(72) / 72
+    ref = A.far_intensity(B, D, phi + phi0 + math.pi)
+    err = np.max(np.abs(r["s2"] - ref)) / ref.max()
+    assert err < 0.05, err
+    if deg != 0.0:
+        mirrored = A.far_intensity(B, D, -phi + phi0 + math.pi)
+        assert np.max(np.abs(r["s2"] - mirrored)) / ref.max() > 0.2
+
+
+@pytest.mark.parametrize("case", ["mie", "janus"])
+def test_far_field_momentum_balance_gives_the_stress_force(case):
+    """Lossless body: F = (1 / (2 k0)) int |S|^2 (k_inc - r_hat) dphi in units
+    of E0^2 (|S|^2 = k0 r |E^S|^2 / |E^I|^2, energy density flux |E|^2 / 2);
+    normalised by F0 = pi a / 4 it must agree with the contour stress."""
+    p = W.config1() if case == "mie" else W.small_mdjc(4.0, 30.0, a=24)
+    r = O.solve(p, fields=False, far_angles=360)
+    s2 = r["s2"]
+    phi = 2 * math.pi * np.arange(360) / 360
+    k0, f0 = 2 * math.pi / p["wavelength"], math.pi * p["radius"] / 4
+    d = 2 * math.pi / 360
+    fx = np.sum(s2 * (1 - np.cos(phi))) * d / (2 * k0 * f0)
+    fy = -np.sum(s2 * np.sin(phi)) * d / (2 * k0 * f0)
+    assert abs(fx - r["fx"]) < 0.03 * abs(r["fx"]), (fx, r["fx"])
+    assert abs(fy - r["fy"]) < 0.01 + 0.03 * abs(r["fy"]), (fy, r["fy"])
+
