@@ -177,6 +177,31 @@ int jlb_solve(const jlb_problem *prob, void *workspace, size_t workspace_bytes, 
               double *ez, double *hx, double *hy, double *energy, void *stream);
 
 /*
+ * Far field (Sec. II.A, Eq. scattering intensity): the solve of jlb_solve
+ * (same forces in *res) plus the scattering intensity
+ *   |S(phi)|^2 = k0 r |E^S|^2 / |E^I|^2  (r -> infinity)
+ * at the lab angles phi_a = 2 pi a / n_angles, a = 0 .. n_angles - 1 (0 is
+ * the incident direction +x, angles counter-clockwise), into the caller's
+ * device array s2[n_angles] of double.
+ * Method: over the last period T of the run (single-step launches) the
+ * single-bin phasors (2 / T) sum_t F(t) exp(j omega t) of Ez, Hx, Hy are
+ * accumulated in FP64 at the stress contour's samples, together with those
+ * of the lattice's own incident wave (the companion row) at the same x;
+ * scattered = total - incident (Sec. III).  A near-to-far-field transform on
+ * the contour (Green's theorem with the large-argument Hankel form) gives
+ *   |S|^2 = k0^2 |I|^2 / (8 pi |E^I|^2),
+ *   I(phi) = sum_k w [J_z - (n_k . u) E_z^S] exp(-j k0 u . r_k),
+ * J_z = n_x H_y - n_y H_x, u = (cos phi, sin phi), w = 2 pi R_c / N_c,
+ * k0 = 2 pi / lambda, |E^I|^2 the mean incident intensity over the samples.
+ * Errors: as jlb_solve; JLB_E_ARG for s2 NULL or n_angles outside
+ * 1..JLB_MAX_FAR_ANGLES.  The plateau stop applies as in jlb_solve (the
+ * phasors then cover the last period before its stop).
+ */
+#define JLB_MAX_FAR_ANGLES 65536
+int jlb_solve_far_field(const jlb_problem *prob, void *workspace, size_t workspace_bytes, jlb_result *res,
+                        int32_t n_angles, double *s2, void *stream);
+
+/*
  * Times `launches` back-to-back launches of the fused lattice-step kernel
  * of `prob` (no contour work), on `stream`, between two HIP events, after
  * `warmup` untimed launches; *ms_per_launch (host) receives the mean.  The

@@ -80,6 +80,8 @@ def load():
             "jlb_material_map": ([_P(jlb_problem), _vp], ctypes.c_int),
             "jlb_solve": ([_P(jlb_problem), _vp, ctypes.c_size_t, _P(jlb_result), _vp, _vp, _vp, _vp, _vp],
                           ctypes.c_int),
+            "jlb_solve_far_field": ([_P(jlb_problem), _vp, ctypes.c_size_t, _P(jlb_result), ctypes.c_int32, _vp,
+                                     _vp], ctypes.c_int),
             "jlb_time_step_kernel": ([_P(jlb_problem), _vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
                                       _P(ctypes.c_double), _vp], ctypes.c_int),
             "jlb_autotune": ([_P(jlb_problem), _vp, ctypes.c_size_t, ctypes.c_int32, _P(ctypes.c_int32),
@@ -177,6 +179,16 @@ def jlb_solve(prob: jlb_problem, workspace=None, ez=None, hx=None, hy=None, ener
     return res
 
 
+def jlb_solve_far_field(prob: jlb_problem, n_angles: int, s2, workspace=None, stream=None) -> jlb_result:
+    """One solve plus the far-field intensity at n_angles lab angles into the
+    CUDA float64 tensor s2 (see jlb_solve_far_field in include/jlb.h)."""
+    res = jlb_result()
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(load().jlb_solve_far_field(ctypes.byref(prob), _dptr(workspace), nbytes, ctypes.byref(res), int(n_angles),
+                                      _dptr(s2), _stream(stream)))
+    return res
+
+
 def jlb_time_step_kernel(prob: jlb_problem, warmup: int, launches: int, workspace=None, stream=None) -> float:
     ms = ctypes.c_double(0.0)
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
@@ -251,11 +263,20 @@ def jlb_time_two_step_kernel(prob: jlb_problem, warmup: int, launches: int, work
 
 
 def solve(d: dict, precision: str = "fp64", fields: bool = False, energy: bool = False, flags: int = 0,
-          device: str = "cuda") -> dict:
-    """Convenience wrapper: torch-allocated workspace and outputs; returns numpy arrays."""
+          device: str = "cuda", far_angles: int = 0) -> dict:
+    """Convenience wrapper: torch-allocated workspace and outputs; returns
+    numpy arrays.  far_angles > 0 runs jlb_solve_far_field (key "s2"; not
+    combinable with fields or energy)."""
     import torch
     prob = make_problem(d, precision, flags)
     ws = torch.empty(jlb_workspace_size(prob), dtype=torch.uint8, device=device)
+    if far_angles > 0:
+        if fields or energy:
+            raise ValueError("far_angles does not combine with fields or energy")
+        s2 = torch.empty(far_angles, dtype=torch.float64, device=device)
+        out = jlb_solve_far_field(prob, far_angles, s2, ws).as_dict()
+        out["s2"] = s2.cpu().numpy()
+        return out
     f = [torch.empty((prob.ny, prob.nx), dtype=torch.float64, device=device) for _ in range(3)] if fields else [None] * 3
     en = torch.empty(prob.steps, dtype=torch.float64, device=device) if energy else None
     res = jlb_solve(prob, ws, *f, en)

@@ -193,7 +193,7 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
     q[10] = hy / 6.0;
 #pragma unroll
     for (int k = 0; k < 11; ++k) put(&dst[k * P + c], 2.0 * q[k] - f[k], L.stream_stores);
-    if (fields && j < L.ny) {
+    if (fields) {  // row ny: the incident wave's fields (read by the far-field phasors)
         const size_t cf = at(i, j, L.sfld);
         fields[0 * P + cf] = ez;
         fields[1 * P + cf] = hx;
@@ -1210,6 +1210,88 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ContourDev C, double inv
 }
 
 // ---------------------------------------------------------------------------
+// Far field (Sec. II.A).  Single-bin phasors over the last period at the
+// contour samples: for each level t, dft += F(t) (cos, sin)(omega t) for the
+// bilinear Ez, Hx, Hy and for the incident wave's Ez, Hx, Hy from the
+// companion row (row ny) at the sample's x.  Layout [12][n]: (re, im) of
+// Ez, Hx, Hy, then of the incident Ez, Hx, Hy.  FP64 arithmetic on the stored
+// fields; one thread per sample, no atomics.
+// ---------------------------------------------------------------------------
+
+template <typename FT>
+__global__ void k_far_dft(Lattice L, const FT *__restrict__ fld, ContourDev C, double *__restrict__ dft, double cw,
+                          double sw)
+{
+#pragma clang fp contract(off)
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= C.n) return;
+    const size_t P = L.plane;
+    const int i0 = C.i0[k];
+    const size_t c00 = at(i0, C.j0[k], L.sfld);
+    const size_t c10 = c00 + L.sfld;
+    const size_t cs = at(i0, L.ny, L.sfld);
+    const double fx = C.wx[k], fy = C.wy[k];
+    const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy), w10 = (1.0 - fx) * fy, w11 = fx * fy;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const FT *p = fld + a * P;
+        const double v = w00 * (double)p[c00] + w01 * (double)p[c00 + 1] + w10 * (double)p[c10] +
+                         w11 * (double)p[c10 + 1];
+        const double u = (1.0 - fx) * (double)p[cs] + fx * (double)p[cs + 1];
+        dft[(2 * a) * C.n + k] += v * cw;
+        dft[(2 * a + 1) * C.n + k] += v * sw;
+        dft[(6 + 2 * a) * C.n + k] += u * cw;
+        dft[(7 + 2 * a) * C.n + k] += u * sw;
+    }
+}
+
+// Near-to-far-field transform of the phasors (scale 2 / T turns the sums into
+// amplitudes; scattered = total - incident).  With exp(-j omega t), curl E =
+// j k0 H and the outward normal n at r' = rc n:
+//   I(phi) = sum_k w [J_z - (n.u) E_z^S] exp(-j k0 u.r'),  J_z = n_x H_y - n_y H_x,
+//   |S(phi)|^2 = k0^2 |I|^2 / (8 pi |E^I|^2),  u = (cos phi, sin phi),
+// |E^I|^2 the mean incident intensity over the samples, w = 2 pi rc / n.
+// One wave per angle (blocks of 64); fixed-order wave reductions.
+__global__ __launch_bounds__(64) void k_far_field(ContourDev C, const double *__restrict__ dft, double k0,
+                                                  double scale, int nphi, double *__restrict__ s2)
+{
+    const int a = blockIdx.x;
+    const int t = threadIdx.x;
+    if (a >= nphi) return;
+    const int n = C.n;
+    const double phi = 2.0 * M_PI * (double)a / (double)nphi;
+    const double ux = cos(phi), uy = sin(phi);
+    double ire = 0.0, iim = 0.0, ei2 = 0.0;
+    for (int k = t; k < n; k += 64) {
+        const double nx = C.nxk[k], ny = C.nyk[k];
+        double re[3], im[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            re[q] = scale * (dft[(2 * q) * n + k] - dft[(6 + 2 * q) * n + k]);
+            im[q] = scale * (dft[(2 * q + 1) * n + k] - dft[(7 + 2 * q) * n + k]);
+        }
+        const double ir = scale * dft[6 * n + k], ii = scale * dft[7 * n + k];
+        ei2 += ir * ir + ii * ii;
+        const double nu = nx * ux + ny * uy;
+        const double fre = (nx * re[2] - ny * re[1]) - nu * re[0];
+        const double fim = (nx * im[2] - ny * im[1]) - nu * im[0];
+        double sp, cp;
+        sincos(-k0 * C.rc * nu, &sp, &cp);
+        ire += fre * cp - fim * sp;
+        iim += fre * sp + fim * cp;
+    }
+    ire = wave_sum(ire);
+    iim = wave_sum(iim);
+    ei2 = wave_sum(ei2);
+    if (t == 0) {
+        const double w = 2.0 * M_PI * C.rc / (double)n;
+        ire *= w;
+        iim *= w;
+        s2[a] = k0 * k0 * (ire * ire + iim * iim) / (8.0 * M_PI * (ei2 / (double)n));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Field energy sum (eps Ez^2 + Hx^2 + Hy^2) / 2 over the domain rows: one
 // partial per block, then one fixed-order pass.
 // ---------------------------------------------------------------------------
@@ -1400,6 +1482,25 @@ hipError_t launch_contour2(const Lattice &L, const float *mid, const void *state
     const int threads = 128;
     const int blocks = (C.n + threads - 1) / threads;
     hipLaunchKernelGGL(k_contour2_f32, dim3(blocks), dim3(threads), 0, s, L, mid, (const float *)state, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_far_dft(int precision, const Lattice &L, const void *fields, const ContourDev &C, double *dft,
+                          double cw, double sw, hipStream_t s)
+{
+    const int threads = 128, blocks = (C.n + threads - 1) / threads;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_far_dft<double>, dim3(blocks), dim3(threads), 0, s, L, (const double *)fields, C, dft, cw,
+                           sw);
+    else
+        hipLaunchKernelGGL(k_far_dft<float>, dim3(blocks), dim3(threads), 0, s, L, (const float *)fields, C, dft, cw, sw);
+    return hipGetLastError();
+}
+
+hipError_t launch_far_field(const ContourDev &C, const double *dft, double k0, double scale, int nphi, double *s2,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_far_field, dim3(nphi), dim3(64), 0, s, C, dft, k0, scale, nphi, s2);
     return hipGetLastError();
 }
 

@@ -143,6 +143,7 @@ int make_plan(const jlb_problem *p, Plan *pl)
     q.off_nxk = take(q.nc * sizeof(double));
     q.off_nyk = take(q.nc * sizeof(double));
     q.off_acc = take(4 * q.nc * sizeof(double));
+    q.off_dft = take(12 * q.nc * sizeof(double));  // far-field phasor sums
     q.off_out = take(8 * sizeof(double));
     Lattice tmp{};
     tmp.nx = q.nx;
@@ -337,6 +338,7 @@ int upload_setup(const Plan &q, char *ws, hipStream_t s)
     HIP_TRY(hipMemsetAsync(ws + q.off_state[1], 0, q.state_bytes, s));
     if (q.prob.precision == JLB_FP64) HIP_TRY(hipMemsetAsync(ws + q.off_fields, 0, 2 * 3 * q.plane * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(ws + q.off_acc, 0, 4 * q.nc * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(ws + q.off_dft, 0, 12 * q.nc * sizeof(double), s));
     // the host vectors are released on return: finish the copies first
     HIP_TRY(hipStreamSynchronize(s));
     return JLB_OK;
@@ -372,7 +374,7 @@ static int launch_one_step(const Plan &q, char *ws, const Lattice &L, const Cont
 }
 
 int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, double *hy, double *energy,
-              hipStream_t s)
+              hipStream_t s, FarOut far)
 {
     const auto t0 = std::chrono::steady_clock::now();
     memset(res, 0, sizeof(*res));
@@ -462,9 +464,13 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     int64_t n = 0;
     int64_t passes = 0;
     int graph_used = 0;
+    double *dft = (double *)(ws + q.off_dft);
     while (n < steps && rc == JLB_OK) {
         const bool in_window = n >= wstart;
-        const int64_t seg_end = in_window ? steps : wstart;  // chunk must not straddle the window start
+        // chunk must not straddle the window start; the far field's last
+        // period runs as single launches, each followed by its phasor terms
+        const int64_t far_start = far.s2 ? steps - q.T : steps;
+        const int64_t seg_end = std::min(in_window ? steps : wstart, far_start);
         if (use_graph && n >= ramp_end && n + chunk <= seg_end) {
             const int which = in_window ? 1 : 0;
             if (!gexec[which]) {
@@ -500,6 +506,13 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
                                          q.nparts, energy + n, s);
             if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "energy launch: %s", hipGetErrorString(e));
         }
+        if (far.s2 && n >= far_start && rc == JLB_OK) {
+            // level n + 1 is inside the window (window >= T), so its fields are in place
+            const double ph = 2.0 * M_PI * (double)((n + 1) % q.T) / (double)q.T;
+            hipError_t e = launch_far_dft(q.prob.precision, L, fields_ptr(q, ws, n + 1), C, dft, std::cos(ph),
+                                          std::sin(ph), s);
+            if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "far-field phasor launch: %s", hipGetErrorString(e));
+        }
         ++n;
     }
     if (rc == JLB_OK) {
@@ -507,6 +520,8 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
         if (e == hipSuccess) e = launch_reduce(C, 1.0 / (double)q.window, M_PI * q.prob.radius * q.prob.e0 * q.prob.e0 / 4.0,
                                                2.0 * (M_PI * q.prob.radius * q.prob.e0 * q.prob.e0 / 4.0) * q.prob.radius,
                                                (double *)(ws + q.off_out), s);
+        if (e == hipSuccess && far.s2)
+            e = launch_far_field(C, dft, 2.0 * M_PI / q.prob.wavelength, 2.0 / (double)q.T, far.nphi, far.s2, s);
         if (e == hipSuccess && ez && hx && hy)
             e = launch_fields_out(q.prob.precision, L, fields_ptr(q, ws, steps), ez, hx, hy, s);
         double out[8] = {0};
@@ -605,8 +620,8 @@ int jlb_material_map(const jlb_problem *prob, uint8_t *mat)
     return JLB_OK;
 }
 
-int jlb_solve(const jlb_problem *prob, void *workspace, size_t workspace_bytes, jlb_result *res, double *ez,
-              double *hx, double *hy, double *energy, void *stream)
+static int solve_entry(const jlb_problem *prob, void *workspace, size_t workspace_bytes, jlb_result *res, double *ez,
+                       double *hx, double *hy, double *energy, void *stream, FarOut far)
 {
     clear_error();
     if (!res) return fail(JLB_E_ARG, "null result");
@@ -628,13 +643,30 @@ int jlb_solve(const jlb_problem *prob, void *workspace, size_t workspace_bytes, 
         if (e != hipSuccess) return fail(JLB_E_OOM, "hipMalloc(%zu): %s", q.ws_bytes, hipGetErrorString(e));
         owned = true;
     }
-    rc = run_solve(q, ws, res, ez, hx, hy, energy, own);
+    rc = run_solve(q, ws, res, ez, hx, hy, energy, own, far);
     int rc2 = join.end();
     if (owned) {
         (void)hipStreamSynchronize(own);
         (void)hipFree(ws);
     }
     return rc ? rc : rc2;
+}
+
+int jlb_solve(const jlb_problem *prob, void *workspace, size_t workspace_bytes, jlb_result *res, double *ez,
+              double *hx, double *hy, double *energy, void *stream)
+{
+    return solve_entry(prob, workspace, workspace_bytes, res, ez, hx, hy, energy, stream, FarOut{0, nullptr});
+}
+
+int jlb_solve_far_field(const jlb_problem *prob, void *workspace, size_t workspace_bytes, jlb_result *res,
+                        int32_t n_angles, double *s2, void *stream)
+{
+    clear_error();
+    if (!s2) return fail(JLB_E_ARG, "null s2");
+    if (n_angles < 1 || n_angles > JLB_MAX_FAR_ANGLES)
+        return fail(JLB_E_ARG, "n_angles %d outside 1..%d", n_angles, JLB_MAX_FAR_ANGLES);
+    return solve_entry(prob, workspace, workspace_bytes, res, nullptr, nullptr, nullptr, nullptr, stream,
+                       FarOut{n_angles, s2});
 }
 
 static int time_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,

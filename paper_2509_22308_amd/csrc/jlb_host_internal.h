@@ -27,7 +27,7 @@ struct Plan {
     size_t state_bytes;     // one state buffer
     int bytes_per_lup;      // algorithmic HBM bytes per lattice update
     size_t off_state[2], off_fields, off_mid, off_mask, off_i0, off_j0, off_wx, off_wy, off_nxk, off_nyk, off_acc,
-        off_out, off_parts;
+        off_dft, off_out, off_parts;
     int nparts;
     size_t ws_bytes;
 };
@@ -53,7 +53,12 @@ int upload_setup(const Plan &q, char *ws, hipStream_t s);
 int step_variant(int precision);
 // Two-step variant of a precision (-1: single steps only; always -1 for FP64).
 int two_step_variant(int precision);
+// Far-field output of a solve: nphi angles into the device array s2 (nullptr: none).
+struct FarOut {
+    int nphi;
+    double *s2;
+};
 int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, double *hy, double *energy,
-              hipStream_t s);
+              hipStream_t s, FarOut far = {0, nullptr});
 
 }  // namespace jlb

@@ -115,6 +115,13 @@ hipError_t launch_contour2(const Lattice &L, const float *mid, const void *state
 // state for precisions 1 and 2.
 hipError_t launch_contour(int precision, const Lattice &L, const void *fields, const ContourDev &C, hipStream_t s);
 hipError_t launch_reduce(const ContourDev &C, double inv_window, double f0, double m0, double *out, hipStream_t s);
+// Far field: accumulate one level's phasor terms (cw, sw = cos, sin of omega t)
+// at the contour samples into dft[12][n]; then the transform into s2[nphi]
+// (scale = 2 / T).
+hipError_t launch_far_dft(int precision, const Lattice &L, const void *fields, const ContourDev &C, double *dft,
+                          double cw, double sw, hipStream_t s);
+hipError_t launch_far_field(const ContourDev &C, const double *dft, double k0, double scale, int nphi, double *s2,
+                            hipStream_t s);
 hipError_t launch_energy(int precision, const Lattice &L, const void *fields, double *partials, int nparts,
                          double *out, hipStream_t s);
 int energy_partials(const Lattice &L);

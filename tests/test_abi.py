@@ -52,6 +52,19 @@ def test_problem_checks_return_the_documented_codes():
     assert "eps1" in J.jlb_last_error()
 
 
+def test_far_field_entry_checks_its_arguments_before_the_device():
+    import ctypes
+    lib = J.load()
+    prob = J.make_problem(W.config1())
+    res = J.jlb_result()
+    buf = (ctypes.c_double * 4)()
+    assert lib.jlb_solve_far_field(ctypes.byref(prob), None, 0, ctypes.byref(res), 4, None, None) == -1
+    assert "s2" in J.jlb_last_error()
+    for n in (0, -3, 65537):
+        rc = lib.jlb_solve_far_field(ctypes.byref(prob), None, 0, ctypes.byref(res), n, ctypes.cast(buf, J._vp), None)
+        assert rc == -1 and "n_angles" in J.jlb_last_error()
+
+
 def test_workspace_grows_with_precision_and_grid():
     p = W.config2()
     sizes = [J.jlb_workspace_size(J.make_problem(p, prec)) for prec in ("bf16", "fp32", "fp64")]
