@@ -202,6 +202,26 @@ int jlb_solve_far_field(const jlb_problem *prob, void *workspace, size_t workspa
                         int32_t n_angles, double *s2, void *stream);
 
 /*
+ * Overdamped motion of the cylinder under its radiation force and torque
+ * (Sec. IV.C: force and torque balance with the slender-body resistance,
+ * giving in t~ = t / T0, T0 = a eta / F0, (x~, y~) = (x, y) / a:
+ *   dx~/dt~ = log(l/a) F~x(phi0) / (4 pi),  dy~/dt~ = log(l/a) F~y(phi0) / (4 pi),
+ *   dphi0/dt~ = M~z(phi0) / (2 pi)).
+ * F~x, F~y, M~z are one row of a design map: host arrays of n >= 4 samples at
+ * the uniform angles phi_k = phi_first + 2 pi k / n (one period, no repeated
+ * end point), interpolated by the periodic cubic spline through them.  The
+ * classical fourth-order Runge-Kutta method with step dt integrates nsteps
+ * steps from (0, 0, phi_start).  out (host, caller-owned) receives
+ * floor(nsteps / record_every) + 1 rows of (t~, x~, y~, phi0) at steps 0,
+ * record_every, 2 record_every, ...; phi0 is not wrapped.  Host only (no
+ * device work).  Errors: JLB_E_ARG for n < 4, a NULL array, dt <= 0,
+ * nsteps < 0, record_every < 1 or a non-finite input.
+ */
+int jlb_trajectory(int32_t n, double phi_first, const double *fx, const double *fy, const double *tz,
+                   double phi_start, double dt, int64_t nsteps, double log_l_over_a, int32_t record_every,
+                   double *out);
+
+/*
  * Times `launches` back-to-back launches of the fused lattice-step kernel
  * of `prob` (no contour work), on `stream`, between two HIP events, after
  * `warmup` untimed launches; *ms_per_launch (host) receives the mean.  The

@@ -82,6 +82,8 @@ def load():
                           ctypes.c_int),
             "jlb_solve_far_field": ([_P(jlb_problem), _vp, ctypes.c_size_t, _P(jlb_result), ctypes.c_int32, _vp,
                                      _vp], ctypes.c_int),
+            "jlb_trajectory": ([ctypes.c_int32, ctypes.c_double, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _vp], ctypes.c_int),
             "jlb_time_step_kernel": ([_P(jlb_problem), _vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
                                       _P(ctypes.c_double), _vp], ctypes.c_int),
             "jlb_autotune": ([_P(jlb_problem), _vp, ctypes.c_size_t, ctypes.c_int32, _P(ctypes.c_int32),

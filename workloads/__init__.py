@@ -97,6 +97,44 @@ def config5_requests(seed: int = 22308, n_req: int = 256, rate: float = 20.0, a_
     return out
 
 
+def paper_mdjc_map(eps_stride: int = 1, phi_stride: int = 1) -> tuple[list[dict], list[float], list[float]]:
+    """The metallo-dielectric design map of Sec. IV.A (Fig. HS75_Map): a / lambda = 1,
+    a / dx = 40, domain L / a = 4 (160^2); phi0 = j pi / 90 (j = 0..180, i.e. 0..2 pi)
+    and eps_r1 = 1 + 0.04 i (i = 0..100); 52 periods, the last 5 averaged.
+    Returns (problems in row-major (eps, phi) order, eps axis, phi axis)."""
+    a = 40
+    eps = [round(1.0 + 0.04 * i, 10) for i in range(0, 101, eps_stride)]
+    phi = [j * math.pi / 90 for j in range(0, 181, phi_stride)]
+    probs = [problem(nx=4 * a, ny=4 * a, radius=float(a), kind="metallo_dielectric_janus", eps1=e, phi0=f,
+                     wavelength=float(a), steps=steps_for(float(a))) for e in eps for f in phi]
+    return probs, eps, phi
+
+
+def paper_djc_map(eps1: float, eps_stride: int = 1, phi_stride: int = 1) -> tuple[list[dict], list[float], list[float]]:
+    """A dielectric design map of Sec. IV.B (Fig. 2D_map; eps_r1 = 1, 2 or 5): a / lambda = 1,
+    a / dx = 50, L / a = 4 (200^2); phi0 = j pi / 90 (j = 0..180) and
+    eps_r2 / eps_r1 = 1 + 0.04 i (i = 0..100); 52 periods, the last 5 averaged.
+    Returns (problems in row-major (ratio, phi) order, ratio axis, phi axis)."""
+    a = 50
+    ratio = [round(1.0 + 0.04 * i, 10) for i in range(0, 101, eps_stride)]
+    phi = [j * math.pi / 90 for j in range(0, 181, phi_stride)]
+    probs = [problem(nx=4 * a, ny=4 * a, radius=float(a), kind="dielectric_janus", eps1=float(eps1),
+                     eps2=float(eps1) * r, phi0=f, wavelength=float(a), steps=steps_for(float(a)))
+             for r in ratio for f in phi]
+    return probs, ratio, phi
+
+
+def paper_far_field_case(eps1: float, phi0: float) -> dict:
+    """The far-field validation of Sec. IV.A.1 (Fig. SW): metallo-dielectric
+    Janus, a / lambda = 1, lambda_eps / dx = 50 inside the dielectric (lambda =
+    50 sqrt(eps_r1), rounded down so that 3 lambda is whole), L / a = 10;
+    52 periods."""
+    lam = math.floor(3 * 50 * math.sqrt(eps1) + 1e-9) / 3
+    n = int(math.ceil(10 * lam))
+    return problem(nx=n, ny=n, radius=lam, kind="metallo_dielectric_janus", eps1=float(eps1), phi0=float(phi0),
+                   wavelength=lam, steps=steps_for(lam))
+
+
 def small_mdjc(eps1: float = 2.0, phi0_deg: float = 0.0, a: int = 16) -> dict:
     """Metallo-dielectric Janus at a / lambda = 0.5 on an 8a grid (oracle-sized)."""
     lam = 2.0 * a
