@@ -143,6 +143,43 @@ def pec_coeffs(x: float, phi0: float = 0.0, M: int | None = None):
     return _total_from_scattering(x, phi0, M, base * b * np.cos(m * phi0), base * b * np.sin(m * phi0))
 
 
+def mie_te_coeffs(x: float, eps: float, phi0: float = 0.0, M: int | None = None):
+    """Homogeneous dielectric cylinder, TE^z (Hz along the axis): C, S, C', S'
+    of the total Hz on r = a.
+
+    The incident Hz has the series of Eq. (incident field) (impedance 1, so
+    |Hz^I| = E0).  Continuity of Hz and of E_phi = (j / (k0 eps)) dHz/dr at
+    r = a with the interior J_m(n k0 r) series gives
+    b_m = [J_m'(nx) J_m(x) - n J_m(nx) J_m'(x)] / [n J_m(nx) H_m'(x) - J_m'(nx) H_m(x)].
+    The stress tensor is symmetric in E and H, and E (TE) is the curl of Hz
+    up to a sign, as H (TM) is the curl of Ez: forces_closed_form and
+    far_intensity apply to these coefficients unchanged.
+    """
+    if M is None:
+        M = int(x * math.sqrt(eps) + 30)
+    n = math.sqrt(eps)
+    m = np.arange(M + 1)
+    j, jp = _bessel_j(x, M)
+    jn, jnp = _bessel_j(n * x, M)
+    h = special.hankel1(m, x)
+    hp = special.h1vp(m, x)
+    b = (jnp * j - n * jn * jp) / (n * jn * hp - jnp * h)
+    base = alpha(m) * (-1j) ** m
+    return _total_from_scattering(x, phi0, M, base * b * np.cos(m * phi0), base * b * np.sin(m * phi0))
+
+
+def pec_te_coeffs(x: float, phi0: float = 0.0, M: int | None = None):
+    """Homogeneous PEC cylinder, TE^z: E_phi = 0 on r = a, i.e. dHz/dr = 0,
+    b_m = -J_m'(x) / H_m'(x)."""
+    if M is None:
+        M = int(x + 30)
+    m = np.arange(M + 1)
+    _, jp = _bessel_j(x, M)
+    b = -jp / special.h1vp(m, x)
+    base = alpha(m) * (-1j) ** m
+    return _total_from_scattering(x, phi0, M, base * b * np.cos(m * phi0), base * b * np.sin(m * phi0))
+
+
 def mdjc_surface_field(x: float, eps1: float, phi0: float, N: int, M: int | None = None):
     """Solve Eq. (matrix integral equation) for E_z^tot on phi_n = n dphi, n = 0..N-1.
 

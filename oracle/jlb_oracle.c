@@ -98,13 +98,13 @@ typedef struct {
     int32_t threads;          /* OpenMP threads, <= 0 selects 1 */
     double plateau_tol;       /* > 0: stop once the field energy has reached a plateau (see orc_run) */
     int32_t far_angles;       /* > 0: far-field intensity at this many angles (see orc_run) */
-    int32_t pad2;
+    int32_t polarization;     /* 0 TM^z (Ez, Hx, Hy), 1 TE^z (Hz, Ex, Ey); see "TE^z" below */
 } orc_params;
 
 typedef struct {
     double fx, fy, tz;              /* F~x, F~y, M~z */
     double fx_raw, fy_raw, tz_raw;  /* per unit length, lattice units */
-    double energy_final;            /* sum over cells of (eps Ez^2 + Hx^2 + Hy^2)/2 */
+    double energy_final;            /* sum over cells of (eps E^2 + H^2)/2 */
     int64_t window_steps;           /* number of time samples in the average */
     int32_t contour_points;
     int32_t pad;
@@ -265,8 +265,50 @@ static void reduced_equilibrium(double eps, double ez, double hx, double hy, dou
     q[10] = hy / 6.0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* TE^z (Sec. I: the transverse-electric case the paper leaves for later):   */
+/* E = (Ex, Ey, 0), H = (0, 0, Hz), the same lattice and printed equilibria. */
+/* From e_i^eq = (E - c_i x H)/6 and h_i^eq = (H + c_i x E)/6:               */
+/*   h^z_{+-x} = (Hz +- Ey)/6, h^z_{+-y} = (Hz -+ Ex)/6, h^z_{+-z} = Hz/6,     */
+/*   e^x_{+-x} = Ex/6, e^x_{+-y} = (Ex -+ Hz)/6, e^y_{+-y} = Ey/6,             */
+/*   e^y_{+-x} = (Ey +- Hz)/6, e_{+-z} = E/6, e_0 = (eps - 1) E, h_0 = 0.      */
+/* Zero-equilibrium combinations along the links (kept zero, as in TM^z):    */
+/*   e^y_{+x} = h^z_{+x}, e^y_{-x} = -h^z_{-x}, e^x_{+y} = -h^z_{+y},         */
+/*   e^x_{-y} = h^z_{-y}.  The +-z populations merge with the rest ones.     */
+/* The 11 populations, on the same velocities as the TM^z ones:              */
+/*   0 hz_r  1 hz_{+x}  2 hz_{-x}  3 hz_{+y}  4 hz_{-y}                       */
+/*   5 ex_r  6 ex_{+x}  7 ex_{-x}  8 ey_r  9 ey_{+y}  10 ey_{-y}             */
+/* Moments: Hz = sum of 0..4, eps Ex = f5 + f6 + f7 + (f4 - f3),             */
+/*          eps Ey = f8 + f9 + f10 + (f1 - f2).                              */
+/* Conductor walls (the literal rule: E tangential and H normal flip): every */
+/* TE^z population here is either E normal or H tangential to the wall it   */
+/* meets, so all of them bounce back without a sign change.                  */
+/* ------------------------------------------------------------------------ */
+
+static void reduced_te_moments(const double f[NPOP], double eps, double *hz, double *ex, double *ey)
+{
+    *hz = f[0] + f[1] + f[2] + (f[3] + f[4]);
+    *ex = (f[5] + f[6] + f[7] + (f[4] - f[3])) / eps;
+    *ey = (f[8] + f[9] + f[10] + (f[1] - f[2])) / eps;
+}
+
+static void reduced_te_equilibrium(double eps, double hz, double ex, double ey, double q[NPOP])
+{
+    q[0] = hz / 3.0;
+    q[1] = (hz + ey) / 6.0;
+    q[2] = (hz - ey) / 6.0;
+    q[3] = (hz - ex) / 6.0;
+    q[4] = (hz + ex) / 6.0;
+    q[5] = (eps - 2.0 / 3.0) * ex;
+    q[6] = ex / 6.0;
+    q[7] = ex / 6.0;
+    q[8] = (eps - 2.0 / 3.0) * ey;
+    q[9] = ey / 6.0;
+    q[10] = ey / 6.0;
+}
+
 /* One time step: post-collision state src (time n) -> post-collision dst
- * (time n+1); fields at n+1 go to ez/hx/hy.  `strip` is the incident-wave
+ * (time n+1); fields at n+1 go to ez/hx/hy (TE^z: Hz, Ex, Ey).  `strip` is the incident-wave
  * row at time n (EDGE_OPEN only).  In EDGE_STRIP mode the grid is the one-row
  * companion lattice: +-y populations stay in their cell (the row is uniform
  * in y) and nothing enters through the right edge. */
@@ -275,9 +317,13 @@ static void reduced_step(const orc_params *p, int edges, int nx, int ny, const u
                          double *ez, double *hx, double *hy, double einc)
 {
     const size_t plane = (size_t)nx * ny;
-    /* incident-wave equilibria of the populations entering at the left edge */
+    const int te = p->polarization == 1;
+    /* incident-wave equilibria of the populations entering at the left edge:
+     * TM^z Ez = E_inc, Hy = -E_inc; TE^z Ey = E_inc, Hz = E_inc (both travel +x) */
     double inc[NPOP];
-    reduced_equilibrium(1.0, einc, 0.0, -einc, inc);
+    if (te) reduced_te_equilibrium(1.0, einc, 0.0, einc, inc);
+    else reduced_equilibrium(1.0, einc, 0.0, -einc, inc);
+    const double wall = te ? 1.0 : -1.0;   /* conductor reflection sign */
 #pragma omp parallel for schedule(static) num_threads(p->threads > 0 ? p->threads : 1)
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
@@ -310,15 +356,20 @@ static void reduced_step(const orc_params *p, int edges, int nx, int ny, const u
                     else f[q] = (1.0 - OPEN_DELTA) * own + OPEN_DELTA * strip[q * (size_t)nx + i]; /* top, bottom */
                 } else {
                     size_t s = (size_t)sj * nx + si;
-                    if (mat && mat[s] == MAT_PEC) f[q] = -src[pop_opp[q] * plane + c];
+                    if (mat && mat[s] == MAT_PEC) f[q] = wall * src[pop_opp[q] * plane + c];
                     else f[q] = src[q * plane + s];
                 }
             }
             double eps = mat ? eps_of(p, mat[c]) : 1.0;
             double e, a, b;
-            reduced_moments(f, eps, &e, &a, &b);
             double eq[NPOP];
-            reduced_equilibrium(eps, e, a, b, eq);
+            if (te) {
+                reduced_te_moments(f, eps, &e, &a, &b);
+                reduced_te_equilibrium(eps, e, a, b, eq);
+            } else {
+                reduced_moments(f, eps, &e, &a, &b);
+                reduced_equilibrium(eps, e, a, b, eq);
+            }
             for (int q = 0; q < NPOP; ++q) dst[q * plane + c] = 2.0 * eq[q] - f[q];
             ez[c] = e; hx[c] = a; hy[c] = b;
         }
@@ -365,7 +416,12 @@ static void literal_step(const orc_params *p, int edges, int nx, int ny, const u
 {
     const size_t plane = (size_t)nx * ny;
     const size_t splane = (size_t)nx;   /* the strip is one row */
+    const int te = p->polarization == 1;
     double Einc[3] = {0.0, 0.0, einc}, Hinc[3] = {0.0, -einc, 0.0};
+    if (te) {   /* TE^z: Ey = E_inc, Hz = E_inc */
+        Einc[1] = einc; Einc[2] = 0.0;
+        Hinc[1] = 0.0; Hinc[2] = einc;
+    }
 #pragma omp parallel for schedule(static) num_threads(p->threads > 0 ? p->threads : 1)
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
@@ -448,9 +504,19 @@ static void literal_step(const orc_params *p, int edges, int nx, int ny, const u
                     dst[LIDX(1, v, k) + c] = 2.0 * heq[k] - h[v][k];
                 }
             }
-            ez[c] = E[2]; hx[c] = H[0]; hy[c] = H[1];
+            if (te) { ez[c] = H[2]; hx[c] = E[0]; hy[c] = E[1]; }
+            else { ez[c] = E[2]; hx[c] = H[0]; hy[c] = H[1]; }
         }
     }
+}
+
+/* Field energy density (eps E^2 + H^2) / 2 of a cell from its three fields:
+ * TM^z (Ez, Hx, Hy) or TE^z (Hz, Ex, Ey). */
+static double cell_energy(const orc_params *p, uint8_t m, double a, double b, double c)
+{
+    const double eps = eps_of(p, m);
+    if (p->polarization == 1) return 0.5 * (a * a + eps * (b * b + c * c));
+    return 0.5 * (eps * a * a + b * b + c * c);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -593,7 +659,7 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
         if (plateau && n + 1 >= ramp_end + pcheck && (n + 1 - ramp_end) % pcheck == 0) {
             double w = 0.0;
             for (size_t c = 0; c < plane; ++c)
-                w += 0.5 * (eps_of(p, mat[c]) * ez[c] * ez[c] + hx[c] * hx[c] + hy[c] * hy[c]);
+                w += cell_energy(p, mat[c], ez[c], hx[c], hy[c]);
             if (w_prev >= 0.0 && fabs(w - w_prev) <= p->plateau_tol * w && n + 1 + window <= p->steps) {
                 stop = n + 1 + window;
                 plateau = 0;
@@ -633,7 +699,7 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
         if (energy) {
             double w = 0.0;
             for (size_t c = 0; c < plane; ++c)
-                w += 0.5 * (eps_of(p, mat[c]) * ez[c] * ez[c] + hx[c] * hx[c] + hy[c] * hy[c]);
+                w += cell_energy(p, mat[c], ez[c], hx[c], hy[c]);
             energy[n] = w;
         }
     }
@@ -641,7 +707,7 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
     {
         double w = 0.0;
         for (size_t c = 0; c < plane; ++c)
-            w += 0.5 * (eps_of(p, mat[c]) * ez[c] * ez[c] + hx[c] * hx[c] + hy[c] * hy[c]);
+            w += cell_energy(p, mat[c], ez[c], hx[c], hy[c]);
         res->energy_final = w;
         res->steps_done = stop;
     }
@@ -683,12 +749,17 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
         if (!tmp) { free(buf); rc = ORC_E_OOM; goto done; }
         for (int q = 0; q < 3; ++q) { sre[q] = tmp + (2 * q) * nc; sim[q] = tmp + (2 * q + 1) * nc; }
         double ei2 = 0.0;
+        /* TE^z: the scalar field is Hz, and curl H = -j k0 E makes dHz/dn =
+         * -j k0 [n_x (-Ey) - n_y (-Ex)]: the transform of TM^z with (Hx, Hy)
+         * replaced by (-Ex, -Ey) */
+        const double sgn = p->polarization == 1 ? -1.0 : 1.0;
         for (int k = 0; k < nc; ++k) {
             rx[k] = con.rc * con.nxv[k];
             ry[k] = con.rc * con.nyv[k];
             for (int q = 0; q < 3; ++q) {
-                sre[q][k] = sc * (dft[12 * k + 2 * q] - dft[12 * k + 6 + 2 * q]);
-                sim[q][k] = sc * (dft[12 * k + 2 * q + 1] - dft[12 * k + 7 + 2 * q]);
+                const double g = q == 0 ? 1.0 : sgn;
+                sre[q][k] = g * sc * (dft[12 * k + 2 * q] - dft[12 * k + 6 + 2 * q]);
+                sim[q][k] = g * sc * (dft[12 * k + 2 * q + 1] - dft[12 * k + 7 + 2 * q]);
             }
             const double ire = sc * dft[12 * k + 6], iim = sc * dft[12 * k + 7];
             ei2 += ire * ire + iim * iim;

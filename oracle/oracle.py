@@ -40,7 +40,7 @@ class _Params(ctypes.Structure):
         ("avg_periods", ctypes.c_int32), ("ramp_periods", ctypes.c_int32),
         ("contour_offset", ctypes.c_double), ("contour_points", ctypes.c_int32),
         ("boundary", ctypes.c_int32), ("literal", ctypes.c_int32), ("threads", ctypes.c_int32),
-        ("plateau_tol", ctypes.c_double), ("far_angles", ctypes.c_int32), ("pad2", ctypes.c_int32),
+        ("plateau_tol", ctypes.c_double), ("far_angles", ctypes.c_int32), ("polarization", ctypes.c_int32),
     ]
 
 
@@ -93,6 +93,9 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+POLARIZATIONS = {"tm": 0, "te": 1, 0: 0, 1: 1}
+
+
 def _params(prob: dict, boundary: str = "open", literal: bool = False, threads: int | None = None) -> _Params:
     kind = prob.get("kind", "homogeneous")
     kind = KINDS[kind] if isinstance(kind, str) else int(kind)
@@ -112,6 +115,7 @@ def _params(prob: dict, boundary: str = "open", literal: bool = False, threads: 
         contour_points=int(prob.get("contour_points", 0)),
         boundary={"open": 0, "periodic": 1, "x_open_y_periodic": 2}[boundary], literal=int(bool(literal)), threads=int(threads),
         plateau_tol=float(prob.get("plateau_tol", 0.0)),
+        polarization=POLARIZATIONS[prob.get("polarization", "tm")],
     )
 
 
