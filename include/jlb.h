@@ -100,7 +100,22 @@ typedef struct {
     int32_t contour_points;  /* samples on the contour; 0 selects 8 * ceil(2 pi R_c / 8)  */
     uint32_t flags;          /* JLB_F_*                                                   */
     double plateau_tol;      /* > 0: plateau stop (jlb_solve only; see below); 0: off     */
+    int32_t polarization;    /* JLB_TM (0, Sec. II) or JLB_TE (1; see below)               */
+    int32_t reserved;        /* 0                                                         */
 } jlb_problem;
+
+/*
+ * Polarisation.  JLB_TM: Ez, Hx, Hy (the paper's case throughout).  JLB_TE:
+ * Hz, Ex, Ey, the case the paper leaves for later work (Sec. I), on the same
+ * lattice and printed update (Sec. III, Eqs. LBGK equation and equilibrium
+ * distribution functions) with the incident wave Ey = Hz = E_inc travelling
+ * +x; forces use the same stress (Sec. II.B) and normalisation.  For TE the
+ * field outputs of jlb_solve (ez, hx, hy) hold Hz, Ex, Ey, and the far field
+ * of jlb_solve_far_field is k0 r |Hz^S|^2 / |Hz^I|^2.  TE solves run on the
+ * single-step kernels (the two-step kernels are TM).
+ */
+#define JLB_TM 0
+#define JLB_TE 1
 
 /*
  * Plateau stop (Sec. III: convergence is judged by the total field energy

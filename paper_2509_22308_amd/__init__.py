@@ -36,7 +36,7 @@ class jlb_problem(ctypes.Structure):
         ("phi0", ctypes.c_double), ("wavelength", ctypes.c_double), ("e0", ctypes.c_double),
         ("steps", ctypes.c_int64), ("avg_periods", ctypes.c_int32), ("ramp_periods", ctypes.c_int32),
         ("contour_offset", ctypes.c_double), ("contour_points", ctypes.c_int32), ("flags", ctypes.c_uint32),
-        ("plateau_tol", ctypes.c_double),
+        ("plateau_tol", ctypes.c_double), ("polarization", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -118,6 +118,9 @@ def _check(rc: int):
         raise JlbError(rc, load().jlb_last_error().decode())
 
 
+POLARIZATIONS = {"tm": 0, "te": 1, 0: 0, 1: 1}
+
+
 def make_problem(d: dict, precision: str | int | None = None, flags: int = 0) -> jlb_problem:
     """jlb_problem from a problem dict (keys as in the seeded workloads)."""
     kind = d.get("kind", "homogeneous")
@@ -133,6 +136,7 @@ def make_problem(d: dict, precision: str | int | None = None, flags: int = 0) ->
         avg_periods=int(d.get("avg_periods", 5)), ramp_periods=int(d.get("ramp_periods", 1)),
         contour_offset=float(d.get("contour_offset", 3.0)), contour_points=int(d.get("contour_points", 0)),
         flags=int(flags | d.get("flags", 0)), plateau_tol=float(d.get("plateau_tol", 0.0)),
+        polarization=POLARIZATIONS[d.get("polarization", "tm")],
     )
 
 

@@ -34,6 +34,16 @@
 // for hx and hy.  The large rest population (eps - 2/3) Ez therefore never
 // passes through a narrow format.
 //
+// TE^z (Hz, Ex, Ey; the polarisation the paper leaves for later, Sec. I) is
+// the same update under the vacuum duality E -> H, H -> -E: the state holds
+// (Hz, -Ex, -Ey) in the (Ez, Hx, Hy) slots and the populations accordingly,
+// the permittivity moves to the in-plane fields (moments eps Ex, eps Ey; rest
+// equilibria Hz/3 and (eps - 2/3) Ex, (eps - 2/3) Ey), and a conductor link
+// reflects without a sign change (every TE^z population meets a wall as a
+// normal E or a tangential H component).  Source, open edges, companion row,
+// stress sums and far-field phasors are unchanged in the dual storage.
+// Single-step kernels only (the two-step kernels are TM^z).
+//
 // No MFMA: the step is a stencil with about 0.3 flop per byte.
 #include <hip/hip_runtime.h>
 
@@ -132,6 +142,7 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
     const double keep = 1.0 - OPEN_DELTA;
     double f[11];
     double eps = 1.0, eps_rest = 1.0 - 2.0 / 3.0;
+    const double wall = L.te ? 1.0 : -1.0;  // conductor reflection sign
 
     f[0] = src[0 * P + c];
     f[5] = src[5 * P + c];
@@ -155,40 +166,50 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
         const size_t strip = at(i, L.ny, L.sf);
         // +x populations come from (i-1, j)
         if (i == 0) { f[1] = einc / 3.0; f[6] = 0.0; }
-        else if (m & NB_PEC_XM) { f[1] = -src[2 * P + c]; f[6] = -src[7 * P + c]; }
+        else if (m & NB_PEC_XM) { f[1] = wall * src[2 * P + c]; f[6] = wall * src[7 * P + c]; }
         else { f[1] = src[1 * P + c - 1]; f[6] = src[6 * P + c - 1]; }
         // -x populations come from (i+1, j)
         if (i == L.nx - 1) { f[2] = keep * src[2 * P + c]; f[7] = keep * src[7 * P + c]; }
-        else if (m & NB_PEC_XP) { f[2] = -src[1 * P + c]; f[7] = -src[6 * P + c]; }
+        else if (m & NB_PEC_XP) { f[2] = wall * src[1 * P + c]; f[7] = wall * src[6 * P + c]; }
         else { f[2] = src[2 * P + c + 1]; f[7] = src[7 * P + c + 1]; }
         // +y populations come from (i, j-1)
         if (j == 0) {
             f[3] = keep * src[3 * P + c] + OPEN_DELTA * src[3 * P + strip];
             f[9] = keep * src[9 * P + c] + OPEN_DELTA * src[9 * P + strip];
-        } else if (m & NB_PEC_YM) { f[3] = -src[4 * P + c]; f[9] = -src[10 * P + c]; }
+        } else if (m & NB_PEC_YM) { f[3] = wall * src[4 * P + c]; f[9] = wall * src[10 * P + c]; }
         else { f[3] = src[3 * P + c - L.sf]; f[9] = src[9 * P + c - L.sf]; }
         // -y populations come from (i, j+1)
         if (j == L.ny - 1) {
             f[4] = keep * src[4 * P + c] + OPEN_DELTA * src[4 * P + strip];
             f[10] = keep * src[10 * P + c] + OPEN_DELTA * src[10 * P + strip];
-        } else if (m & NB_PEC_YP) { f[4] = -src[3 * P + c]; f[10] = -src[9 * P + c]; }
+        } else if (m & NB_PEC_YP) { f[4] = wall * src[3 * P + c]; f[10] = wall * src[9 * P + c]; }
         else { f[4] = src[4 * P + c + L.sf]; f[10] = src[10 * P + c + L.sf]; }
     }
 
     const double dz = f[0] + f[1] + f[2] + (f[3] + f[4]);
-    const double ez = dz / eps;
-    const double hx = f[5] + f[6] + f[7] + (f[3] - f[4]);
-    const double hy = f[8] + (f[9] + f[10]) + (f[2] - f[1]);
+    double ez, hx, hy;
     double q[11];
-    q[0] = eps_rest * ez;
+    if (L.te) {  // (Hz, -Ex, -Ey): the in-plane fields carry eps
+        ez = dz;
+        hx = (f[5] + f[6] + f[7] + (f[3] - f[4])) / eps;
+        hy = (f[8] + (f[9] + f[10]) + (f[2] - f[1])) / eps;
+        q[0] = ez / 3.0;
+        q[5] = eps_rest * hx;
+        q[8] = eps_rest * hy;
+    } else {
+        ez = dz / eps;
+        hx = f[5] + f[6] + f[7] + (f[3] - f[4]);
+        hy = f[8] + (f[9] + f[10]) + (f[2] - f[1]);
+        q[0] = eps_rest * ez;
+        q[5] = hx / 3.0;
+        q[8] = hy / 3.0;
+    }
     q[1] = (ez - hy) / 6.0;
     q[2] = (ez + hy) / 6.0;
     q[3] = (ez + hx) / 6.0;
     q[4] = (ez - hx) / 6.0;
-    q[5] = hx / 3.0;
     q[6] = hx / 6.0;
     q[7] = hx / 6.0;
-    q[8] = hy / 3.0;
     q[9] = hy / 6.0;
     q[10] = hy / 6.0;
 #pragma unroll
@@ -264,12 +285,28 @@ __device__ __forceinline__ Side load_side(const float *F, const NeqT *N, size_t 
     return s;
 }
 
+// Material coefficients of one node's update.  TM^z: the z field carries the
+// permittivity (Dz = eps Ez, rest equilibrium (eps - 2/3) Ez, in-plane rests
+// H/3) and conductor links reflect with a sign change.  TE^z in the dual
+// storage: the in-plane fields carry it, the z field's rest is Hz/3, and
+// conductor links reflect without a sign change.
+struct Coef {
+    float az, axy;  // field = moment sum * a
+    float cz, cxy;  // rest equilibrium = c * field
+    float wall;     // conductor reflection sign
+};
+__device__ __forceinline__ Coef coef_tm(float inv_eps, float eps_rest) { return Coef{inv_eps, 1.0f, eps_rest, THIRD, -1.0f}; }
+__device__ __forceinline__ Coef coef_of(const Lattice &L, float inv_eps, float eps_rest)
+{
+    return L.te ? Coef{1.0f, inv_eps, THIRD, eps_rest, 1.0f} : coef_tm(inv_eps, eps_rest);
+}
+
 // One node's update from its own data and the four sides.  Sides are read
 // only where the pull crosses an interior, non-conductor link.  `inc_lo` /
 // `inc_hi` hold the incident-wave companion node of the same column
 // (fields + N_{e+y}, N_{hy+y} / N_{e-y}, N_{hy-y}) for the bottom / top rows.
 template <bool STRIP>
-__device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t m, float inv_eps, float eps_rest,
+__device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t m, const Coef &k,
                                          const NodeData &o, const Side &l, const Side &r, const Side &b, const Side &t,
                                          const Side &inc_lo, const Side &inc_hi, float einc, NodeData &out)
 {
@@ -279,9 +316,9 @@ __device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t
     const float keep = (float)(1.0 - OPEN_DELTA);
     const float delta = (float)OPEN_DELTA;
     // rest populations stream in place: f*_r = f_r^eq - N_r with the sum rules
-    const float r_e = eps_rest * o.ez + (o.n[N_EPX] + o.n[N_EMX] + o.n[N_EPY] + o.n[N_EMY]);
-    const float r_hx = o.hx * THIRD + (o.n[N_HXPX] + o.n[N_HXMX] + o.n[N_EPY] - o.n[N_EMY]);
-    const float r_hy = o.hy * THIRD + (o.n[N_HYPY] + o.n[N_HYMY] - o.n[N_EPX] + o.n[N_EMX]);
+    const float r_e = k.cz * o.ez + (o.n[N_EPX] + o.n[N_EMX] + o.n[N_EPY] + o.n[N_EMY]);
+    const float r_hx = o.hx * k.cxy + (o.n[N_HXPX] + o.n[N_HXMX] + o.n[N_EPY] - o.n[N_EMY]);
+    const float r_hy = o.hy * k.cxy + (o.n[N_HYPY] + o.n[N_HYMY] - o.n[N_EPX] + o.n[N_EMX]);
 
     // pulls across interior links: the neighbour's post-collision population
     float e_px = (l.ez - l.hy) * SIXTH - l.na, hx_px = l.hx * SIXTH - l.nb;  // +x from (i-1, j)
@@ -302,11 +339,11 @@ __device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t
         const float s_hypy = o.hy * SIXTH - o.n[N_HYPY];
         const float s_hymy = o.hy * SIXTH - o.n[N_HYMY];
         if (i == 0) { e_px = einc * THIRD; hx_px = 0.0f; }
-        else if (m & NB_PEC_XM) { e_px = -s_emx; hx_px = -s_hxmx; }
+        else if (m & NB_PEC_XM) { e_px = k.wall * s_emx; hx_px = k.wall * s_hxmx; }
         if (i == L.nx - 1) {
             if (STRIP) { e_mx = 0.0f; hx_mx = 0.0f; }
             else { e_mx = keep * s_emx; hx_mx = keep * s_hxmx; }
-        } else if (m & NB_PEC_XP) { e_mx = -s_epx; hx_mx = -s_hxpx; }
+        } else if (m & NB_PEC_XP) { e_mx = k.wall * s_epx; hx_mx = k.wall * s_hxpx; }
         if (STRIP) {
             // uniform in y: the +-y populations stay in their node
             e_py = s_epy; hy_py = s_hypy; e_my = s_emy; hy_my = s_hymy;
@@ -314,18 +351,18 @@ __device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t
             if (j == 0) {
                 e_py = keep * s_epy + delta * ((inc_lo.ez + inc_lo.hx) * SIXTH - inc_lo.na);
                 hy_py = keep * s_hypy + delta * (inc_lo.hy * SIXTH - inc_lo.nb);
-            } else if (m & NB_PEC_YM) { e_py = -s_emy; hy_py = -s_hymy; }
+            } else if (m & NB_PEC_YM) { e_py = k.wall * s_emy; hy_py = k.wall * s_hymy; }
             if (j == L.ny - 1) {
                 e_my = keep * s_emy + delta * ((inc_hi.ez - inc_hi.hx) * SIXTH - inc_hi.na);
                 hy_my = keep * s_hymy + delta * (inc_hi.hy * SIXTH - inc_hi.nb);
-            } else if (m & NB_PEC_YP) { e_my = -s_epy; hy_my = -s_hypy; }
+            } else if (m & NB_PEC_YP) { e_my = k.wall * s_epy; hy_my = k.wall * s_hypy; }
         }
     }
 
     const float dz = r_e + e_px + e_mx + (e_py + e_my);
-    const float ez = dz * inv_eps;
-    const float hx = r_hx + hx_px + hx_mx + (e_py - e_my);
-    const float hy = r_hy + (hy_py + hy_my) + (e_mx - e_px);
+    const float ez = dz * k.az;
+    const float hx = (r_hx + hx_px + hx_mx + (e_py - e_my)) * k.axy;
+    const float hy = (r_hy + (hy_py + hy_my) + (e_mx - e_px)) * k.axy;
     out.ez = ez;
     out.hx = hx;
     out.hy = hy;
@@ -406,12 +443,12 @@ __device__ __forceinline__ void neq_direct_node(const Lattice &L, const void *__
     const NodeData o = load_node(F, N, P, cf, cn);
     NodeData out;
     if (j == L.ny) {
-        neq_core<true>(L, i, j, m, inv_eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
+        neq_core<true>(L, i, j, m, coef_of(L, inv_eps, eps_rest), o, l, r, b, t, lo, hi, einc, out);
     } else {
         if (j > 0 && !(m & NB_PEC_YM)) b = load_side(F, N, P, cf - L.sf, cn - L.sn, N_EPY, N_HYPY);
         if (j < L.ny - 1 && !(m & NB_PEC_YP)) t = load_side(F, N, P, cf + L.sf, cn + L.sn, N_EMY, N_HYMY);
         load_incident_sides(L, F, N, i, j, lo, hi);
-        neq_core<false>(L, i, j, m, inv_eps, eps_rest, o, l, r, b, t, lo, hi, einc, out);
+        neq_core<false>(L, i, j, m, coef_of(L, inv_eps, eps_rest), o, l, r, b, t, lo, hi, einc, out);
     }
     store_node(DF, DN, P, cf, cn, out, L.stream_stores);
 }
@@ -627,7 +664,7 @@ __device__ __forceinline__ void neq_vtile_row(const Lattice &L, const void *__re
         Side lo{}, hi{};
         load_incident_sides(L, F, N, i, j, lo, hi);
         NodeData res;
-        neq_core<false>(L, i, j, m, inv_eps, eps_rest, o, l, r, b, t, lo, hi, einc, res);
+        neq_core<false>(L, i, j, m, coef_of(L, inv_eps, eps_rest), o, l, r, b, t, lo, hi, einc, res);
         out.ez[v] = res.ez;
         out.hx[v] = res.hx;
         out.hy[v] = res.hy;
@@ -746,7 +783,7 @@ __device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, type
         const Side lo{inc.lo.ez[v], inc.lo.hx[v], inc.lo.hy[v], inc.lo.na[v], inc.lo.nb[v]};
         const Side hi{inc.hi.ez[v], inc.hi.hx[v], inc.hi.hy[v], inc.hi.na[v], inc.hi.nb[v]};
         NodeData res;
-        neq_core<STRIP>(L, i, r, m, inv_eps, eps_rest, o, l, rr, b, t, lo, hi, einc, res);
+        neq_core<STRIP>(L, i, r, m, coef_tm(inv_eps, eps_rest), o, l, rr, b, t, lo, hi, einc, res);
         out.ez[v] = res.ez;
         out.hx[v] = res.hx;
         out.hy[v] = res.hy;
@@ -1315,7 +1352,8 @@ __global__ __launch_bounds__(EN_THREADS) void k_energy_partial(Lattice L, const 
             if (mat == MAT_PEC) continue;
             const size_t c = at(i, j, L.sfld);
             const double ez = fld[c], hx = fld[P + c], hy = fld[2 * P + c];
-            s += 0.5 * (mat_eps(L, mat) * ez * ez + hx * hx + hy * hy);
+            if (L.te) s += 0.5 * (ez * ez + mat_eps(L, mat) * (hx * hx + hy * hy));
+            else s += 0.5 * (mat_eps(L, mat) * ez * ez + hx * hx + hy * hy);
         }
     }
     s = wave_sum(s);
@@ -1353,9 +1391,11 @@ __global__ void k_fields_out(Lattice L, const FT *__restrict__ fld, double *ez, 
     const size_t P = L.plane;
     const size_t c = at(i, j, L.sfld);
     const size_t o = (size_t)j * L.nx + i;
+    // TE^z: the dual storage holds (Hz, -Ex, -Ey); report (Hz, Ex, Ey)
+    const double sxy = L.te ? -1.0 : 1.0;
     ez[o] = (double)fld[c];
-    hx[o] = (double)fld[P + c];
-    hy[o] = (double)fld[2 * P + c];
+    hx[o] = sxy * (double)fld[P + c];
+    hy[o] = sxy * (double)fld[2 * P + c];
 }
 
 dim3 step_grid(const Lattice &L) { return dim3((L.nx + BX - 1) / BX, (L.ny + 1 + BY - 1) / BY); }

@@ -78,6 +78,7 @@ int make_plan(const jlb_problem *p, Plan *pl)
     if (p->avg_periods < 1 || p->ramp_periods < 0) return fail(JLB_E_ARG, "avg_periods >= 1 and ramp_periods >= 0");
     if (!(p->contour_offset > 1.5)) return fail(JLB_E_GEOMETRY, "contour_offset must exceed 1.5 cells");
     if (p->contour_points < 0) return fail(JLB_E_ARG, "contour_points must be >= 0");
+    if (p->polarization != JLB_TM && p->polarization != JLB_TE) return fail(JLB_E_ARG, "polarization must be 0 (TM) or 1 (TE)");
 
     Plan &q = *pl;
     q.prob = *p;
@@ -299,6 +300,7 @@ Lattice lattice_of(const Plan &q, const uint8_t *dmask)
         L.eps_rest[k] = q.eps[k] - 2.0 / 3.0;
         L.inv_eps[k] = 1.0 / q.eps[k];
     }
+    L.te = q.prob.polarization == JLB_TE ? 1 : 0;
     L.stream_stores = 2 * q.state_bytes > CACHE_RESIDENT_BYTES ? 1 : 0;
     return L;
 }
@@ -389,7 +391,9 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     // pairs and a chunk leaves state n in buffer n % 2, as single steps do;
     // it is also the spacing of the plateau check points
     const int64_t chunk = q.T % 4 == 0 ? q.T : q.T % 2 == 0 ? 2 * q.T : 4 * q.T;
-    const int two = q.prob.precision == JLB_FP64 ? -1 : two_step_variant(q.prob.precision);
+    // two-step kernels: FP32 / BF16 TM^z
+    const int two = q.prob.precision == JLB_FP64 || q.prob.polarization == JLB_TE ? -1
+                                                                                  : two_step_variant(q.prob.precision);
     const int64_t ramp_end = (int64_t)std::ceil(q.ramp_steps);
     bool plateau = q.prob.plateau_tol > 0.0;
     double w_prev = -1.0;
@@ -732,6 +736,7 @@ int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t wo
     clear_error();
     if (!prob) return fail(JLB_E_ARG, "null problem");
     if (prob->precision != JLB_FP32 && prob->precision != JLB_BF16) return fail(JLB_E_ARG, "two-step kernels are FP32 / BF16");
+    if (prob->polarization != JLB_TM) return fail(JLB_E_ARG, "two-step kernels are TM only");
     const int v = two_step_variant(prob->precision);
     if (v < 0) return fail(JLB_E_ARG, "no two-step variant selected");
     return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, true, ms_per_launch, stream);
@@ -758,7 +763,7 @@ int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_byte
     }
     set_step_variant(prob->precision, bv);
     *best_variant = bv;
-    if (prob->precision == JLB_FP64) return JLB_OK;
+    if (prob->precision == JLB_FP64 || prob->polarization == JLB_TE) return JLB_OK;
     // two-step kernels, compared per lattice step
     int b2 = -1;
     for (int v = 0; v < TWO_STEP_VARIANTS; ++v) {

@@ -53,7 +53,7 @@ struct Lattice {
     double eps_rest[4];   // eps - 2/3: coefficient of Ez in the rest e-population's equilibrium
     double inv_eps[4];    // 1 / eps (the FP32 / BF16 update multiplies by it)
     int stream_stores;    // 1: write the next state past the caches (state larger than the Infinity Cache)
-    int pad;
+    int te;               // 1: TE^z, stored as (Hz, -Ex, -Ey) in the (Ez, Hx, Hy) slots; single-step kernels only
 };
 
 // Working sets above this many bytes do not stay in the 256 MB Infinity Cache

@@ -46,6 +46,10 @@ def test_problem_checks_return_the_documented_codes():
     assert J.jlb_validate(J.make_problem(dict(ok, radius=60.0))) == -2                # JLB_E_GEOMETRY
     assert J.jlb_validate(J.make_problem(dict(ok, eps1=30.0))) == -3                  # JLB_E_RESOLUTION
     assert J.jlb_validate(J.make_problem(dict(ok, plateau_tol=-1e-3))) == -1          # JLB_E_ARG
+    assert J.jlb_validate(J.make_problem(dict(ok, polarization="te"))) == 0
+    bad = J.make_problem(ok)
+    bad.polarization = 2
+    assert J.jlb_validate(bad) == -1 and "polarization" in J.jlb_last_error()
     assert J.jlb_validate(J.make_problem(dict(ok, eps1=30.0), flags=J.JLB_F_ALLOW_UNDERRESOLVED)) == 0
     assert J.jlb_validate(J.make_problem(dict(ok, steps=500))) == -4                  # JLB_E_WINDOW
     assert J.jlb_validate(J.make_problem(dict(ok, eps1=0.5))) == -1
@@ -63,6 +67,14 @@ def test_far_field_entry_checks_its_arguments_before_the_device():
     for n in (0, -3, 65537):
         rc = lib.jlb_solve_far_field(ctypes.byref(prob), None, 0, ctypes.byref(res), n, ctypes.cast(buf, J._vp), None)
         assert rc == -1 and "n_angles" in J.jlb_last_error()
+
+
+def test_two_step_timing_refuses_te_before_the_device():
+    import ctypes
+    prob = J.make_problem(dict(W.config1(), polarization="te"), "fp32")
+    ms = ctypes.c_double(0.0)
+    assert J.load().jlb_time_two_step_kernel(ctypes.byref(prob), None, 0, 0, 1, ctypes.byref(ms), None) == -1
+    assert "TM" in J.jlb_last_error()
 
 
 def test_workspace_grows_with_precision_and_grid():

@@ -124,12 +124,12 @@ def paper_djc_map(eps1: float, eps_stride: int = 1, phi_stride: int = 1) -> tupl
     return probs, ratio, phi
 
 
-def paper_far_field_case(eps1: float, phi0: float) -> dict:
+def paper_far_field_case(eps1: float, phi0: float, res: float = 50.0) -> dict:
     """The far-field validation of Sec. IV.A.1 (Fig. SW): metallo-dielectric
-    Janus, a / lambda = 1, lambda_eps / dx = 50 inside the dielectric (lambda =
-    50 sqrt(eps_r1), rounded down so that 3 lambda is whole), L / a = 10;
-    52 periods."""
-    lam = math.floor(3 * 50 * math.sqrt(eps1) + 1e-9) / 3
+    Janus, a / lambda = 1, lambda_eps / dx = res (50 in the paper) inside the
+    dielectric (lambda = res sqrt(eps_r1), rounded down so that 3 lambda is
+    whole), L / a = 10; 52 periods."""
+    lam = math.floor(3 * res * math.sqrt(eps1) + 1e-9) / 3
     n = int(math.ceil(10 * lam))
     return problem(nx=n, ny=n, radius=lam, kind="metallo_dielectric_janus", eps1=float(eps1), phi0=float(phi0),
                    wavelength=lam, steps=steps_for(lam))
