@@ -162,7 +162,7 @@ int jlb_validate(const jlb_problem *prob);
 /*
  * Device workspace one solve of `prob` needs, in bytes (host out-pointer).
  * The grid carries one extra row for the incident-wave companion lattice and
- * pads rows to a multiple of 64 nodes.
+ * pads rows to a multiple of 16 nodes.
  */
 int jlb_workspace_size(const jlb_problem *prob, size_t *bytes);
 
@@ -261,12 +261,17 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * FP32 / BF16 also have two-step kernels (JLB_TWO_STEP_VARIANTS of them):
  * one launch takes the state from step n to n + 2, reading and writing it
  * once (temporal blocking), with results equal to two single steps bit for
- * bit.  A solve uses the selected two-step variant for the steps outside the
- * averaging window that run in graph-captured periods, and single steps for
- * the ramp and the window.  Variants (V adjacent nodes per lane, H rows per
- * wavefront, HX halo columns per side; HX 8 keeps output strips 64-byte
- * aligned): 0 V1 H8 X2, 1 V1 H16 X2, 2 V2 H8 X2, 3 V2 H16 X2, 4 V1 H8 X8,
- * 5 V2 H16 X8, 6 V2 H32 X8.  Default: off (-1).
+ * bit.  A TM^z solve uses the selected two-step variant for every step that
+ * runs in graph-captured whole periods (inside the averaging window too,
+ * where the middle level's contour fields are kept), and single steps for the
+ * ramp, the steps after the last whole chunk and a far-field solve's last
+ * period; the engine uses it for all steps of its FP32 / BF16 TM^z solves.
+ * Variants (V adjacent nodes per lane, H rows per wavefront, HX halo columns
+ * per side; HX 8 keeps output strips 64-byte aligned; LA2: each input row is
+ * loaded two rows ahead of its first use instead of one): 0 V1 H8 X2,
+ * 1 V1 H16 X2, 2 V2 H8 X2, 3 V2 H16 X2, 4 V1 H8 X8, 5 V2 H16 X8, 6 V2 H32 X8,
+ * 7 V1 H8 X8 LA2, 8 V1 H4 X8 LA2, 9 V1 H16 X8 LA2.  Default: 4 (set -1 for
+ * single steps only).
  *
  * jlb_autotune times every single-step variant of prob->precision on prob's
  * grid (`launches` timed launches each, after 2 warm-up launches; workspace
@@ -281,7 +286,7 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  */
 #define JLB_STEP_VARIANTS 7
 #define JLB_FP64_STEP_VARIANTS 3
-#define JLB_TWO_STEP_VARIANTS 7
+#define JLB_TWO_STEP_VARIANTS 10
 int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t launches,
                  int32_t *best_variant, double *ms_per_variant, void *stream);
 

@@ -208,7 +208,8 @@ STEP_VARIANTS = {0: "direct 64x4", 1: "2-wide tile 64x4", 2: "4-wide tile 64x4",
 FP64_STEP_VARIANTS = {0: "direct 64x4", 1: "direct 256x1", 2: "direct 256x2"}
 TWO_STEP_VARIANTS = {0: "two-step V1 H8 X2", 1: "two-step V1 H16 X2", 2: "two-step V2 H8 X2",
                      3: "two-step V2 H16 X2", 4: "two-step V1 H8 X8", 5: "two-step V2 H16 X8",
-                     6: "two-step V2 H32 X8"}
+                     6: "two-step V2 H32 X8", 7: "two-step V1 H8 X8 LA2", 8: "two-step V1 H4 X8 LA2",
+                     9: "two-step V1 H16 X8 LA2"}
 
 
 def variant_name(precision, best: int) -> str:

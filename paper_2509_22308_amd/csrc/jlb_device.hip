@@ -89,9 +89,15 @@ template <typename R> __device__ __forceinline__ R mat_pick(const double (&v)[4]
 }
 __device__ __forceinline__ double mat_eps(const Lattice &L, int mat) { return mat_pick<double>(L.eps, mat); }
 __device__ __forceinline__ double mat_eps_rest(const Lattice &L, int mat) { return mat_pick<double>(L.eps_rest, mat); }
-__device__ __forceinline__ float mat_eps_f(const Lattice &L, int mat) { return mat_pick<float>(L.eps, mat); }
-__device__ __forceinline__ float mat_eps_rest_f(const Lattice &L, int mat) { return mat_pick<float>(L.eps_rest, mat); }
-__device__ __forceinline__ float mat_inv_eps_f(const Lattice &L, int mat) { return mat_pick<float>(L.inv_eps, mat); }
+// FP32 coefficients: picked among the host-rounded float copies, so the
+// select runs on 32-bit values and needs no conversion per node.
+__device__ __forceinline__ float mat_pick_f(const float (&v)[4], int mat)
+{
+    const float v0 = uniform(v[0]), v1 = uniform(v[1]), v2 = uniform(v[2]);
+    return mat == 0 ? v0 : mat == 1 ? v1 : v2;
+}
+__device__ __forceinline__ float mat_eps_rest_f(const Lattice &L, int mat) { return mat_pick_f(L.eps_rest_f, mat); }
+__device__ __forceinline__ float mat_inv_eps_f(const Lattice &L, int mat) { return mat_pick_f(L.inv_eps_f, mat); }
 
 // Mask index of node (i, j).
 __device__ __forceinline__ size_t node(const Lattice &L, int i, int j) { return (size_t)j * L.pitch + i; }
@@ -807,6 +813,12 @@ template <int V>
 __device__ __forceinline__ void mask_row(const Lattice &L, int i0, typename MaskVec<V>::type mv, bool strip,
                                          RowData<V> &o)
 {
+    bool all = true;
+#pragma unroll
+    for (int v = 0; v < V; ++v) all = all && i0 + v < L.nx && (strip || ((mv >> (8 * v)) & 3) != MAT_PEC);
+    // most rows hold neither conductor nor outside nodes in any lane: skip
+    // the selects for the whole wavefront
+    if (__builtin_amdgcn_ballot_w64(!all) == 0) return;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const bool keep = i0 + v < L.nx && (strip || ((mv >> (8 * v)) & 3) != MAT_PEC);
@@ -839,7 +851,7 @@ constexpr int TWO_STEP_WAVES = 4;  // independent wavefronts per block
 // One wavefront's share of a two-step launch: strip sx, row segment sy.
 // With `one`, only the first step is taken and its result stored (a solve
 // with a single step left).
-template <typename NeqT, int V, int H, int HX>
+template <typename NeqT, int V, int H, int HX, int LA>
 __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__restrict__ srcv,
                                               void *__restrict__ dstv, float einc0, float einc1,
                                               float *__restrict__ mid, int sx, int sy, bool one)
@@ -909,14 +921,17 @@ __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__re
         constexpr int BQA = DIR > 0 ? N_EPY : N_EMY, BQB = DIR > 0 ? N_HYPY : N_HYMY;  // behind
         constexpr int AQA = DIR > 0 ? N_EMY : N_EPY, AQB = DIR > 0 ? N_HYMY : N_HYPY;  // ahead
         const int first = DIR > 0 ? j0 - 1 : j0 + H;  // first row of step n -> n + 1
-        // rows at n: behind (side), cur, ahead (the next one in flight);
-        // rows at n + 1: behind (side), cur
-        RowData<V> a_cur, a_ahead, tmp;
-        MaskT m_cur, m_ahead, m_prev = 0, m_dummy;
+        // rows at n: behind (side), cur, ahead, and the rows in flight (LA of
+        // them: the load of a row is issued LA iterations before its first
+        // use, hiding that much more latency); rows at n + 1: behind (side), cur
+        RowData<V> a_cur, a_ahead, a_pre, tmp;
+        MaskT m_cur, m_ahead, m_pre = 0, m_prev = 0, m_dummy;
         load(first - DIR, tmp, m_dummy);
         SideRow<V> a_behind = side_of(tmp, BQA, BQB);
         load(first, a_cur, m_cur);
         load(first + DIR, a_ahead, m_ahead);
+        if constexpr (LA == 2) load(first + 2 * DIR, a_pre, m_pre);
+        else zero_row(a_pre);
         SideRow<V> b_behind{};
         RowData<V> b_cur;
         zero_row(b_cur);
@@ -926,8 +941,19 @@ __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__re
             RowData<V> a_next;
             MaskT m_next;
             // the last row a step-1 row needs lies one past the segment's halo
-            if (k <= H) load(r1 + 2 * DIR, a_next, m_next);
-            else { a_next = a_ahead; m_next = m_ahead; }
+            if constexpr (LA == 2) {
+                RowData<V> a_far;
+                MaskT m_far;
+                if (k + 1 <= H) load(r1 + 3 * DIR, a_far, m_far);
+                else { a_far = a_pre; m_far = m_pre; }
+                a_next = a_pre;
+                m_next = m_pre;
+                a_pre = a_far;
+                m_pre = m_far;
+            } else {
+                if (k <= H) load(r1 + 2 * DIR, a_next, m_next);
+                else { a_next = a_ahead; m_next = m_ahead; }
+            }
             // keep the look-ahead loads here, ahead of this row's arithmetic
             // (the scheduler would otherwise sink them next to their first use)
             __builtin_amdgcn_sched_barrier(0);
@@ -981,7 +1007,7 @@ __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__re
     else sweep(std::integral_constant<int, 1>{});
 }
 
-template <typename NeqT, int V, int H, int HX>
+template <typename NeqT, int V, int H, int HX, int LA>
 __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, const void *__restrict__ srcv,
                                                                     void *__restrict__ dstv, float einc0, float einc1,
                                                                     float *__restrict__ mid, int nsx, int nsy)
@@ -997,7 +1023,7 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
     const int w = __builtin_amdgcn_readfirstlane(b * TWO_STEP_WAVES + (int)threadIdx.y);
     if (w >= nsx * nsy) return;  // whole wavefront
     const int sx = L.stream_stores ? w % nsx : w / nsy, sy = L.stream_stores ? w / nsx : w % nsy;
-    two_step_wave<NeqT, V, H, HX>(L, srcv, dstv, einc0, einc1, mid, sx, sy, false);
+    two_step_wave<NeqT, V, H, HX, LA>(L, srcv, dstv, einc0, einc1, mid, sx, sy, false);
 }
 
 // Source value of a batched solve at its step n (ramp table, then one period).
@@ -1008,7 +1034,7 @@ __device__ __forceinline__ double batch_incident(const SolveDesc &d, int64_t n)
 
 // Batched two-step launch: wavefront w takes items[w] (slot, strip, row
 // segment) of a resident solve at that solve's own step n.
-template <typename NeqT, int V, int H, int HX>
+template <typename NeqT, int V, int H, int HX, int LA>
 __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq_batch(SolveDesc *__restrict__ D,
                                                                           const Tile *__restrict__ items, int nitems,
                                                                           int remap)
@@ -1024,7 +1050,7 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq_batch(SolveDe
     // middle-level fields are needed when level n + 1 is averaged and a
     // second step follows
     float *mid = !one && n + 1 > d.steps - d.window ? d.mid : nullptr;
-    two_step_wave<NeqT, V, H, HX>(d.L, d.state[d.cur], d.state[d.cur ^ 1], (float)batch_incident(d, n),
+    two_step_wave<NeqT, V, H, HX, LA>(d.L, d.state[d.cur], d.state[d.cur ^ 1], (float)batch_incident(d, n),
                                   one ? 0.0f : (float)batch_incident(d, n + 1), mid, t.tx, t.ty, one);
 }
 
@@ -1443,25 +1469,31 @@ template <typename F> static void two_step_dispatch(int variant, F &&go)
 {
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
+    using H4 = std::integral_constant<int, 4>;
     using H8 = std::integral_constant<int, 8>;
     using H16 = std::integral_constant<int, 16>;
     using H32 = std::integral_constant<int, 32>;
     using X2 = std::integral_constant<int, 2>;
     using X8 = std::integral_constant<int, 8>;
+    using L1 = std::integral_constant<int, 1>;
+    using L2 = std::integral_constant<int, 2>;
     switch (variant) {
-    case TWO_V1_H8_X2: go(I1{}, H8{}, X2{}); break;
-    case TWO_V1_H16_X2: go(I1{}, H16{}, X2{}); break;
-    case TWO_V2_H8_X2: go(I2{}, H8{}, X2{}); break;
-    case TWO_V2_H16_X2: go(I2{}, H16{}, X2{}); break;
-    case TWO_V1_H8_X8: go(I1{}, H8{}, X8{}); break;
-    case TWO_V2_H16_X8: go(I2{}, H16{}, X8{}); break;
-    default: go(I2{}, H32{}, X8{}); break;
+    case TWO_V1_H8_X2: go(I1{}, H8{}, X2{}, L1{}); break;
+    case TWO_V1_H16_X2: go(I1{}, H16{}, X2{}, L1{}); break;
+    case TWO_V2_H8_X2: go(I2{}, H8{}, X2{}, L1{}); break;
+    case TWO_V2_H16_X2: go(I2{}, H16{}, X2{}, L1{}); break;
+    case TWO_V1_H8_X8: go(I1{}, H8{}, X8{}, L1{}); break;
+    case TWO_V2_H16_X8: go(I2{}, H16{}, X8{}, L1{}); break;
+    case TWO_V2_H32_X8: go(I2{}, H32{}, X8{}, L1{}); break;
+    case TWO_V1_H8_X8_LA2: go(I1{}, H8{}, X8{}, L2{}); break;
+    case TWO_V1_H4_X8_LA2: go(I1{}, H4{}, X8{}, L2{}); break;
+    default: go(I1{}, H16{}, X8{}, L2{}); break;
     }
 }
 
 void two_step_shape(int variant, int nx, int ny, int &nsx, int &nsy)
 {
-    two_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag) {
+    two_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag, auto) {
         constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
         nsx = (nx + two_step_width<V, HX>() - 1) / two_step_width<V, HX>();
         nsy = (ny + H - 1) / H;
@@ -1474,12 +1506,13 @@ hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, vo
     const float e0 = (float)einc0, e1 = (float)einc1;
     auto run = [&](auto tag) {
         typedef decltype(tag) T;
-        two_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag) {
+        two_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag, auto ltag) {
             constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
+            constexpr int LA = decltype(ltag)::value;
             const int nsx = (L.nx + two_step_width<V, HX>() - 1) / two_step_width<V, HX>();
             const int nsy = (L.ny + H - 1) / H;
             const int blocks = (nsx * nsy + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
-            hipLaunchKernelGGL((k_step2_neq<T, V, H, HX>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src, dst,
+            hipLaunchKernelGGL((k_step2_neq<T, V, H, HX, LA>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src, dst,
                                e0, e1, mid, nsx, nsy);
         });
     };
@@ -1495,9 +1528,10 @@ hipError_t launch_step2_batch(int precision, int variant, SolveDesc *d, const Ti
     const int blocks = (nitems + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
     auto run = [&](auto tag) {
         typedef decltype(tag) T;
-        two_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag) {
+        two_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag, auto ltag) {
             constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
-            hipLaunchKernelGGL((k_step2_neq_batch<T, V, H, HX>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, d,
+            constexpr int LA = decltype(ltag)::value;
+            hipLaunchKernelGGL((k_step2_neq_batch<T, V, H, HX, LA>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, d,
                                items, nitems, remap);
         });
     };

@@ -241,7 +241,7 @@ double incident(const Plan &q, int64_t n)
 static std::atomic<int> g_variant[3] = {{0}, {NEQ_DIRECT}, {NEQ_DIRECT}};
 // Two-step kernel variant per precision for the steps outside the averaging
 // window, -1 = off (FP64 has none).
-static std::atomic<int> g_two[3] = {{-1}, {-1}, {-1}};
+static std::atomic<int> g_two[3] = {{-1}, {TWO_V1_H8_X8}, {TWO_V1_H8_X8}};
 
 int step_variant(int precision) { return g_variant[precision].load(std::memory_order_relaxed); }
 void set_step_variant(int precision, int v) { g_variant[precision].store(v, std::memory_order_relaxed); }
@@ -299,6 +299,8 @@ Lattice lattice_of(const Plan &q, const uint8_t *dmask)
         L.eps[k] = q.eps[k];
         L.eps_rest[k] = q.eps[k] - 2.0 / 3.0;
         L.inv_eps[k] = 1.0 / q.eps[k];
+        L.inv_eps_f[k] = (float)L.inv_eps[k];
+        L.eps_rest_f[k] = (float)L.eps_rest[k];
     }
     L.te = q.prob.polarization == JLB_TE ? 1 : 0;
     L.stream_stores = 2 * q.state_bytes > CACHE_RESIDENT_BYTES ? 1 : 0;

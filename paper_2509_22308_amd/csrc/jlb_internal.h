@@ -25,8 +25,10 @@ enum : uint8_t { MASK_CONTOUR = 1u << 6 };
 // extrapolation (the entering population is I_ghost + (1 - delta)(f* - I)).
 constexpr double OPEN_DELTA = 1.0 / 20.0;
 
-// Rows are padded to a multiple of this many nodes.
-constexpr int ROW_ALIGN = 64;
+// Rows are padded to a multiple of this many nodes: 64 bytes of FP32, so
+// every FP32 / FP64 plane row starts 64-byte aligned, and a multiple of the
+// widest vector (4 nodes) so vector accesses never leave the padded row.
+constexpr int ROW_ALIGN = 16;
 
 // Lattice of one solve as the kernels see it.  Rows 0..ny-1 are the domain,
 // row ny is the one-row incident-wave companion lattice.
@@ -52,6 +54,8 @@ struct Lattice {
     double eps[4];        // permittivity per material id (id 3 unused)
     double eps_rest[4];   // eps - 2/3: coefficient of Ez in the rest e-population's equilibrium
     double inv_eps[4];    // 1 / eps (the FP32 / BF16 update multiplies by it)
+    float inv_eps_f[4];   // the two above rounded to FP32 once, on the host
+    float eps_rest_f[4];
     int stream_stores;    // 1: write the next state past the caches (state larger than the Infinity Cache)
     int te;               // 1: TE^z, stored as (Hz, -Ex, -Ey) in the (Ez, Hx, Hy) slots; single-step kernels only
 };
@@ -102,7 +106,10 @@ enum TwoStepVariant {
     TWO_V1_H8_X8 = 4,
     TWO_V2_H16_X8 = 5,
     TWO_V2_H32_X8 = 6,
-    TWO_STEP_VARIANTS = 7
+    TWO_V1_H8_X8_LA2 = 7,   // the same with each row's load issued two rows ahead
+    TWO_V1_H4_X8_LA2 = 8,
+    TWO_V1_H16_X8_LA2 = 9,
+    TWO_STEP_VARIANTS = 10
 };
 // mid (optional): the fields at n + 1 of the contour-stencil nodes are
 // written there (3 float planes, row-interleaved, row stride 3 pitch).
