@@ -577,6 +577,9 @@ void orc_ntff(int n, const double *rx, const double *ry, const double *nx, const
  *   acc          optional [N_c][4] output, time sums of Ez^2, Hx^2, Hy^2, HxHy
  *   s2           optional [far_angles] output, far-field intensity |S(phi)|^2
  *                at lab angles phi = 2 pi a / far_angles (0 = forward)
+ *   phasors      optional [N_c][12] output with s2: (re, im) of the single-bin
+ *                phasors of the total Ez, Hx, Hy (TE^z: Hz, Ex, Ey) at the
+ *                contour samples, then of the incident ones
  *
  * Far field (Sec. II.A).  Over the last period of the run the single-bin
  * phasors F = (2/T) sum_t F(t) exp(j omega t) of Ez, Hx, Hy are accumulated at
@@ -598,7 +601,7 @@ void orc_ntff(int n, const double *rx, const double *ry, const double *nx, const
  */
 int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
             double *ez_out, double *hx_out, double *hy_out, double *energy,
-            double *acc_out, double *s2_out, orc_result *res)
+            double *acc_out, double *s2_out, double *phasors_out, orc_result *res)
 {
     if (!p || !res || p->nx < 1 || p->ny < 1 || p->steps < 0 || p->wavelength <= 0.0) return ORC_E_ARG;
     const int nx = p->nx, ny = p->ny;
@@ -749,6 +752,8 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
         if (!tmp) { free(buf); rc = ORC_E_OOM; goto done; }
         for (int q = 0; q < 3; ++q) { sre[q] = tmp + (2 * q) * nc; sim[q] = tmp + (2 * q + 1) * nc; }
         double ei2 = 0.0;
+        if (phasors_out)
+            for (size_t k = 0; k < (size_t)nc * 12; ++k) phasors_out[k] = sc * dft[k];
         /* TE^z: the scalar field is Hz, and curl H = -j k0 E makes dHz/dn =
          * -j k0 [n_x (-Ey) - n_y (-Ex)]: the transform of TM^z with (Hx, Hy)
          * replaced by (-Ex, -Ey) */

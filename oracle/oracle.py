@@ -78,7 +78,7 @@ def _load():
         lib.orc_mask.restype = ctypes.c_int
         lib.orc_run.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Result)]
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Result)]
         lib.orc_run.restype = ctypes.c_int
         lib.orc_ntff.argtypes = ([ctypes.c_int] + [ctypes.c_void_p] * 4 + [ctypes.c_double] + [ctypes.c_void_p] * 6
                                  + [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_void_p])
@@ -158,9 +158,11 @@ def solve(prob: dict, *, literal: bool = False, boundary: str = "open", mat: np.
     ncp = _load().orc_contour_points(ctypes.byref(p))
     acc = np.zeros((ncp, 4)) if accumulators else None
     s2 = np.zeros(far_angles) if far_angles > 0 else None
+    nc = _load().orc_contour_points(ctypes.byref(p)) if far_angles > 0 else 0
+    ph = np.zeros((nc, 12)) if far_angles > 0 else None
     res = _Result()
     rc = _load().orc_run(ctypes.byref(p), _ptr(mat), _ptr(st), _ptr(ez), _ptr(hx), _ptr(hy), _ptr(en),
-                         _ptr(acc), _ptr(s2), ctypes.byref(res))
+                         _ptr(acc), _ptr(s2), _ptr(ph), ctypes.byref(res))
     if rc != 0:
         raise ValueError("oracle run failed: %d" % rc)
     out = {k: getattr(res, k) for k in ("fx", "fy", "tz", "fx_raw", "fy_raw", "tz_raw", "energy_final",
@@ -173,6 +175,8 @@ def solve(prob: dict, *, literal: bool = False, boundary: str = "open", mat: np.
         out["acc"] = acc
     if s2 is not None:
         out["s2"] = s2
+        # complex phasors at the contour samples: total (Ez, Hx, Hy), then incident
+        out["phasors"] = ph[:, 0::2] + 1j * ph[:, 1::2]
     if st is not None:
         out["state"] = st
     return out
