@@ -87,6 +87,8 @@ struct jlb_engine {
     int remap = 0;
     bool dirty = true;
     hipGraphExec_t graph = nullptr;
+    double *h_out = nullptr;    // pinned host staging of finished solves' results
+    size_t h_out_cap = 0;       // solves it holds
 };
 
 namespace {
@@ -97,24 +99,26 @@ size_t footprint_of(const Plan &q)
     return q.ws_bytes + (size_t)(ramp_end + q.T) * sizeof(double);
 }
 
-int admit_one(jlb_engine *e, uint64_t t)
+// Queues the allocation and uploads of one admission; the host data stays
+// in `st` until the caller synchronises the stream.
+int admit_one(jlb_engine *e, uint64_t t, UploadStaging &st)
 {
     Request &r = e->reqs[t];
     const Plan &q = r.plan;
     hipError_t err = hipMallocAsync((void **)&r.ws, r.footprint, e->s);
     if (err != hipSuccess) return fail(JLB_E_OOM, "hipMallocAsync(%zu): %s", r.footprint, hipGetErrorString(err));
-    int rc = upload_setup(q, r.ws, e->s);
+    int rc = upload_setup_async(q, r.ws, e->s, st);
     if (rc) return rc;
     // incident values: the ramp steps one by one, then one period indexed by n mod T
     r.ramp_end = (int64_t)std::ceil(q.ramp_steps);
-    std::vector<double> tab((size_t)(r.ramp_end + q.T));
+    st.bufs.emplace_back((size_t)(r.ramp_end + q.T) * sizeof(double));
+    double *tab = reinterpret_cast<double *>(st.bufs.back().data());
     for (int64_t n = 0; n < r.ramp_end; ++n) tab[n] = incident(q, n);
     for (int64_t k = 0; k < q.T; ++k) {
         const int64_t n = r.ramp_end + ((k - r.ramp_end % q.T) + q.T) % q.T;  // first n >= ramp_end with n % T == k
         tab[r.ramp_end + k] = incident(q, n);
     }
-    err = hipMemcpyAsync(r.ws + q.ws_bytes, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, e->s);
-    if (err == hipSuccess) err = hipStreamSynchronize(e->s);
+    err = hipMemcpyAsync(r.ws + q.ws_bytes, tab, st.bufs.back().size(), hipMemcpyHostToDevice, e->s);
     if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine upload: %s", hipGetErrorString(err));
     r.status = JLB_REQ_RUNNING;
     r.n = 0;
@@ -136,21 +140,34 @@ int admit(jlb_engine *e)
     if (e->policy == JLB_POLICY_SJF)
         std::stable_sort(order.begin(), order.end(),
                          [&](uint64_t a, uint64_t b) { return work_of(e->reqs[a]) < work_of(e->reqs[b]); });
+    // every admission of this call is queued first, then one synchronisation
+    // covers all their uploads
+    UploadStaging st;
+    int rc = JLB_OK;
+    std::vector<uint64_t> taken;
     for (uint64_t t : order) {
         if ((int)e->resident.size() >= e->max_slots) break;
         Request &r = e->reqs[t];
         if (e->in_use + r.footprint > e->budget) continue;
-        e->queue.erase(std::find(e->queue.begin(), e->queue.end(), t));
-        int rc = admit_one(e, t);
+        taken.push_back(t);
+        rc = admit_one(e, t, st);
         if (rc) {
             Request &rr = e->reqs[t];
             rr.status = JLB_REQ_FAILED;
             if (rr.ws) (void)hipFreeAsync(rr.ws, e->s);
             rr.ws = nullptr;
-            return rc;
+            break;
         }
     }
-    return JLB_OK;
+    if (!taken.empty()) {
+        std::sort(taken.begin(), taken.end());
+        e->queue.erase(std::remove_if(e->queue.begin(), e->queue.end(),
+                                      [&](uint64_t t) { return std::binary_search(taken.begin(), taken.end(), t); }),
+                       e->queue.end());
+        hipError_t err = hipStreamSynchronize(e->s);
+        if (err != hipSuccess && rc == JLB_OK) rc = fail(JLB_E_DEVICE, "engine upload: %s", hipGetErrorString(err));
+    }
+    return rc;
 }
 
 int rebuild(jlb_engine *e)
@@ -299,22 +316,38 @@ int capture(jlb_engine *e)
 // Reduces and returns every resident solve whose steps are all done.
 int harvest(jlb_engine *e)
 {
-    for (size_t k = 0; k < e->resident.size();) {
-        Request &r = e->reqs[e->resident[k]];
+    // finished solves: reduce each, copy every result to pinned host memory,
+    // then one synchronisation
+    std::vector<size_t> done;
+    for (size_t k = 0; k < e->resident.size(); ++k)
+        if (e->reqs[e->resident[k]].n >= e->reqs[e->resident[k]].plan.prob.steps) done.push_back(k);
+    if (done.empty()) return JLB_OK;
+    if (e->h_out_cap < done.size()) {
+        if (e->h_out) (void)hipHostFree(e->h_out);
+        e->h_out = nullptr;
+        e->h_out_cap = 0;
+        const size_t cap = std::max<size_t>(done.size(), (size_t)e->max_slots);
+        if (hipHostMalloc((void **)&e->h_out, cap * 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            return fail(JLB_E_OOM, "pinned result staging");
+        e->h_out_cap = cap;
+    }
+    hipError_t err = hipSuccess;
+    for (size_t d = 0; d < done.size() && err == hipSuccess; ++d) {
+        Request &r = e->reqs[e->resident[done[d]]];
         const Plan &q = r.plan;
-        if (r.n < q.prob.steps) {
-            ++k;
-            continue;
-        }
         const ContourDev C = contour_of(q, r.ws);
         const double f0 = M_PI * q.prob.radius * q.prob.e0 * q.prob.e0 / 4.0;
-        double out[8] = {0};
-        hipError_t err = launch_reduce(C, 1.0 / (double)q.window, f0, 2.0 * f0 * q.prob.radius,
-                                       (double *)(r.ws + q.off_out), e->s);
+        err = launch_reduce(C, 1.0 / (double)q.window, f0, 2.0 * f0 * q.prob.radius, (double *)(r.ws + q.off_out), e->s);
         if (err == hipSuccess)
-            err = hipMemcpyAsync(out, r.ws + q.off_out, 6 * sizeof(double), hipMemcpyDeviceToHost, e->s);
-        if (err == hipSuccess) err = hipStreamSynchronize(e->s);
-        if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine harvest: %s", hipGetErrorString(err));
+            err = hipMemcpyAsync(e->h_out + 8 * d, r.ws + q.off_out, 6 * sizeof(double), hipMemcpyDeviceToHost, e->s);
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(e->s);
+    if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine harvest: %s", hipGetErrorString(err));
+    const double t_done = now_ms();
+    for (size_t d = 0; d < done.size(); ++d) {
+        Request &r = e->reqs[e->resident[done[d]]];
+        const Plan &q = r.plan;
+        const double *out = e->h_out + 8 * d;
         r.res.fx = out[0];
         r.res.fy = out[1];
         r.res.tz = out[2];
@@ -327,7 +360,7 @@ int harvest(jlb_engine *e)
         r.res.graph_used = 1;
         r.res.bytes_per_step = (int64_t)q.bytes_per_lup * q.nx * q.ny;
         r.res.state_passes = q.prob.steps;
-        r.t_done = now_ms();
+        r.t_done = t_done;
         r.res.total_ms = r.t_done - r.t_submit;
         r.res.loop_ms = r.t_done - r.t_admit;
         bool finite = true;
@@ -337,9 +370,16 @@ int harvest(jlb_engine *e)
         r.ws = nullptr;
         e->in_use -= r.footprint;
         e->finished += 1;
-        e->resident.erase(e->resident.begin() + (long)k);
-        e->dirty = true;
     }
+    // drop the finished ones from the resident list, keeping the others' order
+    std::vector<uint64_t> keep;
+    keep.reserve(e->resident.size() - done.size());
+    for (size_t k = 0, d = 0; k < e->resident.size(); ++k) {
+        if (d < done.size() && done[d] == k) { ++d; continue; }
+        keep.push_back(e->resident[k]);
+    }
+    e->resident.swap(keep);
+    e->dirty = true;
     return JLB_OK;
 }
 
@@ -503,6 +543,7 @@ int jlb_engine_destroy(jlb_engine *e)
     if (e->d_desc) (void)hipFreeAsync(e->d_desc, e->s);
     if (e->d_tiles) (void)hipFreeAsync(e->d_tiles, e->s);
     (void)hipStreamSynchronize(e->s);
+    if (e->h_out) (void)hipHostFree(e->h_out);
     if (e->own) (void)hipStreamDestroy(e->s);
     delete e;
     return JLB_OK;

@@ -322,8 +322,13 @@ ContourDev contour_of(const Plan &q, char *ws)
     return C;
 }
 
-int upload_setup(const Plan &q, char *ws, hipStream_t s)
+int upload_setup_async(const Plan &q, char *ws, hipStream_t s, UploadStaging &st)
 {
+    // the mask and the contour tables sit back to back in the workspace
+    // (off_mask .. off_acc): one host image of that range, one copy
+    const size_t lo = q.off_mask, hi = q.off_acc;
+    st.bufs.emplace_back(hi - lo, 0);
+    std::vector<uint8_t> &img = st.bufs.back();
     std::vector<uint8_t> mask;
     build_mask(q, mask);
     ContourHost ch;
@@ -331,19 +336,29 @@ int upload_setup(const Plan &q, char *ws, hipStream_t s)
     for (int k = 0; k < q.nc; ++k)
         for (int dj = 0; dj < 2; ++dj)
             for (int di = 0; di < 2; ++di) mask[(size_t)(ch.j0[k] + dj) * q.pitch + ch.i0[k] + di] |= MASK_CONTOUR;
-    HIP_TRY(hipMemcpyAsync(ws + q.off_mask, mask.data(), mask.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ws + q.off_i0, ch.i0.data(), q.nc * sizeof(int), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ws + q.off_j0, ch.j0.data(), q.nc * sizeof(int), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ws + q.off_wx, ch.wx.data(), q.nc * sizeof(double), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ws + q.off_wy, ch.wy.data(), q.nc * sizeof(double), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ws + q.off_nxk, ch.nxk.data(), q.nc * sizeof(double), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ws + q.off_nyk, ch.nyk.data(), q.nc * sizeof(double), hipMemcpyHostToDevice, s));
+    auto put = [&](size_t off, const void *src, size_t bytes) { memcpy(img.data() + (off - lo), src, bytes); };
+    put(q.off_mask, mask.data(), mask.size());
+    put(q.off_i0, ch.i0.data(), q.nc * sizeof(int));
+    put(q.off_j0, ch.j0.data(), q.nc * sizeof(int));
+    put(q.off_wx, ch.wx.data(), q.nc * sizeof(double));
+    put(q.off_wy, ch.wy.data(), q.nc * sizeof(double));
+    put(q.off_nxk, ch.nxk.data(), q.nc * sizeof(double));
+    put(q.off_nyk, ch.nyk.data(), q.nc * sizeof(double));
+    HIP_TRY(hipMemcpyAsync(ws + lo, img.data(), img.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(ws + q.off_state[0], 0, q.state_bytes, s));
     HIP_TRY(hipMemsetAsync(ws + q.off_state[1], 0, q.state_bytes, s));
     if (q.prob.precision == JLB_FP64) HIP_TRY(hipMemsetAsync(ws + q.off_fields, 0, 2 * 3 * q.plane * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(ws + q.off_acc, 0, 4 * q.nc * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(ws + q.off_dft, 0, 12 * q.nc * sizeof(double), s));
-    // the host vectors are released on return: finish the copies first
+    return JLB_OK;
+}
+
+int upload_setup(const Plan &q, char *ws, hipStream_t s)
+{
+    UploadStaging st;
+    int rc = upload_setup_async(q, ws, s, st);
+    if (rc) return rc;
+    // the host image is released on return: finish the copy first
     HIP_TRY(hipStreamSynchronize(s));
     return JLB_OK;
 }
