@@ -55,6 +55,11 @@ struct Request {
     int64_t ramp_end = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     double loop_ms_acc = 0;
+    // host data of the uploads, prepared ahead while the device runs and
+    // released once the admission's copies are done
+    std::vector<uint8_t> img;
+    std::vector<double> tab;
+    bool prepared = false;
 };
 
 }  // namespace
@@ -99,26 +104,35 @@ size_t footprint_of(const Plan &q)
     return q.ws_bytes + (size_t)(ramp_end + q.T) * sizeof(double);
 }
 
+// Host data of one request's uploads: the mask / contour image and the
+// incident values (the ramp steps one by one, then one period indexed by n mod T).
+void prepare(Request &r)
+{
+    if (r.prepared) return;
+    const Plan &q = r.plan;
+    prepare_upload(q, r.img);
+    r.ramp_end = (int64_t)std::ceil(q.ramp_steps);
+    r.tab.assign((size_t)(r.ramp_end + q.T), 0.0);
+    for (int64_t n = 0; n < r.ramp_end; ++n) r.tab[n] = incident(q, n);
+    for (int64_t k = 0; k < q.T; ++k) {
+        const int64_t n = r.ramp_end + ((k - r.ramp_end % q.T) + q.T) % q.T;  // first n >= ramp_end with n % T == k
+        r.tab[r.ramp_end + k] = incident(q, n);
+    }
+    r.prepared = true;
+}
+
 // Queues the allocation and uploads of one admission; the host data stays
-// in `st` until the caller synchronises the stream.
-int admit_one(jlb_engine *e, uint64_t t, UploadStaging &st)
+// in the request until the caller has synchronised the stream.
+int admit_one(jlb_engine *e, uint64_t t)
 {
     Request &r = e->reqs[t];
     const Plan &q = r.plan;
+    prepare(r);
     hipError_t err = hipMallocAsync((void **)&r.ws, r.footprint, e->s);
     if (err != hipSuccess) return fail(JLB_E_OOM, "hipMallocAsync(%zu): %s", r.footprint, hipGetErrorString(err));
-    int rc = upload_setup_async(q, r.ws, e->s, st);
+    int rc = enqueue_upload(q, r.ws, e->s, r.img);
     if (rc) return rc;
-    // incident values: the ramp steps one by one, then one period indexed by n mod T
-    r.ramp_end = (int64_t)std::ceil(q.ramp_steps);
-    st.bufs.emplace_back((size_t)(r.ramp_end + q.T) * sizeof(double));
-    double *tab = reinterpret_cast<double *>(st.bufs.back().data());
-    for (int64_t n = 0; n < r.ramp_end; ++n) tab[n] = incident(q, n);
-    for (int64_t k = 0; k < q.T; ++k) {
-        const int64_t n = r.ramp_end + ((k - r.ramp_end % q.T) + q.T) % q.T;  // first n >= ramp_end with n % T == k
-        tab[r.ramp_end + k] = incident(q, n);
-    }
-    err = hipMemcpyAsync(r.ws + q.ws_bytes, tab, st.bufs.back().size(), hipMemcpyHostToDevice, e->s);
+    err = hipMemcpyAsync(r.ws + q.ws_bytes, r.tab.data(), r.tab.size() * sizeof(double), hipMemcpyHostToDevice, e->s);
     if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine upload: %s", hipGetErrorString(err));
     r.status = JLB_REQ_RUNNING;
     r.n = 0;
@@ -132,17 +146,44 @@ int admit_one(jlb_engine *e, uint64_t t, UploadStaging &st)
 
 double work_of(const Request &r) { return (double)r.plan.nx * r.plan.ny * (double)r.plan.prob.steps; }
 
-// Admit every queued request that fits, in the policy's order: first fit in
-// arrival order, or smallest work first.
-int admit(jlb_engine *e)
+// Queued requests in the order admission considers them: arrival order, or
+// smallest work first.
+std::vector<uint64_t> admission_order(jlb_engine *e)
 {
     std::vector<uint64_t> order(e->queue.begin(), e->queue.end());
     if (e->policy == JLB_POLICY_SJF)
         std::stable_sort(order.begin(), order.end(),
                          [&](uint64_t a, uint64_t b) { return work_of(e->reqs[a]) < work_of(e->reqs[b]); });
+    return order;
+}
+
+// Host preparation of the next admissions while the device runs a chunk:
+// at most PREPARE_PER_CHUNK requests per call and PREPARE_BYTES of images
+// held ahead.
+constexpr int PREPARE_PER_CHUNK = 64;
+constexpr size_t PREPARE_BYTES = (size_t)256 << 20;
+void prepare_ahead(jlb_engine *e)
+{
+    size_t held = 0;
+    int made = 0;
+    for (uint64_t t : admission_order(e)) {
+        Request &r = e->reqs[t];
+        if (!r.prepared) {
+            if (made == PREPARE_PER_CHUNK || held + r.plan.ws_bytes > PREPARE_BYTES) break;
+            prepare(r);
+            ++made;
+        }
+        held += r.img.size() + r.tab.size() * sizeof(double);
+        if (held > PREPARE_BYTES) break;
+    }
+}
+
+// Admit every queued request that fits, in the policy's order (first fit).
+int admit(jlb_engine *e)
+{
+    const std::vector<uint64_t> order = admission_order(e);
     // every admission of this call is queued first, then one synchronisation
     // covers all their uploads
-    UploadStaging st;
     int rc = JLB_OK;
     std::vector<uint64_t> taken;
     for (uint64_t t : order) {
@@ -150,7 +191,7 @@ int admit(jlb_engine *e)
         Request &r = e->reqs[t];
         if (e->in_use + r.footprint > e->budget) continue;
         taken.push_back(t);
-        rc = admit_one(e, t, st);
+        rc = admit_one(e, t);
         if (rc) {
             Request &rr = e->reqs[t];
             rr.status = JLB_REQ_FAILED;
@@ -166,6 +207,11 @@ int admit(jlb_engine *e)
                        e->queue.end());
         hipError_t err = hipStreamSynchronize(e->s);
         if (err != hipSuccess && rc == JLB_OK) rc = fail(JLB_E_DEVICE, "engine upload: %s", hipGetErrorString(err));
+        for (uint64_t t : taken) {
+            Request &r = e->reqs[t];
+            std::vector<uint8_t>().swap(r.img);
+            std::vector<double>().swap(r.tab);
+        }
     }
     return rc;
 }
@@ -448,6 +494,8 @@ int jlb_engine_run(jlb_engine *e, int64_t steps, int32_t *active)
                 if (rc) return rc;
             }
             if (hipGraphLaunch(e->graph, e->s) != hipSuccess) return fail(JLB_E_DEVICE, "engine graph launch");
+            // host work for the next admissions while the chunk runs
+            prepare_ahead(e);
         } else {
             for (int64_t i = 0; i < k / 2; ++i)
                 if (launch_double_step(e) != hipSuccess) return fail(JLB_E_DEVICE, "engine step launch");
@@ -493,6 +541,9 @@ int jlb_engine_cancel(jlb_engine *e, uint64_t ticket)
     Request &r = it->second;
     if (r.status == JLB_REQ_QUEUED) {
         e->queue.erase(std::remove(e->queue.begin(), e->queue.end(), ticket), e->queue.end());
+        std::vector<uint8_t>().swap(r.img);  // host data prepared ahead
+        std::vector<double>().swap(r.tab);
+        r.prepared = false;
     } else if (r.status == JLB_REQ_RUNNING) {
         if (hipStreamSynchronize(e->s) != hipSuccess) return fail(JLB_E_DEVICE, "engine sync");
         (void)hipFreeAsync(r.ws, e->s);

@@ -322,13 +322,12 @@ ContourDev contour_of(const Plan &q, char *ws)
     return C;
 }
 
-int upload_setup_async(const Plan &q, char *ws, hipStream_t s, UploadStaging &st)
+void prepare_upload(const Plan &q, std::vector<uint8_t> &img)
 {
     // the mask and the contour tables sit back to back in the workspace
     // (off_mask .. off_acc): one host image of that range, one copy
     const size_t lo = q.off_mask, hi = q.off_acc;
-    st.bufs.emplace_back(hi - lo, 0);
-    std::vector<uint8_t> &img = st.bufs.back();
+    img.assign(hi - lo, 0);
     std::vector<uint8_t> mask;
     build_mask(q, mask);
     ContourHost ch;
@@ -344,7 +343,11 @@ int upload_setup_async(const Plan &q, char *ws, hipStream_t s, UploadStaging &st
     put(q.off_wy, ch.wy.data(), q.nc * sizeof(double));
     put(q.off_nxk, ch.nxk.data(), q.nc * sizeof(double));
     put(q.off_nyk, ch.nyk.data(), q.nc * sizeof(double));
-    HIP_TRY(hipMemcpyAsync(ws + lo, img.data(), img.size(), hipMemcpyHostToDevice, s));
+}
+
+int enqueue_upload(const Plan &q, char *ws, hipStream_t s, const std::vector<uint8_t> &img)
+{
+    HIP_TRY(hipMemcpyAsync(ws + q.off_mask, img.data(), img.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(ws + q.off_state[0], 0, q.state_bytes, s));
     HIP_TRY(hipMemsetAsync(ws + q.off_state[1], 0, q.state_bytes, s));
     if (q.prob.precision == JLB_FP64) HIP_TRY(hipMemsetAsync(ws + q.off_fields, 0, 2 * 3 * q.plane * sizeof(double), s));
@@ -355,8 +358,9 @@ int upload_setup_async(const Plan &q, char *ws, hipStream_t s, UploadStaging &st
 
 int upload_setup(const Plan &q, char *ws, hipStream_t s)
 {
-    UploadStaging st;
-    int rc = upload_setup_async(q, ws, s, st);
+    std::vector<uint8_t> img;
+    prepare_upload(q, img);
+    int rc = enqueue_upload(q, ws, s, img);
     if (rc) return rc;
     // the host image is released on return: finish the copy first
     HIP_TRY(hipStreamSynchronize(s));

@@ -50,13 +50,11 @@ hipStream_t own_stream();
 Lattice lattice_of(const Plan &q, const uint8_t *dmask);
 ContourDev contour_of(const Plan &q, char *ws);
 int upload_setup(const Plan &q, char *ws, hipStream_t s);
-// Host buffers of uploads in flight, kept alive until the stream passes them.
-struct UploadStaging {
-    std::vector<std::vector<uint8_t>> bufs;
-};
-// upload_setup without the final synchronisation: the caller keeps `st` alive
-// until the stream has passed the copies.
-int upload_setup_async(const Plan &q, char *ws, hipStream_t s, UploadStaging &st);
+// upload_setup in two halves: the host image of the mask and contour tables
+// (host work only), then its copy and the zeroing of the device state on `s`
+// (asynchronous: `img` must stay alive until the stream has passed the copy).
+void prepare_upload(const Plan &q, std::vector<uint8_t> &img);
+int enqueue_upload(const Plan &q, char *ws, hipStream_t s, const std::vector<uint8_t> &img);
 int step_variant(int precision);
 // Two-step variant of a precision (-1: single steps only; always -1 for FP64).
 int two_step_variant(int precision);
