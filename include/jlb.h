@@ -75,6 +75,8 @@ typedef enum {
 #define JLB_F_ALLOW_UNDERRESOLVED 1u  /* skip the lambda / sqrt(eps_max) >= 10 check         */
 #define JLB_F_NO_GRAPH 2u             /* launch every step directly instead of replaying a
                                          captured hipGraph of whole periods                  */
+#define JLB_F_CENTRE 4u               /* place the disk centre at (cx, cy) (node coordinates)
+                                         instead of the grid centre ((nx-1)/2, (ny-1)/2)  */
 
 /*
  * One scattering problem (Sec. II; Sec. III for the domain and the source).
@@ -102,6 +104,7 @@ typedef struct {
     double plateau_tol;      /* > 0: plateau stop (jlb_solve only; see below); 0: off     */
     int32_t polarization;    /* JLB_TM (0, Sec. II) or JLB_TE (1; see below)               */
     int32_t reserved;        /* 0                                                         */
+    double cx, cy;           /* disk centre in node coordinates, with JLB_F_CENTRE         */
 } jlb_problem;
 
 /*

@@ -577,6 +577,9 @@ void orc_ntff(int n, const double *rx, const double *ry, const double *nx, const
  *   acc          optional [N_c][4] output, time sums of Ez^2, Hx^2, Hy^2, HxHy
  *   s2           optional [far_angles] output, far-field intensity |S(phi)|^2
  *                at lab angles phi = 2 pi a / far_angles (0 = forward)
+ *   force        optional [steps][3] output: after each step n, the stress
+ *                integral with the fields at level n + 1 instead of their time
+ *                average (instantaneous F~x, F~y, M~z, same normalisation)
  *   phasors      optional [N_c][12] output with s2: (re, im) of the single-bin
  *                phasors of the total Ez, Hx, Hy (TE^z: Hz, Ex, Ey) at the
  *                contour samples, then of the incident ones
@@ -601,7 +604,7 @@ void orc_ntff(int n, const double *rx, const double *ry, const double *nx, const
  */
 int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
             double *ez_out, double *hx_out, double *hy_out, double *energy,
-            double *acc_out, double *s2_out, double *phasors_out, orc_result *res)
+            double *acc_out, double *s2_out, double *phasors_out, double *force_out, orc_result *res)
 {
     if (!p || !res || p->nx < 1 || p->ny < 1 || p->steps < 0 || p->wavelength <= 0.0) return ORC_E_ARG;
     const int nx = p->nx, ny = p->ny;
@@ -686,6 +689,25 @@ int orc_run(const orc_params *p, const uint8_t *mat_in, double *state_io,
                     dft[12 * k + 2 * q + 1] += g[q] * sn;
                 }
             }
+        }
+        if (force_out && do_contour) {
+            /* the stress of Sec. II.B with the instantaneous fields */
+            const double w = 2.0 * M_PI * con.rc / con.n;
+            const double f0 = M_PI * p->radius * p->e0 * p->e0 / 4.0, m0 = 2.0 * f0 * p->radius;
+            double fx = 0.0, fy = 0.0, tz = 0.0;
+            for (int k = 0; k < con.n; ++k) {
+                const double e = bilinear(ez, nx, con.px[k], con.py[k]);
+                const double u = bilinear(hx, nx, con.px[k], con.py[k]);
+                const double v = bilinear(hy, nx, con.px[k], con.py[k]);
+                const double txx = 0.5 * (u * u - v * v - e * e), tyy = 0.5 * (v * v - u * u - e * e), txy = u * v;
+                const double tx = txx * con.nxv[k] + txy * con.nyv[k], ty = txy * con.nxv[k] + tyy * con.nyv[k];
+                fx += w * tx;
+                fy += w * ty;
+                tz += w * con.rc * (con.nxv[k] * ty - con.nyv[k] * tx);
+            }
+            force_out[3 * n] = fx / f0;
+            force_out[3 * n + 1] = fy / f0;
+            force_out[3 * n + 2] = tz / m0;
         }
         if (do_contour && n + 1 > stop - window) {
             for (int k = 0; k < con.n; ++k) {

@@ -78,7 +78,8 @@ def _load():
         lib.orc_mask.restype = ctypes.c_int
         lib.orc_run.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Result)]
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.POINTER(_Result)]
         lib.orc_run.restype = ctypes.c_int
         lib.orc_ntff.argtypes = ([ctypes.c_int] + [ctypes.c_void_p] * 4 + [ctypes.c_double] + [ctypes.c_void_p] * 6
                                  + [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_void_p])
@@ -136,7 +137,8 @@ def contour_points(prob: dict) -> int:
 
 def solve(prob: dict, *, literal: bool = False, boundary: str = "open", mat: np.ndarray | None = None,
           state: np.ndarray | None = None, fields: bool = True, energy: bool = False,
-          accumulators: bool = False, threads: int | None = None, far_angles: int = 0) -> dict:
+          accumulators: bool = False, threads: int | None = None, far_angles: int = 0,
+          force_trace: bool = False) -> dict:
     """Run the oracle.  Returns forces, optional fields, energy trace, final
     state, and the far-field intensity at far_angles lab angles (key "s2")."""
     p = _params(prob, boundary=boundary, literal=literal, threads=threads)
@@ -160,9 +162,10 @@ def solve(prob: dict, *, literal: bool = False, boundary: str = "open", mat: np.
     s2 = np.zeros(far_angles) if far_angles > 0 else None
     nc = _load().orc_contour_points(ctypes.byref(p)) if far_angles > 0 else 0
     ph = np.zeros((nc, 12)) if far_angles > 0 else None
+    ftr = np.zeros((p.steps, 3)) if force_trace else None
     res = _Result()
     rc = _load().orc_run(ctypes.byref(p), _ptr(mat), _ptr(st), _ptr(ez), _ptr(hx), _ptr(hy), _ptr(en),
-                         _ptr(acc), _ptr(s2), _ptr(ph), ctypes.byref(res))
+                         _ptr(acc), _ptr(s2), _ptr(ph), _ptr(ftr), ctypes.byref(res))
     if rc != 0:
         raise ValueError("oracle run failed: %d" % rc)
     out = {k: getattr(res, k) for k in ("fx", "fy", "tz", "fx_raw", "fy_raw", "tz_raw", "energy_final",
@@ -173,6 +176,8 @@ def solve(prob: dict, *, literal: bool = False, boundary: str = "open", mat: np.
         out["energy"] = en[: p.steps]
     if accumulators:
         out["acc"] = acc
+    if ftr is not None:
+        out["force_trace"] = ftr
     if s2 is not None:
         out["s2"] = s2
         # complex phasors at the contour samples: total (Ez, Hx, Hy), then incident

@@ -26,6 +26,7 @@ KINDS = {"homogeneous": 0, "dielectric_janus": 1, "metallo_dielectric_janus": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 JLB_F_ALLOW_UNDERRESOLVED = 1
 JLB_F_NO_GRAPH = 2
+JLB_F_CENTRE = 4
 REQ_STATUS = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
 
 
@@ -37,6 +38,7 @@ class jlb_problem(ctypes.Structure):
         ("steps", ctypes.c_int64), ("avg_periods", ctypes.c_int32), ("ramp_periods", ctypes.c_int32),
         ("contour_offset", ctypes.c_double), ("contour_points", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("plateau_tol", ctypes.c_double), ("polarization", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("cx", ctypes.c_double), ("cy", ctypes.c_double),
     ]
 
 
@@ -135,8 +137,9 @@ def make_problem(d: dict, precision: str | int | None = None, flags: int = 0) ->
         wavelength=float(d["wavelength"]), e0=float(d.get("e0", 1.0)), steps=int(d["steps"]),
         avg_periods=int(d.get("avg_periods", 5)), ramp_periods=int(d.get("ramp_periods", 1)),
         contour_offset=float(d.get("contour_offset", 3.0)), contour_points=int(d.get("contour_points", 0)),
-        flags=int(flags | d.get("flags", 0)), plateau_tol=float(d.get("plateau_tol", 0.0)),
+        flags=int(flags | d.get("flags", 0) | (JLB_F_CENTRE if "cx" in d or "cy" in d else 0)), plateau_tol=float(d.get("plateau_tol", 0.0)),
         polarization=POLARIZATIONS[d.get("polarization", "tm")],
+        cx=float(d.get("cx", 0.0)), cy=float(d.get("cy", 0.0)),
     )
 
 

@@ -93,13 +93,18 @@ int make_plan(const jlb_problem *p, Plan *pl)
     q.window = (int64_t)p->avg_periods * T;
     q.cx = 0.5 * (p->nx - 1);
     q.cy = 0.5 * (p->ny - 1);
+    if (p->flags & JLB_F_CENTRE) {
+        if (!std::isfinite(p->cx) || !std::isfinite(p->cy)) return fail(JLB_E_ARG, "centre (cx, cy) not finite");
+        q.cx = p->cx;
+        q.cy = p->cy;
+    }
     q.rc = p->radius + p->contour_offset;
     q.nc = p->contour_points > 0 ? p->contour_points : 8 * (int)std::ceil(2.0 * M_PI * q.rc / 8.0);
     // disk, contour and a 4-cell margin inside the grid
     const double reach = q.rc + 4.0;
     if (q.cx - reach < 0.0 || q.cy - reach < 0.0 || q.cx + reach > p->nx - 1 || q.cy + reach > p->ny - 1)
-        return fail(JLB_E_GEOMETRY, "disk radius %.3g + contour offset %.3g + 4 does not fit a %dx%d grid", p->radius,
-                    p->contour_offset, p->nx, p->ny);
+        return fail(JLB_E_GEOMETRY, "disk radius %.3g + contour offset %.3g + 4 around (%.3g, %.3g) does not fit a %dx%d grid",
+                    p->radius, p->contour_offset, q.cx, q.cy, p->nx, p->ny);
     double eps_max = p->eps1;
     if (p->kind == JLB_DIELECTRIC_JANUS) eps_max = std::max(eps_max, p->eps2);
     if (!(p->flags & JLB_F_ALLOW_UNDERRESOLVED) && p->wavelength / std::sqrt(eps_max) < 10.0)

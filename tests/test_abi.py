@@ -32,8 +32,9 @@ def test_library_exports_every_declared_symbol():
 
 @pytest.mark.parametrize("prob", [W.config1(), W.config2(), W.config3(4.0, 45.0), W.small_mdjc(8.0, 135.0),
                                   W.problem(nx=101, ny=77, radius=17.3, kind="dielectric_janus", eps1=3.0, eps2=1.5,
-                                            phi0_deg=225.0, wavelength=40.0, steps=2000)],
-                         ids=["c1", "c2", "c3", "mdjc", "ragged"])
+                                            phi0_deg=225.0, wavelength=40.0, steps=2000),
+                                  dict(W.small_mdjc(2.0, 60.0, a=16), cx=70.0, cy=55.5)],
+                         ids=["c1", "c2", "c3", "mdjc", "ragged", "off-centre"])
 def test_material_map_matches_oracle_bit_for_bit(prob):
     assert np.array_equal(J.jlb_material_map(J.make_problem(prob)), O.mask(prob))
 
@@ -53,6 +54,8 @@ def test_problem_checks_return_the_documented_codes():
     assert J.jlb_validate(J.make_problem(dict(ok, eps1=30.0), flags=J.JLB_F_ALLOW_UNDERRESOLVED)) == 0
     assert J.jlb_validate(J.make_problem(dict(ok, steps=500))) == -4                  # JLB_E_WINDOW
     assert J.jlb_validate(J.make_problem(dict(ok, eps1=0.5))) == -1
+    assert J.jlb_validate(J.make_problem(dict(ok, cx=15.0, cy=63.5))) == -2          # disk + contour off the grid
+    assert J.jlb_validate(J.make_problem(dict(ok, cx=70.0, cy=60.0))) == 0
     assert "eps1" in J.jlb_last_error()
 
 
