@@ -53,9 +53,9 @@ def test_problem_checks_return_the_documented_codes():
     assert J.jlb_validate(bad) == -1 and "polarization" in J.jlb_last_error()
     assert J.jlb_validate(J.make_problem(dict(ok, eps1=30.0), flags=J.JLB_F_ALLOW_UNDERRESOLVED)) == 0
     assert J.jlb_validate(J.make_problem(dict(ok, steps=500))) == -4                  # JLB_E_WINDOW
-    assert J.jlb_validate(J.make_problem(dict(ok, eps1=0.5))) == -1
     assert J.jlb_validate(J.make_problem(dict(ok, cx=15.0, cy=63.5))) == -2          # disk + contour off the grid
     assert J.jlb_validate(J.make_problem(dict(ok, cx=70.0, cy=60.0))) == 0
+    assert J.jlb_validate(J.make_problem(dict(ok, eps1=0.5))) == -1
     assert "eps1" in J.jlb_last_error()
 
 
