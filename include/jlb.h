@@ -195,6 +195,21 @@ int jlb_solve(const jlb_problem *prob, void *workspace, size_t workspace_bytes, 
               double *ez, double *hx, double *hy, double *energy, void *stream);
 
 /*
+ * Instantaneous force trace (Sec. III: the forces settle into a steady
+ * oscillation at twice the frequency of the incident wave).  The solve of
+ * jlb_solve (same result), and after every step n the stress integral of
+ * Sec. II.B evaluated with the fields of level n + 1 instead of their time
+ * average, normalised as F~x, F~y, M~z, into the caller's device array
+ * force[steps][3] of double.  Over the averaging window the entries average
+ * to the result's forces.  Steps are launched one at a time (no graph, no
+ * two-step kernels), as with the energy trace; with the plateau stop, rows
+ * past jlb_result.steps_done are left untouched.
+ * Errors: as jlb_solve; JLB_E_ARG for force NULL.
+ */
+int jlb_solve_force_trace(const jlb_problem *prob, void *workspace, size_t workspace_bytes, jlb_result *res,
+                          double *force, void *stream);
+
+/*
  * Far field (Sec. II.A, Eq. scattering intensity): the solve of jlb_solve
  * (same forces in *res) plus the scattering intensity
  *   |S(phi)|^2 = k0 r |E^S|^2 / |E^I|^2  (r -> infinity)

@@ -82,6 +82,7 @@ def load():
             "jlb_material_map": ([_P(jlb_problem), _vp], ctypes.c_int),
             "jlb_solve": ([_P(jlb_problem), _vp, ctypes.c_size_t, _P(jlb_result), _vp, _vp, _vp, _vp, _vp],
                           ctypes.c_int),
+            "jlb_solve_force_trace": ([_P(jlb_problem), _vp, ctypes.c_size_t, _P(jlb_result), _vp, _vp], ctypes.c_int),
             "jlb_solve_far_field": ([_P(jlb_problem), _vp, ctypes.c_size_t, _P(jlb_result), ctypes.c_int32, _vp,
                                      _vp], ctypes.c_int),
             "jlb_trajectory": ([ctypes.c_int32, ctypes.c_double, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
@@ -188,6 +189,16 @@ def jlb_solve(prob: jlb_problem, workspace=None, ez=None, hx=None, hy=None, ener
     return res
 
 
+def jlb_solve_force_trace(prob: jlb_problem, force, workspace=None, stream=None) -> jlb_result:
+    """One solve plus the instantaneous (F~x, F~y, M~z) after every step into the
+    CUDA float64 tensor force[steps][3] (see jlb_solve_force_trace in include/jlb.h)."""
+    res = jlb_result()
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(load().jlb_solve_force_trace(ctypes.byref(prob), _dptr(workspace), nbytes, ctypes.byref(res), _dptr(force),
+                                        _stream(stream)))
+    return res
+
+
 def jlb_solve_far_field(prob: jlb_problem, n_angles: int, s2, workspace=None, stream=None) -> jlb_result:
     """One solve plus the far-field intensity at n_angles lab angles into the
     CUDA float64 tensor s2 (see jlb_solve_far_field in include/jlb.h)."""
@@ -273,13 +284,20 @@ def jlb_time_two_step_kernel(prob: jlb_problem, warmup: int, launches: int, work
 
 
 def solve(d: dict, precision: str = "fp64", fields: bool = False, energy: bool = False, flags: int = 0,
-          device: str = "cuda", far_angles: int = 0) -> dict:
+          device: str = "cuda", far_angles: int = 0, force_trace: bool = False) -> dict:
     """Convenience wrapper: torch-allocated workspace and outputs; returns
     numpy arrays.  far_angles > 0 runs jlb_solve_far_field (key "s2"; not
     combinable with fields or energy)."""
     import torch
     prob = make_problem(d, precision, flags)
     ws = torch.empty(jlb_workspace_size(prob), dtype=torch.uint8, device=device)
+    if force_trace:
+        if fields or energy or far_angles:
+            raise ValueError("force_trace does not combine with fields, energy or far_angles")
+        ft = torch.zeros((prob.steps, 3), dtype=torch.float64, device=device)
+        out = jlb_solve_force_trace(prob, ft, ws).as_dict()
+        out["force_trace"] = ft.cpu().numpy()
+        return out
     if far_angles > 0:
         if fields or energy:
             raise ValueError("far_angles does not combine with fields or energy")

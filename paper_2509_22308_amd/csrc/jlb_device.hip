@@ -1354,6 +1354,58 @@ __global__ __launch_bounds__(64) void k_far_field(ContourDev C, const double *__
     }
 }
 
+// Instantaneous stress integral (Sec. II.B with the fields of one level
+// instead of their time average): F~x, F~y, M~z into out[0..2].  One block,
+// samples strided over the threads, FP64 sums in a fixed order.  The dual
+// TE^z storage needs no change: the stress only holds squares and the
+// product of the two in-plane components.
+template <typename FT>
+__global__ __launch_bounds__(RED_THREADS) void k_force_now(Lattice L, const FT *__restrict__ fld, ContourDev C,
+                                                           double f0, double m0, double *out)
+{
+    __shared__ double part[3][RED_THREADS / 64];
+    const int t = threadIdx.x;
+    const size_t P = L.plane;
+    const double w = 2.0 * M_PI * C.rc / C.n;
+    double fx = 0.0, fy = 0.0, tz = 0.0;
+    for (int k = t; k < C.n; k += RED_THREADS) {
+        const size_t c00 = at(C.i0[k], C.j0[k], L.sfld), c10 = c00 + L.sfld;
+        const double ax = C.wx[k], ay = C.wy[k];
+        const double w00 = (1.0 - ax) * (1.0 - ay), w01 = ax * (1.0 - ay), w10 = (1.0 - ax) * ay, w11 = ax * ay;
+        double v[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const FT *p = fld + a * P;
+            v[a] = w00 * (double)p[c00] + w01 * (double)p[c00 + 1] + w10 * (double)p[c10] + w11 * (double)p[c10 + 1];
+        }
+        const double txx = 0.5 * (v[1] * v[1] - v[2] * v[2] - v[0] * v[0]);
+        const double tyy = 0.5 * (v[2] * v[2] - v[1] * v[1] - v[0] * v[0]);
+        const double txy = v[1] * v[2];
+        const double nx = C.nxk[k], ny = C.nyk[k];
+        const double tx = txx * nx + txy * ny, ty = txy * nx + tyy * ny;
+        fx += w * tx;
+        fy += w * ty;
+        tz += w * C.rc * (nx * ty - ny * tx);
+    }
+    fx = wave_sum(fx);
+    fy = wave_sum(fy);
+    tz = wave_sum(tz);
+    if ((t & 63) == 0) {
+        part[0][t >> 6] = fx;
+        part[1][t >> 6] = fy;
+        part[2][t >> 6] = tz;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double s3[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < RED_THREADS / 64; ++b) s3[a] += part[a][b];
+        out[0] = s3[0] / f0;
+        out[1] = s3[1] / f0;
+        out[2] = s3[2] / m0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Field energy sum (eps Ez^2 + Hx^2 + Hy^2) / 2 over the domain rows: one
 // partial per block, then one fixed-order pass.
@@ -1568,6 +1620,18 @@ hipError_t launch_far_dft(int precision, const Lattice &L, const void *fields, c
                            sw);
     else
         hipLaunchKernelGGL(k_far_dft<float>, dim3(blocks), dim3(threads), 0, s, L, (const float *)fields, C, dft, cw, sw);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_now(int precision, const Lattice &L, const void *fields, const ContourDev &C, double f0,
+                            double m0, double *out, hipStream_t s)
+{
+    if (precision == 0)
+        hipLaunchKernelGGL(k_force_now<double>, dim3(1), dim3(RED_THREADS), 0, s, L, (const double *)fields, C, f0, m0,
+                           out);
+    else
+        hipLaunchKernelGGL(k_force_now<float>, dim3(1), dim3(RED_THREADS), 0, s, L, (const float *)fields, C, f0, m0,
+                           out);
     return hipGetLastError();
 }
 

@@ -412,7 +412,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     const ContourDev C = contour_of(q, ws);
     int64_t steps = q.prob.steps;
     int64_t wstart = steps - q.window;  // launches from here on produce averaged levels
-    const bool use_graph = !(q.prob.flags & JLB_F_NO_GRAPH) && !energy;
+    const bool use_graph = !(q.prob.flags & JLB_F_NO_GRAPH) && !energy && !far.force;
     // whole periods, a multiple of 4 steps: two-step launches then come in
     // pairs and a chunk leaves state n in buffer n % 2, as single steps do;
     // it is also the spacing of the plateau check points
@@ -524,7 +524,8 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             continue;
         }
         const bool check = !in_window && check_level(n + 1);
-        rc = launch_one_step(q, ws, L, C, n, in_window, energy != nullptr || n == steps - 1 || check, incident(q, n), s);
+        rc = launch_one_step(q, ws, L, C, n, in_window, energy != nullptr || far.force != nullptr || n == steps - 1 || check,
+                             incident(q, n), s);
         if (rc) break;
         ++passes;
         if (check) {
@@ -535,6 +536,12 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             hipError_t e = launch_energy(q.prob.precision, L, fields_ptr(q, ws, n + 1), (double *)(ws + q.off_parts),
                                          q.nparts, energy + n, s);
             if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "energy launch: %s", hipGetErrorString(e));
+        }
+        if (far.force && rc == JLB_OK) {
+            const double f0 = M_PI * q.prob.radius * q.prob.e0 * q.prob.e0 / 4.0;
+            hipError_t e = launch_force_now(q.prob.precision, L, fields_ptr(q, ws, n + 1), C, f0, 2.0 * f0 * q.prob.radius,
+                                            far.force + 3 * n, s);
+            if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "force trace launch: %s", hipGetErrorString(e));
         }
         if (far.s2 && n >= far_start && rc == JLB_OK) {
             // level n + 1 is inside the window (window >= T), so its fields are in place
@@ -686,6 +693,15 @@ int jlb_solve(const jlb_problem *prob, void *workspace, size_t workspace_bytes, 
               double *hx, double *hy, double *energy, void *stream)
 {
     return solve_entry(prob, workspace, workspace_bytes, res, ez, hx, hy, energy, stream, FarOut{0, nullptr});
+}
+
+int jlb_solve_force_trace(const jlb_problem *prob, void *workspace, size_t workspace_bytes, jlb_result *res,
+                          double *force, void *stream)
+{
+    clear_error();
+    if (!force) return fail(JLB_E_ARG, "null force");
+    return solve_entry(prob, workspace, workspace_bytes, res, nullptr, nullptr, nullptr, nullptr, stream,
+                       FarOut{0, nullptr, force});
 }
 
 int jlb_solve_far_field(const jlb_problem *prob, void *workspace, size_t workspace_bytes, jlb_result *res,

@@ -58,10 +58,12 @@ int enqueue_upload(const Plan &q, char *ws, hipStream_t s, const std::vector<uin
 int step_variant(int precision);
 // Two-step variant of a precision (-1: single steps only; always -1 for FP64).
 int two_step_variant(int precision);
-// Far-field output of a solve: nphi angles into the device array s2 (nullptr: none).
+// Optional outputs of a solve: the far field at nphi angles into the device
+// array s2, and the instantaneous force trace [steps][3] (nullptr: none).
 struct FarOut {
     int nphi;
     double *s2;
+    double *force = nullptr;
 };
 int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, double *hy, double *energy,
               hipStream_t s, FarOut far = {0, nullptr});

@@ -127,6 +127,9 @@ hipError_t launch_reduce(const ContourDev &C, double inv_window, double f0, doub
 // (scale = 2 / T).
 hipError_t launch_far_dft(int precision, const Lattice &L, const void *fields, const ContourDev &C, double *dft,
                           double cw, double sw, hipStream_t s);
+// The stress integral with the fields of one level (not averaged): F~x, F~y, M~z.
+hipError_t launch_force_now(int precision, const Lattice &L, const void *fields, const ContourDev &C, double f0,
+                            double m0, double *out, hipStream_t s);
 hipError_t launch_far_field(const ContourDev &C, const double *dft, double k0, double scale, int nphi, double *s2,
                             hipStream_t s);
 hipError_t launch_energy(int precision, const Lattice &L, const void *fields, double *partials, int nparts,
