@@ -145,6 +145,7 @@ typedef struct {
     int32_t graph_used;             /* 1 when whole periods were replayed from a hipGraph     */
     int64_t bytes_per_step;         /* algorithmic HBM bytes of one pass over the state        */
     int64_t state_passes;           /* step-kernel launches (a two-step launch is one pass)    */
+    double energy_final;            /* field energy sum (eps E^2 + H^2)/2 after the last step  */
 } jlb_result;
 
 /* Library version (major * 10000 + minor * 100 + patch). */

@@ -49,7 +49,7 @@ class jlb_result(ctypes.Structure):
         ("loop_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
         ("steps_done", ctypes.c_int64), ("window_steps", ctypes.c_int64),
         ("contour_points", ctypes.c_int32), ("graph_used", ctypes.c_int32),
-        ("bytes_per_step", ctypes.c_int64), ("state_passes", ctypes.c_int64),
+        ("bytes_per_step", ctypes.c_int64), ("state_passes", ctypes.c_int64), ("energy_final", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

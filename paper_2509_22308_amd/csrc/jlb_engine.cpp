@@ -384,8 +384,16 @@ int harvest(jlb_engine *e)
         const ContourDev C = contour_of(q, r.ws);
         const double f0 = M_PI * q.prob.radius * q.prob.e0 * q.prob.e0 / 4.0;
         err = launch_reduce(C, 1.0 / (double)q.window, f0, 2.0 * f0 * q.prob.radius, (double *)(r.ws + q.off_out), e->s);
+        if (err == hipSuccess) {
+            // the final fields: FP64 keeps them in its field planes (written through the window), the
+            // others in the state buffer that holds the last level
+            const Lattice L = lattice_of(q, (const uint8_t *)(r.ws + q.off_mask));
+            const void *fld = q.prob.precision == JLB_FP64 ? (const void *)(r.ws + q.off_fields) : r.ws + q.off_state[r.cur];
+            err = launch_energy(q.prob.precision, L, fld, (double *)(r.ws + q.off_parts), q.nparts,
+                                (double *)(r.ws + q.off_out) + 6, e->s);
+        }
         if (err == hipSuccess)
-            err = hipMemcpyAsync(e->h_out + 8 * d, r.ws + q.off_out, 6 * sizeof(double), hipMemcpyDeviceToHost, e->s);
+            err = hipMemcpyAsync(e->h_out + 8 * d, r.ws + q.off_out, 7 * sizeof(double), hipMemcpyDeviceToHost, e->s);
     }
     if (err == hipSuccess) err = hipStreamSynchronize(e->s);
     if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine harvest: %s", hipGetErrorString(err));
@@ -406,6 +414,7 @@ int harvest(jlb_engine *e)
         r.res.graph_used = 1;
         r.res.bytes_per_step = (int64_t)q.bytes_per_lup * q.nx * q.ny;
         r.res.state_passes = q.prob.steps;
+        r.res.energy_final = out[6];
         r.t_done = t_done;
         r.res.total_ms = r.t_done - r.t_submit;
         r.res.loop_ms = r.t_done - r.t_admit;

@@ -561,8 +561,11 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             e = launch_far_field(C, dft, 2.0 * M_PI / q.prob.wavelength, 2.0 / (double)q.T, far.nphi, far.s2, s);
         if (e == hipSuccess && ez && hx && hy)
             e = launch_fields_out(q.prob.precision, L, fields_ptr(q, ws, steps), ez, hx, hy, s);
+        if (e == hipSuccess)
+            e = launch_energy(q.prob.precision, L, fields_ptr(q, ws, steps), (double *)(ws + q.off_parts), q.nparts,
+                              (double *)(ws + q.off_out) + 6, s);
         double out[8] = {0};
-        if (e == hipSuccess) e = hipMemcpyAsync(out, ws + q.off_out, 6 * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(out, ws + q.off_out, 7 * sizeof(double), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "finishing the solve: %s", hipGetErrorString(e));
         if (rc == JLB_OK) {
@@ -581,6 +584,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             res->graph_used = graph_used;
             res->bytes_per_step = (int64_t)q.bytes_per_lup * q.nx * q.ny;
             res->state_passes = passes;
+            res->energy_final = out[6];
             for (int k = 0; k < 6; ++k)
                 if (!std::isfinite(out[k])) rc = fail(JLB_E_NONFINITE, "forces are not finite");
         }

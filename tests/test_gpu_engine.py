@@ -161,7 +161,7 @@ def test_two_step_and_single_step_solves_share_an_engine(jlb, two_step):
                           budget=sum(jlb.jlb_workspace_size(jlb.make_problem(p, pr)) for p, pr in
                                      zip(_mix()[:3], precs[:3])) + (1 << 24), chunk=128)
     for s, b in zip(single, batched):
-        for q in ("fx", "fy", "tz"):
+        for q in ("fx", "fy", "tz", "energy_final"):
             assert s[q] == b[q], (q, s[q], b[q])
 
 

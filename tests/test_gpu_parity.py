@@ -40,6 +40,7 @@ def _field_scale(ref):
 def _check_fp64(gpu, ref, label=""):
     for q in ("fx", "fy", "tz"):
         assert abs(gpu[q] - ref[q]) <= 1e-12 * max(1.0, abs(ref[q])), (label, q, gpu[q], ref[q])
+    assert abs(gpu["energy_final"] - ref["energy_final"]) <= 1e-12 * ref["energy_final"], (label, "energy_final")
     s = _field_scale(ref)
     for f in ("ez", "hx", "hy"):
         err = np.abs(gpu[f] - ref[f]).max()
@@ -134,6 +135,7 @@ def test_reduced_precision_forces_within_targets(jlb, oracle, precision, case):
     ferr = {f: float(np.abs(g[f] - r[f]).max() / s) for f in ("ez", "hx", "hy")}
     for q in ("fx", "fy", "tz"):
         assert _rel(g[q], r[q]) <= TOL[precision], (case, precision, q, g[q], r[q], ferr)
+    assert abs(g["energy_final"] - r["energy_final"]) <= TOL[precision] * r["energy_final"], (case, precision)
 
 
 def test_config2_cropped_fp64_matches_oracle(jlb, oracle):
