@@ -114,8 +114,8 @@ typedef struct {
  * distribution functions) with the incident wave Ey = Hz = E_inc travelling
  * +x; forces use the same stress (Sec. II.B) and normalisation.  For TE the
  * field outputs of jlb_solve (ez, hx, hy) hold Hz, Ex, Ey, and the far field
- * of jlb_solve_far_field is k0 r |Hz^S|^2 / |Hz^I|^2.  TE solves run on the
- * single-step kernels (the two-step kernels are TM).
+ * of jlb_solve_far_field is k0 r |Hz^S|^2 / |Hz^I|^2.  Every kernel, the
+ * two-step ones included, runs both polarisations.
  */
 #define JLB_TM 0
 #define JLB_TE 1
@@ -280,11 +280,11 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * FP32 / BF16 also have two-step kernels (JLB_TWO_STEP_VARIANTS of them):
  * one launch takes the state from step n to n + 2, reading and writing it
  * once (temporal blocking), with results equal to two single steps bit for
- * bit.  A TM^z solve uses the selected two-step variant for every step that
+ * bit.  An FP32 / BF16 solve uses the selected two-step variant for every step that
  * runs in graph-captured whole periods (inside the averaging window too,
  * where the middle level's contour fields are kept), and single steps for the
  * ramp, the steps after the last whole chunk and a far-field solve's last
- * period; the engine uses it for all steps of its FP32 / BF16 TM^z solves.
+ * period; the engine uses it for all steps of its FP32 / BF16 solves.
  * Variants (V adjacent nodes per lane, H rows per wavefront, HX halo columns
  * per side; HX 8 keeps output strips 64-byte aligned; LA2: each input row is
  * loaded two rows ahead of its first use instead of one): 0 V1 H8 X2,

@@ -42,7 +42,6 @@
 // reflects without a sign change (every TE^z population meets a wall as a
 // normal E or a tangential H component).  Source, open edges, companion row,
 // stress sums and far-field phasors are unchanged in the dual storage.
-// Single-step kernels only (the two-step kernels are TM^z).
 //
 // No MFMA: the step is a stencil with about 0.3 flop per byte.
 #include <hip/hip_runtime.h>
@@ -789,7 +788,7 @@ __device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, type
         const Side lo{inc.lo.ez[v], inc.lo.hx[v], inc.lo.hy[v], inc.lo.na[v], inc.lo.nb[v]};
         const Side hi{inc.hi.ez[v], inc.hi.hx[v], inc.hi.hy[v], inc.hi.na[v], inc.hi.nb[v]};
         NodeData res;
-        neq_core<STRIP>(L, i, r, m, coef_tm(inv_eps, eps_rest), o, l, rr, b, t, lo, hi, einc, res);
+        neq_core<STRIP>(L, i, r, m, coef_of(L, inv_eps, eps_rest), o, l, rr, b, t, lo, hi, einc, res);
         out.ez[v] = res.ez;
         out.hx[v] = res.hx;
         out.hy[v] = res.hy;

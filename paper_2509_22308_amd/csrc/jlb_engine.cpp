@@ -258,7 +258,7 @@ int rebuild(jlb_engine *e)
         d.precision = q.prob.precision;
         e->max_nc = std::max(e->max_nc, q.nc);
         const int p = q.prob.precision;
-        d.two = e->two[p] >= 0 && q.prob.polarization == JLB_TM ? 1 : 0;  // two-step kernels are TM^z
+        d.two = e->two[p] >= 0 ? 1 : 0;
         if (d.two) {
             // one wavefront per (strip, row segment), in the order the
             // single-solve launch uses for this residency
@@ -513,7 +513,7 @@ int jlb_engine_run(jlb_engine *e, int64_t steps, int32_t *active)
         for (uint64_t t : e->resident) {
             Request &r = e->reqs[t];
             const int64_t total = r.plan.prob.steps;
-            const bool two = e->two[r.plan.prob.precision] >= 0 && r.plan.prob.polarization == JLB_TM;
+            const bool two = e->two[r.plan.prob.precision] >= 0;
             for (int64_t i = 0; i < (two ? k / 2 : k) && r.n < total; ++i) {
                 r.n = two ? std::min<int64_t>(r.n + 2, total) : r.n + 1;
                 r.cur ^= 1;

@@ -417,9 +417,8 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     // pairs and a chunk leaves state n in buffer n % 2, as single steps do;
     // it is also the spacing of the plateau check points
     const int64_t chunk = q.T % 4 == 0 ? q.T : q.T % 2 == 0 ? 2 * q.T : 4 * q.T;
-    // two-step kernels: FP32 / BF16 TM^z
-    const int two = q.prob.precision == JLB_FP64 || q.prob.polarization == JLB_TE ? -1
-                                                                                  : two_step_variant(q.prob.precision);
+    // two-step kernels: FP32 / BF16
+    const int two = q.prob.precision == JLB_FP64 ? -1 : two_step_variant(q.prob.precision);
     const int64_t ramp_end = (int64_t)std::ceil(q.ramp_steps);
     bool plateau = q.prob.plateau_tol > 0.0;
     double w_prev = -1.0;
@@ -782,7 +781,6 @@ int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t wo
     clear_error();
     if (!prob) return fail(JLB_E_ARG, "null problem");
     if (prob->precision != JLB_FP32 && prob->precision != JLB_BF16) return fail(JLB_E_ARG, "two-step kernels are FP32 / BF16");
-    if (prob->polarization != JLB_TM) return fail(JLB_E_ARG, "two-step kernels are TM only");
     const int v = two_step_variant(prob->precision);
     if (v < 0) return fail(JLB_E_ARG, "no two-step variant selected");
     return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, true, ms_per_launch, stream);
@@ -809,7 +807,7 @@ int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_byte
     }
     set_step_variant(prob->precision, bv);
     *best_variant = bv;
-    if (prob->precision == JLB_FP64 || prob->polarization == JLB_TE) return JLB_OK;
+    if (prob->precision == JLB_FP64) return JLB_OK;
     // two-step kernels, compared per lattice step
     int b2 = -1;
     for (int v = 0; v < TWO_STEP_VARIANTS; ++v) {

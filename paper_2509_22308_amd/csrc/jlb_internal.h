@@ -57,7 +57,7 @@ struct Lattice {
     float inv_eps_f[4];   // the two above rounded to FP32 once, on the host
     float eps_rest_f[4];
     int stream_stores;    // 1: write the next state past the caches (state larger than the Infinity Cache)
-    int te;               // 1: TE^z, stored as (Hz, -Ex, -Ey) in the (Ez, Hx, Hy) slots; single-step kernels only
+    int te;               // 1: TE^z, stored as (Hz, -Ex, -Ey) in the (Ez, Hx, Hy) slots
 };
 
 // Working sets above this many bytes do not stay in the 256 MB Infinity Cache

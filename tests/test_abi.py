@@ -72,12 +72,12 @@ def test_far_field_entry_checks_its_arguments_before_the_device():
         assert rc == -1 and "n_angles" in J.jlb_last_error()
 
 
-def test_two_step_timing_refuses_te_before_the_device():
+def test_two_step_timing_refuses_fp64_before_the_device():
     import ctypes
-    prob = J.make_problem(dict(W.config1(), polarization="te"), "fp32")
+    prob = J.make_problem(dict(W.config1(), polarization="te"), "fp64")
     ms = ctypes.c_double(0.0)
     assert J.load().jlb_time_two_step_kernel(ctypes.byref(prob), None, 0, 0, 1, ctypes.byref(ms), None) == -1
-    assert "TM" in J.jlb_last_error()
+    assert "FP32 / BF16" in J.jlb_last_error()
 
 
 def test_workspace_grows_with_precision_and_grid():

@@ -187,14 +187,15 @@ def test_step_kernel_variants_give_identical_results(jlb, precision):
         jlb.jlb_set_step_variant(prec, before)
 
 
+@pytest.mark.parametrize("polarization", ["tm", "te"])
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_two_step_kernels_equal_single_steps(jlb, precision):
+def test_two_step_kernels_equal_single_steps(jlb, precision, polarization):
     """A two-step launch (temporal blocking) takes the state from n to n + 2
     with the single-step arithmetic and the intermediate deviations rounded
     to the storage type: solves that run their out-of-window periods on any
     two-step variant equal the single-step solve bit for bit, fields and
     forces (ragged strips and row segments, conductor links, all edges, the
-    companion row)."""
+    companion row), in both polarisations."""
     prec = jlb.PRECISIONS[precision]
     before = jlb.jlb_get_two_step_variant(prec)
     cases = [W.problem(nx=203, ny=150, radius=20.0, kind="metallo_dielectric_janus", eps1=3.0, phi0_deg=110.0,
@@ -203,9 +204,10 @@ def test_two_step_kernels_equal_single_steps(jlb, precision):
                        wavelength=40.0, steps=650, avg_periods=1),
              W.problem(nx=530, ny=97, radius=20.0, kind="dielectric_janus", eps1=4.0, eps2=1.5, phi0_deg=200.0,
                        wavelength=40.0, steps=700, avg_periods=1)]
+    cases = [dict(p, polarization=polarization) for p in cases]
     try:
         for p in cases:
-            _print_case(f"two-step {precision}", p)
+            _print_case(f"two-step {precision} {polarization}", p)
             jlb.jlb_set_two_step_variant(prec, -1)
             ref = jlb.solve(p, precision, fields=True)
             assert ref["state_passes"] == p["steps"]

@@ -5,8 +5,8 @@ work, Sec. I, on the same lattice and update of Sec. III).
 Bars as for TM^z: FP64 forces within 1e-12 and fields within 1e-12 of the
 field scale; FP32 / BF16 forces within 1e-3 / 1e-2 of max(|F|, 0.05); far
 field FP64 within 1e-11 of the peak.  The engine runs TE^z solves next to
-TM^z ones (single-step and two-step launches in one batch) and returns what
-jlb_solve returns, bit for bit.
+TM^z ones (FP64 single steps and FP32 / BF16 two-step launches in one batch)
+and returns what jlb_solve returns, bit for bit.
 """
 import numpy as np
 import pytest
@@ -91,8 +91,9 @@ def test_te_far_field_matches_the_oracle(jlb, refs, precision):
 
 
 def test_te_and_tm_share_an_engine(jlb):
-    """TE^z solves (single steps) and TM^z solves (two-step kernels in FP32)
-    in one engine: each result equals its own jlb_solve bit for bit."""
+    """TE^z and TM^z solves in one engine, FP32 / BF16 on the two-step
+    kernels and FP64 on single steps: each result equals its own jlb_solve
+    bit for bit."""
     probs = [CASES["config1"], W.config1(), CASES["ragged-djc"], W.small_mdjc(4.0, 30.0, a=16)]
     precs = ["fp32", "fp32", "bf16", "fp64"]
     prec = jlb.PRECISIONS["fp32"]
