@@ -40,6 +40,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 BYTES_PER_LUP = {"fp64": 177, "fp32": 89, "bf16": 57}
 KERNEL_NAME = {"fp64": "k_step_f64", "fp32": "k_step_neq*<float>", "bf16": "k_step_neq*<__bf16>"}
 TWO_STEP_KERNEL_NAME = {"fp32": "k_step2_neq<float>", "bf16": "k_step2_neq<__bf16>"}
+MULTI_STEP_KERNEL_NAME = {"fp32": "k_stepm_neq<float>", "bf16": "k_stepm_neq<__bf16>"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 DEVICE_SRC = os.path.join(ROOT, "paper_2509_22308_amd", "csrc", "jlb_device.hip")
 
@@ -68,16 +69,18 @@ def measured_traffic(precision: str, variant: int):
     return e.get("hbm_bytes_per_launch") if e else None
 
 
-def _single_and_two_step(jlb, prob, ws, prec: str, launches: int):
+def _chosen_kernels(jlb, prob, ws, prec: str, launches: int):
     """Autotune, then time the chosen kernels: ms per launch of the best
-    single step and (FP32 / BF16, when the autotuner selected one) of the
-    two-step kernel."""
+    single step and (FP32 / BF16, when the autotuner selected them) of the
+    two-step and multi-step kernels."""
     best, tune = jlb.jlb_autotune(prob, launches, ws)
     one = jlb.jlb_time_step_kernel(prob, 5, 4 * launches, ws)
-    two = None
+    two = multi = None
     if prec != "fp64" and jlb.jlb_get_two_step_variant(jlb.PRECISIONS[prec]) >= 0:
         two = jlb.jlb_time_two_step_kernel(prob, 5, 2 * launches, ws)
-    return best, tune, one, two
+    if prec != "fp64" and jlb.jlb_get_multi_step_variant(jlb.PRECISIONS[prec]) >= 0:
+        multi = jlb.jlb_time_multi_step_kernel(prob, 5, launches, ws)
+    return best, tune, one, two, multi
 
 
 def gpu_leg(args):
@@ -94,6 +97,7 @@ def gpu_leg(args):
     # for this device and grid
     variant, tune_ms = jlb.jlb_autotune(prob, 20, ws)
     two_variant = jlb.jlb_get_two_step_variant(jlb.PRECISIONS[args.precision]) if args.precision != "fp64" else -1
+    multi_variant = jlb.jlb_get_multi_step_variant(jlb.PRECISIONS[args.precision]) if args.precision != "fp64" else -1
     lups_per_solve = p["nx"] * p["ny"] * p["steps"]
 
     for _ in range(args.warmup):
@@ -108,28 +112,34 @@ def gpu_leg(args):
 
     ms_per_solve = 1e3 * wall / args.steps
     value = lups_per_solve * args.steps / wall
-    # dominant kernel: the fused step (two steps per launch outside the
-    # averaging window when the autotuner picked a two-step kernel).  HIP
-    # events on the library's stream bracket each solve's time loop; every
-    # step-kernel launch reads and writes the state once (a "pass"), so the
-    # loop's algorithmic bytes are passes x bytes per pass.  The loop also
-    # holds the small contour kernels of the window: a lower bound on the
-    # kernels' own rate.
+    # Dominant kernel: the one that runs the whole periods before the
+    # averaging window (most of the solve), replayed from a hipGraph.  The
+    # library brackets that stretch with HIP events on its stream, so
+    # main_ms / main_launches is that kernel's mean launch duration over the
+    # timed solves.  A launch advances the state by `depth` lattice steps,
+    # i.e. depth x nx x ny lattice updates at the algorithmic bytes per update.
     loop_ms = sum(r.loop_ms for r in results) / len(results)
     r0 = results[0]
     passes = r0.state_passes
-    launch_ms = loop_ms / passes
-    bytes_per_launch = r0.bytes_per_step
-    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    main_kind, main_variant = r0.main_kind, r0.main_variant
+    depth = {1: 1, 2: 2}.get(main_kind) or jlb.jlb_multi_step_shape(main_variant)[0]
+    launch_ms = sum(r.main_ms for r in results) / sum(r.main_launches for r in results)
+    bytes_per_pass = r0.bytes_per_step
+    achieved = depth * bytes_per_pass / (launch_ms * 1e-3) / 1e9
     extra = {"forces": {"fx": r0.fx, "fy": r0.fy, "tz": r0.tz}, "loop_ms_per_solve": loop_ms,
              "state_passes_per_solve": passes, "graph_used": r0.graph_used,
+             "main_stretch": {"kind": {1: "single step", 2: "two-step", 3: "multi-step"}[main_kind],
+                              "ms_per_solve": r0.main_ms, "launches_per_solve": r0.main_launches},
              "step_variant": jlb.STEP_VARIANTS.get(jlb.jlb_get_step_variant(jlb.PRECISIONS[args.precision]))
              if args.precision != "fp64" else jlb.FP64_STEP_VARIANTS.get(variant),
              "two_step_variant": jlb.TWO_STEP_VARIANTS.get(two_variant) if two_variant >= 0 else None,
+             "multi_step_variant": jlb.MULTI_STEP_VARIANTS.get(multi_variant) if multi_variant >= 0 else None,
              "autotune_ms_per_step": [round(m, 5) for m in tune_ms],
              "step_kernel_ms_alone": jlb.jlb_time_step_kernel(prob, 20, 200, ws)}
     if two_variant >= 0:
         extra["two_step_kernel_ms_alone"] = jlb.jlb_time_two_step_kernel(prob, 10, 100, ws)
+    if multi_variant >= 0:
+        extra["multi_step_kernel_ms_alone"] = jlb.jlb_time_multi_step_kernel(prob, 10, 100, ws)
     if not args.quick:
         nb = 4 << 30
         ms = jlb.jlb_copy_bandwidth(nb, 10)
@@ -141,7 +151,7 @@ def gpu_leg(args):
         for prec in ("fp64", "fp32", "bf16"):
             bp = jlb.make_problem(big, prec)
             bws = _workspace(jlb, bp)
-            best, _, one, two = _single_and_two_step(jlb, bp, bws, prec, 10)
+            best, _, one, two, multi = _chosen_kernels(jlb, bp, bws, prec, 10)
             gbs = nodes * BYTES_PER_LUP[prec] / (one * 1e-3) / 1e9
             ent = {"single_step": {"variant": (jlb.FP64_STEP_VARIANTS if prec == "fp64" else jlb.STEP_VARIANTS).get(
                        jlb.jlb_get_step_variant(jlb.PRECISIONS[prec])), "ms_per_launch": one,
@@ -151,6 +161,13 @@ def gpu_leg(args):
                 ent["two_step"] = {"variant": jlb.TWO_STEP_VARIANTS.get(jlb.jlb_get_two_step_variant(
                     jlb.PRECISIONS[prec])), "ms_per_launch": two, "glups": 2 * nodes / (two * 1e-3) / 1e9,
                     "gbs": gbs2, "hbm_frac": gbs2 / HBM_PEAK_GBS}
+            if multi is not None:
+                mv = jlb.jlb_get_multi_step_variant(jlb.PRECISIONS[prec])
+                depth, _ = jlb.jlb_multi_step_shape(mv)
+                gbsm = nodes * BYTES_PER_LUP[prec] / (multi * 1e-3) / 1e9
+                ent["multi_step"] = {"variant": jlb.MULTI_STEP_VARIANTS.get(mv), "ms_per_launch": multi,
+                                     "glups": depth * nodes / (multi * 1e-3) / 1e9, "gbs": gbsm,
+                                     "hbm_frac": gbsm / HBM_PEAK_GBS}
             extra[f"grid4096_{prec}"] = ent
             del bws
         for prec in ("fp64", "fp32", "bf16"):
@@ -166,18 +183,29 @@ def gpu_leg(args):
             extra[f"config2_{prec}"] = {"glups": lups_per_solve / dt / 1e9, "ms_per_solve": 1e3 * dt,
                                         "loop_ms": r.loop_ms, "fx": r.fx, "fy": r.fy, "tz": r.tz}
             del pws
-    kname = KERNEL_NAME[args.precision]
-    if two_variant >= 0:
-        kname = TWO_STEP_KERNEL_NAME[args.precision] + " (two steps per launch), " + kname + " (ramp and window)"
+    if main_kind == 3:
+        kname = f"{MULTI_STEP_KERNEL_NAME[args.precision]} ({jlb.MULTI_STEP_VARIANTS.get(main_variant)})"
+        index = len(jlb.STEP_VARIANTS) + len(jlb.TWO_STEP_VARIANTS) + main_variant
+    elif main_kind == 2:
+        kname = f"{TWO_STEP_KERNEL_NAME[args.precision]} ({jlb.TWO_STEP_VARIANTS.get(main_variant)})"
+        index = len(jlb.STEP_VARIANTS) + main_variant
+    else:
+        kname = KERNEL_NAME[args.precision]
+        index = main_variant
     roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.precision, variant),
-            "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms, "launches_per_solve": passes,
-            "effective_gbs": value * BYTES_PER_LUP[args.precision] / 1e9,
-            "note": "achieved = algorithmic bytes per pass (one read and one write of the state) x passes / loop "
-                    "time; a two-step launch is one pass for two lattice updates, so effective_gbs (LUPS x bytes "
-                    "per single-step update) exceeds it.  Config 2 (FP32 state 2 x 46 MB) stays in the 256 MB "
-                    "Infinity Cache between steps; the HBM-bound figures are extra.grid4096_*"}
+            "traffic": measured_traffic(args.precision, index),
+            "steps_per_launch": depth, "algorithmic_bytes_per_launch": depth * bytes_per_pass,
+            "launch_ms": launch_ms, "launches_per_solve": r0.main_launches,
+            "per_pass_gbs": bytes_per_pass / (launch_ms * 1e-3) / 1e9,
+            "per_pass_frac": bytes_per_pass / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "note": f"achieved = {BYTES_PER_LUP[args.precision]} B per lattice update x {depth} x nx x ny updates "
+                    "per launch / mean launch duration (HIP events around the graph-replayed periods before the "
+                    "window, over the timed solves).  Temporal blocking reads and writes the state once per "
+                    "launch, so achieved exceeds the HBM peak when it pays: per_pass_gbs counts the state once "
+                    "(the least a launch must move) and traffic is the measured HBM bytes per launch.  Config 2 "
+                    "(FP32 state 2 x 46 MB) stays in the 256 MB Infinity Cache between launches; the HBM-bound "
+                    "figures are extra.grid4096_*"}
     return p, value, ms_per_solve, roof, extra
 
 
@@ -295,7 +323,11 @@ def run_kernel_only(args):
         p = workloads.config2()
     prob = jlb.make_problem(p, args.precision)
     ws = _workspace(jlb, prob)
-    if args.two_step >= 0:
+    if args.multi_step >= 0:
+        jlb.jlb_set_multi_step_variant(jlb.PRECISIONS[args.precision], args.multi_step)
+        variant = len(jlb.STEP_VARIANTS) + len(jlb.TWO_STEP_VARIANTS) + args.multi_step
+        ms = jlb.jlb_time_multi_step_kernel(prob, 2, args.launches, ws)
+    elif args.two_step >= 0:
         # the two-step kernel alone (counter passes serialise kernels, which
         # would mislead the autotuner: the variant is given)
         jlb.jlb_set_two_step_variant(jlb.PRECISIONS[args.precision], args.two_step)
@@ -416,6 +448,7 @@ def main():
     ap.add_argument("--grid", type=int, default=0, help="kernel-only: an n x n grid instead of config 2")
     ap.add_argument("--variant", type=int, default=-1, help="kernel-only: this step variant instead of the autotuner's")
     ap.add_argument("--two-step", type=int, default=-1, help="kernel-only: time this two-step variant instead")
+    ap.add_argument("--multi-step", type=int, default=-1, help="kernel-only: time this multi-step variant instead")
     ap.add_argument("--summarize", default=None)
     ap.add_argument("--record-traffic", default=None, help="workload key (config2, grid4096): merge counter passes")
     ap.add_argument("--fetch-dir", default=None)

@@ -146,6 +146,14 @@ typedef struct {
     int64_t bytes_per_step;         /* algorithmic HBM bytes of one pass over the state        */
     int64_t state_passes;           /* step-kernel launches (a two-step launch is one pass)    */
     double energy_final;            /* field energy sum (eps E^2 + H^2)/2 after the last step  */
+    /* The whole periods before the window replayed from a hipGraph (the bulk
+       of a long solve): HIP-event time on the solve's stream, step-kernel
+       launches in it, and which kernel ran there: main_kind 1 single step
+       (main_variant: step variant), 2 two-step, 3 multi-step; 0 when no such
+       stretch ran (jlb_solve only; the engine leaves these 0). */
+    double main_ms;
+    int64_t main_launches;
+    int32_t main_kind, main_variant;
 } jlb_result;
 
 /* Library version (major * 10000 + minor * 100 + patch). */
@@ -297,11 +305,15 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * as for jlb_solve) and makes the fastest the current choice; for FP32 /
  * BF16 it then times the two-step variants and selects the fastest of them
  * when its time per lattice step beats the best single step (else turns
- * two-step kernels off).  *best_variant receives the winner: a single-step
- * variant index, or JLB_STEP_VARIANTS + the two-step index.  ms_per_variant
- * (host, optional) receives the mean time per lattice step in ms, single-step
- * variants first, then the two-step ones (JLB_STEP_VARIANTS +
- * JLB_TWO_STEP_VARIANTS entries are always enough).
+ * two-step kernels off), then the multi-step variants the grid allows and
+ * selects the fastest of them when its time per lattice step beats the best
+ * so far (else turns them off).  *best_variant receives the winner of the
+ * first two rounds: a single-step variant index, or JLB_STEP_VARIANTS + the
+ * two-step index (jlb_get_multi_step_variant reports the third).
+ * ms_per_variant (host, optional) receives the mean time per lattice step in
+ * ms, single-step variants first, then the two-step ones, then the
+ * multi-step ones, 0 for those not timed (JLB_STEP_VARIANTS +
+ * JLB_TWO_STEP_VARIANTS + JLB_MULTI_STEP_VARIANTS entries are always enough).
  */
 #define JLB_STEP_VARIANTS 7
 #define JLB_FP64_STEP_VARIANTS 3
@@ -321,6 +333,30 @@ int jlb_get_two_step_variant(int32_t precision, int32_t *variant);
  */
 int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
                              int32_t launches, double *ms_per_launch, void *stream);
+/*
+ * Multi-step kernels (FP32 / BF16, JLB_MULTI_STEP_VARIANTS of them): one
+ * launch takes the state from step n to n + S, S = 3 or 4 (S levels in
+ * flight in each wavefront's sweep), bit for bit equal to S single steps.
+ * When a variant is selected, jlb_solve runs the whole periods before the
+ * averaging window on it (the window keeps the two-step kernel, or single
+ * steps), provided the captured chunk is a multiple of 2 S steps and
+ * ny >= rows + S; otherwise those periods run as without it.  The engine
+ * does not use them.  Variants (depth S, rows per wavefront; 48 output
+ * columns per 64-lane strip; registers for two wavefronts per SIMD unless
+ * noted): 0 S3 H8, 1 S3 H12, 2 S3 H16, 3 S3 H8 held to three wavefronts per
+ * SIMD (spills), 4 S4 H8, 5 S4 H12, 6 S4 H16.  jlb_multi_step_shape reports
+ * S and the rows of a variant.  Default: 1 (set -1 for none); jlb_autotune
+ * selects one when it beats the other kernels per lattice step.
+ * jlb_time_multi_step_kernel: mean time of one launch (S lattice steps) of
+ * the selected variant, as jlb_time_step_kernel; JLB_E_ARG for FP64, when
+ * none is selected or when ny < rows + S.
+ */
+#define JLB_MULTI_STEP_VARIANTS 7
+int jlb_set_multi_step_variant(int32_t precision, int32_t variant);
+int jlb_get_multi_step_variant(int32_t precision, int32_t *variant);
+int jlb_multi_step_shape(int32_t variant, int32_t *depth, int32_t *rows);
+int jlb_time_multi_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
+                               int32_t launches, double *ms_per_launch, void *stream);
 int jlb_get_step_variant(int32_t precision, int32_t *variant);
 
 /*

@@ -50,6 +50,8 @@ class jlb_result(ctypes.Structure):
         ("steps_done", ctypes.c_int64), ("window_steps", ctypes.c_int64),
         ("contour_points", ctypes.c_int32), ("graph_used", ctypes.c_int32),
         ("bytes_per_step", ctypes.c_int64), ("state_passes", ctypes.c_int64), ("energy_final", ctypes.c_double),
+        ("main_ms", ctypes.c_double), ("main_launches", ctypes.c_int64), ("main_kind", ctypes.c_int32),
+        ("main_variant", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -97,6 +99,11 @@ def load():
             "jlb_get_two_step_variant": ([ctypes.c_int32, _P(ctypes.c_int32)], ctypes.c_int),
             "jlb_time_two_step_kernel": ([_P(jlb_problem), _vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
                                           _P(ctypes.c_double), _vp], ctypes.c_int),
+            "jlb_set_multi_step_variant": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+            "jlb_get_multi_step_variant": ([ctypes.c_int32, _P(ctypes.c_int32)], ctypes.c_int),
+            "jlb_multi_step_shape": ([ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32)], ctypes.c_int),
+            "jlb_time_multi_step_kernel": ([_P(jlb_problem), _vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                            _P(ctypes.c_double), _vp], ctypes.c_int),
             "jlb_copy_bandwidth": ([ctypes.c_size_t, ctypes.c_int32, _P(ctypes.c_double), _vp], ctypes.c_int),
             "jlb_engine_create": ([ctypes.c_size_t, ctypes.c_int32, _vp, _P(_vp)], ctypes.c_int),
             "jlb_engine_submit": ([_vp, _P(jlb_problem), _P(ctypes.c_uint64)], ctypes.c_int),
@@ -224,6 +231,8 @@ TWO_STEP_VARIANTS = {0: "two-step V1 H8 X2", 1: "two-step V1 H16 X2", 2: "two-st
                      3: "two-step V2 H16 X2", 4: "two-step V1 H8 X8", 5: "two-step V2 H16 X8",
                      6: "two-step V2 H32 X8", 7: "two-step V1 H8 X8 LA2", 8: "two-step V1 H4 X8 LA2",
                      9: "two-step V1 H16 X8 LA2"}
+MULTI_STEP_VARIANTS = {0: "three-step H8", 1: "three-step H12", 2: "three-step H16", 3: "three-step H8 W3",
+                       4: "four-step H8", 5: "four-step H12", 6: "four-step H16"}
 
 
 def variant_name(precision, best: int) -> str:
@@ -238,9 +247,10 @@ def variant_name(precision, best: int) -> str:
 
 def jlb_autotune(prob: jlb_problem, launches: int = 20, workspace=None, stream=None):
     """Times every step variant of prob's precision (single steps, then
-    two-step kernels per lattice step); returns (best, [ms per step])."""
+    two-step and multi-step kernels per lattice step); returns (best, [ms per
+    step]); the multi-step choice is reported by jlb_get_multi_step_variant."""
     best = ctypes.c_int32(0)
-    ms = (ctypes.c_double * (len(STEP_VARIANTS) + len(TWO_STEP_VARIANTS)))()
+    ms = (ctypes.c_double * (len(STEP_VARIANTS) + len(TWO_STEP_VARIANTS) + len(MULTI_STEP_VARIANTS)))()
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(load().jlb_autotune(ctypes.byref(prob), _dptr(workspace), nbytes, int(launches), ctypes.byref(best), ms,
                                _stream(stream)))
@@ -280,6 +290,32 @@ def jlb_time_two_step_kernel(prob: jlb_problem, warmup: int, launches: int, work
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(load().jlb_time_two_step_kernel(ctypes.byref(prob), _dptr(workspace), nbytes, int(warmup), int(launches),
                                            ctypes.byref(ms), _stream(stream)))
+    return ms.value
+
+
+def jlb_set_multi_step_variant(precision: int, variant: int):
+    _check(load().jlb_set_multi_step_variant(int(precision), int(variant)))
+
+
+def jlb_get_multi_step_variant(precision: int) -> int:
+    v = ctypes.c_int32(0)
+    _check(load().jlb_get_multi_step_variant(int(precision), ctypes.byref(v)))
+    return v.value
+
+
+def jlb_multi_step_shape(variant: int):
+    """(steps per launch, rows per wavefront) of a multi-step variant."""
+    d, r = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load().jlb_multi_step_shape(int(variant), ctypes.byref(d), ctypes.byref(r)))
+    return d.value, r.value
+
+
+def jlb_time_multi_step_kernel(prob: jlb_problem, warmup: int, launches: int, workspace=None, stream=None) -> float:
+    """Mean ms of one launch of the current multi-step kernel (S lattice steps)."""
+    ms = ctypes.c_double(0.0)
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(load().jlb_time_multi_step_kernel(ctypes.byref(prob), _dptr(workspace), nbytes, int(warmup), int(launches),
+                                             ctypes.byref(ms), _stream(stream)))
     return ms.value
 
 

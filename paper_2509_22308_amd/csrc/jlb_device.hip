@@ -1053,6 +1053,171 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq_batch(SolveDe
                                   one ? 0.0f : (float)batch_incident(d, n + 1), mid, t.tx, t.ty, one);
 }
 
+// S steps per launch (temporal blocking, S >= 2), for the whole periods
+// outside the averaging window: the two-step sweep with S levels in flight.
+// Level s (1-based) updates row r1 - (s - 1) DIR of the sweep from the three
+// level-(s - 1) rows around it, the last of which level s - 1 has just
+// produced; intermediate levels are rounded to the storage type as a store
+// would round them, so the result equals S single steps bit for bit.  A
+// segment of H output rows takes H + 2 (S - 1) level-1 rows, and a strip
+// needs at least S halo columns at each side.
+template <typename NeqT, int V, int H, int HX, int S>
+__device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__restrict__ srcv,
+                                                void *__restrict__ dstv, const float (&einc)[S], int sx, int sy)
+{
+    constexpr int OW = two_step_width<V, HX>();
+    static_assert(S >= 2 && HX >= S && HX % V == 0 && OW > 0, "multi-step strip shape");
+    typedef typename MaskVec<V>::type MaskT;
+    const int x0 = sx * OW, j0 = sy * H;
+    const int lane = threadIdx.x;
+    const int i0 = x0 - HX + V * lane;
+    const bool act = i0 >= 0 && i0 < L.nx;
+    const bool out_lane = act && lane >= HX / V && lane < (HX + OW) / V;
+
+    const size_t P = L.plane;
+    const float *F = reinterpret_cast<const float *>(srcv);
+    float *DF = reinterpret_cast<float *>(dstv);
+    const unsigned Pu = (unsigned)P;
+    // clamped (always valid) row and column: what a lane loads outside the
+    // domain is never used (edge nodes take their edge rules)
+    const unsigned ic = (unsigned)(min(max(i0, 0), L.nx - 1) / V * V);
+    auto load = [&](int r, RowData<V> &d, MaskT &m) {
+        const int rc = min(max(r, 0), L.ny - 1);
+        load_row_at<NeqT, V>(F + (size_t)rc * L.sf, Pu, ic, d);
+        m = *byte_at<MaskT>(L.mask + (size_t)rc * L.pitch, ic);
+    };
+
+    // companion row at n .. n + S - 1 where rows 0 or ny - 1 are updated at
+    // some level; the segment at the bottom also advances it to n + S.  A
+    // segment reaches row 0 or row ny - 1, never both (the caller keeps
+    // ny >= H + S), so one side per level is kept: the one row 0 pulls from
+    // at the bottom, the one row ny - 1 pulls from at the top.
+    SideRow<V> edge[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) edge[s] = SideRow<V>{};
+    if (j0 <= S - 1 || j0 + H >= L.ny - (S - 1)) {
+        const bool bottom = j0 <= S - 1;
+        RowData<V> c;
+        zero_row(c);
+        load_row_at<NeqT, V>(F + (size_t)L.ny * L.sf, Pu, ic, c);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            edge[s] = bottom ? side_of(c, N_EPY, N_HYPY) : side_of(c, N_EMY, N_HYMY);
+            if (s == S - 1 && j0 != 0) break;
+            RowData<V> c2;
+            row_update<NeqT, V, true>(L, i0, L.ny, 0, c, SideRow<V>{}, SideRow<V>{}, StripSides<V>{}, einc[s], c2);
+            if (s < S - 1) round_row<NeqT, V>(c2);
+            c = c2;
+        }
+        if (j0 == 0) {
+            mask_row<V>(L, i0, 0, true, c);
+            if (out_lane) store_row_at<NeqT, V>(DF + (size_t)L.ny * L.sf, Pu, (unsigned)i0, c, L.stream_stores);
+        }
+    }
+
+    // consecutive row segments sweep in opposite directions (seam rows are
+    // read by both neighbours at the same moment and hit in L2)
+    auto sweep = [&](auto dir_tag) {
+        constexpr int DIR = decltype(dir_tag)::value;
+        constexpr int BQA = DIR > 0 ? N_EPY : N_EMY, BQB = DIR > 0 ? N_HYPY : N_HYMY;  // behind
+        constexpr int AQA = DIR > 0 ? N_EMY : N_EPY, AQB = DIR > 0 ? N_HYMY : N_HYPY;  // ahead
+        constexpr int K = H + 2 * (S - 1);                                             // level-1 rows
+        const int first = DIR > 0 ? j0 - (S - 1) : j0 + H - 1 + (S - 1);
+        // level 0 (the state at n): behind (side), cur, ahead; levels 1 .. S - 1:
+        // behind (side) and cur, the rows level s + 1 is about to update
+        RowData<V> a_cur, a_ahead, tmp;
+        MaskT m_ahead, m_dummy;
+        MaskT mk[S];  // mk[s]: mask of row r1 - s DIR
+#pragma unroll
+        for (int s = 0; s < S; ++s) mk[s] = 0;
+        load(first - DIR, tmp, m_dummy);
+        SideRow<V> a_behind = side_of(tmp, BQA, BQB);
+        load(first, a_cur, mk[0]);
+        load(first + DIR, a_ahead, m_ahead);
+        SideRow<V> lv_behind[S];
+        RowData<V> lv_cur[S];
+#pragma unroll
+        for (int s = 1; s < S; ++s) {
+            lv_behind[s] = SideRow<V>{};
+            zero_row(lv_cur[s]);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int r1 = first + DIR * k;
+            RowData<V> a_next;
+            MaskT m_next;
+            if (k <= K - 2) load(r1 + 2 * DIR, a_next, m_next);
+            else {
+                a_next = a_ahead;
+                m_next = m_ahead;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // level 1 on row r1
+            RowData<V> nw;
+            {
+                const SideRow<V> side = side_of(a_ahead, AQA, AQB);
+                row_update<NeqT, V, false>(L, i0, r1, mk[0], a_cur, DIR > 0 ? a_behind : side,
+                                           DIR > 0 ? side : a_behind, StripSides<V>{edge[0], edge[0]}, einc[0], nw);
+                round_row<NeqT, V>(nw);
+            }
+            // levels 2 .. S on the rows behind; nw is the level-s row just made
+#pragma unroll
+            for (int s = 1; s < S; ++s) {
+                if (k < 2 * (s - 1)) break;  // level s has made no row yet
+                RowData<V> o;
+                const bool go = k >= 2 * s;
+                if (go) {
+                    const int rs = r1 - s * DIR;
+                    const SideRow<V> side = side_of(nw, AQA, AQB);
+                    row_update<NeqT, V, false>(L, i0, rs, mk[s], lv_cur[s], DIR > 0 ? lv_behind[s] : side,
+                                               DIR > 0 ? side : lv_behind[s], StripSides<V>{edge[s], edge[s]},
+                                               einc[s], o);
+                    if (s < S - 1) {
+                        round_row<NeqT, V>(o);
+                    } else {
+                        mask_row<V>(L, i0, mk[s], false, o);
+                        if (out_lane && rs < L.ny)
+                            store_row_at<NeqT, V>(DF + (size_t)rs * L.sf, Pu, (unsigned)i0, o, L.stream_stores);
+                    }
+                }
+                lv_behind[s] = side_of(lv_cur[s], BQA, BQB);
+                lv_cur[s] = nw;
+                if (!go) break;
+                nw = o;
+            }
+#pragma unroll
+            for (int s = S - 1; s > 0; --s) mk[s] = mk[s - 1];
+            a_behind = side_of(a_cur, BQA, BQB);
+            a_cur = a_ahead;
+            mk[0] = m_ahead;
+            a_ahead = a_next;
+            m_ahead = m_next;
+        }
+    };
+    if (sy & 1) sweep(std::integral_constant<int, -1>{});
+    else sweep(std::integral_constant<int, 1>{});
+}
+
+// S lattice steps per launch; W: wavefronts per SIMD the register
+// allocation must allow (more than the registers want costs spills).
+// einc: source values of steps n .. n + S - 1.
+template <int S> struct Incident {
+    float v[S];
+};
+template <typename NeqT, int V, int H, int HX, int S, int W>
+__global__ __launch_bounds__(64 * TWO_STEP_WAVES, W) void k_stepm_neq(Lattice L, const void *__restrict__ srcv,
+                                                                     void *__restrict__ dstv, Incident<S> einc,
+                                                                     int nsx, int nsy)
+{
+    // work order as for the two-step launch
+    const int nb = gridDim.x;
+    const int b = L.stream_stores ? (int)blockIdx.x : xcd_tile(blockIdx.x, nb);
+    const int w = __builtin_amdgcn_readfirstlane(b * TWO_STEP_WAVES + (int)threadIdx.y);
+    if (w >= nsx * nsy) return;  // whole wavefront
+    const int sx = L.stream_stores ? w % nsx : w / nsy, sy = L.stream_stores ? w / nsx : w % nsy;
+    multi_step_wave<NeqT, V, H, HX, S>(L, srcv, dstv, einc.v, sx, sy);
+}
+
 // ---------------------------------------------------------------------------
 // Batched steps: block b works on tiles[b] of solve tiles[b].slot at that
 // solve's own step n (finished solves return at once).
@@ -1584,6 +1749,60 @@ hipError_t launch_step2_batch(int precision, int variant, SolveDesc *d, const Ti
             constexpr int LA = decltype(ltag)::value;
             hipLaunchKernelGGL((k_step2_neq_batch<T, V, H, HX, LA>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, d,
                                items, nitems, remap);
+        });
+    };
+    if (precision == 1) run(float{});
+    else run(__bf16{});
+    return hipGetLastError();
+}
+
+// Variant table of the multi-step kernels: depth S, rows H, wavefronts W.
+template <typename F> static void multi_step_dispatch(int variant, F &&go)
+{
+    using I1 = std::integral_constant<int, 1>;
+    using X8 = std::integral_constant<int, 8>;
+    using S3 = std::integral_constant<int, 3>;
+    using S4 = std::integral_constant<int, 4>;
+    using W2 = std::integral_constant<int, 2>;
+    using W3 = std::integral_constant<int, 3>;
+    using H8 = std::integral_constant<int, 8>;
+    using H12 = std::integral_constant<int, 12>;
+    using H16 = std::integral_constant<int, 16>;
+    switch (variant) {
+    case MULTI_S3_H8: go(I1{}, H8{}, X8{}, S3{}, W2{}); break;
+    case MULTI_S3_H12: go(I1{}, H12{}, X8{}, S3{}, W2{}); break;
+    case MULTI_S3_H16: go(I1{}, H16{}, X8{}, S3{}, W2{}); break;
+    case MULTI_S3_H8_W3: go(I1{}, H8{}, X8{}, S3{}, W3{}); break;
+    case MULTI_S4_H8: go(I1{}, H8{}, X8{}, S4{}, W2{}); break;
+    case MULTI_S4_H12: go(I1{}, H12{}, X8{}, S4{}, W2{}); break;
+    default: go(I1{}, H16{}, X8{}, S4{}, W2{}); break;
+    }
+}
+
+void multi_step_shape(int variant, int &depth, int &rows)
+{
+    multi_step_dispatch(variant, [&](auto, auto htag, auto, auto stag, auto) {
+        rows = decltype(htag)::value;
+        depth = decltype(stag)::value;
+    });
+}
+
+hipError_t launch_stepm_neq(int precision, const Lattice &L, const void *src, void *dst, const double *einc,
+                            hipStream_t s, int variant)
+{
+    auto run = [&](auto tag) {
+        typedef decltype(tag) T;
+        multi_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag, auto stag, auto wtag) {
+            constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
+            constexpr int S = decltype(stag)::value, W = decltype(wtag)::value;
+            if (L.ny < H + S) return;  // a segment would reach both edge rows (callers check first)
+            Incident<S> e;
+            for (int k = 0; k < S; ++k) e.v[k] = (float)einc[k];
+            const int nsx = (L.nx + two_step_width<V, HX>() - 1) / two_step_width<V, HX>();
+            const int nsy = (L.ny + H - 1) / H;
+            const int blocks = (nsx * nsy + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
+            hipLaunchKernelGGL((k_stepm_neq<T, V, H, HX, S, W>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src,
+                               dst, e, nsx, nsy);
         });
     };
     if (precision == 1) run(float{});

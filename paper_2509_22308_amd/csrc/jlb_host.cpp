@@ -252,6 +252,12 @@ int step_variant(int precision) { return g_variant[precision].load(std::memory_o
 void set_step_variant(int precision, int v) { g_variant[precision].store(v, std::memory_order_relaxed); }
 int two_step_variant(int precision) { return g_two[precision].load(std::memory_order_relaxed); }
 static void set_two_step_variant(int precision, int v) { g_two[precision].store(v, std::memory_order_relaxed); }
+// Multi-step (three or four steps per launch) kernel variant per precision
+// for the whole periods outside the window (inside it the two-step kernel or
+// single steps run), -1 = off.
+static std::atomic<int> g_multi[3] = {{-1}, {MULTI_S3_H12}, {MULTI_S3_H12}};
+int multi_step_variant(int precision) { return g_multi[precision].load(std::memory_order_relaxed); }
+static void set_multi_step_variant(int precision, int v) { g_multi[precision].store(v, std::memory_order_relaxed); }
 
 hipError_t launch_step(const Plan &q, const Lattice &L, void *src, void *dst, double *fields, double einc, hipStream_t s,
                        int variant)
@@ -419,6 +425,13 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     const int64_t chunk = q.T % 4 == 0 ? q.T : q.T % 2 == 0 ? 2 * q.T : 4 * q.T;
     // two-step kernels: FP32 / BF16
     const int two = q.prob.precision == JLB_FP64 ? -1 : two_step_variant(q.prob.precision);
+    // multi-step kernels (depth S) outside the window: chunk / S launches
+    // must be a whole, even number (the chunk then leaves state n in buffer
+    // n % 2), and a row segment must not reach both the bottom and the top row
+    int multi = q.prob.precision == JLB_FP64 ? -1 : multi_step_variant(q.prob.precision);
+    int depth = 0, mrows = 0;
+    if (multi >= 0) multi_step_shape(multi, depth, mrows);
+    if (multi >= 0 && (chunk % (2 * depth) != 0 || q.ny < mrows + depth)) multi = -1;
     const int64_t ramp_end = (int64_t)std::ceil(q.ramp_steps);
     bool plateau = q.prob.plateau_tol > 0.0;
     double w_prev = -1.0;
@@ -442,17 +455,38 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
         return JLB_OK;
     };
 
-    hipEvent_t ev0, ev1;
+    hipEvent_t ev0, ev1, evm0, evm1;
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
+    HIP_TRY(hipEventCreate(&evm0));
+    HIP_TRY(hipEventCreate(&evm1));
     HIP_TRY(hipEventRecord(ev0, s));
+    // the graph-replayed periods before the window: which kernel, how many launches
+    const int main_kind = multi >= 0 ? 3 : two >= 0 ? 2 : 1;
+    const int main_variant = multi >= 0 ? multi : two >= 0 ? two : step_variant(q.prob.precision);
+    const int64_t main_per_chunk = multi >= 0 ? chunk / depth : two >= 0 ? chunk / 2 : chunk;
+    int64_t main_launches = 0;
 
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] outside the window, [1] inside
     int64_t gstart[2] = {-1, -1};
     auto capture = [&](int which, int64_t n0) -> int {
         hipGraph_t g;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        if (two >= 0) {
+        if (which == 0 && multi >= 0) {
+            // launch m takes state n0 + S m from buffer (n0 + m) % 2 to the other one
+            for (int64_t m = 0; m < chunk / depth; ++m) {
+                const int64_t n = n0 + depth * m;
+                double einc[4];
+                for (int k = 0; k < depth; ++k) einc[k] = incident(q, n + k);
+                hipError_t e = launch_stepm_neq(q.prob.precision, L, ws + q.off_state[(n0 + m) & 1],
+                                                ws + q.off_state[(n0 + m + 1) & 1], einc, s, multi);
+                if (e != hipSuccess) {
+                    hipGraph_t dummy;
+                    (void)hipStreamEndCapture(s, &dummy);
+                    return fail(JLB_E_DEVICE, "multi-step launch: %s", hipGetErrorString(e));
+                }
+            }
+        } else if (two >= 0) {
             // launch m takes state n0 + 2m from buffer (n0 + m) % 2 to the
             // other one; inside the window it also leaves the contour-stencil
             // fields of level n0 + 2m + 1 in mid, and both levels are
@@ -511,13 +545,16 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
                 rc = fail(JLB_E_DEVICE, "internal: graph phase mismatch");
                 break;
             }
-            hipError_t e = hipGraphLaunch(gexec[which], s);
+            hipError_t e = which == 0 && main_launches == 0 ? hipEventRecord(evm0, s) : hipSuccess;
+            if (e == hipSuccess) e = hipGraphLaunch(gexec[which], s);
+            if (e == hipSuccess && which == 0) e = hipEventRecord(evm1, s);
             if (e != hipSuccess) {
                 rc = fail(JLB_E_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
                 break;
             }
+            if (which == 0) main_launches += main_per_chunk;
             graph_used = 1;
-            passes += two >= 0 ? chunk / 2 : chunk;
+            passes += which == 0 && multi >= 0 ? chunk / depth : two >= 0 ? chunk / 2 : chunk;
             n += chunk;
             if (!in_window && check_level(n)) rc = plateau_check(n);
             continue;
@@ -584,6 +621,14 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             res->bytes_per_step = (int64_t)q.bytes_per_lup * q.nx * q.ny;
             res->state_passes = passes;
             res->energy_final = out[6];
+            if (main_launches > 0 && !(q.prob.plateau_tol > 0.0)) {
+                float mms = 0.0f;
+                (void)hipEventElapsedTime(&mms, evm0, evm1);
+                res->main_ms = mms;
+                res->main_launches = main_launches;
+                res->main_kind = main_kind;
+                res->main_variant = main_variant;
+            }
             for (int k = 0; k < 6; ++k)
                 if (!std::isfinite(out[k])) rc = fail(JLB_E_NONFINITE, "forces are not finite");
         }
@@ -594,6 +639,8 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
         if (g) (void)hipGraphExecDestroy(g);
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
+    (void)hipEventDestroy(evm0);
+    (void)hipEventDestroy(evm1);
     res->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return rc;
 }
@@ -718,8 +765,9 @@ int jlb_solve_far_field(const jlb_problem *prob, void *workspace, size_t workspa
                        FarOut{n_angles, s2});
 }
 
+// kind: 1 single-step, 2 two-step, 3 multi-step variant
 static int time_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
-                            int32_t launches, int variant, bool two, double *ms_per_launch, void *stream)
+                            int32_t launches, int variant, int kind, double *ms_per_launch, void *stream)
 {
     if (!ms_per_launch || launches < 1 || warmup < 0) return fail(JLB_E_ARG, "bad launch counts");
     Plan q;
@@ -744,11 +792,20 @@ static int time_step_kernel(const jlb_problem *prob, void *workspace, size_t wor
     const Lattice L = lattice_of(q, (const uint8_t *)(ws + q.off_mask));
     for (int64_t n = 0; rc == JLB_OK && n < (int64_t)warmup + launches; ++n) {
         if (n == warmup && hipEventRecord(e0, own) != hipSuccess) rc = fail(JLB_E_DEVICE, "event record");
-        hipError_t e = two ? launch_step2_neq(q.prob.precision, L, ws + q.off_state[n & 1],
-                                              ws + q.off_state[(n + 1) & 1], incident(q, 2 * n), incident(q, 2 * n + 1),
-                                              nullptr, own, variant)
-                           : launch_step(q, L, ws + q.off_state[n & 1], ws + q.off_state[(n + 1) & 1], nullptr,
-                                         incident(q, n), own, variant);
+        void *src = ws + q.off_state[n & 1], *dst = ws + q.off_state[(n + 1) & 1];
+        hipError_t e;
+        if (kind == 3) {
+            int depth = 0, rows = 0;
+            multi_step_shape(variant, depth, rows);
+            double einc[4];
+            for (int k = 0; k < depth; ++k) einc[k] = incident(q, depth * n + k);
+            e = launch_stepm_neq(q.prob.precision, L, src, dst, einc, own, variant);
+        } else if (kind == 2) {
+            e = launch_step2_neq(q.prob.precision, L, src, dst, incident(q, 2 * n), incident(q, 2 * n + 1), nullptr, own,
+                                 variant);
+        } else {
+            e = launch_step(q, L, src, dst, nullptr, incident(q, n), own, variant);
+        }
         if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "step launch: %s", hipGetErrorString(e));
     }
     if (rc == JLB_OK) {
@@ -772,7 +829,7 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
     clear_error();
     if (!prob) return fail(JLB_E_ARG, "null problem");
     const int v = prob->precision >= 0 && prob->precision <= 2 ? step_variant(prob->precision) : 0;
-    return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, false, ms_per_launch, stream);
+    return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, 1, ms_per_launch, stream);
 }
 
 int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
@@ -783,7 +840,34 @@ int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t wo
     if (prob->precision != JLB_FP32 && prob->precision != JLB_BF16) return fail(JLB_E_ARG, "two-step kernels are FP32 / BF16");
     const int v = two_step_variant(prob->precision);
     if (v < 0) return fail(JLB_E_ARG, "no two-step variant selected");
-    return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, true, ms_per_launch, stream);
+    return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, 2, ms_per_launch, stream);
+}
+
+int jlb_time_multi_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
+                               int32_t launches, double *ms_per_launch, void *stream)
+{
+    clear_error();
+    if (!prob) return fail(JLB_E_ARG, "null problem");
+    if (prob->precision != JLB_FP32 && prob->precision != JLB_BF16)
+        return fail(JLB_E_ARG, "multi-step kernels are FP32 / BF16");
+    const int v = multi_step_variant(prob->precision);
+    if (v < 0) return fail(JLB_E_ARG, "no multi-step variant selected");
+    int depth = 0, rows = 0;
+    multi_step_shape(v, depth, rows);
+    if (prob->ny < rows + depth) return fail(JLB_E_ARG, "grid too short for this multi-step variant");
+    return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, 3, ms_per_launch, stream);
+}
+
+int jlb_multi_step_shape(int32_t variant, int32_t *depth, int32_t *rows)
+{
+    clear_error();
+    if (variant < 0 || variant >= MULTI_STEP_VARIANTS || !depth || !rows)
+        return fail(JLB_E_ARG, "variant 0..%d and non-null outputs", MULTI_STEP_VARIANTS - 1);
+    int d = 0, r = 0;
+    multi_step_shape(variant, d, r);
+    *depth = d;
+    *rows = r;
+    return JLB_OK;
 }
 
 int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t launches,
@@ -797,7 +881,7 @@ int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_byte
     int bv = step_variant(prob->precision);
     for (int v = 0; v < nvar; ++v) {
         double ms = 0.0;
-        int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, v, false, &ms, stream);
+        int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, v, 1, &ms, stream);
         if (rc) return rc;
         if (ms_per_variant) ms_per_variant[v] = ms;
         if (ms < best) {
@@ -812,7 +896,7 @@ int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_byte
     int b2 = -1;
     for (int v = 0; v < TWO_STEP_VARIANTS; ++v) {
         double ms = 0.0;
-        int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, v, true, &ms, stream);
+        int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, v, 2, &ms, stream);
         if (rc) return rc;
         ms *= 0.5;
         if (ms_per_variant) ms_per_variant[NEQ_VARIANTS + v] = ms;
@@ -823,6 +907,26 @@ int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_byte
     }
     set_two_step_variant(prob->precision, b2);
     if (b2 >= 0) *best_variant = NEQ_VARIANTS + b2;
+    // multi-step kernels (the periods before the window), per lattice step,
+    // against the best of the above; variants the grid is too short for are
+    // skipped (their entry stays 0)
+    int bm = -1;
+    for (int v = 0; v < MULTI_STEP_VARIANTS; ++v) {
+        if (ms_per_variant) ms_per_variant[NEQ_VARIANTS + TWO_STEP_VARIANTS + v] = 0.0;
+        int depth = 0, rows = 0;
+        multi_step_shape(v, depth, rows);
+        if (prob->ny < rows + depth) continue;
+        double ms = 0.0;
+        int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, v, 3, &ms, stream);
+        if (rc) return rc;
+        ms /= depth;
+        if (ms_per_variant) ms_per_variant[NEQ_VARIANTS + TWO_STEP_VARIANTS + v] = ms;
+        if (ms < best) {
+            best = ms;
+            bm = v;
+        }
+    }
+    set_multi_step_variant(prob->precision, bm);
     return JLB_OK;
 }
 
@@ -843,6 +947,24 @@ int jlb_set_two_step_variant(int32_t precision, int32_t variant)
         (precision == JLB_FP64 && variant != -1))
         return fail(JLB_E_ARG, "precision 1..2 and variant -1..%d (FP64: -1 only)", TWO_STEP_VARIANTS - 1);
     set_two_step_variant(precision, variant);
+    return JLB_OK;
+}
+
+int jlb_set_multi_step_variant(int32_t precision, int32_t variant)
+{
+    clear_error();
+    if (precision < 0 || precision > 2 || variant < -1 || variant >= MULTI_STEP_VARIANTS ||
+        (precision == JLB_FP64 && variant != -1))
+        return fail(JLB_E_ARG, "precision 1..2 and variant -1..%d (FP64: -1 only)", MULTI_STEP_VARIANTS - 1);
+    set_multi_step_variant(precision, variant);
+    return JLB_OK;
+}
+
+int jlb_get_multi_step_variant(int32_t precision, int32_t *variant)
+{
+    clear_error();
+    if (precision < 0 || precision > 2 || !variant) return fail(JLB_E_ARG, "bad precision or null variant");
+    *variant = multi_step_variant(precision);
     return JLB_OK;
 }
 

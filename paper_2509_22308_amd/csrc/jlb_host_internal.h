@@ -58,6 +58,7 @@ int enqueue_upload(const Plan &q, char *ws, hipStream_t s, const std::vector<uin
 int step_variant(int precision);
 // Two-step variant of a precision (-1: single steps only; always -1 for FP64).
 int two_step_variant(int precision);
+int multi_step_variant(int precision);
 // Optional outputs of a solve: the far field at nphi angles into the device
 // array s2, and the instantaneous force trace [steps][3] (nullptr: none).
 struct FarOut {

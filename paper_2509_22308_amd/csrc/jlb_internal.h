@@ -115,6 +115,23 @@ enum TwoStepVariant {
 // written there (3 float planes, row-interleaved, row stride 3 pitch).
 hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, void *dst, double einc0, double einc1,
                             float *mid, hipStream_t s, int variant);
+// S steps per launch (FP32 / BF16, S = 3 or 4 by variant): state n in src ->
+// state n + S in dst (src and dst must differ); einc[0..S-1] are the source
+// values of steps n .. n + S - 1.  No contour fields: for steps outside the
+// averaging window.  Launches need ny >= rows + S.
+enum MultiStepVariant {
+    MULTI_S3_H8 = 0,
+    MULTI_S3_H12 = 1,
+    MULTI_S3_H16 = 2,
+    MULTI_S3_H8_W3 = 3,  // registers held to three wavefronts per SIMD (spills)
+    MULTI_S4_H8 = 4,
+    MULTI_S4_H12 = 5,
+    MULTI_S4_H16 = 6,
+    MULTI_STEP_VARIANTS = 7
+};
+hipError_t launch_stepm_neq(int precision, const Lattice &L, const void *src, void *dst, const double *einc,
+                            hipStream_t s, int variant);
+void multi_step_shape(int variant, int &depth, int &rows);
 // Contour accumulation of two consecutive time levels: the fields in mid
 // (as written by a two-step launch), then those of the FP32 / BF16 state.
 hipError_t launch_contour2(const Lattice &L, const float *mid, const void *state, const ContourDev &C, hipStream_t s);

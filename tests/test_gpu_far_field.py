@@ -69,18 +69,42 @@ def test_far_field_matches_the_oracle(jlb, refs, precision, case):
         assert g[q] == plain[q], (q, g[q], plain[q])
 
 
+def test_far_field_after_multi_step_kernels(jlb, refs):
+    """Periods before the window on the four-step kernel, the window on the
+    two-step kernel, the last period on single steps."""
+    prec = jlb.PRECISIONS["fp32"]
+    before, multi0 = jlb.jlb_get_two_step_variant(prec), jlb.jlb_get_multi_step_variant(prec)
+    try:
+        jlb.jlb_set_two_step_variant(prec, 4)
+        jlb.jlb_set_multi_step_variant(prec, 5)
+        _print_case("mdjc-fp32-multi-step-5", CASES["mdjc"], 72)
+        g = jlb.solve(CASES["mdjc"], "fp32", far_angles=72)
+        plain = jlb.solve(CASES["mdjc"], "fp32")
+    finally:
+        jlb.jlb_set_two_step_variant(prec, before)
+        jlb.jlb_set_multi_step_variant(prec, multi0)
+    ref = refs["mdjc"]["s2"]
+    assert np.abs(g["s2"] - ref).max() <= 1e-3 * ref.max()
+    assert plain["main_kind"] == 3 and plain["main_launches"] > 0
+    for q in ("fx", "fy", "tz"):
+        assert g[q] == plain[q]
+
+
 @pytest.mark.parametrize("variant", [0, 4, 5])
 def test_far_field_after_two_step_kernels(jlb, refs, variant):
-    """The window runs in two-step launches until the last period."""
+    """The window runs in two-step launches until the last period (and, with
+    the multi-step kernels off, the periods before it too)."""
     prec = jlb.PRECISIONS["fp32"]
-    before = jlb.jlb_get_two_step_variant(prec)
+    before, multi0 = jlb.jlb_get_two_step_variant(prec), jlb.jlb_get_multi_step_variant(prec)
     try:
+        jlb.jlb_set_multi_step_variant(prec, -1)
         jlb.jlb_set_two_step_variant(prec, variant)
         _print_case(f"mdjc-fp32-two-step-{variant}", CASES["mdjc"], 72)
         g = jlb.solve(CASES["mdjc"], "fp32", far_angles=72)
         plain = jlb.solve(CASES["mdjc"], "fp32")
     finally:
         jlb.jlb_set_two_step_variant(prec, before)
+        jlb.jlb_set_multi_step_variant(prec, multi0)
     ref = refs["mdjc"]["s2"]
     assert np.abs(g["s2"] - ref).max() <= 1e-3 * ref.max()
     assert g["state_passes"] > plain["state_passes"] // 2  # the last period ran as single steps

@@ -197,7 +197,8 @@ def test_two_step_kernels_equal_single_steps(jlb, precision, polarization):
     forces (ragged strips and row segments, conductor links, all edges, the
     companion row), in both polarisations."""
     prec = jlb.PRECISIONS[precision]
-    before = jlb.jlb_get_two_step_variant(prec)
+    before, multi0 = jlb.jlb_get_two_step_variant(prec), jlb.jlb_get_multi_step_variant(prec)
+    jlb.jlb_set_multi_step_variant(prec, -1)  # the two-step kernels outside the window too
     cases = [W.problem(nx=203, ny=150, radius=20.0, kind="metallo_dielectric_janus", eps1=3.0, phi0_deg=110.0,
                        wavelength=40.0, steps=700, avg_periods=1),
              W.problem(nx=130, ny=171, radius=16.0, kind="dielectric_janus", eps1=2.0, eps2=6.0, phi0_deg=45.0,
@@ -221,6 +222,78 @@ def test_two_step_kernels_equal_single_steps(jlb, precision, polarization):
                     assert np.array_equal(o[f], ref[f]), (v, f, np.abs(o[f] - ref[f]).max())
     finally:
         jlb.jlb_set_two_step_variant(prec, before)
+        jlb.jlb_set_multi_step_variant(prec, multi0)
+
+
+@pytest.mark.parametrize("polarization", ["tm", "te"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_multi_step_kernels_equal_single_steps(jlb, precision, polarization):
+    """Three or four levels in flight per sweep: solves whose periods before
+    the window run on any multi-step variant (the window on the two-step
+    kernel or on single steps) equal the single-step solve bit for bit,
+    fields and forces; grids from ny = 20 (the shortest a four-step H16
+    segment allows) to wide ragged strips, conductor links, all edges, the
+    companion row."""
+    prec = jlb.PRECISIONS[precision]
+    two0, multi0 = jlb.jlb_get_two_step_variant(prec), jlb.jlb_get_multi_step_variant(prec)
+    cases = [W.problem(nx=203, ny=150, radius=20.0, kind="metallo_dielectric_janus", eps1=3.0, phi0_deg=110.0,
+                       wavelength=40.0, steps=720, avg_periods=1),
+             W.problem(nx=130, ny=171, radius=16.0, kind="dielectric_janus", eps1=2.0, eps2=6.0, phi0_deg=45.0,
+                       wavelength=40.0, steps=720, avg_periods=1),
+             W.problem(nx=530, ny=97, radius=20.0, kind="dielectric_janus", eps1=4.0, eps2=1.5, phi0_deg=200.0,
+                       wavelength=40.0, steps=720, avg_periods=1),
+             W.problem(nx=64, ny=20, radius=3.0, kind="dielectric_janus", eps1=2.0, eps2=3.0, phi0_deg=60.0,
+                       wavelength=40.0, steps=720, avg_periods=1, contour_offset=2.0)]
+    cases = [dict(p, polarization=polarization) for p in cases]
+    try:
+        for p in cases:
+            _print_case(f"multi-step {precision} {polarization}", p)
+            jlb.jlb_set_two_step_variant(prec, -1)
+            jlb.jlb_set_multi_step_variant(prec, -1)
+            ref = jlb.solve(p, precision, fields=True)
+            assert ref["state_passes"] == p["steps"]
+            for v in range(len(jlb.MULTI_STEP_VARIANTS)):
+                for two in (-1, 4):
+                    jlb.jlb_set_two_step_variant(prec, two)
+                    jlb.jlb_set_multi_step_variant(prec, v)
+                    o = jlb.solve(p, precision, fields=True)
+                    assert o["graph_used"] == 1 and o["state_passes"] < p["steps"] * 0.6, (v, o["state_passes"])
+                    depth, _ = jlb.jlb_multi_step_shape(v)
+                    assert o["state_passes"] == (480 // depth + (120 if two < 0 else 60) + 120), o["state_passes"]
+                    for q in ("fx", "fy", "tz"):
+                        assert o[q] == ref[q], (v, two, q, o[q], ref[q])
+                    for f in ("ez", "hx", "hy"):
+                        assert np.array_equal(o[f], ref[f]), (v, two, f, np.abs(o[f] - ref[f]).max())
+    finally:
+        jlb.jlb_set_two_step_variant(prec, two0)
+        jlb.jlb_set_multi_step_variant(prec, multi0)
+
+
+def test_multi_step_config2_matches_single_steps(jlb):
+    """The headline workload: forces identical to single steps for every
+    multi-step variant."""
+    p = W.config2()
+    prec = jlb.PRECISIONS["fp32"]
+    two0, multi0 = jlb.jlb_get_two_step_variant(prec), jlb.jlb_get_multi_step_variant(prec)
+    try:
+        jlb.jlb_set_two_step_variant(prec, -1)
+        jlb.jlb_set_multi_step_variant(prec, -1)
+        ref = jlb.solve(p, "fp32")
+        jlb.jlb_set_two_step_variant(prec, 4)
+        for v in range(len(jlb.MULTI_STEP_VARIANTS)):
+            jlb.jlb_set_multi_step_variant(prec, v)
+            o = jlb.solve(p, "fp32")
+            print(f"[multi-step] config2 variant {v}: loop {o['loop_ms']:.1f} ms, passes {o['state_passes']}, "
+                  f"pre-window {o['main_ms']:.1f} ms in {o['main_launches']} launches", flush=True)
+            for q in ("fx", "fy", "tz"):
+                assert o[q] == ref[q], (v, q, o[q], ref[q])
+            # 384 ramp steps, 46 periods of 384 steps before the 1920-step window
+            depth, _ = jlb.jlb_multi_step_shape(v)
+            assert (o["main_kind"], o["main_variant"], o["main_launches"]) == (3, v, 46 * 384 // depth)
+            assert 0.0 < o["main_ms"] < o["loop_ms"]
+    finally:
+        jlb.jlb_set_two_step_variant(prec, two0)
+        jlb.jlb_set_multi_step_variant(prec, multi0)
 
 
 def test_two_step_config2_matches_single_steps(jlb):
@@ -228,8 +301,9 @@ def test_two_step_config2_matches_single_steps(jlb):
     single steps."""
     p = W.config2()
     prec = jlb.PRECISIONS["fp32"]
-    before = jlb.jlb_get_two_step_variant(prec)
+    before, multi0 = jlb.jlb_get_two_step_variant(prec), jlb.jlb_get_multi_step_variant(prec)
     try:
+        jlb.jlb_set_multi_step_variant(prec, -1)
         jlb.jlb_set_two_step_variant(prec, -1)
         ref = jlb.solve(p, "fp32")
         for v in range(len(jlb.TWO_STEP_VARIANTS)):
@@ -239,6 +313,7 @@ def test_two_step_config2_matches_single_steps(jlb):
                 assert o[q] == ref[q], (v, q, o[q], ref[q])
     finally:
         jlb.jlb_set_two_step_variant(prec, before)
+        jlb.jlb_set_multi_step_variant(prec, multi0)
 
 
 def test_plateau_stop_matches_the_oracle(jlb, oracle):
