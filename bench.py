@@ -249,6 +249,17 @@ def run_default(args):
     return base_line(args, value, ms, config, roof, cpu, extra)
 
 
+def _kernel_choice(jlb, prec: str) -> dict:
+    """The step kernels the autotuner left selected for prec."""
+    if prec == "fp64":
+        return {"single_step": jlb.FP64_STEP_VARIANTS.get(jlb.jlb_get_step_variant(0))}
+    p = jlb.PRECISIONS[prec]
+    two, multi = jlb.jlb_get_two_step_variant(p), jlb.jlb_get_multi_step_variant(p)
+    return {"single_step": jlb.STEP_VARIANTS.get(jlb.jlb_get_step_variant(p)),
+            "two_step": jlb.TWO_STEP_VARIANTS.get(two) if two >= 0 else None,
+            "multi_step": jlb.MULTI_STEP_VARIANTS.get(multi) if multi >= 0 else None}
+
+
 def run_designmap(args):
     import torch
 
@@ -279,7 +290,8 @@ def run_designmap(args):
              "baseline_fp64_one_at_a_time": {"lups": base_lups, "solves_per_hour_extrapolated":
                                              len(probs) / (total / base_lups) * 3600.0,
                                              "sample": "4 solves stratified by radius"},
-             "failed": sum(1 for r in out["results"] if r["status"] != "done")}
+             "failed": sum(1 for r in out["results"] if r["status"] != "done"),
+             "kernels": _kernel_choice(jlb, args.precision)}
     config = {"workload": f"config 4 design map: {len(probs)} dielectric Janus solves, eps2/eps1 1.1..10 "
                           f"(16 log-spaced) x 36 orientations, a ~ U{{32..128}}, grid 8a, lambda 2a, 52 periods",
               "precision": args.precision}
@@ -300,6 +312,7 @@ def run_serve(args):
     extra = {k: out[k] for k in ("requests", "completed", "wall_s", "p50_s", "p99_s", "mean_s", "queue_p50_s",
                                  "queue_p99_s", "solves_per_hour", "offered_lups", "peak_resident", "budget_bytes",
                                  "policy", "max_slots")}
+    extra["kernels"] = _kernel_choice(jlb, args.precision)
     config = {"workload": f"config 5 serving: {args.requests} Poisson arrivals at 20/s (seed 22308), dielectric "
                           f"Janus a ~ U{{{args.a_min}..{args.a_max}}}, grid 8a, eps ~ U[1.5,10], lambda 2a, "
                           "52 periods, byte-budget admission", "precision": args.precision}

@@ -1031,6 +1031,13 @@ __device__ __forceinline__ double batch_incident(const SolveDesc &d, int64_t n)
     return n < d.ramp_end ? d.src_tab[n] : d.src_tab[d.ramp_end + n % d.T];
 }
 
+// A two-step solve takes a multi-step launch while its next mdepth levels
+// all lie before the averaging window.
+__device__ __forceinline__ bool multi_mode(const SolveDesc &d, int64_t n)
+{
+    return d.mdepth > 0 && n + d.mdepth <= d.steps - d.window;
+}
+
 // Batched two-step launch: wavefront w takes items[w] (slot, strip, row
 // segment) of a resident solve at that solve's own step n.
 template <typename NeqT, int V, int H, int HX, int LA>
@@ -1044,7 +1051,7 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq_batch(SolveDe
     const Tile t = items[w];
     const SolveDesc &d = D[t.slot];
     const int64_t n = d.n;
-    if (n >= d.steps) return;
+    if (n >= d.steps || multi_mode(d, n)) return;
     const bool one = d.steps - n == 1;
     // middle-level fields are needed when level n + 1 is averaged and a
     // second step follows
@@ -1218,6 +1225,26 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES, W) void k_stepm_neq(Lattice L,
     multi_step_wave<NeqT, V, H, HX, S>(L, srcv, dstv, einc.v, sx, sy);
 }
 
+// Batched multi-step launch: wavefront w takes items[w] of a resident solve
+// in multi mode at that solve's own step n.
+template <typename NeqT, int V, int H, int HX, int S, int W>
+__global__ __launch_bounds__(64 * TWO_STEP_WAVES, W) void k_stepm_neq_batch(SolveDesc *__restrict__ D,
+                                                                           const Tile *__restrict__ items, int nitems,
+                                                                           int remap)
+{
+    const int b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(b * TWO_STEP_WAVES + (int)threadIdx.y);
+    if (w >= nitems) return;
+    const Tile t = items[w];
+    const SolveDesc &d = D[t.slot];
+    const int64_t n = d.n;
+    if (n >= d.steps || d.mdepth != S || !multi_mode(d, n)) return;
+    float einc[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) einc[k] = (float)batch_incident(d, n + k);
+    multi_step_wave<NeqT, V, H, HX, S>(d.L, d.state[d.cur], d.state[d.cur ^ 1], einc, t.tx, t.ty);
+}
+
 // ---------------------------------------------------------------------------
 // Batched steps: block b works on tiles[b] of solve tiles[b].slot at that
 // solve's own step n (finished solves return at once).
@@ -1270,8 +1297,14 @@ __global__ void k_advance(SolveDesc *D, int nslots, int which)
     for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
         SolveDesc &d = D[s];
         const int64_t n = d.n;
-        if (d.two != which || n >= d.steps) continue;
-        d.n = which ? min(n + 2, d.steps) : n + 1;
+        if (n >= d.steps) continue;
+        if (which == 2) {
+            if (!d.two || !multi_mode(d, n)) continue;
+            d.n = n + d.mdepth;
+        } else {
+            if (d.two != which || (which == 1 && multi_mode(d, n))) continue;
+            d.n = which ? min(n + 2, d.steps) : n + 1;
+        }
         d.cur ^= 1;
     }
 }
@@ -1366,7 +1399,7 @@ __global__ void k_contour2_batch(SolveDesc *__restrict__ D)
 {
     const SolveDesc &d = D[blockIdx.y];
     const int64_t n = d.n;
-    if (!d.two || n >= d.steps) return;
+    if (!d.two || n >= d.steps || multi_mode(d, n)) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.C.n) return;
     const float *next = reinterpret_cast<const float *>(d.state[d.cur ^ 1]);
@@ -1779,6 +1812,15 @@ template <typename F> static void multi_step_dispatch(int variant, F &&go)
     }
 }
 
+void multi_step_grid(int variant, int nx, int ny, int &nsx, int &nsy)
+{
+    multi_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag, auto, auto) {
+        constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
+        nsx = (nx + two_step_width<V, HX>() - 1) / two_step_width<V, HX>();
+        nsy = (ny + H - 1) / H;
+    });
+}
+
 void multi_step_shape(int variant, int &depth, int &rows)
 {
     multi_step_dispatch(variant, [&](auto, auto htag, auto, auto stag, auto) {
@@ -1803,6 +1845,25 @@ hipError_t launch_stepm_neq(int precision, const Lattice &L, const void *src, vo
             const int blocks = (nsx * nsy + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
             hipLaunchKernelGGL((k_stepm_neq<T, V, H, HX, S, W>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src,
                                dst, e, nsx, nsy);
+        });
+    };
+    if (precision == 1) run(float{});
+    else run(__bf16{});
+    return hipGetLastError();
+}
+
+hipError_t launch_stepm_batch(int precision, int variant, SolveDesc *d, const Tile *items, int nitems, int remap,
+                              hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    const int blocks = (nitems + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
+    auto run = [&](auto tag) {
+        typedef decltype(tag) T;
+        multi_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag, auto stag, auto wtag) {
+            constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
+            constexpr int S = decltype(stag)::value, W = decltype(wtag)::value;
+            hipLaunchKernelGGL((k_stepm_neq_batch<T, V, H, HX, S, W>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s,
+                               d, items, nitems, remap);
         });
     };
     if (precision == 1) run(float{});

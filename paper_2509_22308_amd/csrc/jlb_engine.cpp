@@ -6,12 +6,16 @@
 // device memory carries its step counter and the index of the buffer that
 // holds its current state, which the device advances, so a chunk of K
 // lattice steps is captured once in a hipGraph and replayed while the set of
-// resident solves is unchanged.  The chunk is K / 2 double steps; in each,
-// solves on single steps (FP64, or with two-step kernels off) take two
-// rounds of one launch per precision over their tiles, one batched contour
-// launch and one advance launch, and FP32 / BF16 solves take one batched
-// two-step launch over their (strip, row segment) items, one two-level
-// contour launch and one advance-by-two launch.  Solves that finish inside a chunk idle
+// resident solves is unchanged.  The chunk is K / 4 rounds of four steps:
+// one batched four-step launch over the (strip, row segment) items of the
+// FP32 / BF16 solves whose next four levels lie before their averaging window
+// (then their advance-by-four launch at the end of the round), and two double
+// steps for the others.  In a double step, solves on single steps (FP64, or
+// with two-step kernels off) take two rounds of one launch per precision
+// over their tiles, one batched contour launch and one advance launch, and
+// FP32 / BF16 solves take one batched two-step launch over their items, one
+// two-level contour launch and one advance-by-two launch.  Each kernel skips
+// the solves that are not its own at their current step.  Solves that finish inside a chunk idle
 // (their tiles return at once) until the chunk boundary, where the engine
 // reduces their contour sums, returns their memory and admits waiting
 // requests that fit the byte budget (continuous batching).
@@ -87,7 +91,13 @@ struct jlb_engine {
     int two[3] = {-1, -1, -1};  // two-step variant per precision (-1: single steps)
     int nitems[3] = {0, 0, 0};  // two-step work items per precision
     int item_off[3] = {0, 0, 0};
-    bool any_single = false, any_two = false;
+    int multi[3] = {-1, -1, -1};  // four-step variant per precision (-1: none)
+    int nmitems[3] = {0, 0, 0};   // four-step work items per precision
+    int mitem_off[3] = {0, 0, 0};
+    bool any_single = false, any_two = false, any_multi = false;
+    // per resident solve (in resident order), the launches the captured
+    // chunk holds items for: 1 two-step, 2 four-step, 3 both
+    std::vector<uint8_t> part;
     int max_nc = 0;
     int remap = 0;
     bool dirty = true;
@@ -97,6 +107,37 @@ struct jlb_engine {
 };
 
 namespace {
+
+// The engine steps in rounds of four: a depth-3 choice maps to the
+// four-step variant with 12-row segments (with many solves resident the
+// launches are large, and 12 rows carry less halo work than 8 at the same
+// two wavefronts per SIMD).
+int engine_multi_variant(int v)
+{
+    if (v < 0) return -1;
+    int depth = 0, rows = 0;
+    multi_step_shape(v, depth, rows);
+    return depth == 4 ? v : MULTI_S4_H12;
+}
+
+// Which batched launches a resident solve needs over the next chunk of
+// CHUNK steps from its step n: four-step launches while its next four levels
+// lie before the window (mode checked per round on the device), two-step
+// launches otherwise.  Solves that stay in one mode for the whole chunk get
+// items in one list only, so a launch does not spend wavefronts on solves
+// that skip it.
+uint8_t launch_part(const jlb_engine *e, const Request &r)
+{
+    const int p = r.plan.prob.precision;
+    if (e->two[p] < 0) return 0;
+    int depth = 0, rows = 0;
+    if (e->multi[p] >= 0) multi_step_shape(e->multi[p], depth, rows);
+    if (e->multi[p] < 0 || r.plan.ny < rows + depth) return 1;
+    const int64_t wstart = r.plan.prob.steps - r.plan.window;
+    if (r.n + depth > wstart) return 1;          // never in four-step mode again
+    if (r.n + CHUNK <= wstart) return 2;         // four-step mode in every round of the chunk
+    return 3;
+}
 
 size_t footprint_of(const Plan &q)
 {
@@ -224,7 +265,7 @@ int rebuild(jlb_engine *e)
     }
     const int ns = (int)e->resident.size();
     std::vector<SolveDesc> desc(ns);
-    std::vector<Tile> tiles[3], items[3];
+    std::vector<Tile> tiles[3], items[3], mitems[3];
     e->max_nc = 0;
     // the resident states together decide whether they stay cache-resident
     size_t working_set = 0;
@@ -234,8 +275,10 @@ int rebuild(jlb_engine *e)
     for (int p = 0; p < 3; ++p) {
         e->variant[p] = jlb::step_variant(p);
         e->two[p] = p == JLB_FP64 ? -1 : jlb::two_step_variant(p);
+        e->multi[p] = e->two[p] >= 0 ? engine_multi_variant(jlb::multi_step_variant(p)) : -1;
     }
-    e->any_single = e->any_two = false;
+    e->any_single = e->any_two = e->any_multi = false;
+    e->part.assign(ns, 0);
     for (int k = 0; k < ns; ++k) {
         Request &r = e->reqs[e->resident[k]];
         const Plan &q = r.plan;
@@ -260,17 +303,37 @@ int rebuild(jlb_engine *e)
         const int p = q.prob.precision;
         d.two = e->two[p] >= 0 ? 1 : 0;
         if (d.two) {
+            const uint8_t part = launch_part(e, r);
+            e->part[k] = part;
             // one wavefront per (strip, row segment), in the order the
             // single-solve launch uses for this residency
-            e->any_two = true;
             int nsx, nsy;
             two_step_shape(e->two[p], q.nx, q.ny, nsx, nsy);
-            if (stream_stores) {
-                for (int y = 0; y < nsy; ++y)
-                    for (int x = 0; x < nsx; ++x) items[p].push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
-            } else {
-                for (int x = 0; x < nsx; ++x)
-                    for (int y = 0; y < nsy; ++y) items[p].push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
+            if (part & 1) {
+                e->any_two = true;
+                if (stream_stores) {
+                    for (int y = 0; y < nsy; ++y)
+                        for (int x = 0; x < nsx; ++x) items[p].push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
+                } else {
+                    for (int x = 0; x < nsx; ++x)
+                        for (int y = 0; y < nsy; ++y) items[p].push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
+                }
+            }
+            int depth = 0, rows = 0;
+            if (e->multi[p] >= 0) multi_step_shape(e->multi[p], depth, rows);
+            if (e->multi[p] >= 0 && q.ny >= rows + depth) d.mdepth = depth;
+            if (part & 2) {
+                // the same orders for the four-step items
+                e->any_multi = true;
+                int mx, my;
+                multi_step_grid(e->multi[p], q.nx, q.ny, mx, my);
+                if (stream_stores) {
+                    for (int y = 0; y < my; ++y)
+                        for (int x = 0; x < mx; ++x) mitems[p].push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
+                } else {
+                    for (int x = 0; x < mx; ++x)
+                        for (int y = 0; y < my; ++y) mitems[p].push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
+                }
             }
             continue;
         }
@@ -294,6 +357,11 @@ int rebuild(jlb_engine *e)
         e->nitems[p] = (int)items[p].size();
         total += items[p].size();
     }
+    for (int p = 0; p < 3; ++p) {
+        e->mitem_off[p] = (int)total;
+        e->nmitems[p] = (int)mitems[p].size();
+        total += mitems[p].size();
+    }
     hipError_t err = hipSuccess;
     if (!e->d_desc) {
         e->slots_cap = e->max_slots;
@@ -312,6 +380,9 @@ int rebuild(jlb_engine *e)
                                  hipMemcpyHostToDevice, e->s);
         if (err == hipSuccess && !items[p].empty())
             err = hipMemcpyAsync(e->d_tiles + e->item_off[p], items[p].data(), sizeof(Tile) * items[p].size(),
+                                 hipMemcpyHostToDevice, e->s);
+        if (err == hipSuccess && !mitems[p].empty())
+            err = hipMemcpyAsync(e->d_tiles + e->mitem_off[p], mitems[p].data(), sizeof(Tile) * mitems[p].size(),
                                  hipMemcpyHostToDevice, e->s);
     }
     if (err == hipSuccess) err = hipStreamSynchronize(e->s);  // host vectors go out of scope
@@ -344,13 +415,28 @@ hipError_t launch_double_step(jlb_engine *e)
     return err;
 }
 
+// Four steps: one four-step launch of the solves in multi mode, two double
+// steps of the others, then the four-step solves' advance.
+hipError_t launch_quad_step(jlb_engine *e)
+{
+    const int ns = (int)e->resident.size();
+    hipError_t err = hipSuccess;
+    for (int p = 1; p < 3 && e->any_multi && err == hipSuccess; ++p)
+        if (e->nmitems[p] > 0)
+            err = launch_stepm_batch(p, e->multi[p], e->d_desc, e->d_tiles + e->mitem_off[p], e->nmitems[p], e->remap,
+                                     e->s);
+    for (int k = 0; k < 2 && err == hipSuccess; ++k) err = launch_double_step(e);
+    if (e->any_multi && err == hipSuccess) err = launch_advance(e->d_desc, ns, 2, e->s);
+    return err;
+}
+
 int capture(jlb_engine *e)
 {
     hipGraph_t g;
     if (hipStreamBeginCapture(e->s, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(JLB_E_DEVICE, "engine capture begin");
     hipError_t err = hipSuccess;
-    for (int64_t k = 0; k < CHUNK / 2 && err == hipSuccess; ++k) err = launch_double_step(e);
+    for (int64_t k = 0; k < CHUNK / 4 && err == hipSuccess; ++k) err = launch_quad_step(e);
     hipError_t err2 = hipStreamEndCapture(e->s, &g);
     if (err != hipSuccess || err2 != hipSuccess) return fail(JLB_E_DEVICE, "engine capture failed");
     err = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
@@ -495,6 +581,13 @@ int jlb_engine_run(jlb_engine *e, int64_t steps, int32_t *active)
             rc = rebuild(e);
             if (rc) return rc;
         }
+        // a solve that changed launch part since the capture needs new item lists
+        for (size_t j = 0; j < e->resident.size() && !e->dirty; ++j)
+            if (launch_part(e, e->reqs[e->resident[j]]) != e->part[j]) e->dirty = true;
+        if (e->dirty) {
+            rc = rebuild(e);
+            if (rc) return rc;
+        }
         // whole double steps
         const int64_t k = std::min<int64_t>(CHUNK, (steps - done + 1) / 2 * 2);
         if (k == CHUNK) {
@@ -506,18 +599,37 @@ int jlb_engine_run(jlb_engine *e, int64_t steps, int32_t *active)
             // host work for the next admissions while the chunk runs
             prepare_ahead(e);
         } else {
-            for (int64_t i = 0; i < k / 2; ++i)
-                if (launch_double_step(e) != hipSuccess) return fail(JLB_E_DEVICE, "engine step launch");
+            for (int64_t i = 0; i < k / 4; ++i)
+                if (launch_quad_step(e) != hipSuccess) return fail(JLB_E_DEVICE, "engine step launch");
+            if (k % 4 && launch_double_step(e) != hipSuccess) return fail(JLB_E_DEVICE, "engine step launch");
         }
         // host mirrors of the device counters (the advance kernels' rules)
         for (uint64_t t : e->resident) {
             Request &r = e->reqs[t];
-            const int64_t total = r.plan.prob.steps;
-            const bool two = e->two[r.plan.prob.precision] >= 0;
-            for (int64_t i = 0; i < (two ? k / 2 : k) && r.n < total; ++i) {
-                r.n = two ? std::min<int64_t>(r.n + 2, total) : r.n + 1;
-                r.cur ^= 1;
+            const int64_t total = r.plan.prob.steps, wstart = total - r.plan.window;
+            const int p = r.plan.prob.precision;
+            const bool two = e->two[p] >= 0;
+            int mdepth = 0, mrows = 0;
+            if (two && e->multi[p] >= 0) multi_step_shape(e->multi[p], mdepth, mrows);
+            if (r.plan.ny < mrows + mdepth) mdepth = 0;
+            auto multi_mode = [&] { return mdepth > 0 && r.n + mdepth <= wstart; };
+            auto double_step = [&] {
+                for (int i = 0; i < (two ? 1 : 2) && r.n < total; ++i) {
+                    if (two && multi_mode()) return;
+                    r.n = two ? std::min<int64_t>(r.n + 2, total) : r.n + 1;
+                    r.cur ^= 1;
+                }
+            };
+            for (int64_t i = 0; i < k / 4; ++i) {
+                if (r.n < total && multi_mode()) {
+                    r.n += mdepth;
+                    r.cur ^= 1;
+                } else {
+                    double_step();
+                    double_step();
+                }
             }
+            if (k % 4) double_step();
         }
         done += k;
         rc = harvest(e);

@@ -559,6 +559,23 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             if (!in_window && check_level(n)) rc = plateau_check(n);
             continue;
         }
+        // outside the window with no per-step output (the ramp, the steps
+        // before the first whole chunk of the window): multi-step launches
+        // in pairs, which leave state n + 2 S in buffer n % 2 as single steps do
+        const int64_t pair_end = n < ramp_end ? std::min(ramp_end, seg_end) : seg_end;
+        if (multi >= 0 && !in_window && !plateau && !energy && !far.force && n + 2 * depth <= pair_end) {
+            for (int k = 0; k < 2 && rc == JLB_OK; ++k) {
+                const int64_t m = n + k * depth;
+                double einc[4];
+                for (int j = 0; j < depth; ++j) einc[j] = incident(q, m + j);
+                hipError_t e = launch_stepm_neq(q.prob.precision, L, ws + q.off_state[(n + k) & 1],
+                                                ws + q.off_state[(n + k + 1) & 1], einc, s, multi);
+                if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "multi-step launch: %s", hipGetErrorString(e));
+            }
+            passes += 2;
+            n += 2 * depth;
+            continue;
+        }
         const bool check = !in_window && check_level(n + 1);
         rc = launch_one_step(q, ws, L, C, n, in_window, energy != nullptr || far.force != nullptr || n == steps - 1 || check,
                              incident(q, n), s);

@@ -132,6 +132,8 @@ enum MultiStepVariant {
 hipError_t launch_stepm_neq(int precision, const Lattice &L, const void *src, void *dst, const double *einc,
                             hipStream_t s, int variant);
 void multi_step_shape(int variant, int &depth, int &rows);
+// Strip and segment counts of a multi-step variant for an nx x ny lattice.
+void multi_step_grid(int variant, int nx, int ny, int &nsx, int &nsy);
 // Contour accumulation of two consecutive time levels: the fields in mid
 // (as written by a two-step launch), then those of the FP32 / BF16 state.
 hipError_t launch_contour2(const Lattice &L, const float *mid, const void *state, const ContourDev &C, hipStream_t s);
@@ -176,7 +178,7 @@ struct SolveDesc {
     int precision;
     int cur;                 // buffer holding the state at step n (device-updated)
     int two;                 // 1: advanced by two-step launches
-    int pad;
+    int mdepth;              // > 0: four-step launches while four levels fit before the window
 };
 
 // One block of work: a tile of one resident solve.
@@ -200,8 +202,14 @@ hipError_t launch_step2_batch(int precision, int variant, SolveDesc *d, const Ti
 // Strip and segment counts of a two-step variant for an nx x ny lattice.
 void two_step_shape(int variant, int nx, int ny, int &nsx, int &nsy);
 hipError_t launch_contour2_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s);
+// Multi-step launches (variant of depth mdepth) over the two-step solves
+// whose next mdepth levels all lie before the window ("multi mode"); the
+// two-step launches, their contour launches and advances skip those solves.
+hipError_t launch_stepm_batch(int precision, int variant, SolveDesc *d, const Tile *items, int nitems, int remap,
+                              hipStream_t s);
 // Advances the solves with two == which by one step (which = 0) or by up
-// to two (which = 1) and flips their buffers.
+// to two (which = 1; not those in multi mode) and flips their buffers;
+// which = 2 advances the solves in multi mode by mdepth.
 hipError_t launch_advance(SolveDesc *d, int nslots, int which, hipStream_t s);
 
 }  // namespace jlb

@@ -151,6 +151,34 @@ def test_two_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, precisi
             assert s[q] == b[q], (precision, variant, q, s[q], b[q])
 
 
+@pytest.mark.parametrize("multi", [1, 4, 6])
+@pytest.mark.parametrize("chunk", [256, 130])
+def test_four_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, multi, chunk):
+    """Rounds of four steps: solves whose next four levels lie before their
+    window take one batched four-step launch, the others two double steps;
+    every solve at its own step.  A run of 130 steps ends on a lone double
+    step in which the four-step solves wait.  A grid too short for the
+    variant (ny = 19) stays on two-step launches.  Each result equals its
+    single solve bit for bit."""
+    prec = jlb.PRECISIONS["fp32"]
+    multi0 = jlb.jlb_get_multi_step_variant(prec)
+    probs = _mix() + [W.problem(nx=64, ny=19, radius=3.0, kind="dielectric_janus", eps1=2.0, eps2=3.0,
+                                phi0_deg=60.0, wavelength=40.0, steps=720, avg_periods=1, contour_offset=2.0)]
+    try:
+        two_step(-1)
+        jlb.jlb_set_multi_step_variant(prec, -1)
+        single = [jlb.solve(p, "fp32") for p in probs]
+        two_step(4)
+        jlb.jlb_set_multi_step_variant(prec, multi)
+        batched = _run_engine(jlb, [jlb.make_problem(p, "fp32") for p in probs], chunk=chunk)
+    finally:
+        jlb.jlb_set_multi_step_variant(prec, multi0)
+    for s, b in zip(single, batched):
+        for q in ("fx", "fy", "tz", "energy_final"):
+            assert s[q] == b[q], (multi, chunk, q, s[q], b[q])
+        assert b["steps_done"] == s["steps_done"]
+
+
 def test_two_step_and_single_step_solves_share_an_engine(jlb, two_step):
     """FP64 solves on single steps and FP32 / BF16 solves on two-step launches
     in one engine, admitted at different times: each equals its single solve."""

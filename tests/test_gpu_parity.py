@@ -259,7 +259,8 @@ def test_multi_step_kernels_equal_single_steps(jlb, precision, polarization):
                     o = jlb.solve(p, precision, fields=True)
                     assert o["graph_used"] == 1 and o["state_passes"] < p["steps"] * 0.6, (v, o["state_passes"])
                     depth, _ = jlb.jlb_multi_step_shape(v)
-                    assert o["state_passes"] == (480 // depth + (120 if two < 0 else 60) + 120), o["state_passes"]
+                    # ramp and the periods before the window on multi-step launches
+                    assert o["state_passes"] == 600 // depth + (120 if two < 0 else 60), o["state_passes"]
                     for q in ("fx", "fy", "tz"):
                         assert o[q] == ref[q], (v, two, q, o[q], ref[q])
                     for f in ("ez", "hx", "hy"):
