@@ -289,10 +289,12 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * one launch takes the state from step n to n + 2, reading and writing it
  * once (temporal blocking), with results equal to two single steps bit for
  * bit.  An FP32 / BF16 solve uses the selected two-step variant for every step that
- * runs in graph-captured whole periods (inside the averaging window too,
- * where the middle level's contour fields are kept), and single steps for the
- * ramp, the steps after the last whole chunk and a far-field solve's last
- * period; the engine uses it for all steps of its FP32 / BF16 solves.
+ * runs in graph-captured whole periods inside the averaging window (where the
+ * middle level's contour fields are kept) and before it when no multi-step
+ * variant applies, and single steps for the steps after the last whole chunk
+ * and a far-field solve's last period (and for the ramp without a multi-step
+ * variant); the engine uses it for the steps of its FP32 / BF16 solves that
+ * its four-step launches do not take.
  * Variants (V adjacent nodes per lane, H rows per wavefront, HX halo columns
  * per side; HX 8 keeps output strips 64-byte aligned; LA2: each input row is
  * loaded two rows ahead of its first use instead of one): 0 V1 H8 X2,
