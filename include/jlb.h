@@ -343,17 +343,18 @@ int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t wo
  * averaging window on it (the window keeps the two-step kernel, or single
  * steps), provided the captured chunk is a multiple of 2 S steps and
  * ny >= rows + S; otherwise those periods run as without it.  The engine
- * does not use them.  Variants (depth S, rows per wavefront; 48 output
- * columns per 64-lane strip; registers for two wavefronts per SIMD unless
- * noted): 0 S3 H8, 1 S3 H12, 2 S3 H16, 3 S3 H8 held to three wavefronts per
- * SIMD (spills), 4 S4 H8, 5 S4 H12, 6 S4 H16.  jlb_multi_step_shape reports
- * S and the rows of a variant.  Default: 1 (set -1 for none); jlb_autotune
+ * runs rounds of four steps with variant 8 whenever a variant is selected.  Variants (depth S, rows per wavefront; 48 output
+ * columns per 64-lane strip, or 56 with X4; registers for two wavefronts per
+ * SIMD unless noted): 0 S3 H8, 1 S3 H12, 2 S3 H16, 3 S3 H8 held to three
+ * wavefronts per SIMD (spills), 4 S4 H8, 5 S4 H12, 6 S4 H16, 7 S4 H12 X4,
+ * 8 S4 H16 X4, 9 S3 H12 X4, 10 S4 H10 X4, 11 S3 H10 X4.  jlb_multi_step_shape reports
+ * S and the rows of a variant.  Default: 10 (set -1 for none); jlb_autotune
  * selects one when it beats the other kernels per lattice step.
  * jlb_time_multi_step_kernel: mean time of one launch (S lattice steps) of
  * the selected variant, as jlb_time_step_kernel; JLB_E_ARG for FP64, when
  * none is selected or when ny < rows + S.
  */
-#define JLB_MULTI_STEP_VARIANTS 7
+#define JLB_MULTI_STEP_VARIANTS 12
 int jlb_set_multi_step_variant(int32_t precision, int32_t variant);
 int jlb_get_multi_step_variant(int32_t precision, int32_t *variant);
 int jlb_multi_step_shape(int32_t variant, int32_t *depth, int32_t *rows);

@@ -1794,11 +1794,13 @@ template <typename F> static void multi_step_dispatch(int variant, F &&go)
 {
     using I1 = std::integral_constant<int, 1>;
     using X8 = std::integral_constant<int, 8>;
+    using X4 = std::integral_constant<int, 4>;
     using S3 = std::integral_constant<int, 3>;
     using S4 = std::integral_constant<int, 4>;
     using W2 = std::integral_constant<int, 2>;
     using W3 = std::integral_constant<int, 3>;
     using H8 = std::integral_constant<int, 8>;
+    using H10 = std::integral_constant<int, 10>;
     using H12 = std::integral_constant<int, 12>;
     using H16 = std::integral_constant<int, 16>;
     switch (variant) {
@@ -1808,7 +1810,12 @@ template <typename F> static void multi_step_dispatch(int variant, F &&go)
     case MULTI_S3_H8_W3: go(I1{}, H8{}, X8{}, S3{}, W3{}); break;
     case MULTI_S4_H8: go(I1{}, H8{}, X8{}, S4{}, W2{}); break;
     case MULTI_S4_H12: go(I1{}, H12{}, X8{}, S4{}, W2{}); break;
-    default: go(I1{}, H16{}, X8{}, S4{}, W2{}); break;
+    case MULTI_S4_H16: go(I1{}, H16{}, X8{}, S4{}, W2{}); break;
+    case MULTI_S4_H12_X4: go(I1{}, H12{}, X4{}, S4{}, W2{}); break;
+    case MULTI_S4_H16_X4: go(I1{}, H16{}, X4{}, S4{}, W2{}); break;
+    case MULTI_S3_H12_X4: go(I1{}, H12{}, X4{}, S3{}, W2{}); break;
+    case MULTI_S4_H10_X4: go(I1{}, H10{}, X4{}, S4{}, W2{}); break;
+    default: go(I1{}, H10{}, X4{}, S3{}, W2{}); break;
     }
 }
 

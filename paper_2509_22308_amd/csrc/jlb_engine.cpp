@@ -108,16 +108,15 @@ struct jlb_engine {
 
 namespace {
 
-// The engine steps in rounds of four: a depth-3 choice maps to the
-// four-step variant with 12-row segments (with many solves resident the
-// launches are large, and 12 rows carry less halo work than 8 at the same
-// two wavefronts per SIMD).
+// The engine steps in rounds of four, and with many solves resident its
+// launches hold far more wavefronts than the device runs at once, so the
+// halo work per update decides: whenever multi-step kernels are selected it
+// takes the four-step variant with the least of it (16-row segments, 4 halo
+// columns).  The autotuner's choice, made on one solve's grid, is about
+// latency instead.
 int engine_multi_variant(int v)
 {
-    if (v < 0) return -1;
-    int depth = 0, rows = 0;
-    multi_step_shape(v, depth, rows);
-    return depth == 4 ? v : MULTI_S4_H12;
+    return v < 0 ? -1 : MULTI_S4_H16_X4;
 }
 
 // Which batched launches a resident solve needs over the next chunk of

@@ -255,7 +255,7 @@ static void set_two_step_variant(int precision, int v) { g_two[precision].store(
 // Multi-step (three or four steps per launch) kernel variant per precision
 // for the whole periods outside the window (inside it the two-step kernel or
 // single steps run), -1 = off.
-static std::atomic<int> g_multi[3] = {{-1}, {MULTI_S3_H12}, {MULTI_S3_H12}};
+static std::atomic<int> g_multi[3] = {{-1}, {MULTI_S4_H10_X4}, {MULTI_S4_H10_X4}};
 int multi_step_variant(int precision) { return g_multi[precision].load(std::memory_order_relaxed); }
 static void set_multi_step_variant(int precision, int v) { g_multi[precision].store(v, std::memory_order_relaxed); }
 

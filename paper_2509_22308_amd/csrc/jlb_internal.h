@@ -127,7 +127,12 @@ enum MultiStepVariant {
     MULTI_S4_H8 = 4,
     MULTI_S4_H12 = 5,
     MULTI_S4_H16 = 6,
-    MULTI_STEP_VARIANTS = 7
+    MULTI_S4_H12_X4 = 7,  // 4 halo columns per side: 56 output columns per strip
+    MULTI_S4_H16_X4 = 8,
+    MULTI_S3_H12_X4 = 9,
+    MULTI_S4_H10_X4 = 10,
+    MULTI_S3_H10_X4 = 11,
+    MULTI_STEP_VARIANTS = 12
 };
 hipError_t launch_stepm_neq(int precision, const Lattice &L, const void *src, void *dst, const double *einc,
                             hipStream_t s, int variant);

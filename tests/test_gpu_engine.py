@@ -151,7 +151,7 @@ def test_two_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, precisi
             assert s[q] == b[q], (precision, variant, q, s[q], b[q])
 
 
-@pytest.mark.parametrize("multi", [1, 4, 6])
+@pytest.mark.parametrize("multi", [1, -1])
 @pytest.mark.parametrize("chunk", [256, 130])
 def test_four_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, multi, chunk):
     """Rounds of four steps: solves whose next four levels lie before their
@@ -159,7 +159,8 @@ def test_four_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, multi,
     every solve at its own step.  A run of 130 steps ends on a lone double
     step in which the four-step solves wait.  A grid too short for the
     variant (ny = 19) stays on two-step launches.  Each result equals its
-    single solve bit for bit."""
+    single solve bit for bit, with the four-step launches on (any selected
+    variant gives the engine's four-step H16 X4) and off."""
     prec = jlb.PRECISIONS["fp32"]
     multi0 = jlb.jlb_get_multi_step_variant(prec)
     probs = _mix() + [W.problem(nx=64, ny=19, radius=3.0, kind="dielectric_janus", eps1=2.0, eps2=3.0,
