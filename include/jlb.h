@@ -288,13 +288,12 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * FP32 / BF16 also have two-step kernels (JLB_TWO_STEP_VARIANTS of them):
  * one launch takes the state from step n to n + 2, reading and writing it
  * once (temporal blocking), with results equal to two single steps bit for
- * bit.  An FP32 / BF16 solve uses the selected two-step variant for every step that
- * runs in graph-captured whole periods inside the averaging window (where the
- * middle level's contour fields are kept) and before it when no multi-step
- * variant applies, and single steps for the steps after the last whole chunk
- * and a far-field solve's last period (and for the ramp without a multi-step
- * variant); the engine uses it for the steps of its FP32 / BF16 solves that
- * its four-step launches do not take.
+ * bit.  When no multi-step variant applies, an FP32 / BF16 solve uses the
+ * selected two-step variant for every step that runs in graph-captured whole
+ * periods (inside the averaging window too, where the middle level's contour
+ * fields are kept), and single steps for the ramp, the steps after the last
+ * whole chunk and a far-field solve's last period; the engine uses it for the
+ * steps of its FP32 / BF16 solves that its four-step launches do not take.
  * Variants (V adjacent nodes per lane, H rows per wavefront, HX halo columns
  * per side; HX 8 keeps output strips 64-byte aligned; LA2: each input row is
  * loaded two rows ahead of its first use instead of one): 0 V1 H8 X2,
@@ -339,22 +338,24 @@ int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t wo
  * Multi-step kernels (FP32 / BF16, JLB_MULTI_STEP_VARIANTS of them): one
  * launch takes the state from step n to n + S, S = 3 or 4 (S levels in
  * flight in each wavefront's sweep), bit for bit equal to S single steps.
- * When a variant is selected, jlb_solve runs the whole periods before the
- * averaging window on it (the window keeps the two-step kernel, or single
- * steps), provided the captured chunk is a multiple of 2 S steps and
- * ny >= rows + S; otherwise those periods run as without it.  The engine
- * runs rounds of four steps with variant 8 whenever a variant is selected.  Variants (depth S, rows per wavefront; 48 output
- * columns per 64-lane strip, or 56 with X4; registers for two wavefronts per
- * SIMD unless noted): 0 S3 H8, 1 S3 H12, 2 S3 H16, 3 S3 H8 held to three
- * wavefronts per SIMD (spills), 4 S4 H8, 5 S4 H12, 6 S4 H16, 7 S4 H12 X4,
- * 8 S4 H16 X4, 9 S3 H12 X4, 10 S4 H10 X4, 11 S3 H10 X4.  jlb_multi_step_shape reports
- * S and the rows of a variant.  Default: 10 (set -1 for none); jlb_autotune
- * selects one when it beats the other kernels per lattice step.
+ * When a variant is selected, jlb_solve runs every graph-captured chunk on
+ * it, the averaging window included (there the launch also keeps the
+ * contour-stencil fields of its intermediate levels and all S levels are
+ * accumulated after it, in time order), and the ramp and the steps before
+ * the window's first chunk as pairs of launches, provided the chunk is a
+ * multiple of 2 S steps and ny >= rows + S; otherwise the solve runs as
+ * without it.  The engine runs rounds of four steps with variant 2 whenever
+ * a variant is selected.  Variants (depth S, rows per wavefront, halo
+ * columns per side: 56 output columns per 64-lane strip with X4, 48 with
+ * X8; registers for two wavefronts per SIMD): 0 S4 H10 X4, 1 S4 H12 X4,
+ * 2 S4 H16 X4, 3 S3 H10 X4, 4 S3 H12 X4, 5 S4 H12 X8.  jlb_multi_step_shape
+ * reports S and the rows of a variant.  Default: 0 (set -1 for none);
+ * jlb_autotune selects one when it beats the other kernels per lattice step.
  * jlb_time_multi_step_kernel: mean time of one launch (S lattice steps) of
  * the selected variant, as jlb_time_step_kernel; JLB_E_ARG for FP64, when
  * none is selected or when ny < rows + S.
  */
-#define JLB_MULTI_STEP_VARIANTS 12
+#define JLB_MULTI_STEP_VARIANTS 6
 int jlb_set_multi_step_variant(int32_t precision, int32_t variant);
 int jlb_get_multi_step_variant(int32_t precision, int32_t *variant);
 int jlb_multi_step_shape(int32_t variant, int32_t *depth, int32_t *rows);

@@ -231,10 +231,8 @@ TWO_STEP_VARIANTS = {0: "two-step V1 H8 X2", 1: "two-step V1 H16 X2", 2: "two-st
                      3: "two-step V2 H16 X2", 4: "two-step V1 H8 X8", 5: "two-step V2 H16 X8",
                      6: "two-step V2 H32 X8", 7: "two-step V1 H8 X8 LA2", 8: "two-step V1 H4 X8 LA2",
                      9: "two-step V1 H16 X8 LA2"}
-MULTI_STEP_VARIANTS = {0: "three-step H8", 1: "three-step H12", 2: "three-step H16", 3: "three-step H8 W3",
-                       4: "four-step H8", 5: "four-step H12", 6: "four-step H16", 7: "four-step H12 X4",
-                       8: "four-step H16 X4", 9: "three-step H12 X4", 10: "four-step H10 X4",
-                       11: "three-step H10 X4"}
+MULTI_STEP_VARIANTS = {0: "four-step H10 X4", 1: "four-step H12 X4", 2: "four-step H16 X4",
+                       3: "three-step H10 X4", 4: "three-step H12 X4", 5: "four-step H12 X8"}
 
 
 def variant_name(precision, best: int) -> str:

@@ -1067,10 +1067,14 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq_batch(SolveDe
 // produced; intermediate levels are rounded to the storage type as a store
 // would round them, so the result equals S single steps bit for bit.  A
 // segment of H output rows takes H + 2 (S - 1) level-1 rows, and a strip
-// needs at least S halo columns at each side.
-template <typename NeqT, int V, int H, int HX, int S>
+// needs at least S halo columns at each side.  With MID (inside the
+// averaging window) the fields at n + 1 .. n + S - 1 of the contour-stencil
+// nodes of the segment's own rows are written to mid, level after level
+// (mid_level floats apart, each 3 planes row-interleaved, row stride 3 pitch).
+template <typename NeqT, int V, int H, int HX, int S, bool MID>
 __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__restrict__ srcv,
-                                                void *__restrict__ dstv, const float (&einc)[S], int sx, int sy)
+                                                void *__restrict__ dstv, const float (&einc)[S], float *__restrict__ mid,
+                                                size_t mid_level, int sx, int sy)
 {
     constexpr int OW = two_step_width<V, HX>();
     static_assert(S >= 2 && HX >= S && HX % V == 0 && OW > 0, "multi-step strip shape");
@@ -1092,6 +1096,21 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
         const int rc = min(max(r, 0), L.ny - 1);
         load_row_at<NeqT, V>(F + (size_t)rc * L.sf, Pu, ic, d);
         m = *byte_at<MaskT>(L.mask + (size_t)rc * L.pitch, ic);
+    };
+    // fields of level `lev` (1 .. S - 1) on row r, at its contour-stencil nodes
+    auto keep_mid = [&](int lev, int r, const RowData<V> &d, MaskT m) {
+        if constexpr (MID) {
+            if (out_lane && r >= j0 && r < j0 + H && r < L.ny) {
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if ((m >> (8 * v)) & MASK_CONTOUR) {
+                        float *f = mid + (size_t)(lev - 1) * mid_level + (size_t)r * 3 * P + i0 + v;
+                        f[0] = d.ez[v];
+                        f[P] = d.hx[v];
+                        f[2 * P] = d.hy[v];
+                    }
+            }
+        }
     };
 
     // companion row at n .. n + S - 1 where rows 0 or ny - 1 are updated at
@@ -1166,6 +1185,7 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
                 row_update<NeqT, V, false>(L, i0, r1, mk[0], a_cur, DIR > 0 ? a_behind : side,
                                            DIR > 0 ? side : a_behind, StripSides<V>{edge[0], edge[0]}, einc[0], nw);
                 round_row<NeqT, V>(nw);
+                keep_mid(1, r1, nw, mk[0]);
             }
             // levels 2 .. S on the rows behind; nw is the level-s row just made
 #pragma unroll
@@ -1181,6 +1201,7 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
                                                einc[s], o);
                     if (s < S - 1) {
                         round_row<NeqT, V>(o);
+                        keep_mid(s + 1, rs, o, mk[s]);
                     } else {
                         mask_row<V>(L, i0, mk[s], false, o);
                         if (out_lane && rs < L.ny)
@@ -1211,9 +1232,10 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
 template <int S> struct Incident {
     float v[S];
 };
-template <typename NeqT, int V, int H, int HX, int S, int W>
+template <typename NeqT, int V, int H, int HX, int S, int W, bool MID>
 __global__ __launch_bounds__(64 * TWO_STEP_WAVES, W) void k_stepm_neq(Lattice L, const void *__restrict__ srcv,
                                                                      void *__restrict__ dstv, Incident<S> einc,
+                                                                     float *__restrict__ mid, size_t mid_level,
                                                                      int nsx, int nsy)
 {
     // work order as for the two-step launch
@@ -1222,7 +1244,7 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES, W) void k_stepm_neq(Lattice L,
     const int w = __builtin_amdgcn_readfirstlane(b * TWO_STEP_WAVES + (int)threadIdx.y);
     if (w >= nsx * nsy) return;  // whole wavefront
     const int sx = L.stream_stores ? w % nsx : w / nsy, sy = L.stream_stores ? w / nsx : w % nsy;
-    multi_step_wave<NeqT, V, H, HX, S>(L, srcv, dstv, einc.v, sx, sy);
+    multi_step_wave<NeqT, V, H, HX, S, MID>(L, srcv, dstv, einc.v, mid, mid_level, sx, sy);
 }
 
 // Batched multi-step launch: wavefront w takes items[w] of a resident solve
@@ -1242,7 +1264,7 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES, W) void k_stepm_neq_batch(Solv
     float einc[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) einc[k] = (float)batch_incident(d, n + k);
-    multi_step_wave<NeqT, V, H, HX, S>(d.L, d.state[d.cur], d.state[d.cur ^ 1], einc, t.tx, t.ty);
+    multi_step_wave<NeqT, V, H, HX, S, false>(d.L, d.state[d.cur], d.state[d.cur ^ 1], einc, nullptr, 0, t.tx, t.ty);
 }
 
 // ---------------------------------------------------------------------------
@@ -1375,6 +1397,18 @@ __global__ void k_contour2_f32(Lattice L, const float *__restrict__ mid, const f
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < C.n) {
         contour_sample_f32(L, mid, 3 * L.plane, C, k);
+        contour_sample_f32(L, fld, L.sfld, C, k);
+    }
+}
+
+// After a multi-step launch inside the window: levels n + 1 .. n + S - 1 from
+// mid (mid_level floats apart), then level n + S from the state, in time order.
+__global__ void k_contourm_f32(Lattice L, const float *__restrict__ mid, size_t mid_level, int nmid,
+                               const float *__restrict__ fld, ContourDev C)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < C.n) {
+        for (int m = 0; m < nmid; ++m) contour_sample_f32(L, mid + (size_t)m * mid_level, 3 * L.plane, C, k);
         contour_sample_f32(L, fld, L.sfld, C, k);
     }
 }
@@ -1789,33 +1823,26 @@ hipError_t launch_step2_batch(int precision, int variant, SolveDesc *d, const Ti
     return hipGetLastError();
 }
 
-// Variant table of the multi-step kernels: depth S, rows H, wavefronts W.
+// Variant table of the multi-step kernels: depth S, rows H, halo columns HX,
+// wavefronts per SIMD W.
 template <typename F> static void multi_step_dispatch(int variant, F &&go)
 {
     using I1 = std::integral_constant<int, 1>;
-    using X8 = std::integral_constant<int, 8>;
     using X4 = std::integral_constant<int, 4>;
+    using X8 = std::integral_constant<int, 8>;
     using S3 = std::integral_constant<int, 3>;
     using S4 = std::integral_constant<int, 4>;
     using W2 = std::integral_constant<int, 2>;
-    using W3 = std::integral_constant<int, 3>;
-    using H8 = std::integral_constant<int, 8>;
     using H10 = std::integral_constant<int, 10>;
     using H12 = std::integral_constant<int, 12>;
     using H16 = std::integral_constant<int, 16>;
     switch (variant) {
-    case MULTI_S3_H8: go(I1{}, H8{}, X8{}, S3{}, W2{}); break;
-    case MULTI_S3_H12: go(I1{}, H12{}, X8{}, S3{}, W2{}); break;
-    case MULTI_S3_H16: go(I1{}, H16{}, X8{}, S3{}, W2{}); break;
-    case MULTI_S3_H8_W3: go(I1{}, H8{}, X8{}, S3{}, W3{}); break;
-    case MULTI_S4_H8: go(I1{}, H8{}, X8{}, S4{}, W2{}); break;
-    case MULTI_S4_H12: go(I1{}, H12{}, X8{}, S4{}, W2{}); break;
-    case MULTI_S4_H16: go(I1{}, H16{}, X8{}, S4{}, W2{}); break;
+    case MULTI_S4_H10_X4: go(I1{}, H10{}, X4{}, S4{}, W2{}); break;
     case MULTI_S4_H12_X4: go(I1{}, H12{}, X4{}, S4{}, W2{}); break;
     case MULTI_S4_H16_X4: go(I1{}, H16{}, X4{}, S4{}, W2{}); break;
+    case MULTI_S3_H10_X4: go(I1{}, H10{}, X4{}, S3{}, W2{}); break;
     case MULTI_S3_H12_X4: go(I1{}, H12{}, X4{}, S3{}, W2{}); break;
-    case MULTI_S4_H10_X4: go(I1{}, H10{}, X4{}, S4{}, W2{}); break;
-    default: go(I1{}, H10{}, X4{}, S3{}, W2{}); break;
+    default: go(I1{}, H12{}, X8{}, S4{}, W2{}); break;
     }
 }
 
@@ -1837,7 +1864,7 @@ void multi_step_shape(int variant, int &depth, int &rows)
 }
 
 hipError_t launch_stepm_neq(int precision, const Lattice &L, const void *src, void *dst, const double *einc,
-                            hipStream_t s, int variant)
+                            float *mid, size_t mid_level, hipStream_t s, int variant)
 {
     auto run = [&](auto tag) {
         typedef decltype(tag) T;
@@ -1850,8 +1877,12 @@ hipError_t launch_stepm_neq(int precision, const Lattice &L, const void *src, vo
             const int nsx = (L.nx + two_step_width<V, HX>() - 1) / two_step_width<V, HX>();
             const int nsy = (L.ny + H - 1) / H;
             const int blocks = (nsx * nsy + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
-            hipLaunchKernelGGL((k_stepm_neq<T, V, H, HX, S, W>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s, L, src,
-                               dst, e, nsx, nsy);
+            if (mid)
+                hipLaunchKernelGGL((k_stepm_neq<T, V, H, HX, S, W, true>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0,
+                                   s, L, src, dst, e, mid, mid_level, nsx, nsy);
+            else
+                hipLaunchKernelGGL((k_stepm_neq<T, V, H, HX, S, W, false>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0,
+                                   s, L, src, dst, e, nullptr, (size_t)0, nsx, nsy);
         });
     };
     if (precision == 1) run(float{});
@@ -1869,8 +1900,10 @@ hipError_t launch_stepm_batch(int precision, int variant, SolveDesc *d, const Ti
         multi_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag, auto stag, auto wtag) {
             constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
             constexpr int S = decltype(stag)::value, W = decltype(wtag)::value;
-            hipLaunchKernelGGL((k_stepm_neq_batch<T, V, H, HX, S, W>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0, s,
-                               d, items, nitems, remap);
+            // the engine steps in rounds of four
+            if constexpr (S == 4)
+                hipLaunchKernelGGL((k_stepm_neq_batch<T, V, H, HX, S, W>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0,
+                                   s, d, items, nitems, remap);
         });
     };
     if (precision == 1) run(float{});
@@ -1894,6 +1927,16 @@ hipError_t launch_contour2(const Lattice &L, const float *mid, const void *state
     const int threads = 128;
     const int blocks = (C.n + threads - 1) / threads;
     hipLaunchKernelGGL(k_contour2_f32, dim3(blocks), dim3(threads), 0, s, L, mid, (const float *)state, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_contourm(const Lattice &L, const float *mid, size_t mid_level, int nmid, const void *state,
+                           const ContourDev &C, hipStream_t s)
+{
+    const int threads = 128;
+    const int blocks = (C.n + threads - 1) / threads;
+    hipLaunchKernelGGL(k_contourm_f32, dim3(blocks), dim3(threads), 0, s, L, mid, mid_level, nmid,
+                       (const float *)state, C);
     return hipGetLastError();
 }
 

@@ -140,7 +140,9 @@ int make_plan(const jlb_problem *p, Plan *pl)
     q.off_fields = p->precision == JLB_FP64 ? take(2 * 3 * q.plane * sizeof(double)) : 0;
     // FP32 / BF16: fields at the middle level of a two-step launch, written
     // only at the contour-stencil nodes
-    q.off_mid = p->precision == JLB_FP64 ? 0 : take((size_t)3 * q.pitch * q.ny * sizeof(float));
+    // contour-stencil fields of up to three intermediate levels (a four-step
+    // launch inside the window; a two-step launch uses the first)
+    q.off_mid = p->precision == JLB_FP64 ? 0 : take((size_t)3 * 3 * q.pitch * q.ny * sizeof(float));
     q.off_mask = take((size_t)q.ny * q.pitch);
     q.off_i0 = take(q.nc * sizeof(int));
     q.off_j0 = take(q.nc * sizeof(int));
@@ -425,7 +427,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     const int64_t chunk = q.T % 4 == 0 ? q.T : q.T % 2 == 0 ? 2 * q.T : 4 * q.T;
     // two-step kernels: FP32 / BF16
     const int two = q.prob.precision == JLB_FP64 ? -1 : two_step_variant(q.prob.precision);
-    // multi-step kernels (depth S) outside the window: chunk / S launches
+    // multi-step kernels (depth S) for the captured chunks: chunk / S launches
     // must be a whole, even number (the chunk then leaves state n in buffer
     // n % 2), and a row segment must not reach both the bottom and the top row
     int multi = q.prob.precision == JLB_FP64 ? -1 : multi_step_variant(q.prob.precision);
@@ -472,14 +474,21 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     auto capture = [&](int which, int64_t n0) -> int {
         hipGraph_t g;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        if (which == 0 && multi >= 0) {
-            // launch m takes state n0 + S m from buffer (n0 + m) % 2 to the other one
+        if (multi >= 0) {
+            // launch m takes state n0 + S m from buffer (n0 + m) % 2 to the
+            // other one; inside the window it also leaves the contour-stencil
+            // fields of levels n0 + S m + 1 .. + S - 1 in mid, and all S levels
+            // are accumulated after it
+            float *mid = (float *)(ws + q.off_mid);
+            const size_t mid_level = (size_t)3 * q.pitch * q.ny;
             for (int64_t m = 0; m < chunk / depth; ++m) {
                 const int64_t n = n0 + depth * m;
                 double einc[4];
                 for (int k = 0; k < depth; ++k) einc[k] = incident(q, n + k);
-                hipError_t e = launch_stepm_neq(q.prob.precision, L, ws + q.off_state[(n0 + m) & 1],
-                                                ws + q.off_state[(n0 + m + 1) & 1], einc, s, multi);
+                void *dst = ws + q.off_state[(n0 + m + 1) & 1];
+                hipError_t e = launch_stepm_neq(q.prob.precision, L, ws + q.off_state[(n0 + m) & 1], dst, einc,
+                                                which == 1 ? mid : nullptr, mid_level, s, multi);
+                if (e == hipSuccess && which == 1) e = launch_contourm(L, mid, mid_level, depth - 1, dst, C, s);
                 if (e != hipSuccess) {
                     hipGraph_t dummy;
                     (void)hipStreamEndCapture(s, &dummy);
@@ -554,7 +563,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             }
             if (which == 0) main_launches += main_per_chunk;
             graph_used = 1;
-            passes += which == 0 && multi >= 0 ? chunk / depth : two >= 0 ? chunk / 2 : chunk;
+            passes += multi >= 0 ? chunk / depth : two >= 0 ? chunk / 2 : chunk;
             n += chunk;
             if (!in_window && check_level(n)) rc = plateau_check(n);
             continue;
@@ -569,7 +578,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
                 double einc[4];
                 for (int j = 0; j < depth; ++j) einc[j] = incident(q, m + j);
                 hipError_t e = launch_stepm_neq(q.prob.precision, L, ws + q.off_state[(n + k) & 1],
-                                                ws + q.off_state[(n + k + 1) & 1], einc, s, multi);
+                                                ws + q.off_state[(n + k + 1) & 1], einc, nullptr, 0, s, multi);
                 if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "multi-step launch: %s", hipGetErrorString(e));
             }
             passes += 2;
@@ -816,7 +825,7 @@ static int time_step_kernel(const jlb_problem *prob, void *workspace, size_t wor
             multi_step_shape(variant, depth, rows);
             double einc[4];
             for (int k = 0; k < depth; ++k) einc[k] = incident(q, depth * n + k);
-            e = launch_stepm_neq(q.prob.precision, L, src, dst, einc, own, variant);
+            e = launch_stepm_neq(q.prob.precision, L, src, dst, einc, nullptr, 0, own, variant);
         } else if (kind == 2) {
             e = launch_step2_neq(q.prob.precision, L, src, dst, incident(q, 2 * n), incident(q, 2 * n + 1), nullptr, own,
                                  variant);

@@ -117,25 +117,25 @@ hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, vo
                             float *mid, hipStream_t s, int variant);
 // S steps per launch (FP32 / BF16, S = 3 or 4 by variant): state n in src ->
 // state n + S in dst (src and dst must differ); einc[0..S-1] are the source
-// values of steps n .. n + S - 1.  No contour fields: for steps outside the
-// averaging window.  Launches need ny >= rows + S.
+// values of steps n .. n + S - 1.  Launches need ny >= rows + S.
 enum MultiStepVariant {
-    MULTI_S3_H8 = 0,
-    MULTI_S3_H12 = 1,
-    MULTI_S3_H16 = 2,
-    MULTI_S3_H8_W3 = 3,  // registers held to three wavefronts per SIMD (spills)
-    MULTI_S4_H8 = 4,
-    MULTI_S4_H12 = 5,
-    MULTI_S4_H16 = 6,
-    MULTI_S4_H12_X4 = 7,  // 4 halo columns per side: 56 output columns per strip
-    MULTI_S4_H16_X4 = 8,
-    MULTI_S3_H12_X4 = 9,
-    MULTI_S4_H10_X4 = 10,
-    MULTI_S3_H10_X4 = 11,
-    MULTI_STEP_VARIANTS = 12
+    MULTI_S4_H10_X4 = 0,  // X4: 4 halo columns per side, 56 output columns per strip
+    MULTI_S4_H12_X4 = 1,
+    MULTI_S4_H16_X4 = 2,
+    MULTI_S3_H10_X4 = 3,
+    MULTI_S3_H12_X4 = 4,
+    MULTI_S4_H12_X8 = 5,  // X8: 48 output columns per strip
+    MULTI_STEP_VARIANTS = 6
 };
+// mid (inside the window, else null): the fields at n + 1 .. n + S - 1 of the
+// contour-stencil nodes, one block of 3 row-interleaved float planes (row
+// stride 3 pitch) every mid_level floats.
 hipError_t launch_stepm_neq(int precision, const Lattice &L, const void *src, void *dst, const double *einc,
-                            hipStream_t s, int variant);
+                            float *mid, size_t mid_level, hipStream_t s, int variant);
+// Contour accumulation of the levels of a multi-step launch: nmid levels from
+// mid, then the state's.
+hipError_t launch_contourm(const Lattice &L, const float *mid, size_t mid_level, int nmid, const void *state,
+                           const ContourDev &C, hipStream_t s);
 void multi_step_shape(int variant, int &depth, int &rows);
 // Strip and segment counts of a multi-step variant for an nx x ny lattice.
 void multi_step_grid(int variant, int nx, int ny, int &nsx, int &nsy);

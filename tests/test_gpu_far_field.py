@@ -70,8 +70,9 @@ def test_far_field_matches_the_oracle(jlb, refs, precision, case):
 
 
 def test_far_field_after_multi_step_kernels(jlb, refs):
-    """Periods before the window on the four-step kernel, the window on the
-    two-step kernel, the last period on single steps."""
+    """The periods before the window and the window up to its last period on
+    the four-step kernel (with the intermediate levels' contour fields), the
+    last period on single steps."""
     prec = jlb.PRECISIONS["fp32"]
     before, multi0 = jlb.jlb_get_two_step_variant(prec), jlb.jlb_get_multi_step_variant(prec)
     try:

@@ -228,12 +228,12 @@ def test_two_step_kernels_equal_single_steps(jlb, precision, polarization):
 @pytest.mark.parametrize("polarization", ["tm", "te"])
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_multi_step_kernels_equal_single_steps(jlb, precision, polarization):
-    """Three or four levels in flight per sweep: solves whose periods before
-    the window run on any multi-step variant (the window on the two-step
-    kernel or on single steps) equal the single-step solve bit for bit,
-    fields and forces; grids from ny = 20 (the shortest a four-step H16
-    segment allows) to wide ragged strips, conductor links, all edges, the
-    companion row."""
+    """Three or four levels in flight per sweep: solves that run on any
+    multi-step variant (the window too, with the intermediate levels'
+    contour fields) equal the single-step solve bit for bit, fields and
+    forces, whatever the two-step choice; grids from ny = 20 (the shortest a
+    four-step H16 segment allows) to wide ragged strips, conductor links,
+    all edges, the companion row."""
     prec = jlb.PRECISIONS[precision]
     two0, multi0 = jlb.jlb_get_two_step_variant(prec), jlb.jlb_get_multi_step_variant(prec)
     cases = [W.problem(nx=203, ny=150, radius=20.0, kind="metallo_dielectric_janus", eps1=3.0, phi0_deg=110.0,
@@ -259,8 +259,8 @@ def test_multi_step_kernels_equal_single_steps(jlb, precision, polarization):
                     o = jlb.solve(p, precision, fields=True)
                     assert o["graph_used"] == 1 and o["state_passes"] < p["steps"] * 0.6, (v, o["state_passes"])
                     depth, _ = jlb.jlb_multi_step_shape(v)
-                    # ramp and the periods before the window on multi-step launches
-                    assert o["state_passes"] == 600 // depth + (120 if two < 0 else 60), o["state_passes"]
+                    # ramp, the periods before the window and the window on multi-step launches
+                    assert o["state_passes"] == 720 // depth, o["state_passes"]
                     for q in ("fx", "fy", "tz"):
                         assert o[q] == ref[q], (v, two, q, o[q], ref[q])
                     for f in ("ez", "hx", "hy"):
