@@ -257,7 +257,9 @@ def _kernel_choice(jlb, prec: str) -> dict:
     two, multi = jlb.jlb_get_two_step_variant(p), jlb.jlb_get_multi_step_variant(p)
     return {"single_step": jlb.STEP_VARIANTS.get(jlb.jlb_get_step_variant(p)),
             "two_step": jlb.TWO_STEP_VARIANTS.get(two) if two >= 0 else None,
-            "multi_step": jlb.MULTI_STEP_VARIANTS.get(multi) if multi >= 0 else None}
+            "multi_step": jlb.MULTI_STEP_VARIANTS.get(multi) if multi >= 0 else None,
+            "engine_rounds": ("four-step H16 X4 before each solve's window, two-step after" if two >= 0
+                              else "single steps")}
 
 
 def run_designmap(args):

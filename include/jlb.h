@@ -344,8 +344,8 @@ int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t wo
  * accumulated after it, in time order), and the ramp and the steps before
  * the window's first chunk as pairs of launches, provided the chunk is a
  * multiple of 2 S steps and ny >= rows + S; otherwise the solve runs as
- * without it.  The engine runs rounds of four steps with variant 2 whenever
- * a variant is selected.  Variants (depth S, rows per wavefront, halo
+ * without it.  The engine has its own switch (jlb_engine_set_four_step).
+ * Variants (depth S, rows per wavefront, halo
  * columns per side: 56 output columns per 64-lane strip with X4, 48 with
  * X8; registers for two wavefronts per SIMD): 0 S4 H10 X4, 1 S4 H12 X4,
  * 2 S4 H16 X4, 3 S3 H10 X4, 4 S3 H12 X4, 5 S4 H12 X8.  jlb_multi_step_shape
@@ -433,6 +433,16 @@ int jlb_engine_stats(jlb_engine *eng, int32_t *queued, int32_t *resident, int32_
 #define JLB_POLICY_FIFO 0
 #define JLB_POLICY_SJF 1
 int jlb_engine_set_policy(jlb_engine *eng, int32_t policy, int32_t max_slots);
+/*
+ * Four-step rounds (on by default): with `on`, the engine's FP32 / BF16
+ * solves that use two-step kernels take one batched four-step launch
+ * (multi-step variant 2, S4 H16 X4) per round of four steps while their next
+ * four levels lie before their averaging window; with many solves resident
+ * that variant has the least halo work per update, whatever jlb_autotune
+ * chose for a single solve.  Results are the same bits either way.  Takes
+ * effect at the next chunk.  JLB_E_ARG for a null engine.
+ */
+int jlb_engine_set_four_step(jlb_engine *eng, int32_t on);
 
 /* Releases every resource of the engine. */
 int jlb_engine_destroy(jlb_engine *eng);

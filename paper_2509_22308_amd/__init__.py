@@ -114,6 +114,7 @@ def load():
                                   _P(ctypes.c_size_t)], ctypes.c_int),
             "jlb_engine_destroy": ([_vp], ctypes.c_int),
             "jlb_engine_set_policy": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+            "jlb_engine_set_four_step": ([_vp, ctypes.c_int32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -384,6 +385,10 @@ class Engine:
     def set_policy(self, policy: str = "fifo", max_slots: int = 0):
         """Admission order ("fifo" or "sjf": smallest work first) and, when > 0, a new slot count."""
         _check(load().jlb_engine_set_policy(self._h, self.POLICIES[policy], int(max_slots)))
+
+    def set_four_step(self, on: bool):
+        """Four-step rounds for the two-step solves (on by default)."""
+        _check(load().jlb_engine_set_four_step(self._h, int(bool(on))))
 
     def stats(self) -> dict:
         q, r, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

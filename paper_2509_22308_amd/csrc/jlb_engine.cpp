@@ -98,6 +98,7 @@ struct jlb_engine {
     // per resident solve (in resident order), the launches the captured
     // chunk holds items for: 1 two-step, 2 four-step, 3 both
     std::vector<uint8_t> part;
+    bool four_step = true;  // four-step rounds for two-step solves
     int max_nc = 0;
     int remap = 0;
     bool dirty = true;
@@ -110,13 +111,13 @@ namespace {
 
 // The engine steps in rounds of four, and with many solves resident its
 // launches hold far more wavefronts than the device runs at once, so the
-// halo work per update decides: whenever multi-step kernels are selected it
-// takes the four-step variant with the least of it (16-row segments, 4 halo
-// columns).  The autotuner's choice, made on one solve's grid, is about
-// latency instead.
-int engine_multi_variant(int v)
+// halo work per update decides: it takes the four-step variant with the
+// least of it (16-row segments, 4 halo columns).  The autotuner's multi-step
+// choice, made on one solve's grid, is about latency instead and does not
+// apply here.
+int engine_multi_variant(bool on)
 {
-    return v < 0 ? -1 : MULTI_S4_H16_X4;
+    return on ? MULTI_S4_H16_X4 : -1;
 }
 
 // Which batched launches a resident solve needs over the next chunk of
@@ -274,7 +275,7 @@ int rebuild(jlb_engine *e)
     for (int p = 0; p < 3; ++p) {
         e->variant[p] = jlb::step_variant(p);
         e->two[p] = p == JLB_FP64 ? -1 : jlb::two_step_variant(p);
-        e->multi[p] = e->two[p] >= 0 ? engine_multi_variant(jlb::multi_step_variant(p)) : -1;
+        e->multi[p] = e->two[p] >= 0 ? engine_multi_variant(e->four_step) : -1;
     }
     e->any_single = e->any_two = e->any_multi = false;
     e->part.assign(ns, 0);
@@ -675,6 +676,17 @@ int jlb_engine_cancel(jlb_engine *e, uint64_t ticket)
         return fail(JLB_E_STATE, "ticket %llu already finished", (unsigned long long)ticket);
     }
     r.status = JLB_REQ_CANCELLED;
+    return JLB_OK;
+}
+
+int jlb_engine_set_four_step(jlb_engine *e, int32_t on)
+{
+    clear_error();
+    if (!e) return fail(JLB_E_ARG, "null engine");
+    if (e->four_step != (on != 0)) {
+        e->four_step = on != 0;
+        e->dirty = true;
+    }
     return JLB_OK;
 }
 

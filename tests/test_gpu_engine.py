@@ -41,8 +41,9 @@ def _mix():
     ]
 
 
-def _run_engine(jlb, probs, budget=8 << 30, slots=64, chunk=300):
+def _run_engine(jlb, probs, budget=8 << 30, slots=64, chunk=300, four=True):
     eng = jlb.Engine(budget, slots)
+    eng.set_four_step(four)
     tickets = [eng.submit(p) for p in probs]
     out = {}
     for _ in range(10000):
@@ -151,16 +152,16 @@ def test_two_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, precisi
             assert s[q] == b[q], (precision, variant, q, s[q], b[q])
 
 
-@pytest.mark.parametrize("multi", [1, -1])
+@pytest.mark.parametrize("four", [True, False])
 @pytest.mark.parametrize("chunk", [256, 130])
-def test_four_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, multi, chunk):
+def test_four_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, four, chunk):
     """Rounds of four steps: solves whose next four levels lie before their
     window take one batched four-step launch, the others two double steps;
     every solve at its own step.  A run of 130 steps ends on a lone double
     step in which the four-step solves wait.  A grid too short for the
     variant (ny = 19) stays on two-step launches.  Each result equals its
-    single solve bit for bit, with the four-step launches on (any selected
-    variant gives the engine's four-step H16 X4) and off."""
+    single solve bit for bit, with the engine's four-step rounds on and off
+    (and single solves on no multi-step kernels)."""
     prec = jlb.PRECISIONS["fp32"]
     multi0 = jlb.jlb_get_multi_step_variant(prec)
     probs = _mix() + [W.problem(nx=64, ny=19, radius=3.0, kind="dielectric_janus", eps1=2.0, eps2=3.0,
@@ -170,13 +171,12 @@ def test_four_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, multi,
         jlb.jlb_set_multi_step_variant(prec, -1)
         single = [jlb.solve(p, "fp32") for p in probs]
         two_step(4)
-        jlb.jlb_set_multi_step_variant(prec, multi)
-        batched = _run_engine(jlb, [jlb.make_problem(p, "fp32") for p in probs], chunk=chunk)
+        batched = _run_engine(jlb, [jlb.make_problem(p, "fp32") for p in probs], chunk=chunk, four=four)
     finally:
         jlb.jlb_set_multi_step_variant(prec, multi0)
     for s, b in zip(single, batched):
         for q in ("fx", "fy", "tz", "energy_final"):
-            assert s[q] == b[q], (multi, chunk, q, s[q], b[q])
+            assert s[q] == b[q], (four, chunk, q, s[q], b[q])
         assert b["steps_done"] == s["steps_done"]
 
 
