@@ -347,15 +347,15 @@ int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t wo
  * without it.  The engine has its own switch (jlb_engine_set_four_step).
  * Variants (depth S, rows per wavefront, halo
  * columns per side: 56 output columns per 64-lane strip with X4, 48 with
- * X8; registers for two wavefronts per SIMD): 0 S4 H10 X4, 1 S4 H12 X4,
- * 2 S4 H16 X4, 3 S3 H10 X4, 4 S3 H12 X4, 5 S4 H12 X8.  jlb_multi_step_shape
+ * X8): 0 S4 H10 X4, 1 S4 H12 X4, 2 S4 H16 X4, 3 S3 H10 X4, 4 S3 H12 X4,
+ * 5 S4 H12 X8, 6 S3 H7 X4, 7 S3 H8 X4.  jlb_multi_step_shape
  * reports S and the rows of a variant.  Default: 0 (set -1 for none);
  * jlb_autotune selects one when it beats the other kernels per lattice step.
  * jlb_time_multi_step_kernel: mean time of one launch (S lattice steps) of
  * the selected variant, as jlb_time_step_kernel; JLB_E_ARG for FP64, when
  * none is selected or when ny < rows + S.
  */
-#define JLB_MULTI_STEP_VARIANTS 6
+#define JLB_MULTI_STEP_VARIANTS 8
 int jlb_set_multi_step_variant(int32_t precision, int32_t variant);
 int jlb_get_multi_step_variant(int32_t precision, int32_t *variant);
 int jlb_multi_step_shape(int32_t variant, int32_t *depth, int32_t *rows);

@@ -233,7 +233,8 @@ TWO_STEP_VARIANTS = {0: "two-step V1 H8 X2", 1: "two-step V1 H16 X2", 2: "two-st
                      6: "two-step V2 H32 X8", 7: "two-step V1 H8 X8 LA2", 8: "two-step V1 H4 X8 LA2",
                      9: "two-step V1 H16 X8 LA2"}
 MULTI_STEP_VARIANTS = {0: "four-step H10 X4", 1: "four-step H12 X4", 2: "four-step H16 X4",
-                       3: "three-step H10 X4", 4: "three-step H12 X4", 5: "four-step H12 X8"}
+                       3: "three-step H10 X4", 4: "three-step H12 X4", 5: "four-step H12 X8",
+                       6: "three-step H7 X4", 7: "three-step H8 X4"}
 
 
 def variant_name(precision, best: int) -> str:

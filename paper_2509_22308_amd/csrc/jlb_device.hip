@@ -306,14 +306,48 @@ __device__ __forceinline__ Coef coef_of(const Lattice &L, float inv_eps, float e
     return L.te ? Coef{1.0f, inv_eps, THIRD, eps_rest, 1.0f} : coef_tm(inv_eps, eps_rest);
 }
 
-// One node's update from its own data and the four sides.  Sides are read
-// only where the pull crosses an interior, non-conductor link.  `inc_lo` /
-// `inc_hi` hold the incident-wave companion node of the same column
-// (fields + N_{e+y}, N_{hy+y} / N_{e-y}, N_{hy-y}) for the bottom / top rows.
-template <bool STRIP>
-__device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t m, const Coef &k,
-                                         const NodeData &o, const Side &l, const Side &r, const Side &b, const Side &t,
-                                         const Side &inc_lo, const Side &inc_hi, float einc, NodeData &out)
+// The post-collision pair a node sends along an axis: the e population and
+// the h population of that direction, f* = f^eq - N.  "up" is what the row
+// above pulls (+y), "down" what the row below pulls (-y), "east" what the
+// node to the right pulls (+x), "west" what the node to the left pulls (-x).
+struct Pair {
+    float e, h;
+};
+__device__ __forceinline__ float up_e(const Side &s)
+{
+#pragma clang fp contract(off)
+    return (s.ez + s.hx) * SIXTH - s.na;
+}
+__device__ __forceinline__ float up_h(const Side &s)
+{
+#pragma clang fp contract(off)
+    return s.hy * SIXTH - s.nb;
+}
+__device__ __forceinline__ float down_e(const Side &s)
+{
+#pragma clang fp contract(off)
+    return (s.ez - s.hx) * SIXTH - s.na;
+}
+__device__ __forceinline__ float down_h(const Side &s)
+{
+#pragma clang fp contract(off)
+    return s.hy * SIXTH - s.nb;
+}
+__device__ __forceinline__ float up_e(const Pair &p) { return p.e; }
+__device__ __forceinline__ float up_h(const Pair &p) { return p.h; }
+__device__ __forceinline__ float down_e(const Pair &p) { return p.e; }
+__device__ __forceinline__ float down_h(const Pair &p) { return p.h; }
+
+// One node's update from its own data and the populations pulled across its
+// four links (interior values; edges, conductor links and the companion row
+// replace some of them here).  `inc_lo` / `inc_hi` stand for the incident-wave
+// companion node of the same column, as a Side (fields + N_{e+y}, N_{hy+y} /
+// N_{e-y}, N_{hy-y}) or as its up / down Pair, for the bottom / top rows.
+template <bool STRIP, typename Inc>
+__device__ __forceinline__ void neq_pulled(const Lattice &L, int i, int j, uint8_t m, const Coef &k,
+                                           const NodeData &o, float e_px, float hx_px, float e_mx, float hx_mx,
+                                           float e_py, float hy_py, float e_my, float hy_my, const Inc &inc_lo,
+                                           const Inc &inc_hi, float einc, NodeData &out)
 {
     // no FMA contraction: every kernel variant that inlines this core must
     // round the same operations the same way
@@ -325,12 +359,7 @@ __device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t
     const float r_hx = o.hx * k.cxy + (o.n[N_HXPX] + o.n[N_HXMX] + o.n[N_EPY] - o.n[N_EMY]);
     const float r_hy = o.hy * k.cxy + (o.n[N_HYPY] + o.n[N_HYMY] - o.n[N_EPX] + o.n[N_EMX]);
 
-    // pulls across interior links: the neighbour's post-collision population
-    float e_px = (l.ez - l.hy) * SIXTH - l.na, hx_px = l.hx * SIXTH - l.nb;  // +x from (i-1, j)
-    float e_mx = (r.ez + r.hy) * SIXTH - r.na, hx_mx = r.hx * SIXTH - r.nb;  // -x from (i+1, j)
-    float e_py = (b.ez + b.hx) * SIXTH - b.na, hy_py = b.hy * SIXTH - b.nb;  // +y from (i, j-1)
-    float e_my = (t.ez - t.hx) * SIXTH - t.na, hy_my = t.hy * SIXTH - t.nb;  // -y from (i, j+1)
-    // edges, conductor links and the companion row replace some of them
+    // edges, conductor links and the companion row replace some pulls
     // (most wavefronts have no such node and skip this block)
     if (STRIP || i == 0 || i == L.nx - 1 || j == 0 || j == L.ny - 1 ||
         (m & (NB_PEC_XM | NB_PEC_XP | NB_PEC_YM | NB_PEC_YP))) {
@@ -354,12 +383,12 @@ __device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t
             e_py = s_epy; hy_py = s_hypy; e_my = s_emy; hy_my = s_hymy;
         } else {
             if (j == 0) {
-                e_py = keep * s_epy + delta * ((inc_lo.ez + inc_lo.hx) * SIXTH - inc_lo.na);
-                hy_py = keep * s_hypy + delta * (inc_lo.hy * SIXTH - inc_lo.nb);
+                e_py = keep * s_epy + delta * up_e(inc_lo);
+                hy_py = keep * s_hypy + delta * up_h(inc_lo);
             } else if (m & NB_PEC_YM) { e_py = k.wall * s_emy; hy_py = k.wall * s_hymy; }
             if (j == L.ny - 1) {
-                e_my = keep * s_emy + delta * ((inc_hi.ez - inc_hi.hx) * SIXTH - inc_hi.na);
-                hy_my = keep * s_hymy + delta * (inc_hi.hy * SIXTH - inc_hi.nb);
+                e_my = keep * s_emy + delta * down_e(inc_hi);
+                hy_my = keep * s_hymy + delta * down_h(inc_hi);
             } else if (m & NB_PEC_YP) { e_my = k.wall * s_epy; hy_my = k.wall * s_hypy; }
         }
     }
@@ -379,6 +408,22 @@ __device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t
     out.n[N_HXMX] = hx_mx - hx * SIXTH;
     out.n[N_HYPY] = hy_py - hy * SIXTH;
     out.n[N_HYMY] = hy_my - hy * SIXTH;
+}
+
+// One node's update from its own data and the four sides (fields and the two
+// deviations of the populations it pulls): the interior pulls, then the core.
+template <bool STRIP>
+__device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t m, const Coef &k,
+                                         const NodeData &o, const Side &l, const Side &r, const Side &b, const Side &t,
+                                         const Side &inc_lo, const Side &inc_hi, float einc, NodeData &out)
+{
+#pragma clang fp contract(off)
+    // pulls across interior links: the neighbour's post-collision population
+    const float e_px = (l.ez - l.hy) * SIXTH - l.na, hx_px = l.hx * SIXTH - l.nb;  // +x from (i-1, j)
+    const float e_mx = (r.ez + r.hy) * SIXTH - r.na, hx_mx = r.hx * SIXTH - r.nb;  // -x from (i+1, j)
+    const float e_py = up_e(b), hy_py = up_h(b);                                    // +y from (i, j-1)
+    const float e_my = down_e(t), hy_my = down_h(t);                                // -y from (i, j+1)
+    neq_pulled<STRIP>(L, i, j, m, k, o, e_px, hx_px, e_mx, hx_mx, e_py, hy_py, e_my, hy_my, inc_lo, inc_hi, einc, out);
 }
 
 template <typename NeqT>
@@ -715,37 +760,41 @@ __global__ __launch_bounds__(CX *R) void k_step_neq_vtile(Lattice L, const void 
 
 template <typename NeqT> __device__ __forceinline__ float rt(float x) { return (float)(NeqT)x; }
 
+// What the rows next to a row pull from it: per node, the post-collision
+// pair (e, h) it sends up (+y: N_{e+y}, N_{hy+y}) or down (-y: N_{e-y},
+// N_{hy-y}), computed once per row instead of per pulling node.
 template <int V>
 struct SideRow {
-    float ez[V], hx[V], hy[V], na[V], nb[V];
+    float e[V], h[V];
 };
 
+// qa / qb: N_EPY, N_HYPY for the pair sent up; N_EMY, N_HYMY for the pair
+// sent down (compile-time constants at every call).
 template <int V>
 __device__ __forceinline__ SideRow<V> side_of(const RowData<V> &r, int qa, int qb)
 {
+#pragma clang fp contract(off)
     SideRow<V> s;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        s.ez[v] = r.ez[v];
-        s.hx[v] = r.hx[v];
-        s.hy[v] = r.hy[v];
-        s.na[v] = r.n[qa][v];
-        s.nb[v] = r.n[qb][v];
+        const Side d{r.ez[v], r.hx[v], r.hy[v], r.n[qa][v], r.n[qb][v]};
+        s.e[v] = qa == N_EPY ? up_e(d) : down_e(d);
+        s.h[v] = qa == N_EPY ? up_h(d) : down_h(d);
     }
     return s;
 }
 
-// Companion-row values rows 0 and ny - 1 pull from.
+// Companion-row pairs rows 0 and ny - 1 pull from: lo = sent up, hi = sent down.
 template <int V>
 struct StripSides {
     SideRow<V> lo, hi;
 };
 
-// One row's update from its own data (row r), the rows below and above (as
-// sides), the x-neighbours across lanes, and the companion row.  Every node
-// of the row is updated without branching on its kind: for nodes that hold
-// nothing (conductors, padding, rows or columns outside the domain) the
-// result is a finite value that no valid node ever reads -- a valid node
+// One row's update from its own data (row r), the pairs the rows below and
+// above send it, the x-neighbours across lanes, and the companion row.
+// Every node of the row is updated without branching on its kind: for nodes
+// that hold nothing (conductors, padding, rows or columns outside the domain)
+// the result is a finite value that no valid node ever reads -- a valid node
 // next to such a node takes an edge or conductor rule instead -- and
 // store_row_masked writes zeros for them.
 template <typename NeqT, int V, bool STRIP>
@@ -753,17 +802,18 @@ __device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, type
                                            const RowData<V> &cur, const SideRow<V> &below, const SideRow<V> &above,
                                            const StripSides<V> &inc, float einc, RowData<V> &out)
 {
-    Side xl, xr;
-    xl.ez = from_left(cur.ez[V - 1]);
-    xl.hx = from_left(cur.hx[V - 1]);
-    xl.hy = from_left(cur.hy[V - 1]);
-    xl.na = from_left(cur.n[N_EPX][V - 1]);
-    xl.nb = from_left(cur.n[N_HXPX][V - 1]);
-    xr.ez = from_right(cur.ez[0]);
-    xr.hx = from_right(cur.hx[0]);
-    xr.hy = from_right(cur.hy[0]);
-    xr.na = from_right(cur.n[N_EMX][0]);
-    xr.nb = from_right(cur.n[N_HXMX][0]);
+#pragma clang fp contract(off)
+    // the pairs each node sends east (+x) and west (-x)
+    float ee[V], eh[V], we[V], wh[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        ee[v] = (cur.ez[v] - cur.hy[v]) * SIXTH - cur.n[N_EPX][v];
+        eh[v] = cur.hx[v] * SIXTH - cur.n[N_HXPX][v];
+        we[v] = (cur.ez[v] + cur.hy[v]) * SIXTH - cur.n[N_EMX][v];
+        wh[v] = cur.hx[v] * SIXTH - cur.n[N_HXMX][v];
+    }
+    const float xl_e = from_left(ee[V - 1]), xl_h = from_left(eh[V - 1]);
+    const float xr_e = from_right(we[0]), xr_h = from_right(wh[0]);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const int i = i0 + v;
@@ -781,14 +831,12 @@ __device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, type
         o.hy = cur.hy[v];
 #pragma unroll
         for (int q = 0; q < 8; ++q) o.n[q] = cur.n[q][v];
-        const Side l = v == 0 ? xl : Side{cur.ez[v - 1], cur.hx[v - 1], cur.hy[v - 1], cur.n[N_EPX][v - 1], cur.n[N_HXPX][v - 1]};
-        const Side rr = v == V - 1 ? xr : Side{cur.ez[v + 1], cur.hx[v + 1], cur.hy[v + 1], cur.n[N_EMX][v + 1], cur.n[N_HXMX][v + 1]};
-        const Side b{below.ez[v], below.hx[v], below.hy[v], below.na[v], below.nb[v]};
-        const Side t{above.ez[v], above.hx[v], above.hy[v], above.na[v], above.nb[v]};
-        const Side lo{inc.lo.ez[v], inc.lo.hx[v], inc.lo.hy[v], inc.lo.na[v], inc.lo.nb[v]};
-        const Side hi{inc.hi.ez[v], inc.hi.hx[v], inc.hi.hy[v], inc.hi.na[v], inc.hi.nb[v]};
+        const float e_px = v == 0 ? xl_e : ee[v - 1], hx_px = v == 0 ? xl_h : eh[v - 1];
+        const float e_mx = v == V - 1 ? xr_e : we[v + 1], hx_mx = v == V - 1 ? xr_h : wh[v + 1];
         NodeData res;
-        neq_core<STRIP>(L, i, r, m, coef_of(L, inv_eps, eps_rest), o, l, rr, b, t, lo, hi, einc, res);
+        neq_pulled<STRIP>(L, i, r, m, coef_of(L, inv_eps, eps_rest), o, e_px, hx_px, e_mx, hx_mx, below.e[v],
+                          below.h[v], above.e[v], above.h[v], Pair{inc.lo.e[v], inc.lo.h[v]},
+                          Pair{inc.hi.e[v], inc.hi.h[v]}, einc, res);
         out.ez[v] = res.ez;
         out.hx[v] = res.hx;
         out.hy[v] = res.hy;
@@ -1842,7 +1890,9 @@ template <typename F> static void multi_step_dispatch(int variant, F &&go)
     case MULTI_S4_H16_X4: go(I1{}, H16{}, X4{}, S4{}, W2{}); break;
     case MULTI_S3_H10_X4: go(I1{}, H10{}, X4{}, S3{}, W2{}); break;
     case MULTI_S3_H12_X4: go(I1{}, H12{}, X4{}, S3{}, W2{}); break;
-    default: go(I1{}, H12{}, X8{}, S4{}, W2{}); break;
+    case MULTI_S4_H12_X8: go(I1{}, H12{}, X8{}, S4{}, W2{}); break;
+    case MULTI_S3_H7_X4: go(I1{}, std::integral_constant<int, 7>{}, X4{}, S3{}, W2{}); break;
+    default: go(I1{}, std::integral_constant<int, 8>{}, X4{}, S3{}, W2{}); break;
     }
 }
 

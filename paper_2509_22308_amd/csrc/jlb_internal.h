@@ -125,7 +125,9 @@ enum MultiStepVariant {
     MULTI_S3_H10_X4 = 3,
     MULTI_S3_H12_X4 = 4,
     MULTI_S4_H12_X8 = 5,  // X8: 48 output columns per strip
-    MULTI_STEP_VARIANTS = 6
+    MULTI_S3_H7_X4 = 6,
+    MULTI_S3_H8_X4 = 7,
+    MULTI_STEP_VARIANTS = 8
 };
 // mid (inside the window, else null): the fields at n + 1 .. n + S - 1 of the
 // contour-stencil nodes, one block of 3 row-interleaved float planes (row
