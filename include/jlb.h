@@ -265,10 +265,12 @@ int jlb_trajectory(int32_t n, double phi_first, const double *fx, const double *
 
 /*
  * Times `launches` back-to-back launches of the fused lattice-step kernel
- * of `prob` (no contour work), on `stream`, between two HIP events, after
- * `warmup` untimed launches; *ms_per_launch (host) receives the mean.  The
- * workspace is as for jlb_solve (NULL allocates).  The state starts at zero
- * and the source is on, so the kernel takes the same paths as in a solve.
+ * of `prob` (no contour work), on `stream`: after `warmup` untimed direct
+ * launches, the `launches` launches are captured into a hipGraph, replayed
+ * once untimed and once between two HIP events, as a solve replays its
+ * periods; *ms_per_launch (host) receives the mean.  The workspace is as
+ * for jlb_solve (NULL allocates).  The state starts at zero and the source
+ * is on, so the kernel takes the same paths as in a solve.
  */
 int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
                          int32_t launches, double *ms_per_launch, void *stream);
@@ -308,7 +310,9 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * when its time per lattice step beats the best single step (else turns
  * two-step kernels off), then the multi-step variants the grid allows and
  * selects the fastest of them when its time per lattice step beats the best
- * so far (else turns them off).  *best_variant receives the winner of the
+ * so far (else turns them off); a three-step variant's time counts 3 % more
+ * (over a whole solve its extra state passes and launches cost more than the
+ * short timing shows).  Timings are graph replays (jlb_time_step_kernel).  *best_variant receives the winner of the
  * first two rounds: a single-step variant index, or JLB_STEP_VARIANTS + the
  * two-step index (jlb_get_multi_step_variant reports the third).
  * ms_per_variant (host, optional) receives the mean time per lattice step in

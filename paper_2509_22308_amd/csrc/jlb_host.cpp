@@ -816,8 +816,14 @@ static int time_step_kernel(const jlb_problem *prob, void *workspace, size_t wor
     if (rc == JLB_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         rc = fail(JLB_E_DEVICE, "event create");
     const Lattice L = lattice_of(q, (const uint8_t *)(ws + q.off_mask));
+    // warm-up launches directly, then the timed launches captured into a
+    // hipGraph and replayed (once to warm it, once timed), as a solve runs them
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
     for (int64_t n = 0; rc == JLB_OK && n < (int64_t)warmup + launches; ++n) {
-        if (n == warmup && hipEventRecord(e0, own) != hipSuccess) rc = fail(JLB_E_DEVICE, "event record");
+        if (n == warmup && hipStreamBeginCapture(own, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            rc = fail(JLB_E_DEVICE, "capture begin");
+        if (rc) break;
         void *src = ws + q.off_state[n & 1], *dst = ws + q.off_state[(n + 1) & 1];
         hipError_t e;
         if (kind == 3) {
@@ -834,13 +840,22 @@ static int time_step_kernel(const jlb_problem *prob, void *workspace, size_t wor
         }
         if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "step launch: %s", hipGetErrorString(e));
     }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(own, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone) {
+        if (hipStreamEndCapture(own, &graph) != hipSuccess && rc == JLB_OK) rc = fail(JLB_E_DEVICE, "capture end");
+    }
+    if (rc == JLB_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = fail(JLB_E_DEVICE, "graph instantiate");
     if (rc == JLB_OK) {
         float ms = 0.0f;
-        if (hipEventRecord(e1, own) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        if (hipGraphLaunch(exec, own) != hipSuccess || hipEventRecord(e0, own) != hipSuccess ||
+            hipGraphLaunch(exec, own) != hipSuccess || hipEventRecord(e1, own) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
             rc = fail(JLB_E_DEVICE, "event timing");
         *ms_per_launch = (double)ms / launches;
     }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     int rc2 = join.end();
@@ -947,8 +962,13 @@ int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_byte
         if (rc) return rc;
         ms /= depth;
         if (ms_per_variant) ms_per_variant[NEQ_VARIANTS + TWO_STEP_VARIANTS + v] = ms;
-        if (ms < best) {
-            best = ms;
+        // a three-step variant has to win by 3 %: over a whole solve its extra
+        // state passes and launches cost more than this short timing shows
+        // (1024^2: three-step H7 timed within 1 % of four-step H10 ran 10 %
+        // slower in the solve)
+        const double score = depth == 3 ? 1.03 * ms : ms;
+        if (score < best) {
+            best = score;
             bm = v;
         }
     }
