@@ -26,13 +26,17 @@
 // the link midpoint).  Conductor nodes hold nothing and are never written.
 //
 // Storage: FP64 keeps the 11 populations per node (176 bytes per update).
-// FP32 and BF16 keep the fields (Ez, Hx, Hy) in FP32 and the deviations from
-// equilibrium N_q = f_q - f_q^eq of the 8 moving populations in FP32 or
-// bfloat16 (88 or 56 bytes per update): post-collision f*_q = f_q^eq - N_q,
-// and the rest deviations follow from the moments, which every equilibrium
-// reproduces: N_er = -(N_{e+x} + N_{e-x} + N_{e+y} + N_{e-y}) and likewise
-// for hx and hy.  The large rest population (eps - 2/3) Ez therefore never
-// passes through a narrow format.
+// FP32 and BF16 keep one sixth of the fields, (Ez, Hx, Hy) / 6, in FP32 and
+// the deviations from equilibrium N_q = f_q - f_q^eq of the 8 moving
+// populations in FP32 or bfloat16 (88 or 56 bytes per update): a moving
+// equilibrium is then a plain sum of stored fields (e.g. f^eq_{e+x} =
+// (Ez - Hy) / 6), so post-collision f*_q = f_q^eq - N_q needs no multiply, and
+// the factors 1/6 and 6 go into the per-material moment and rest-equilibrium
+// coefficients.  The rest deviations follow from the moments, which every
+// equilibrium reproduces: N_er = -(N_{e+x} + N_{e-x} + N_{e+y} + N_{e-y}) and
+// likewise for hx and hy.  The large rest population (eps - 2/3) Ez
+// therefore never passes through a narrow format.  Readers of the FP32
+// field planes (contour sums, far field, energy, field output) scale by 6.
 //
 // TE^z (Hz, Ex, Ey; the polarisation the paper leaves for later, Sec. I) is
 // the same update under the vacuum duality E -> H, H -> -E: the state holds
@@ -251,6 +255,8 @@ template <typename T> __device__ __forceinline__ float ld(const T *p) { return (
 template <typename T> __device__ __forceinline__ void st(T *p, float v, bool stream) { put(p, (T)v, stream); }
 
 constexpr float SIXTH = 1.0f / 6.0f;
+// Physical fields per stored field: FP32 / BF16 states keep one sixth of them.
+template <typename FT> __device__ __forceinline__ double field_scale() { return sizeof(FT) == 4 ? 6.0 : 1.0; }
 constexpr float THIRD = 1.0f / 3.0f;
 
 // Fields and deviations of one node at time n.
@@ -295,15 +301,20 @@ __device__ __forceinline__ Side load_side(const float *F, const NeqT *N, size_t 
 // H/3) and conductor links reflect with a sign change.  TE^z in the dual
 // storage: the in-plane fields carry it, the z field's rest is Hz/3, and
 // conductor links reflect without a sign change.
+// With the stored fields one sixth of the physical ones, a carries a factor
+// 1/6 and c a factor 6: inv_eps6 = 1 / (6 eps), eps_rest6 = 6 (eps - 2/3).
 struct Coef {
-    float az, axy;  // field = moment sum * a
-    float cz, cxy;  // rest equilibrium = c * field
+    float az, axy;  // stored field = moment sum * a
+    float cz, cxy;  // rest equilibrium = c * stored field
     float wall;     // conductor reflection sign
 };
-__device__ __forceinline__ Coef coef_tm(float inv_eps, float eps_rest) { return Coef{inv_eps, 1.0f, eps_rest, THIRD, -1.0f}; }
-__device__ __forceinline__ Coef coef_of(const Lattice &L, float inv_eps, float eps_rest)
+__device__ __forceinline__ Coef coef_tm(float inv_eps6, float eps_rest6)
 {
-    return L.te ? Coef{1.0f, inv_eps, THIRD, eps_rest, 1.0f} : coef_tm(inv_eps, eps_rest);
+    return Coef{inv_eps6, SIXTH, eps_rest6, 2.0f, -1.0f};
+}
+__device__ __forceinline__ Coef coef_of(const Lattice &L, float inv_eps6, float eps_rest6)
+{
+    return L.te ? Coef{SIXTH, inv_eps6, 2.0f, eps_rest6, 1.0f} : coef_tm(inv_eps6, eps_rest6);
 }
 
 // The post-collision pair a node sends along an axis: the e population and
@@ -313,26 +324,11 @@ __device__ __forceinline__ Coef coef_of(const Lattice &L, float inv_eps, float e
 struct Pair {
     float e, h;
 };
-__device__ __forceinline__ float up_e(const Side &s)
-{
-#pragma clang fp contract(off)
-    return (s.ez + s.hx) * SIXTH - s.na;
-}
-__device__ __forceinline__ float up_h(const Side &s)
-{
-#pragma clang fp contract(off)
-    return s.hy * SIXTH - s.nb;
-}
-__device__ __forceinline__ float down_e(const Side &s)
-{
-#pragma clang fp contract(off)
-    return (s.ez - s.hx) * SIXTH - s.na;
-}
-__device__ __forceinline__ float down_h(const Side &s)
-{
-#pragma clang fp contract(off)
-    return s.hy * SIXTH - s.nb;
-}
+// (stored fields are one sixth of the physical ones: f^eq is a plain sum)
+__device__ __forceinline__ float up_e(const Side &s) { return (s.ez + s.hx) - s.na; }
+__device__ __forceinline__ float up_h(const Side &s) { return s.hy - s.nb; }
+__device__ __forceinline__ float down_e(const Side &s) { return (s.ez - s.hx) - s.na; }
+__device__ __forceinline__ float down_h(const Side &s) { return s.hy - s.nb; }
 __device__ __forceinline__ float up_e(const Pair &p) { return p.e; }
 __device__ __forceinline__ float up_h(const Pair &p) { return p.h; }
 __device__ __forceinline__ float down_e(const Pair &p) { return p.e; }
@@ -364,14 +360,14 @@ __device__ __forceinline__ void neq_pulled(const Lattice &L, int i, int j, uint8
     if (STRIP || i == 0 || i == L.nx - 1 || j == 0 || j == L.ny - 1 ||
         (m & (NB_PEC_XM | NB_PEC_XP | NB_PEC_YM | NB_PEC_YP))) {
         // own post-collision moving populations
-        const float s_epx = (o.ez - o.hy) * SIXTH - o.n[N_EPX];
-        const float s_emx = (o.ez + o.hy) * SIXTH - o.n[N_EMX];
-        const float s_epy = (o.ez + o.hx) * SIXTH - o.n[N_EPY];
-        const float s_emy = (o.ez - o.hx) * SIXTH - o.n[N_EMY];
-        const float s_hxpx = o.hx * SIXTH - o.n[N_HXPX];
-        const float s_hxmx = o.hx * SIXTH - o.n[N_HXMX];
-        const float s_hypy = o.hy * SIXTH - o.n[N_HYPY];
-        const float s_hymy = o.hy * SIXTH - o.n[N_HYMY];
+        const float s_epx = (o.ez - o.hy) - o.n[N_EPX];
+        const float s_emx = (o.ez + o.hy) - o.n[N_EMX];
+        const float s_epy = (o.ez + o.hx) - o.n[N_EPY];
+        const float s_emy = (o.ez - o.hx) - o.n[N_EMY];
+        const float s_hxpx = o.hx - o.n[N_HXPX];
+        const float s_hxmx = o.hx - o.n[N_HXMX];
+        const float s_hypy = o.hy - o.n[N_HYPY];
+        const float s_hymy = o.hy - o.n[N_HYMY];
         if (i == 0) { e_px = einc * THIRD; hx_px = 0.0f; }
         else if (m & NB_PEC_XM) { e_px = k.wall * s_emx; hx_px = k.wall * s_hxmx; }
         if (i == L.nx - 1) {
@@ -400,14 +396,14 @@ __device__ __forceinline__ void neq_pulled(const Lattice &L, int i, int j, uint8
     out.ez = ez;
     out.hx = hx;
     out.hy = hy;
-    out.n[N_EPX] = e_px - (ez - hy) * SIXTH;
-    out.n[N_EMX] = e_mx - (ez + hy) * SIXTH;
-    out.n[N_EPY] = e_py - (ez + hx) * SIXTH;
-    out.n[N_EMY] = e_my - (ez - hx) * SIXTH;
-    out.n[N_HXPX] = hx_px - hx * SIXTH;
-    out.n[N_HXMX] = hx_mx - hx * SIXTH;
-    out.n[N_HYPY] = hy_py - hy * SIXTH;
-    out.n[N_HYMY] = hy_my - hy * SIXTH;
+    out.n[N_EPX] = e_px - (ez - hy);
+    out.n[N_EMX] = e_mx - (ez + hy);
+    out.n[N_EPY] = e_py - (ez + hx);
+    out.n[N_EMY] = e_my - (ez - hx);
+    out.n[N_HXPX] = hx_px - hx;
+    out.n[N_HXMX] = hx_mx - hx;
+    out.n[N_HYPY] = hy_py - hy;
+    out.n[N_HYMY] = hy_my - hy;
 }
 
 // One node's update from its own data and the four sides (fields and the two
@@ -419,8 +415,8 @@ __device__ __forceinline__ void neq_core(const Lattice &L, int i, int j, uint8_t
 {
 #pragma clang fp contract(off)
     // pulls across interior links: the neighbour's post-collision population
-    const float e_px = (l.ez - l.hy) * SIXTH - l.na, hx_px = l.hx * SIXTH - l.nb;  // +x from (i-1, j)
-    const float e_mx = (r.ez + r.hy) * SIXTH - r.na, hx_mx = r.hx * SIXTH - r.nb;  // -x from (i+1, j)
+    const float e_px = (l.ez - l.hy) - l.na, hx_px = l.hx - l.nb;  // +x from (i-1, j)
+    const float e_mx = (r.ez + r.hy) - r.na, hx_mx = r.hx - r.nb;  // -x from (i+1, j)
     const float e_py = up_e(b), hy_py = up_h(b);                                    // +y from (i, j-1)
     const float e_my = down_e(t), hy_my = down_h(t);                                // -y from (i, j+1)
     neq_pulled<STRIP>(L, i, j, m, k, o, e_px, hx_px, e_mx, hx_mx, e_py, hy_py, e_my, hy_my, inc_lo, inc_hi, einc, out);
@@ -444,8 +440,8 @@ __device__ __forceinline__ bool node_setup(const Lattice &L, const float *F, con
 {
     const size_t P = L.plane;
     m = 0;
-    inv_eps = 1.0f;
-    eps_rest = (float)(1.0 - 2.0 / 3.0);
+    inv_eps = SIXTH;  // vacuum, scaled as the stored coefficients
+    eps_rest = 2.0f;
     if (j < L.ny) {
         m = L.mask[node(L, i, j)];
         const int mat = m & 3;
@@ -807,10 +803,10 @@ __device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, type
     float ee[V], eh[V], we[V], wh[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        ee[v] = (cur.ez[v] - cur.hy[v]) * SIXTH - cur.n[N_EPX][v];
-        eh[v] = cur.hx[v] * SIXTH - cur.n[N_HXPX][v];
-        we[v] = (cur.ez[v] + cur.hy[v]) * SIXTH - cur.n[N_EMX][v];
-        wh[v] = cur.hx[v] * SIXTH - cur.n[N_HXMX][v];
+        ee[v] = (cur.ez[v] - cur.hy[v]) - cur.n[N_EPX][v];
+        eh[v] = cur.hx[v] - cur.n[N_HXPX][v];
+        we[v] = (cur.ez[v] + cur.hy[v]) - cur.n[N_EMX][v];
+        wh[v] = cur.hx[v] - cur.n[N_HXMX][v];
     }
     const float xl_e = from_left(ee[V - 1]), xl_h = from_left(eh[V - 1]);
     const float xr_e = from_right(we[0]), xr_h = from_right(wh[0]);
@@ -818,7 +814,7 @@ __device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, type
     for (int v = 0; v < V; ++v) {
         const int i = i0 + v;
         uint8_t m = 0;
-        float inv_eps = 1.0f, eps_rest = (float)(1.0 - 2.0 / 3.0);
+        float inv_eps = SIXTH, eps_rest = 2.0f;  // vacuum, scaled as the stored coefficients
         if (!STRIP) {
             m = (uint8_t)(mv >> (8 * v));
             const int mat = m & 3;
@@ -1418,7 +1414,8 @@ __device__ __forceinline__ void contour_sample_f32(const Lattice &L, const float
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float *p = fld + a * P;
-        v[a] = w00 * p[c00] + w01 * p[c00 + 1] + w10 * p[c10] + w11 * p[c10 + 1];
+        // stored fields are one sixth of the physical ones
+        v[a] = 6.0f * (w00 * p[c00] + w01 * p[c00 + 1] + w10 * p[c10] + w11 * p[c10 + 1]);
     }
     C.acc[0 * C.n + k] += (double)(v[0] * v[0]);
     C.acc[1 * C.n + k] += (double)(v[1] * v[1]);
@@ -1574,12 +1571,13 @@ __global__ void k_far_dft(Lattice L, const FT *__restrict__ fld, ContourDev C, d
     const size_t cs = at(i0, L.ny, L.sfld);
     const double fx = C.wx[k], fy = C.wy[k];
     const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy), w10 = (1.0 - fx) * fy, w11 = fx * fy;
+    const double fs = field_scale<FT>();
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const FT *p = fld + a * P;
-        const double v = w00 * (double)p[c00] + w01 * (double)p[c00 + 1] + w10 * (double)p[c10] +
-                         w11 * (double)p[c10 + 1];
-        const double u = (1.0 - fx) * (double)p[cs] + fx * (double)p[cs + 1];
+        const double v = fs * (w00 * (double)p[c00] + w01 * (double)p[c00 + 1] + w10 * (double)p[c10] +
+                               w11 * (double)p[c10 + 1]);
+        const double u = fs * ((1.0 - fx) * (double)p[cs] + fx * (double)p[cs + 1]);
         dft[(2 * a) * C.n + k] += v * cw;
         dft[(2 * a + 1) * C.n + k] += v * sw;
         dft[(6 + 2 * a) * C.n + k] += u * cw;
@@ -1655,7 +1653,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_force_now(Lattice L, const FT *
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const FT *p = fld + a * P;
-            v[a] = w00 * (double)p[c00] + w01 * (double)p[c00 + 1] + w10 * (double)p[c10] + w11 * (double)p[c10 + 1];
+            v[a] = field_scale<FT>() *
+                   (w00 * (double)p[c00] + w01 * (double)p[c00 + 1] + w10 * (double)p[c10] + w11 * (double)p[c10 + 1]);
         }
         const double txx = 0.5 * (v[1] * v[1] - v[2] * v[2] - v[0] * v[0]);
         const double tyy = 0.5 * (v[2] * v[2] - v[1] * v[1] - v[0] * v[0]);
@@ -1708,7 +1707,8 @@ __global__ __launch_bounds__(EN_THREADS) void k_energy_partial(Lattice L, const 
             const int mat = L.mask[node(L, i, j)] & 3;
             if (mat == MAT_PEC) continue;
             const size_t c = at(i, j, L.sfld);
-            const double ez = fld[c], hx = fld[P + c], hy = fld[2 * P + c];
+            const double fs = field_scale<FT>();
+            const double ez = fs * fld[c], hx = fs * fld[P + c], hy = fs * fld[2 * P + c];
             if (L.te) s += 0.5 * (ez * ez + mat_eps(L, mat) * (hx * hx + hy * hy));
             else s += 0.5 * (mat_eps(L, mat) * ez * ez + hx * hx + hy * hy);
         }
@@ -1750,9 +1750,10 @@ __global__ void k_fields_out(Lattice L, const FT *__restrict__ fld, double *ez, 
     const size_t o = (size_t)j * L.nx + i;
     // TE^z: the dual storage holds (Hz, -Ex, -Ey); report (Hz, Ex, Ey)
     const double sxy = L.te ? -1.0 : 1.0;
-    ez[o] = (double)fld[c];
-    hx[o] = sxy * (double)fld[P + c];
-    hy[o] = sxy * (double)fld[2 * P + c];
+    const double fs = field_scale<FT>();
+    ez[o] = fs * (double)fld[c];
+    hx[o] = sxy * fs * (double)fld[P + c];
+    hy[o] = sxy * fs * (double)fld[2 * P + c];
 }
 
 dim3 step_grid(const Lattice &L) { return dim3((L.nx + BX - 1) / BX, (L.ny + 1 + BY - 1) / BY); }

@@ -312,8 +312,10 @@ Lattice lattice_of(const Plan &q, const uint8_t *dmask)
         L.eps[k] = q.eps[k];
         L.eps_rest[k] = q.eps[k] - 2.0 / 3.0;
         L.inv_eps[k] = 1.0 / q.eps[k];
-        L.inv_eps_f[k] = (float)L.inv_eps[k];
-        L.eps_rest_f[k] = (float)L.eps_rest[k];
+        // FP32 / BF16 states keep one sixth of the fields: the coefficients
+        // carry the factor
+        L.inv_eps_f[k] = (float)(1.0 / (6.0 * q.eps[k]));
+        L.eps_rest_f[k] = (float)(6.0 * L.eps_rest[k]);
     }
     L.te = q.prob.polarization == JLB_TE ? 1 : 0;
     L.stream_stores = 2 * q.state_bytes > CACHE_RESIDENT_BYTES ? 1 : 0;

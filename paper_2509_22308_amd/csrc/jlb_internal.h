@@ -54,8 +54,8 @@ struct Lattice {
     double eps[4];        // permittivity per material id (id 3 unused)
     double eps_rest[4];   // eps - 2/3: coefficient of Ez in the rest e-population's equilibrium
     double inv_eps[4];    // 1 / eps (the FP32 / BF16 update multiplies by it)
-    float inv_eps_f[4];   // the two above rounded to FP32 once, on the host
-    float eps_rest_f[4];
+    float inv_eps_f[4];   // FP32 / BF16: 1 / (6 eps) and 6 (eps - 2/3), rounded once on the host
+    float eps_rest_f[4];  // (those states keep one sixth of the fields)
     int stream_stores;    // 1: write the next state past the caches (state larger than the Infinity Cache)
     int te;               // 1: TE^z, stored as (Hz, -Ex, -Ey) in the (Ez, Hx, Hy) slots
 };
