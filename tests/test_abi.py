@@ -80,6 +80,44 @@ def test_two_step_timing_refuses_fp64_before_the_device():
     assert "FP32 / BF16" in J.jlb_last_error()
 
 
+def test_multi_step_variant_table_and_argument_checks():
+    """Variant shapes as documented in include/jlb.h; out-of-range variants,
+    FP64 and grids too short for a variant are refused before the device."""
+    import ctypes
+    shapes = [J.jlb_multi_step_shape(v) for v in range(len(J.MULTI_STEP_VARIANTS))]
+    assert shapes == [(4, 10), (4, 12), (4, 16), (3, 10), (3, 12), (4, 12), (3, 7), (3, 8)]
+    with pytest.raises(J.JlbError):
+        J.jlb_multi_step_shape(len(J.MULTI_STEP_VARIANTS))
+    prec = J.PRECISIONS["fp32"]
+    before = J.jlb_get_multi_step_variant(prec)
+    try:
+        with pytest.raises(J.JlbError):
+            J.jlb_set_multi_step_variant(prec, len(J.MULTI_STEP_VARIANTS))
+        with pytest.raises(J.JlbError):
+            J.jlb_set_multi_step_variant(J.PRECISIONS["fp64"], 0)
+        J.jlb_set_multi_step_variant(J.PRECISIONS["fp64"], -1)
+        ms = ctypes.c_double(0.0)
+        lib = J.load()
+        p64 = J.make_problem(W.config1(), "fp64")
+        assert lib.jlb_time_multi_step_kernel(ctypes.byref(p64), None, 0, 0, 1, ctypes.byref(ms), None) == -1
+        assert "FP32 / BF16" in J.jlb_last_error()
+        J.jlb_set_multi_step_variant(prec, 2)  # 16-row segments need ny >= 20
+        short = J.make_problem(W.problem(nx=64, ny=19, radius=3.0, kind="dielectric_janus", eps1=2.0, eps2=3.0,
+                                         phi0_deg=60.0, wavelength=40.0, steps=720, avg_periods=1,
+                                         contour_offset=2.0), "fp32")
+        assert lib.jlb_time_multi_step_kernel(ctypes.byref(short), None, 0, 0, 1, ctypes.byref(ms), None) == -1
+        assert "too short" in J.jlb_last_error()
+        J.jlb_set_multi_step_variant(prec, -1)
+        assert lib.jlb_time_multi_step_kernel(ctypes.byref(short), None, 0, 0, 1, ctypes.byref(ms), None) == -1
+        assert "no multi-step variant" in J.jlb_last_error()
+    finally:
+        J.jlb_set_multi_step_variant(prec, before)
+
+
+def test_engine_four_step_switch_checks_its_engine():
+    assert J.load().jlb_engine_set_four_step(None, 1) == -1
+
+
 def test_workspace_grows_with_precision_and_grid():
     p = W.config2()
     sizes = [J.jlb_workspace_size(J.make_problem(p, prec)) for prec in ("bf16", "fp32", "fp64")]
