@@ -1401,8 +1401,9 @@ __device__ __forceinline__ void contour_sample_f64(const Lattice &L, const doubl
     C.acc[3 * C.n + k] += v[1] * v[2];
 }
 
-__device__ __forceinline__ void contour_sample_f32(const Lattice &L, const float *__restrict__ fld, size_t stride,
-                                                   const ContourDev &C, int k)
+// One level's products at sample k added to the running sums s[4].
+__device__ __forceinline__ void contour_add_f32(const Lattice &L, const float *__restrict__ fld, size_t stride,
+                                                const ContourDev &C, int k, double (&s)[4])
 {
 #pragma clang fp contract(off)
     const size_t P = L.plane;
@@ -1417,10 +1418,33 @@ __device__ __forceinline__ void contour_sample_f32(const Lattice &L, const float
         // stored fields are one sixth of the physical ones
         v[a] = 6.0f * (w00 * p[c00] + w01 * p[c00 + 1] + w10 * p[c10] + w11 * p[c10 + 1]);
     }
-    C.acc[0 * C.n + k] += (double)(v[0] * v[0]);
-    C.acc[1 * C.n + k] += (double)(v[1] * v[1]);
-    C.acc[2 * C.n + k] += (double)(v[2] * v[2]);
-    C.acc[3 * C.n + k] += (double)(v[1] * v[2]);
+    s[0] += (double)(v[0] * v[0]);
+    s[1] += (double)(v[1] * v[1]);
+    s[2] += (double)(v[2] * v[2]);
+    s[3] += (double)(v[1] * v[2]);
+}
+
+__device__ __forceinline__ void contour_load(const ContourDev &C, int k, double (&s)[4])
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] = C.acc[q * C.n + k];
+}
+
+__device__ __forceinline__ void contour_store(const ContourDev &C, int k, const double (&s)[4])
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) C.acc[q * C.n + k] = s[q];
+}
+
+// One level's products added to the time sums of sample k (the same
+// additions, in the same order, as several levels through contour_add_f32).
+__device__ __forceinline__ void contour_sample_f32(const Lattice &L, const float *__restrict__ fld, size_t stride,
+                                                   const ContourDev &C, int k)
+{
+    double s[4];
+    contour_load(C, k, s);
+    contour_add_f32(L, fld, stride, C, k, s);
+    contour_store(C, k, s);
 }
 
 __global__ void k_contour_f64(Lattice L, const double *__restrict__ fld, ContourDev C)
@@ -1441,8 +1465,11 @@ __global__ void k_contour2_f32(Lattice L, const float *__restrict__ mid, const f
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < C.n) {
-        contour_sample_f32(L, mid, 3 * L.plane, C, k);
-        contour_sample_f32(L, fld, L.sfld, C, k);
+        double s[4];
+        contour_load(C, k, s);
+        contour_add_f32(L, mid, 3 * L.plane, C, k, s);
+        contour_add_f32(L, fld, L.sfld, C, k, s);
+        contour_store(C, k, s);
     }
 }
 
@@ -1453,8 +1480,11 @@ __global__ void k_contourm_f32(Lattice L, const float *__restrict__ mid, size_t 
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < C.n) {
-        for (int m = 0; m < nmid; ++m) contour_sample_f32(L, mid + (size_t)m * mid_level, 3 * L.plane, C, k);
-        contour_sample_f32(L, fld, L.sfld, C, k);
+        double s[4];
+        contour_load(C, k, s);
+        for (int m = 0; m < nmid; ++m) contour_add_f32(L, mid + (size_t)m * mid_level, 3 * L.plane, C, k, s);
+        contour_add_f32(L, fld, L.sfld, C, k, s);
+        contour_store(C, k, s);
     }
 }
 
