@@ -1104,8 +1104,8 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq_batch(SolveDe
                                   one ? 0.0f : (float)batch_incident(d, n + 1), mid, t.tx, t.ty, one);
 }
 
-// S steps per launch (temporal blocking, S >= 2), for the whole periods
-// outside the averaging window: the two-step sweep with S levels in flight.
+// S steps per launch (temporal blocking, S >= 2): the two-step sweep with S
+// levels in flight.
 // Level s (1-based) updates row r1 - (s - 1) DIR of the sweep from the three
 // level-(s - 1) rows around it, the last of which level s - 1 has just
 // produced; intermediate levels are rounded to the storage type as a store
@@ -1947,12 +1947,15 @@ void multi_step_shape(int variant, int &depth, int &rows)
 hipError_t launch_stepm_neq(int precision, const Lattice &L, const void *src, void *dst, const double *einc,
                             float *mid, size_t mid_level, hipStream_t s, int variant)
 {
+    int depth = 0, rows = 0;
+    multi_step_shape(variant, depth, rows);
+    // a segment must not reach both edge rows (callers check first)
+    if (L.ny < rows + depth) return hipErrorInvalidValue;
     auto run = [&](auto tag) {
         typedef decltype(tag) T;
         multi_step_dispatch(variant, [&](auto vtag, auto htag, auto xtag, auto stag, auto wtag) {
             constexpr int V = decltype(vtag)::value, H = decltype(htag)::value, HX = decltype(xtag)::value;
             constexpr int S = decltype(stag)::value, W = decltype(wtag)::value;
-            if (L.ny < H + S) return;  // a segment would reach both edge rows (callers check first)
             Incident<S> e;
             for (int k = 0; k < S; ++k) e.v[k] = (float)einc[k];
             const int nsx = (L.nx + two_step_width<V, HX>() - 1) / two_step_width<V, HX>();
@@ -1974,6 +1977,9 @@ hipError_t launch_stepm_neq(int precision, const Lattice &L, const void *src, vo
 hipError_t launch_stepm_batch(int precision, int variant, SolveDesc *d, const Tile *items, int nitems, int remap,
                               hipStream_t s)
 {
+    int depth = 0, rows = 0;
+    multi_step_shape(variant, depth, rows);
+    if (depth != 4) return hipErrorInvalidValue;  // the engine steps in rounds of four
     if (nitems <= 0) return hipSuccess;
     const int blocks = (nitems + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
     auto run = [&](auto tag) {

@@ -255,8 +255,7 @@ void set_step_variant(int precision, int v) { g_variant[precision].store(v, std:
 int two_step_variant(int precision) { return g_two[precision].load(std::memory_order_relaxed); }
 static void set_two_step_variant(int precision, int v) { g_two[precision].store(v, std::memory_order_relaxed); }
 // Multi-step (three or four steps per launch) kernel variant per precision
-// for the whole periods outside the window (inside it the two-step kernel or
-// single steps run), -1 = off.
+// for the graph-captured periods and the ramp of a single solve, -1 = off.
 static std::atomic<int> g_multi[3] = {{-1}, {MULTI_S4_H10_X4}, {MULTI_S4_H10_X4}};
 int multi_step_variant(int precision) { return g_multi[precision].load(std::memory_order_relaxed); }
 static void set_multi_step_variant(int precision, int v) { g_multi[precision].store(v, std::memory_order_relaxed); }

@@ -117,7 +117,8 @@ hipError_t launch_step2_neq(int precision, const Lattice &L, const void *src, vo
                             float *mid, hipStream_t s, int variant);
 // S steps per launch (FP32 / BF16, S = 3 or 4 by variant): state n in src ->
 // state n + S in dst (src and dst must differ); einc[0..S-1] are the source
-// values of steps n .. n + S - 1.  Launches need ny >= rows + S.
+// values of steps n .. n + S - 1.  Launches need ny >= rows + S
+// (hipErrorInvalidValue otherwise).
 enum MultiStepVariant {
     MULTI_S4_H10_X4 = 0,  // X4: 4 halo columns per side, 56 output columns per strip
     MULTI_S4_H12_X4 = 1,
@@ -209,7 +210,7 @@ hipError_t launch_step2_batch(int precision, int variant, SolveDesc *d, const Ti
 // Strip and segment counts of a two-step variant for an nx x ny lattice.
 void two_step_shape(int variant, int nx, int ny, int &nsx, int &nsy);
 hipError_t launch_contour2_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s);
-// Multi-step launches (variant of depth mdepth) over the two-step solves
+// Four-step launches (a depth-4 variant; others: hipErrorInvalidValue) over the two-step solves
 // whose next mdepth levels all lie before the window ("multi mode"); the
 // two-step launches, their contour launches and advances skip those solves.
 hipError_t launch_stepm_batch(int precision, int variant, SolveDesc *d, const Tile *items, int nitems, int remap,
