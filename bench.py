@@ -209,12 +209,13 @@ def gpu_leg(args):
     return p, value, ms_per_solve, roof, extra
 
 
-def cpu_leg(p, budget_s: float = 15.0):
-    """The FP64 oracle as it stands, on the host cores, on a bounded sample:
-    the headline workload's first n steps (n sized to about budget_s)."""
+def cpu_leg(p, budget_s: float = 15.0, threads: int = 0):
+    """The FP64 oracle as it stands, on the host cores (all of them, or
+    `threads`), on a bounded sample: the headline workload's first n steps
+    (n sized to about budget_s)."""
     from oracle import oracle
 
-    threads = int(os.environ.get("JLB_ORACLE_THREADS", os.cpu_count() or 1))
+    threads = threads or int(os.environ.get("JLB_ORACLE_THREADS", os.cpu_count() or 1))
     probe = dict(p, steps=20, avg_periods=0)
     t = time.perf_counter()
     oracle.solve(probe, fields=False, threads=threads)
@@ -243,6 +244,9 @@ def base_line(args, metric_value, ms, config, roof=None, cpu=None, extra=None, d
 def run_default(args):
     p, value, ms, roof, extra = gpu_leg(args)
     cpu = None if args.no_cpu else cpu_leg(p)
+    if cpu is not None:
+        # the same oracle on one host thread, a shorter sample
+        extra["cpu_baseline_single_thread"] = cpu_leg(p, budget_s=6.0, threads=1)
     config = {"workload": "dielectric Janus cylinder eps 2.25/4.0, phi0 30 deg, a=64, 1024x1024, lambda=128, "
                           "20000 steps, 5-period stress average (one full solve per step)",
               "nx": p["nx"], "ny": p["ny"], "steps_per_solve": p["steps"], "precision": args.precision}
