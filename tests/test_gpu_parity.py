@@ -297,6 +297,33 @@ def test_multi_step_config2_matches_single_steps(jlb):
         jlb.jlb_set_multi_step_variant(prec, multi0)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_pre_window_stretch_is_reported_per_kernel(jlb, precision):
+    """jlb_result names the kernel of the graph-replayed periods before the
+    window and counts its launches: single steps, two-step or multi-step by
+    what is selected; the forces do not depend on it."""
+    prec = jlb.PRECISIONS[precision]
+    two0, multi0 = jlb.jlb_get_two_step_variant(prec), jlb.jlb_get_multi_step_variant(prec)
+    p = W.problem(nx=203, ny=150, radius=20.0, kind="dielectric_janus", eps1=2.0, eps2=6.0, phi0_deg=45.0,
+                  wavelength=40.0, steps=1080, avg_periods=2)  # T 120: 120 ramp, 720 before the 240-step window
+    out = {}
+    try:
+        for two, multi in ((-1, -1), (4, -1), (4, 0), (4, 3)):
+            jlb.jlb_set_two_step_variant(prec, two)
+            jlb.jlb_set_multi_step_variant(prec, multi)
+            out[(two, multi)] = jlb.solve(p, precision)
+    finally:
+        jlb.jlb_set_two_step_variant(prec, two0)
+        jlb.jlb_set_multi_step_variant(prec, multi0)
+    expect = {(-1, -1): (1, 720), (4, -1): (2, 360), (4, 0): (3, 180), (4, 3): (3, 240)}
+    for key, (kind, launches) in expect.items():
+        o = out[key]
+        assert (o["main_kind"], o["main_launches"]) == (kind, launches), (key, o["main_kind"], o["main_launches"])
+        assert 0.0 < o["main_ms"] < o["loop_ms"]
+        for q in ("fx", "fy", "tz"):
+            assert o[q] == out[(-1, -1)][q], (key, q)
+
+
 def test_two_step_config2_matches_single_steps(jlb):
     """The headline workload with the autotuner's choice: forces identical to
     single steps."""
