@@ -93,7 +93,7 @@ def gpu_leg(args):
     p = workloads.config2()
     prob = jlb.make_problem(p, args.precision)
     ws = _workspace(jlb, prob)
-    # the autotuner picks the step kernels (tile shape, single or two-step)
+    # the autotuner picks the step kernels (tile shape; single, two- or multi-step)
     # for this device and grid
     variant, tune_ms = jlb.jlb_autotune(prob, 20, ws)
     two_variant = jlb.jlb_get_two_step_variant(jlb.PRECISIONS[args.precision]) if args.precision != "fp64" else -1
