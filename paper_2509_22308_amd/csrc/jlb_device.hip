@@ -793,10 +793,31 @@ struct StripSides {
 // the result is a finite value that no valid node ever reads -- a valid node
 // next to such a node takes an edge or conductor rule instead -- and
 // store_row_masked writes zeros for them.
+// Per-node material coefficients of a row (scaled as stored: 1 / (6 eps) and
+// 6 (eps - 2/3)); the companion row is vacuum.
+template <int V, bool STRIP>
+__device__ __forceinline__ void row_coefs(const Lattice &L, typename MaskVec<V>::type mv, float (&ie)[V],
+                                          float (&er)[V])
+{
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        ie[v] = SIXTH;  // vacuum
+        er[v] = 2.0f;
+        if (!STRIP) {
+            const int mat = (int)((mv >> (8 * v)) & 3);
+            ie[v] = mat_inv_eps_f(L, mat);
+            er[v] = mat_eps_rest_f(L, mat);
+        }
+    }
+}
+
+// One row's update with its material coefficients given (a sweep that
+// updates the same row at several levels picks them once).
 template <typename NeqT, int V, bool STRIP>
-__device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, typename MaskVec<V>::type mv,
-                                           const RowData<V> &cur, const SideRow<V> &below, const SideRow<V> &above,
-                                           const StripSides<V> &inc, float einc, RowData<V> &out)
+__device__ __forceinline__ void row_update_k(const Lattice &L, int i0, int r, typename MaskVec<V>::type mv,
+                                             const float (&ie)[V], const float (&er)[V], const RowData<V> &cur,
+                                             const SideRow<V> &below, const SideRow<V> &above,
+                                             const StripSides<V> &inc, float einc, RowData<V> &out)
 {
 #pragma clang fp contract(off)
     // the pairs each node sends east (+x) and west (-x)
@@ -813,14 +834,7 @@ __device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, type
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const int i = i0 + v;
-        uint8_t m = 0;
-        float inv_eps = SIXTH, eps_rest = 2.0f;  // vacuum, scaled as the stored coefficients
-        if (!STRIP) {
-            m = (uint8_t)(mv >> (8 * v));
-            const int mat = m & 3;
-            inv_eps = mat_inv_eps_f(L, mat);
-            eps_rest = mat_eps_rest_f(L, mat);
-        }
+        const uint8_t m = STRIP ? (uint8_t)0 : (uint8_t)(mv >> (8 * v));
         NodeData o;
         o.ez = cur.ez[v];
         o.hx = cur.hx[v];
@@ -830,15 +844,32 @@ __device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, type
         const float e_px = v == 0 ? xl_e : ee[v - 1], hx_px = v == 0 ? xl_h : eh[v - 1];
         const float e_mx = v == V - 1 ? xr_e : we[v + 1], hx_mx = v == V - 1 ? xr_h : wh[v + 1];
         NodeData res;
-        neq_pulled<STRIP>(L, i, r, m, coef_of(L, inv_eps, eps_rest), o, e_px, hx_px, e_mx, hx_mx, below.e[v],
-                          below.h[v], above.e[v], above.h[v], Pair{inc.lo.e[v], inc.lo.h[v]},
-                          Pair{inc.hi.e[v], inc.hi.h[v]}, einc, res);
+        neq_pulled<STRIP>(L, i, r, m, coef_of(L, ie[v], er[v]), o, e_px, hx_px, e_mx, hx_mx, below.e[v], below.h[v],
+                          above.e[v], above.h[v], Pair{inc.lo.e[v], inc.lo.h[v]}, Pair{inc.hi.e[v], inc.hi.h[v]}, einc,
+                          res);
         out.ez[v] = res.ez;
         out.hx[v] = res.hx;
         out.hy[v] = res.hy;
 #pragma unroll
         for (int q = 0; q < 8; ++q) out.n[q][v] = res.n[q];
     }
+}
+
+// One row's update from its own data (row r), the pairs the rows below and
+// above send it, the x-neighbours across lanes, and the companion row.
+// Every node of the row is updated without branching on its kind: for nodes
+// that hold nothing (conductors, padding, rows or columns outside the domain)
+// the result is a finite value that no valid node ever reads -- a valid node
+// next to such a node takes an edge or conductor rule instead -- and
+// store_row_masked writes zeros for them.
+template <typename NeqT, int V, bool STRIP>
+__device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, typename MaskVec<V>::type mv,
+                                           const RowData<V> &cur, const SideRow<V> &below, const SideRow<V> &above,
+                                           const StripSides<V> &inc, float einc, RowData<V> &out)
+{
+    float ie[V], er[V];
+    row_coefs<V, STRIP>(L, mv, ie, er);
+    row_update_k<NeqT, V, STRIP>(L, i0, r, mv, ie, er, cur, below, above, inc, einc, out);
 }
 
 template <typename NeqT, int V>
@@ -1198,8 +1229,13 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
         RowData<V> a_cur, a_ahead, tmp;
         MaskT m_ahead, m_dummy;
         MaskT mk[S];  // mk[s]: mask of row r1 - s DIR
+        float kie[S][V], ker[S][V];  // its material coefficients (picked at level 1)
 #pragma unroll
-        for (int s = 0; s < S; ++s) mk[s] = 0;
+        for (int s = 0; s < S; ++s) {
+            mk[s] = 0;
+#pragma unroll
+            for (int v = 0; v < V; ++v) kie[s][v] = ker[s][v] = 0.0f;
+        }
         load(first - DIR, tmp, m_dummy);
         SideRow<V> a_behind = side_of(tmp, BQA, BQB);
         load(first, a_cur, mk[0]);
@@ -1226,8 +1262,9 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
             RowData<V> nw;
             {
                 const SideRow<V> side = side_of(a_ahead, AQA, AQB);
-                row_update<NeqT, V, false>(L, i0, r1, mk[0], a_cur, DIR > 0 ? a_behind : side,
-                                           DIR > 0 ? side : a_behind, StripSides<V>{edge[0], edge[0]}, einc[0], nw);
+                row_coefs<V, false>(L, mk[0], kie[0], ker[0]);
+                row_update_k<NeqT, V, false>(L, i0, r1, mk[0], kie[0], ker[0], a_cur, DIR > 0 ? a_behind : side,
+                                             DIR > 0 ? side : a_behind, StripSides<V>{edge[0], edge[0]}, einc[0], nw);
                 round_row<NeqT, V>(nw);
                 keep_mid(1, r1, nw, mk[0]);
             }
@@ -1240,7 +1277,8 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
                 if (go) {
                     const int rs = r1 - s * DIR;
                     const SideRow<V> side = side_of(nw, AQA, AQB);
-                    row_update<NeqT, V, false>(L, i0, rs, mk[s], lv_cur[s], DIR > 0 ? lv_behind[s] : side,
+                    row_update_k<NeqT, V, false>(L, i0, rs, mk[s], kie[s], ker[s], lv_cur[s],
+                                                 DIR > 0 ? lv_behind[s] : side,
                                                DIR > 0 ? side : lv_behind[s], StripSides<V>{edge[s], edge[s]},
                                                einc[s], o);
                     if (s < S - 1) {
@@ -1258,7 +1296,14 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
                 nw = o;
             }
 #pragma unroll
-            for (int s = S - 1; s > 0; --s) mk[s] = mk[s - 1];
+            for (int s = S - 1; s > 0; --s) {
+                mk[s] = mk[s - 1];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    kie[s][v] = kie[s - 1][v];
+                    ker[s][v] = ker[s - 1][v];
+                }
+            }
             a_behind = side_of(a_cur, BQA, BQB);
             a_cur = a_ahead;
             mk[0] = m_ahead;
