@@ -482,8 +482,8 @@ def main():
         record_traffic(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X (independent solves shard with no "
-              "communication; see the design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs each solve on a single MI355X (independent solves "
+              "shard across GPUs with no communication); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.kernel_only:
         run_kernel_only(args)

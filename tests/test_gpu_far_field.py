@@ -172,7 +172,7 @@ def test_far_field_reproduces_the_papers_validation(jlb, eps1, phi0):
     = 50, L / a = 10, against the analytic scattered series (Eq. constants_Bm_Dm
     and the Hankel asymptotics).  The paper reports per-angle relative errors
     generally below 5 %, larger where the intensity varies sharply.  With the
-    staircase boundary of this build the error at this resolution is 1-6 % of
+    staircase boundary of the lattice here the error at this resolution is 1-6 % of
     the peak intensity, and up to 16 % for eps_r1 = 5 at phi0 = -pi/4 (a
     resonant body, 4.5 internal wavelengths across); held here to 20 %."""
     assert _fig_sw(jlb, eps1, phi0) < 0.20
