@@ -347,8 +347,9 @@ int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t wo
  * contour-stencil fields of its intermediate levels and all S levels are
  * accumulated after it, in time order), and the ramp and the steps before
  * the window's first chunk as pairs of launches, provided the chunk is a
- * multiple of 2 S steps and ny >= rows + S; otherwise the solve runs as
- * without it.  The engine has its own switch (jlb_engine_set_four_step).
+ * multiple of 2 S steps and ny >= rows + S; a four-step variant whose chunk
+ * is 4 (mod 8) steps gives way to variant 3 (S3 H10 X4); otherwise the solve
+ * runs as without it.  The engine has its own switch (jlb_engine_set_four_step).
  * Variants (depth S, rows per wavefront, halo
  * columns per side: 56 output columns per 64-lane strip with X4, 48 with
  * X8): 0 S4 H10 X4, 1 S4 H12 X4, 2 S4 H16 X4, 3 S3 H10 X4, 4 S3 H12 X4,

@@ -434,6 +434,12 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     int multi = q.prob.precision == JLB_FP64 ? -1 : multi_step_variant(q.prob.precision);
     int depth = 0, mrows = 0;
     if (multi >= 0) multi_step_shape(multi, depth, mrows);
+    if (multi >= 0 && depth == 4 && chunk % 8 != 0) {
+        // a chunk of 4 (mod 8) steps: three steps per launch (whole-step
+        // wavelengths give periods that are multiples of 3, chunks of 12)
+        multi = MULTI_S3_H10_X4;
+        multi_step_shape(multi, depth, mrows);
+    }
     if (multi >= 0 && (chunk % (2 * depth) != 0 || q.ny < mrows + depth)) multi = -1;
     const int64_t ramp_end = (int64_t)std::ceil(q.ramp_steps);
     bool plateau = q.prob.plateau_tol > 0.0;

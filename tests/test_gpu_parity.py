@@ -324,6 +324,31 @@ def test_pre_window_stretch_is_reported_per_kernel(jlb, precision):
             assert o[q] == out[(-1, -1)][q], (key, q)
 
 
+def test_four_step_choice_gives_way_to_three_steps_on_odd_chunks(jlb):
+    """lambda = 50: a period of 150 steps, chunks of 300 = 4 (mod 8), so the
+    default four-step variant gives way to three-step H10 X4 (100 launches per
+    chunk); the result still equals single steps bit for bit."""
+    p = W.problem(nx=120, ny=100, radius=12.0, kind="dielectric_janus", eps1=2.0, eps2=4.0, phi0_deg=30.0,
+                  wavelength=50.0, steps=900, avg_periods=1)  # ramp 150, 2 chunks of 300, window 150
+    prec = jlb.PRECISIONS["fp32"]
+    two0, multi0 = jlb.jlb_get_two_step_variant(prec), jlb.jlb_get_multi_step_variant(prec)
+    try:
+        jlb.jlb_set_two_step_variant(prec, -1)
+        jlb.jlb_set_multi_step_variant(prec, -1)
+        ref = jlb.solve(p, "fp32", fields=True)
+        jlb.jlb_set_two_step_variant(prec, 4)
+        jlb.jlb_set_multi_step_variant(prec, 0)
+        o = jlb.solve(p, "fp32", fields=True)
+    finally:
+        jlb.jlb_set_two_step_variant(prec, two0)
+        jlb.jlb_set_multi_step_variant(prec, multi0)
+    assert (o["main_kind"], o["main_variant"], o["main_launches"]) == (3, 3, 200)
+    for q in ("fx", "fy", "tz"):
+        assert o[q] == ref[q], q
+    for f in ("ez", "hx", "hy"):
+        assert np.array_equal(o[f], ref[f]), f
+
+
 def test_two_step_config2_matches_single_steps(jlb):
     """The headline workload with the autotuner's choice: forces identical to
     single steps."""
