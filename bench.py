@@ -262,7 +262,7 @@ def _kernel_choice(jlb, prec: str) -> dict:
     return {"single_step": jlb.STEP_VARIANTS.get(jlb.jlb_get_step_variant(p)),
             "two_step": jlb.TWO_STEP_VARIANTS.get(two) if two >= 0 else None,
             "multi_step": jlb.MULTI_STEP_VARIANTS.get(multi) if multi >= 0 else None,
-            "engine_rounds": ("four-step H16 X4 before each solve's window, two-step after" if two >= 0
+            "engine_rounds": ("four-step H16 X4, two-step for each solve's last one to three steps" if two >= 0
                               else "single steps")}
 
 

@@ -441,8 +441,8 @@ int jlb_engine_set_policy(jlb_engine *eng, int32_t policy, int32_t max_slots);
 /*
  * Four-step rounds (on by default): with `on`, the engine's FP32 / BF16
  * solves that use two-step kernels take one batched four-step launch
- * (multi-step variant 2, S4 H16 X4) per round of four steps while their next
- * four levels lie before their averaging window; with many solves resident
+ * (multi-step variant 2, S4 H16 X4) per round of four steps while four more
+ * levels remain (inside the averaging window too); with many solves resident
  * that variant has the least halo work per update, whatever jlb_autotune
  * chose for a single solve.  Results are the same bits either way.  Takes
  * effect at the next chunk.  JLB_E_ARG for a null engine.

@@ -1106,11 +1106,12 @@ __device__ __forceinline__ double batch_incident(const SolveDesc &d, int64_t n)
     return n < d.ramp_end ? d.src_tab[n] : d.src_tab[d.ramp_end + n % d.T];
 }
 
-// A two-step solve takes a multi-step launch while its next mdepth levels
-// all lie before the averaging window.
+// A two-step solve takes a multi-step launch while mdepth more levels remain
+// (inside the averaging window too: the launch keeps its intermediate levels'
+// contour fields and a batched contour launch accumulates the levels).
 __device__ __forceinline__ bool multi_mode(const SolveDesc &d, int64_t n)
 {
-    return d.mdepth > 0 && n + d.mdepth <= d.steps - d.window;
+    return d.mdepth > 0 && n + d.mdepth <= d.steps;
 }
 
 // Batched two-step launch: wavefront w takes items[w] (slot, strip, row
@@ -1175,7 +1176,7 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
     // fields of level `lev` (1 .. S - 1) on row r, at its contour-stencil nodes
     auto keep_mid = [&](int lev, int r, const RowData<V> &d, MaskT m) {
         if constexpr (MID) {
-            if (out_lane && r >= j0 && r < j0 + H && r < L.ny) {
+            if (mid && out_lane && r >= j0 && r < j0 + H && r < L.ny) {
 #pragma unroll
                 for (int v = 0; v < V; ++v)
                     if ((m >> (8 * v)) & MASK_CONTOUR) {
@@ -1353,7 +1354,11 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES, W) void k_stepm_neq_batch(Solv
     float einc[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) einc[k] = (float)batch_incident(d, n + k);
-    multi_step_wave<NeqT, V, H, HX, S, false>(d.L, d.state[d.cur], d.state[d.cur ^ 1], einc, nullptr, 0, t.tx, t.ty);
+    // intermediate levels' contour fields when one of them is averaged
+    float *mid = n + S - 1 > d.steps - d.window ? d.mid : nullptr;
+    const size_t mid_level = (size_t)3 * d.L.pitch * d.L.ny;
+    multi_step_wave<NeqT, V, H, HX, S, true>(d.L, d.state[d.cur], d.state[d.cur ^ 1], einc, mid, mid_level, t.tx,
+                                             t.ty);
 }
 
 // ---------------------------------------------------------------------------
@@ -1563,6 +1568,27 @@ __global__ void k_contour2_batch(SolveDesc *__restrict__ D)
         else contour_sample_f32(d.L, d.mid, 3 * d.L.plane, d.C, k);
     }
     if (!one && n + 2 > d.steps - d.window) contour_sample_f32(d.L, next, d.L.sfld, d.C, k);
+}
+
+// After a batched multi-step launch from level n (before the advance): the
+// averaged levels among n + 1 .. n + S, in time order -- the intermediate
+// ones from mid, the last from the state it wrote.
+__global__ void k_contourm_batch(SolveDesc *__restrict__ D)
+{
+    const SolveDesc &d = D[blockIdx.y];
+    const int64_t n = d.n;
+    if (!d.two || n >= d.steps || !multi_mode(d, n)) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.C.n) return;
+    const int64_t w0 = d.steps - d.window;  // levels above w0 are averaged
+    if (n + d.mdepth <= w0) return;
+    const size_t mid_level = (size_t)3 * d.L.pitch * d.L.ny;
+    double s[4];
+    contour_load(d.C, k, s);
+    for (int l = 1; l < d.mdepth; ++l)
+        if (n + l > w0) contour_add_f32(d.L, d.mid + (size_t)(l - 1) * mid_level, 3 * d.L.plane, d.C, k, s);
+    contour_add_f32(d.L, reinterpret_cast<const float *>(d.state[d.cur ^ 1]), d.L.sfld, d.C, k, s);
+    contour_store(d.C, k, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -2169,6 +2195,13 @@ hipError_t launch_contour2_batch(SolveDesc *d, int nslots, int max_nc, hipStream
 {
     if (nslots <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_contour2_batch, dim3((max_nc + 127) / 128, nslots), dim3(128), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_contourm_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s)
+{
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_contourm_batch, dim3((max_nc + 127) / 128, nslots), dim3(128), 0, s, d);
     return hipGetLastError();
 }
 

@@ -8,9 +8,10 @@
 // lattice steps is captured once in a hipGraph and replayed while the set of
 // resident solves is unchanged.  The chunk is K / 4 rounds of four steps:
 // one batched four-step launch over the (strip, row segment) items of the
-// FP32 / BF16 solves whose next four levels lie before their averaging window
-// (then their advance-by-four launch at the end of the round), and two double
-// steps for the others.  In a double step, solves on single steps (FP64, or
+// FP32 / BF16 solves with at least four levels to go, then the batched
+// contour launch of the averaged levels among them (the launch keeps its
+// intermediate levels' contour fields when one is averaged), two double steps
+// for the others, and the four-step solves' advance-by-four launch.  In a double step, solves on single steps (FP64, or
 // with two-step kernels off) take two rounds of one launch per precision
 // over their tiles, one batched contour launch and one advance launch, and
 // FP32 / BF16 solves take one batched two-step launch over their items, one
@@ -121,9 +122,9 @@ int engine_multi_variant(bool on)
 }
 
 // Which batched launches a resident solve needs over the next chunk of
-// CHUNK steps from its step n: four-step launches while its next four levels
-// lie before the window (mode checked per round on the device), two-step
-// launches otherwise.  Solves that stay in one mode for the whole chunk get
+// CHUNK steps from its step n: four-step launches while four more levels
+// remain (mode checked per round on the device), two-step launches for the
+// last one to three steps.  Solves that stay in one mode for the whole chunk get
 // items in one list only, so a launch does not spend wavefronts on solves
 // that skip it.
 uint8_t launch_part(const jlb_engine *e, const Request &r)
@@ -133,9 +134,9 @@ uint8_t launch_part(const jlb_engine *e, const Request &r)
     int depth = 0, rows = 0;
     if (e->multi[p] >= 0) multi_step_shape(e->multi[p], depth, rows);
     if (e->multi[p] < 0 || r.plan.ny < rows + depth) return 1;
-    const int64_t wstart = r.plan.prob.steps - r.plan.window;
-    if (r.n + depth > wstart) return 1;          // never in four-step mode again
-    if (r.n + CHUNK <= wstart) return 2;         // four-step mode in every round of the chunk
+    const int64_t total = r.plan.prob.steps;
+    if (r.n + depth > total) return 1;           // never in four-step mode again
+    if (r.n + CHUNK <= total) return 2;          // four-step mode in every round of the chunk
     return 3;
 }
 
@@ -425,6 +426,7 @@ hipError_t launch_quad_step(jlb_engine *e)
         if (e->nmitems[p] > 0)
             err = launch_stepm_batch(p, e->multi[p], e->d_desc, e->d_tiles + e->mitem_off[p], e->nmitems[p], e->remap,
                                      e->s);
+    if (e->any_multi && err == hipSuccess) err = launch_contourm_batch(e->d_desc, ns, e->max_nc, e->s);
     for (int k = 0; k < 2 && err == hipSuccess; ++k) err = launch_double_step(e);
     if (e->any_multi && err == hipSuccess) err = launch_advance(e->d_desc, ns, 2, e->s);
     return err;
@@ -606,13 +608,13 @@ int jlb_engine_run(jlb_engine *e, int64_t steps, int32_t *active)
         // host mirrors of the device counters (the advance kernels' rules)
         for (uint64_t t : e->resident) {
             Request &r = e->reqs[t];
-            const int64_t total = r.plan.prob.steps, wstart = total - r.plan.window;
+            const int64_t total = r.plan.prob.steps;
             const int p = r.plan.prob.precision;
             const bool two = e->two[p] >= 0;
             int mdepth = 0, mrows = 0;
             if (two && e->multi[p] >= 0) multi_step_shape(e->multi[p], mdepth, mrows);
             if (r.plan.ny < mrows + mdepth) mdepth = 0;
-            auto multi_mode = [&] { return mdepth > 0 && r.n + mdepth <= wstart; };
+            auto multi_mode = [&] { return mdepth > 0 && r.n + mdepth <= total; };
             auto double_step = [&] {
                 for (int i = 0; i < (two ? 1 : 2) && r.n < total; ++i) {
                     if (two && multi_mode()) return;

@@ -186,7 +186,7 @@ struct SolveDesc {
     int precision;
     int cur;                 // buffer holding the state at step n (device-updated)
     int two;                 // 1: advanced by two-step launches
-    int mdepth;              // > 0: four-step launches while four levels fit before the window
+    int mdepth;              // > 0: four-step launches while four more levels remain
 };
 
 // One block of work: a tile of one resident solve.
@@ -210,9 +210,14 @@ hipError_t launch_step2_batch(int precision, int variant, SolveDesc *d, const Ti
 // Strip and segment counts of a two-step variant for an nx x ny lattice.
 void two_step_shape(int variant, int nx, int ny, int &nsx, int &nsy);
 hipError_t launch_contour2_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s);
-// Four-step launches (a depth-4 variant; others: hipErrorInvalidValue) over the two-step solves
-// whose next mdepth levels all lie before the window ("multi mode"); the
-// two-step launches, their contour launches and advances skip those solves.
+// After a batched multi-step launch: the averaged levels of each solve in
+// multi mode, in time order.
+hipError_t launch_contourm_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s);
+// Four-step launches (a depth-4 variant; others: hipErrorInvalidValue) over
+// the two-step solves with at least mdepth levels to go ("multi mode"; the
+// launch keeps the intermediate levels' contour fields in the solve's mid
+// buffer when one of them is averaged); the two-step launches, their contour
+// launches and advances skip those solves.
 hipError_t launch_stepm_batch(int precision, int variant, SolveDesc *d, const Tile *items, int nitems, int remap,
                               hipStream_t s);
 // Advances the solves with two == which by one step (which = 0) or by up
