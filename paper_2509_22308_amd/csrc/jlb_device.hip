@@ -1000,6 +1000,9 @@ __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__re
         // use, hiding that much more latency); rows at n + 1: behind (side), cur
         RowData<V> a_cur, a_ahead, a_pre, tmp;
         MaskT m_cur, m_ahead, m_pre = 0, m_prev = 0, m_dummy;
+        float ie_prev[V], er_prev[V];  // coefficients of the row behind (m_prev)
+#pragma unroll
+        for (int v = 0; v < V; ++v) ie_prev[v] = er_prev[v] = 0.0f;
         load(first - DIR, tmp, m_dummy);
         SideRow<V> a_behind = side_of(tmp, BQA, BQB);
         load(first, a_cur, m_cur);
@@ -1034,8 +1037,10 @@ __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__re
             // step n -> n + 1 on row r1
             RowData<V> b_new;
             const SideRow<V> a_side = side_of(a_ahead, AQA, AQB);
-            row_update<NeqT, V, false>(L, i0, r1, m_cur, a_cur, DIR > 0 ? a_behind : a_side,
-                                       DIR > 0 ? a_side : a_behind, s0, einc0, b_new);
+            float ie[V], er[V];  // the row's material coefficients, reused by the second step
+            row_coefs<V, false>(L, m_cur, ie, er);
+            row_update_k<NeqT, V, false>(L, i0, r1, m_cur, ie, er, a_cur, DIR > 0 ? a_behind : a_side,
+                                         DIR > 0 ? a_side : a_behind, s0, einc0, b_new);
             round_row<NeqT, V>(b_new);
             if (one) {
                 // a single step: this row's result is the new state
@@ -1061,8 +1066,8 @@ __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__re
                 const int r2 = r1 - DIR;
                 RowData<V> o;
                 const SideRow<V> b_side = side_of(b_new, AQA, AQB);
-                row_update<NeqT, V, false>(L, i0, r2, m_prev, b_cur, DIR > 0 ? b_behind : b_side,
-                                           DIR > 0 ? b_side : b_behind, s1, einc1, o);
+                row_update_k<NeqT, V, false>(L, i0, r2, m_prev, ie_prev, er_prev, b_cur,
+                                             DIR > 0 ? b_behind : b_side, DIR > 0 ? b_side : b_behind, s1, einc1, o);
                 mask_row<V>(L, i0, m_prev, false, o);
                 if (out_lane && r2 < L.ny)
                     store_row_at<NeqT, V>(DF + (size_t)r2 * L.sf, Pu, (unsigned)i0, o, L.stream_stores);
@@ -1070,6 +1075,11 @@ __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__re
             b_behind = side_of(b_cur, BQA, BQB);
             b_cur = b_new;
             m_prev = m_cur;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                ie_prev[v] = ie[v];
+                er_prev[v] = er[v];
+            }
             a_behind = side_of(a_cur, BQA, BQB);
             a_cur = a_ahead;
             m_cur = m_ahead;
