@@ -70,11 +70,19 @@ _vp = ctypes.c_void_p
 
 
 def load():
-    """Load libjlb.so (raises if it is missing: there is no fallback path)."""
+    """Load libjlb.so (raises if it is missing: there is no fallback path).
+
+    PyTorch ships its own HIP runtime under the same soname as the system
+    one.  The library must bind to the runtime torch uses, so torch is
+    imported and its runtime initialised before the library is opened;
+    opened first, the library would pull in the system runtime and the
+    process would hold two, neither of which can then serve both."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run python paper_2509_22308_amd/build.py")
+        import torch
+        torch.cuda.is_available()
         lib = ctypes.CDLL(LIB_PATH)
         sig = {
             "jlb_version": ([], ctypes.c_int),

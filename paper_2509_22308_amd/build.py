@@ -22,18 +22,24 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 
 def build(verbose: bool = False) -> str:
     with tempfile.TemporaryDirectory(prefix="jlb_build_") as tmp:
-        objs = []
+        objs, procs = [], []
+        # the translation units compile side by side
         for src in SOURCES:
             obj = os.path.join(tmp, src + ".o")
             lang = ["-x", "hip"] if src.endswith(".hip") else []
             cmd = [HIPCC, f"--offload-arch={ARCH}", *COMMON, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            r = subprocess.run(cmd, capture_output=True, text=True)
-            if r.returncode != 0:
-                sys.stderr.write(r.stdout + r.stderr)
-                raise RuntimeError(f"hipcc failed on {src}")
+            procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
             objs.append(obj)
+        failed = []
+        for src, pr in procs:
+            out, _ = pr.communicate()
+            if pr.returncode != 0:
+                sys.stderr.write(out)
+                failed.append(src)
+        if failed:
+            raise RuntimeError(f"hipcc failed on {', '.join(failed)}")
         out = LIB + ".tmp%d" % os.getpid()
         cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out, *objs]
         r = subprocess.run(cmd, capture_output=True, text=True)
