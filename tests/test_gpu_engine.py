@@ -155,9 +155,13 @@ def test_two_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, precisi
 @pytest.mark.parametrize("four", [True, False])
 @pytest.mark.parametrize("chunk", [256, 130])
 def test_four_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, four, chunk):
-    """Rounds of four steps: solves whose next four levels lie before their
-    window take one batched four-step launch, the others two double steps;
-    every solve at its own step.  A run of 130 steps ends on a lone double
+    """Rounds of four steps: a solve with at least four more levels to go
+    takes the round's batched four-step launch, inside its averaging window
+    too (the launch keeps the intermediate levels' contour fields); a solve
+    with one to three levels left takes double steps; every solve runs at
+    its own step.  The mix has window starts that are not multiples of four
+    (steps 530 and 361), so four-step rounds straddle a window start.  A run
+    of 130 steps ends on a lone double
     step in which the four-step solves wait.  A grid too short for the
     variant (ny = 19) stays on two-step launches.  Each result equals its
     single solve bit for bit, with the engine's four-step rounds on and off
