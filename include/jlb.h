@@ -244,6 +244,29 @@ int jlb_solve_far_field(const jlb_problem *prob, void *workspace, size_t workspa
                         int32_t n_angles, double *s2, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it): the
+ * solve of jlb_solve on a workspace the library holds itself, a file-scope
+ * device array of JLB_STATIC_SCRATCH_BYTES bytes per device, created when the
+ * library is loaded on that device and kept until the process ends.  The call
+ * allocates no device memory and creates no stream, event or graph: every
+ * step is a direct launch on `stream`, and the results equal those of
+ * jlb_solve bit for bit.
+ *   prob             as for jlb_solve (no plateau stop: JLB_E_ARG)
+ *   res              host struct; loop_ms is host time, main_* are 0
+ *   ez, hx, hy       optional device arrays [ny][nx] of double, as jlb_solve
+ *   stream           hipStream_t as void* (NULL = the null stream)
+ * The array is shared by every call on a device and keeps the last call's
+ * contents; the call clears what must start at zero.  Calls that overlap on
+ * one device (other threads, other streams) race on it and must not be made.
+ * Errors: as jlb_validate; JLB_E_OOM when jlb_workspace_size(prob) exceeds
+ * JLB_STATIC_SCRATCH_BYTES (use jlb_solve then); JLB_E_DEVICE;
+ * JLB_E_NONFINITE.
+ */
+#define JLB_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int jlb_solve_static(const jlb_problem *prob, jlb_result *res, double *ez, double *hx, double *hy, void *stream);
+
+/*
  * Overdamped motion of the cylinder under its radiation force and torque
  * (Sec. IV.C: force and torque balance with the slender-body resistance,
  * giving in t~ = t / T0, T0 = a eta / F0, (x~, y~) = (x, y) / a:

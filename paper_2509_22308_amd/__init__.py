@@ -95,6 +95,7 @@ def load():
             "jlb_solve_force_trace": ([_P(jlb_problem), _vp, ctypes.c_size_t, _P(jlb_result), _vp, _vp], ctypes.c_int),
             "jlb_solve_far_field": ([_P(jlb_problem), _vp, ctypes.c_size_t, _P(jlb_result), ctypes.c_int32, _vp,
                                      _vp], ctypes.c_int),
+            "jlb_solve_static": ([_P(jlb_problem), _P(jlb_result), _vp, _vp, _vp, _vp], ctypes.c_int),
             "jlb_trajectory": ([ctypes.c_int32, ctypes.c_double, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _vp], ctypes.c_int),
             "jlb_time_step_kernel": ([_P(jlb_problem), _vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
@@ -222,6 +223,18 @@ def jlb_solve_far_field(prob: jlb_problem, n_angles: int, s2, workspace=None, st
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(load().jlb_solve_far_field(ctypes.byref(prob), _dptr(workspace), nbytes, ctypes.byref(res), int(n_angles),
                                       _dptr(s2), _stream(stream)))
+    return res
+
+
+JLB_STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def jlb_solve_static(prob: jlb_problem, ez=None, hx=None, hy=None, stream=None) -> jlb_result:
+    """The solve of jlb_solve on the library-held scratch (no device allocation
+    by the library; fields are optional CUDA float64 tensors [ny][nx])."""
+    res = jlb_result()
+    _check(load().jlb_solve_static(ctypes.byref(prob), ctypes.byref(res), _dptr(ez), _dptr(hx), _dptr(hy),
+                                   _stream(stream)))
     return res
 
 

@@ -51,6 +51,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "jlb_internal.h"
@@ -2267,6 +2268,38 @@ hipError_t launch_fields_out(int precision, const Lattice &L, const void *fields
     else
         hipLaunchKernelGGL(k_fields_out<float>, grid, dim3(256), 0, s, L, (const float *)fields, ez, hx, hy);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Library-held scratch for callers that cannot allocate device memory
+// (jlb_solve_static).  One array per device, zero at load, kept until the
+// process ends.  In host code the array's name is only a stand-in: its
+// device address comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that address is ever handed to kernels or
+// copies.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(void **ptr)
+{
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void *addr[MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace jlb

@@ -23,6 +23,7 @@ namespace jlb {
 static_assert(JLB_STEP_VARIANTS == NEQ_VARIANTS, "single-step variant count");
 static_assert(JLB_FP64_STEP_VARIANTS == F64_VARIANTS, "FP64 variant count");
 static_assert(JLB_TWO_STEP_VARIANTS == TWO_STEP_VARIANTS, "two-step variant count");
+static_assert(JLB_STATIC_SCRATCH_BYTES == STATIC_SCRATCH_BYTES, "library-held scratch size");
 
 // ---------------------------------------------------------------------------
 // Errors
@@ -411,7 +412,7 @@ static int launch_one_step(const Plan &q, char *ws, const Lattice &L, const Cont
 }
 
 int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, double *hy, double *energy,
-              hipStream_t s, FarOut far)
+              hipStream_t s, FarOut far, bool events)
 {
     const auto t0 = std::chrono::steady_clock::now();
     memset(res, 0, sizeof(*res));
@@ -464,12 +465,18 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
         return JLB_OK;
     };
 
-    hipEvent_t ev0, ev1, evm0, evm1;
-    HIP_TRY(hipEventCreate(&ev0));
-    HIP_TRY(hipEventCreate(&ev1));
-    HIP_TRY(hipEventCreate(&evm0));
-    HIP_TRY(hipEventCreate(&evm1));
-    HIP_TRY(hipEventRecord(ev0, s));
+    // timing events (a solve that may not create device objects runs without
+    // them: its loop time is then the host's, and the pre-window stretch is
+    // not timed)
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evm0 = nullptr, evm1 = nullptr;
+    if (events) {
+        HIP_TRY(hipEventCreate(&ev0));
+        HIP_TRY(hipEventCreate(&ev1));
+        HIP_TRY(hipEventCreate(&evm0));
+        HIP_TRY(hipEventCreate(&evm1));
+        HIP_TRY(hipEventRecord(ev0, s));
+    }
+    const auto loop_t0 = std::chrono::steady_clock::now();
     // the graph-replayed periods before the window: which kernel, how many launches
     const int main_kind = multi >= 0 ? 3 : two >= 0 ? 2 : 1;
     const int main_variant = multi >= 0 ? multi : two >= 0 ? two : step_variant(q.prob.precision);
@@ -561,9 +568,9 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
                 rc = fail(JLB_E_DEVICE, "internal: graph phase mismatch");
                 break;
             }
-            hipError_t e = which == 0 && main_launches == 0 ? hipEventRecord(evm0, s) : hipSuccess;
+            hipError_t e = events && which == 0 && main_launches == 0 ? hipEventRecord(evm0, s) : hipSuccess;
             if (e == hipSuccess) e = hipGraphLaunch(gexec[which], s);
-            if (e == hipSuccess && which == 0) e = hipEventRecord(evm1, s);
+            if (e == hipSuccess && events && which == 0) e = hipEventRecord(evm1, s);
             if (e != hipSuccess) {
                 rc = fail(JLB_E_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
                 break;
@@ -622,7 +629,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
         ++n;
     }
     if (rc == JLB_OK) {
-        hipError_t e = hipEventRecord(ev1, s);
+        hipError_t e = events ? hipEventRecord(ev1, s) : hipSuccess;
         if (e == hipSuccess) e = launch_reduce(C, 1.0 / (double)q.window, M_PI * q.prob.radius * q.prob.e0 * q.prob.e0 / 4.0,
                                                2.0 * (M_PI * q.prob.radius * q.prob.e0 * q.prob.e0 / 4.0) * q.prob.radius,
                                                (double *)(ws + q.off_out), s);
@@ -639,7 +646,8 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
         if (e != hipSuccess) rc = fail(JLB_E_DEVICE, "finishing the solve: %s", hipGetErrorString(e));
         if (rc == JLB_OK) {
             float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, ev0, ev1);
+            if (events) (void)hipEventElapsedTime(&ms, ev0, ev1);
+            else ms = (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - loop_t0).count();
             res->fx = out[0];
             res->fy = out[1];
             res->tz = out[2];
@@ -654,7 +662,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             res->bytes_per_step = (int64_t)q.bytes_per_lup * q.nx * q.ny;
             res->state_passes = passes;
             res->energy_final = out[6];
-            if (main_launches > 0 && !(q.prob.plateau_tol > 0.0)) {
+            if (events && main_launches > 0 && !(q.prob.plateau_tol > 0.0)) {
                 float mms = 0.0f;
                 (void)hipEventElapsedTime(&mms, evm0, evm1);
                 res->main_ms = mms;
@@ -670,10 +678,8 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     }
     for (auto &g : gexec)
         if (g) (void)hipGraphExecDestroy(g);
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
-    (void)hipEventDestroy(evm0);
-    (void)hipEventDestroy(evm1);
+    for (hipEvent_t ev : {ev0, ev1, evm0, evm1})
+        if (ev) (void)hipEventDestroy(ev);
     res->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return rc;
 }
@@ -796,6 +802,27 @@ int jlb_solve_far_field(const jlb_problem *prob, void *workspace, size_t workspa
         return fail(JLB_E_ARG, "n_angles %d outside 1..%d", n_angles, JLB_MAX_FAR_ANGLES);
     return solve_entry(prob, workspace, workspace_bytes, res, nullptr, nullptr, nullptr, nullptr, stream,
                        FarOut{n_angles, s2});
+}
+
+int jlb_solve_static(const jlb_problem *prob, jlb_result *res, double *ez, double *hx, double *hy, void *stream)
+{
+    clear_error();
+    if (!res) return fail(JLB_E_ARG, "null result");
+    Plan q;
+    int rc = make_plan(prob, &q);
+    if (rc) return rc;
+    if ((ez || hx || hy) && !(ez && hx && hy)) return fail(JLB_E_ARG, "ez, hx, hy must all be given or all NULL");
+    if (q.prob.plateau_tol > 0.0) return fail(JLB_E_ARG, "jlb_solve_static has no plateau stop");
+    if (q.ws_bytes > JLB_STATIC_SCRATCH_BYTES)
+        return fail(JLB_E_OOM, "problem needs %zu bytes of scratch, more than the library-held %zu (use jlb_solve)",
+                    q.ws_bytes, (size_t)JLB_STATIC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    hipError_t e = static_scratch(&ws);
+    if (e != hipSuccess) return fail(JLB_E_DEVICE, "scratch address: %s", hipGetErrorString(e));
+    // direct launches on the caller's stream: no graph, no stream or event of
+    // the library's own
+    q.prob.flags |= JLB_F_NO_GRAPH;
+    return run_solve(q, (char *)ws, res, ez, hx, hy, nullptr, (hipStream_t)stream, FarOut{0, nullptr}, false);
 }
 
 // kind: 1 single-step, 2 two-step, 3 multi-step variant

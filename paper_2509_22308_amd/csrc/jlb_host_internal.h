@@ -67,6 +67,6 @@ struct FarOut {
     double *force = nullptr;
 };
 int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, double *hy, double *energy,
-              hipStream_t s, FarOut far = {0, nullptr});
+              hipStream_t s, FarOut far = {0, nullptr}, bool events = true);
 
 }  // namespace jlb

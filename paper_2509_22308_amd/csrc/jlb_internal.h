@@ -163,6 +163,10 @@ hipError_t launch_energy(int precision, const Lattice &L, const void *fields, do
                          double *out, hipStream_t s);
 int energy_partials(const Lattice &L);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+// Device address of the library-held scratch array of the current device
+// (JLB_STATIC_SCRATCH_BYTES bytes, 256-byte aligned), looked up once per device.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)64 << 20;
+hipError_t static_scratch(void **ptr);
 hipError_t launch_fields_out(int precision, const Lattice &L, const void *fields, double *ez, double *hx, double *hy,
                              hipStream_t s);
 
