@@ -12,7 +12,10 @@
  *   Sec. III, Eqs. (LBGK equation), (equilibrium distribution functions)
  *                               D3Q7 electric and magnetic populations,
  *                               tau = 1/2 update f -> 2 f^eq - f, fields as
- *                               moments, per-cell permittivity, mu_r = 1.
+ *                               moments, per-cell permittivity, mu_r = 1;
+ *                               a perfect conductor (E_z^tot = 0, Sec. II)
+ *                               is a node whose electric field is zero, the
+ *                               update's limit of infinite permittivity.
  *   Sec. II.B, Eqs. (stress tensor average), (force), (torque)
  *                               time-averaged Maxwell stress on a closed
  *                               contour around the body -> F_x, F_y, M_z,

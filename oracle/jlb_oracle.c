@@ -45,10 +45,11 @@
  *     relaxed by delta so that non-radiating static fields around a PEC body
  *     are not fed by the edges.  At the right edge I_q = 0; at the bottom and
  *     top I_q(ghost) = I_q(x_b) = strip value in the same column;
- *   - PEC: link-wise reflection with the wall half-way along the link;
- *     electric components tangential to the wall and the magnetic component
- *     normal to it are reflected with a sign change, the others without;
- *     PEC cells carry no populations and report zero fields;
+ *   - PEC: a conductor node is a lattice node whose electric field is zero,
+ *     the limit of the update for infinite permittivity (E = D / eps -> 0):
+ *     it pulls, collides and streams like every other node with E set to 0
+ *     in its equilibria, so E_z^tot = 0 holds on the conductor nodes and the
+ *     wall sits on them.  Conductor nodes report zero fields;
  *   - staircase geometry on node coordinates, centre ((nx-1)/2, (ny-1)/2),
  *     inside when |d|^2 <= a^2, region II on the side of
  *     n_II = (-sin phi0, -cos phi0) when d.n_II > 1e-9, otherwise region III;
@@ -240,7 +241,6 @@ enum { EDGE_OPEN = 0, EDGE_PERIODIC = 1, EDGE_STRIP = 2, EDGE_XOPEN = 3 };
 #define OPEN_DELTA (1.0 / 20.0)
 static const int pop_cx[NPOP] = {0, 1, -1, 0, 0, 0, 1, -1, 0, 0, 0};
 static const int pop_cy[NPOP] = {0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1};
-static const int pop_opp[NPOP] = {0, 2, 1, 4, 3, 5, 7, 6, 8, 10, 9};
 
 static void reduced_moments(const double f[NPOP], double eps, double *ez, double *hx, double *hy)
 {
@@ -280,9 +280,7 @@ static void reduced_equilibrium(double eps, double ez, double hx, double hy, dou
 /*   5 ex_r  6 ex_{+x}  7 ex_{-x}  8 ey_r  9 ey_{+y}  10 ey_{-y}             */
 /* Moments: Hz = sum of 0..4, eps Ex = f5 + f6 + f7 + (f4 - f3),             */
 /*          eps Ey = f8 + f9 + f10 + (f1 - f2).                              */
-/* Conductor walls (the literal rule: E tangential and H normal flip): every */
-/* TE^z population here is either E normal or H tangential to the wall it   */
-/* meets, so all of them bounce back without a sign change.                  */
+/* Conductor nodes hold Ex = Ey = 0 (the whole in-plane electric field).    */
 /* ------------------------------------------------------------------------ */
 
 static void reduced_te_moments(const double f[NPOP], double eps, double *hz, double *ex, double *ey)
@@ -323,16 +321,11 @@ static void reduced_step(const orc_params *p, int edges, int nx, int ny, const u
     double inc[NPOP];
     if (te) reduced_te_equilibrium(1.0, einc, 0.0, einc, inc);
     else reduced_equilibrium(1.0, einc, 0.0, -einc, inc);
-    const double wall = te ? 1.0 : -1.0;   /* conductor reflection sign */
 #pragma omp parallel for schedule(static) num_threads(p->threads > 0 ? p->threads : 1)
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
             size_t c = (size_t)j * nx + i;
-            if (mat && mat[c] == MAT_PEC) {
-                for (int q = 0; q < NPOP; ++q) dst[q * plane + c] = 0.0;
-                ez[c] = hx[c] = hy[c] = 0.0;
-                continue;
-            }
+            const int conductor = mat && mat[c] == MAT_PEC;
             double f[NPOP];
             for (int q = 0; q < NPOP; ++q) {
                 int si = i - pop_cx[q], sj = j - pop_cy[q];
@@ -355,9 +348,7 @@ static void reduced_step(const orc_params *p, int edges, int nx, int ny, const u
                     else if (pop_cx[q] == -1) f[q] = (1.0 - OPEN_DELTA) * own;            /* right */
                     else f[q] = (1.0 - OPEN_DELTA) * own + OPEN_DELTA * strip[q * (size_t)nx + i]; /* top, bottom */
                 } else {
-                    size_t s = (size_t)sj * nx + si;
-                    if (mat && mat[s] == MAT_PEC) f[q] = wall * src[pop_opp[q] * plane + c];
-                    else f[q] = src[q * plane + s];
+                    f[q] = src[q * plane + (size_t)sj * nx + si];
                 }
             }
             double eps = mat ? eps_of(p, mat[c]) : 1.0;
@@ -365,12 +356,15 @@ static void reduced_step(const orc_params *p, int edges, int nx, int ny, const u
             double eq[NPOP];
             if (te) {
                 reduced_te_moments(f, eps, &e, &a, &b);
+                if (conductor) { a = 0.0; b = 0.0; }   /* Ex = Ey = 0 */
                 reduced_te_equilibrium(eps, e, a, b, eq);
             } else {
                 reduced_moments(f, eps, &e, &a, &b);
+                if (conductor) e = 0.0;                /* Ez = 0 */
                 reduced_equilibrium(eps, e, a, b, eq);
             }
             for (int q = 0; q < NPOP; ++q) dst[q * plane + c] = 2.0 * eq[q] - f[q];
+            if (conductor) e = a = b = 0.0;           /* reported fields */
             ez[c] = e; hx[c] = a; hy[c] = b;
         }
     }
@@ -382,7 +376,6 @@ static void reduced_step(const orc_params *p, int edges, int nx, int ny, const u
 /* ------------------------------------------------------------------------ */
 
 static const int lit_c[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
-static const int lit_opp[7] = {0, 2, 1, 4, 3, 6, 5};
 
 static void cross3(const double a[3], const double b[3], double r[3])
 {
@@ -426,11 +419,7 @@ static void literal_step(const orc_params *p, int edges, int nx, int ny, const u
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
             size_t c = (size_t)j * nx + i;
-            if (mat && mat[c] == MAT_PEC) {
-                for (size_t q = 0; q < 42; ++q) dst[q * plane + c] = 0.0;
-                ez[c] = hx[c] = hy[c] = 0.0;
-                continue;
-            }
+            const int conductor = mat && mat[c] == MAT_PEC;
             double e[7][3], h[7][3];
             for (int v = 0; v < 7; ++v) {
                 int si = i - lit_c[v][0], sj = j - lit_c[v][1];
@@ -474,21 +463,9 @@ static void literal_step(const orc_params *p, int edges, int nx, int ny, const u
                     continue;
                 }
                 size_t s = (size_t)sj * nx + si;
-                if (mat && mat[s] == MAT_PEC) {
-                    /* wall normal along the link axis */
-                    int axis = lit_c[v][0] != 0 ? 0 : 1;
-                    int o = lit_opp[v];
-                    for (int k = 0; k < 3; ++k) {
-                        double se = (k == axis) ? 1.0 : -1.0;   /* E: tangential flips */
-                        double sh = (k == axis) ? -1.0 : 1.0;   /* H: normal flips */
-                        e[v][k] = se * src[LIDX(0, o, k) + c];
-                        h[v][k] = sh * src[LIDX(1, o, k) + c];
-                    }
-                } else {
-                    for (int k = 0; k < 3; ++k) {
-                        e[v][k] = src[LIDX(0, v, k) + s];
-                        h[v][k] = src[LIDX(1, v, k) + s];
-                    }
+                for (int k = 0; k < 3; ++k) {
+                    e[v][k] = src[LIDX(0, v, k) + s];
+                    h[v][k] = src[LIDX(1, v, k) + s];
                 }
             }
             double eps = mat ? eps_of(p, mat[c]) : 1.0;
@@ -496,6 +473,7 @@ static void literal_step(const orc_params *p, int edges, int nx, int ny, const u
             for (int v = 0; v < 7; ++v)
                 for (int k = 0; k < 3; ++k) { E[k] += e[v][k]; H[k] += h[v][k]; }
             for (int k = 0; k < 3; ++k) { E[k] /= eps; H[k] /= 1.0; }
+            if (conductor) E[0] = E[1] = E[2] = 0.0;   /* E = 0 on a conductor node */
             for (int v = 0; v < 7; ++v) {
                 double eeq[3], heq[3];
                 literal_equilibrium(v, eps, E, H, eeq, heq);
@@ -504,7 +482,8 @@ static void literal_step(const orc_params *p, int edges, int nx, int ny, const u
                     dst[LIDX(1, v, k) + c] = 2.0 * heq[k] - h[v][k];
                 }
             }
-            if (te) { ez[c] = H[2]; hx[c] = E[0]; hy[c] = E[1]; }
+            if (conductor) ez[c] = hx[c] = hy[c] = 0.0;   /* reported fields */
+            else if (te) { ez[c] = H[2]; hx[c] = E[0]; hy[c] = E[1]; }
             else { ez[c] = E[2]; hx[c] = H[0]; hy[c] = H[1]; }
         }
     }

@@ -21,9 +21,11 @@
 // edge are the incident-wave equilibria (E_z = E_inc, H_y = -E_inc); those
 // entering through the other edges extrapolate the scattered part with
 // zero gradient relaxed by OPEN_DELTA against the undisturbed incident wave,
-// which a one-row companion lattice (row ny) carries; a link to a perfect
-// conductor reflects the opposite population with a sign change (wall at
-// the link midpoint).  Conductor nodes hold nothing and are never written.
+// which a one-row companion lattice (row ny) carries.  A perfect conductor
+// (Sec. II: E_z^tot = 0) is the update's limit of infinite permittivity: its
+// nodes are updated like every other node with the electric field set to
+// zero (the coefficient 1/eps of the moment that carries the permittivity is
+// 0), so the wall sits on the conductor nodes.
 //
 // Storage: FP64 keeps the 11 populations per node (176 bytes per update).
 // FP32 and BF16 keep one sixth of the fields, (Ez, Hx, Hy) / 6, in FP32 and
@@ -41,11 +43,10 @@
 // TE^z (Hz, Ex, Ey; the polarisation the paper leaves for later, Sec. I) is
 // the same update under the vacuum duality E -> H, H -> -E: the state holds
 // (Hz, -Ex, -Ey) in the (Ez, Hx, Hy) slots and the populations accordingly,
-// the permittivity moves to the in-plane fields (moments eps Ex, eps Ey; rest
-// equilibria Hz/3 and (eps - 2/3) Ex, (eps - 2/3) Ey), and a conductor link
-// reflects without a sign change (every TE^z population meets a wall as a
-// normal E or a tangential H component).  Source, open edges, companion row,
-// stress sums and far-field phasors are unchanged in the dual storage.
+// and the permittivity moves to the in-plane fields (moments eps Ex, eps Ey;
+// rest equilibria Hz/3 and (eps - 2/3) Ex, (eps - 2/3) Ey), so a conductor
+// node holds Ex = Ey = 0.  Source, open edges, companion row, stress sums and
+// far-field phasors are unchanged in the dual storage.
 //
 // No MFMA: the step is a stencil with about 0.3 flop per byte.
 #include <hip/hip_runtime.h>
@@ -76,8 +77,7 @@ constexpr int BY = 4;   // four rows per block
 // Material parameters by id.  Ids vary per lane; the compiler would turn a
 // select among the uniform values back into an indexed vector load (whose
 // wait also waits for every load issued before it, look-ahead rows
-// included), so the values pass through readfirstlane first.  Id 3
-// (conductor) is never asked for.
+// included), so the values pass through readfirstlane first.
 __device__ __forceinline__ float uniform(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
 __device__ __forceinline__ double uniform(double x)
 {
@@ -88,8 +88,8 @@ __device__ __forceinline__ double uniform(double x)
 }
 template <typename R> __device__ __forceinline__ R mat_pick(const double (&v)[4], int mat)
 {
-    const R v0 = uniform((R)v[0]), v1 = uniform((R)v[1]), v2 = uniform((R)v[2]);
-    return mat == 0 ? v0 : mat == 1 ? v1 : v2;
+    const R v0 = uniform((R)v[0]), v1 = uniform((R)v[1]), v2 = uniform((R)v[2]), v3 = uniform((R)v[3]);
+    return mat == 0 ? v0 : mat == 1 ? v1 : mat == 2 ? v2 : v3;
 }
 __device__ __forceinline__ double mat_eps(const Lattice &L, int mat) { return mat_pick<double>(L.eps, mat); }
 __device__ __forceinline__ double mat_eps_rest(const Lattice &L, int mat) { return mat_pick<double>(L.eps_rest, mat); }
@@ -97,8 +97,8 @@ __device__ __forceinline__ double mat_eps_rest(const Lattice &L, int mat) { retu
 // select runs on 32-bit values and needs no conversion per node.
 __device__ __forceinline__ float mat_pick_f(const float (&v)[4], int mat)
 {
-    const float v0 = uniform(v[0]), v1 = uniform(v[1]), v2 = uniform(v[2]);
-    return mat == 0 ? v0 : mat == 1 ? v1 : v2;
+    const float v0 = uniform(v[0]), v1 = uniform(v[1]), v2 = uniform(v[2]), v3 = uniform(v[3]);
+    return mat == 0 ? v0 : mat == 1 ? v1 : mat == 2 ? v2 : v3;
 }
 __device__ __forceinline__ float mat_eps_rest_f(const Lattice &L, int mat) { return mat_pick_f(L.eps_rest_f, mat); }
 __device__ __forceinline__ float mat_inv_eps_f(const Lattice &L, int mat) { return mat_pick_f(L.inv_eps_f, mat); }
@@ -152,7 +152,7 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
     const double keep = 1.0 - OPEN_DELTA;
     double f[11];
     double eps = 1.0, eps_rest = 1.0 - 2.0 / 3.0;
-    const double wall = L.te ? 1.0 : -1.0;  // conductor reflection sign
+    bool conductor = false;
 
     f[0] = src[0 * P + c];
     f[5] = src[5 * P + c];
@@ -168,32 +168,27 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
         if (i == L.nx - 1) { f[2] = 0.0; f[7] = 0.0; }
         else { f[2] = src[2 * P + c + 1]; f[7] = src[7 * P + c + 1]; }
     } else {
-        const uint8_t m = L.mask[node(L, i, j)];
-        const int mat = m & 3;
-        if (mat == MAT_PEC) return;
+        const int mat = L.mask[node(L, i, j)] & 3;
+        conductor = mat == MAT_PEC;
         eps = mat_eps(L, mat);
         eps_rest = mat_eps_rest(L, mat);
         const size_t strip = at(i, L.ny, L.sf);
         // +x populations come from (i-1, j)
         if (i == 0) { f[1] = einc / 3.0; f[6] = 0.0; }
-        else if (m & NB_PEC_XM) { f[1] = wall * src[2 * P + c]; f[6] = wall * src[7 * P + c]; }
         else { f[1] = src[1 * P + c - 1]; f[6] = src[6 * P + c - 1]; }
         // -x populations come from (i+1, j)
         if (i == L.nx - 1) { f[2] = keep * src[2 * P + c]; f[7] = keep * src[7 * P + c]; }
-        else if (m & NB_PEC_XP) { f[2] = wall * src[1 * P + c]; f[7] = wall * src[6 * P + c]; }
         else { f[2] = src[2 * P + c + 1]; f[7] = src[7 * P + c + 1]; }
         // +y populations come from (i, j-1)
         if (j == 0) {
             f[3] = keep * src[3 * P + c] + OPEN_DELTA * src[3 * P + strip];
             f[9] = keep * src[9 * P + c] + OPEN_DELTA * src[9 * P + strip];
-        } else if (m & NB_PEC_YM) { f[3] = wall * src[4 * P + c]; f[9] = wall * src[10 * P + c]; }
-        else { f[3] = src[3 * P + c - L.sf]; f[9] = src[9 * P + c - L.sf]; }
+        } else { f[3] = src[3 * P + c - L.sf]; f[9] = src[9 * P + c - L.sf]; }
         // -y populations come from (i, j+1)
         if (j == L.ny - 1) {
             f[4] = keep * src[4 * P + c] + OPEN_DELTA * src[4 * P + strip];
             f[10] = keep * src[10 * P + c] + OPEN_DELTA * src[10 * P + strip];
-        } else if (m & NB_PEC_YP) { f[4] = wall * src[3 * P + c]; f[10] = wall * src[9 * P + c]; }
-        else { f[4] = src[4 * P + c + L.sf]; f[10] = src[10 * P + c + L.sf]; }
+        } else { f[4] = src[4 * P + c + L.sf]; f[10] = src[10 * P + c + L.sf]; }
     }
 
     const double dz = f[0] + f[1] + f[2] + (f[3] + f[4]);
@@ -203,6 +198,7 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
         ez = dz;
         hx = (f[5] + f[6] + f[7] + (f[3] - f[4])) / eps;
         hy = (f[8] + (f[9] + f[10]) + (f[2] - f[1])) / eps;
+        if (conductor) { hx = 0.0; hy = 0.0; }  // Ex = Ey = 0
         q[0] = ez / 3.0;
         q[5] = eps_rest * hx;
         q[8] = eps_rest * hy;
@@ -210,6 +206,7 @@ __device__ __forceinline__ void f64_node(const Lattice &L, const double *__restr
         ez = dz / eps;
         hx = f[5] + f[6] + f[7] + (f[3] - f[4]);
         hy = f[8] + (f[9] + f[10]) + (f[2] - f[1]);
+        if (conductor) ez = 0.0;  // Ez = 0
         q[0] = eps_rest * ez;
         q[5] = hx / 3.0;
         q[8] = hy / 3.0;
@@ -299,23 +296,22 @@ __device__ __forceinline__ Side load_side(const float *F, const NeqT *N, size_t 
 
 // Material coefficients of one node's update.  TM^z: the z field carries the
 // permittivity (Dz = eps Ez, rest equilibrium (eps - 2/3) Ez, in-plane rests
-// H/3) and conductor links reflect with a sign change.  TE^z in the dual
-// storage: the in-plane fields carry it, the z field's rest is Hz/3, and
-// conductor links reflect without a sign change.
-// With the stored fields one sixth of the physical ones, a carries a factor
-// 1/6 and c a factor 6: inv_eps6 = 1 / (6 eps), eps_rest6 = 6 (eps - 2/3).
+// H/3).  TE^z in the dual storage: the in-plane fields carry it and the z
+// field's rest is Hz/3.  With the stored fields one sixth of the physical
+// ones, a carries a factor 1/6 and c a factor 6: inv_eps6 = 1 / (6 eps),
+// eps_rest6 = 6 (eps - 2/3); a conductor node has inv_eps6 = 0 (its
+// electric field is zero) and eps_rest6 = 0.
 struct Coef {
     float az, axy;  // stored field = moment sum * a
     float cz, cxy;  // rest equilibrium = c * stored field
-    float wall;     // conductor reflection sign
 };
 __device__ __forceinline__ Coef coef_tm(float inv_eps6, float eps_rest6)
 {
-    return Coef{inv_eps6, SIXTH, eps_rest6, 2.0f, -1.0f};
+    return Coef{inv_eps6, SIXTH, eps_rest6, 2.0f};
 }
 __device__ __forceinline__ Coef coef_of(const Lattice &L, float inv_eps6, float eps_rest6)
 {
-    return L.te ? Coef{SIXTH, inv_eps6, 2.0f, eps_rest6, 1.0f} : coef_tm(inv_eps6, eps_rest6);
+    return L.te ? Coef{SIXTH, inv_eps6, 2.0f, eps_rest6} : coef_tm(inv_eps6, eps_rest6);
 }
 
 // The post-collision pair a node sends along an axis: the e population and
@@ -336,8 +332,8 @@ __device__ __forceinline__ float down_e(const Pair &p) { return p.e; }
 __device__ __forceinline__ float down_h(const Pair &p) { return p.h; }
 
 // One node's update from its own data and the populations pulled across its
-// four links (interior values; edges, conductor links and the companion row
-// replace some of them here).  `inc_lo` / `inc_hi` stand for the incident-wave
+// four links (interior values; edges and the companion row replace some of
+// them here).  `inc_lo` / `inc_hi` stand for the incident-wave
 // companion node of the same column, as a Side (fields + N_{e+y}, N_{hy+y} /
 // N_{e-y}, N_{hy-y}) or as its up / down Pair, for the bottom / top rows.
 template <bool STRIP, typename Inc>
@@ -356,10 +352,9 @@ __device__ __forceinline__ void neq_pulled(const Lattice &L, int i, int j, uint8
     const float r_hx = o.hx * k.cxy + (o.n[N_HXPX] + o.n[N_HXMX] + o.n[N_EPY] - o.n[N_EMY]);
     const float r_hy = o.hy * k.cxy + (o.n[N_HYPY] + o.n[N_HYMY] - o.n[N_EPX] + o.n[N_EMX]);
 
-    // edges, conductor links and the companion row replace some pulls
-    // (most wavefronts have no such node and skip this block)
-    if (STRIP || i == 0 || i == L.nx - 1 || j == 0 || j == L.ny - 1 ||
-        (m & (NB_PEC_XM | NB_PEC_XP | NB_PEC_YM | NB_PEC_YP))) {
+    // edges and the companion row replace some pulls (most wavefronts have
+    // no such node and skip this block)
+    if (STRIP || i == 0 || i == L.nx - 1 || j == 0 || j == L.ny - 1) {
         // own post-collision moving populations
         const float s_epx = (o.ez - o.hy) - o.n[N_EPX];
         const float s_emx = (o.ez + o.hy) - o.n[N_EMX];
@@ -370,11 +365,10 @@ __device__ __forceinline__ void neq_pulled(const Lattice &L, int i, int j, uint8
         const float s_hypy = o.hy - o.n[N_HYPY];
         const float s_hymy = o.hy - o.n[N_HYMY];
         if (i == 0) { e_px = einc * THIRD; hx_px = 0.0f; }
-        else if (m & NB_PEC_XM) { e_px = k.wall * s_emx; hx_px = k.wall * s_hxmx; }
         if (i == L.nx - 1) {
             if (STRIP) { e_mx = 0.0f; hx_mx = 0.0f; }
             else { e_mx = keep * s_emx; hx_mx = keep * s_hxmx; }
-        } else if (m & NB_PEC_XP) { e_mx = k.wall * s_epx; hx_mx = k.wall * s_hxpx; }
+        }
         if (STRIP) {
             // uniform in y: the +-y populations stay in their node
             e_py = s_epy; hy_py = s_hypy; e_my = s_emy; hy_my = s_hymy;
@@ -382,11 +376,11 @@ __device__ __forceinline__ void neq_pulled(const Lattice &L, int i, int j, uint8
             if (j == 0) {
                 e_py = keep * s_epy + delta * up_e(inc_lo);
                 hy_py = keep * s_hypy + delta * up_h(inc_lo);
-            } else if (m & NB_PEC_YM) { e_py = k.wall * s_emy; hy_py = k.wall * s_hymy; }
+            }
             if (j == L.ny - 1) {
                 e_my = keep * s_emy + delta * down_e(inc_hi);
                 hy_my = keep * s_hymy + delta * down_h(inc_hi);
-            } else if (m & NB_PEC_YP) { e_my = k.wall * s_epy; hy_my = k.wall * s_hypy; }
+            }
         }
     }
 
@@ -434,9 +428,9 @@ __device__ __forceinline__ void store_node(float *F, NeqT *N, size_t P, size_t c
     for (int k = 0; k < 8; ++k) st(&N[k * P + cn], d.n[k], stream);
 }
 
-// Sides along x of node (i, j) and the material parameters; false for a conductor node.
+// Sides along x of node (i, j) and the material parameters.
 template <typename NeqT>
-__device__ __forceinline__ bool node_setup(const Lattice &L, const float *F, const NeqT *N, int i, int j, size_t cf,
+__device__ __forceinline__ void node_setup(const Lattice &L, const float *F, const NeqT *N, int i, int j, size_t cf,
                                            size_t cn, uint8_t &m, float &inv_eps, float &eps_rest, Side &l, Side &r)
 {
     const size_t P = L.plane;
@@ -446,13 +440,11 @@ __device__ __forceinline__ bool node_setup(const Lattice &L, const float *F, con
     if (j < L.ny) {
         m = L.mask[node(L, i, j)];
         const int mat = m & 3;
-        if (mat == MAT_PEC) return false;
         inv_eps = mat_inv_eps_f(L, mat);
         eps_rest = mat_eps_rest_f(L, mat);
     }
-    if (i > 0 && !(m & NB_PEC_XM)) l = load_side(F, N, P, cf - 1, cn - 1, N_EPX, N_HXPX);
-    if (i < L.nx - 1 && !(m & NB_PEC_XP)) r = load_side(F, N, P, cf + 1, cn + 1, N_EMX, N_HXMX);
-    return true;
+    if (i > 0) l = load_side(F, N, P, cf - 1, cn - 1, N_EPX, N_HXPX);
+    if (i < L.nx - 1) r = load_side(F, N, P, cf + 1, cn + 1, N_EMX, N_HXMX);
 }
 
 template <typename NeqT>
@@ -486,14 +478,14 @@ __device__ __forceinline__ void neq_direct_node(const Lattice &L, const void *__
     uint8_t m;
     float inv_eps, eps_rest;
     Side l{}, r{}, b{}, t{}, lo{}, hi{};
-    if (!node_setup(L, F, N, i, j, cf, cn, m, inv_eps, eps_rest, l, r)) return;
+    node_setup(L, F, N, i, j, cf, cn, m, inv_eps, eps_rest, l, r);
     const NodeData o = load_node(F, N, P, cf, cn);
     NodeData out;
     if (j == L.ny) {
         neq_core<true>(L, i, j, m, coef_of(L, inv_eps, eps_rest), o, l, r, b, t, lo, hi, einc, out);
     } else {
-        if (j > 0 && !(m & NB_PEC_YM)) b = load_side(F, N, P, cf - L.sf, cn - L.sn, N_EPY, N_HYPY);
-        if (j < L.ny - 1 && !(m & NB_PEC_YP)) t = load_side(F, N, P, cf + L.sf, cn + L.sn, N_EMY, N_HYMY);
+        if (j > 0) b = load_side(F, N, P, cf - L.sf, cn - L.sn, N_EPY, N_HYPY);
+        if (j < L.ny - 1) t = load_side(F, N, P, cf + L.sf, cn + L.sn, N_EMY, N_HYMY);
         load_incident_sides(L, F, N, i, j, lo, hi);
         neq_core<false>(L, i, j, m, coef_of(L, inv_eps, eps_rest), o, l, r, b, t, lo, hi, einc, out);
     }
@@ -695,7 +687,7 @@ __device__ __forceinline__ void neq_vtile_row(const Lattice &L, const void *__re
         const int i = i0 + v;
         const uint8_t m = (uint8_t)(mv >> (8 * v));
         const int mat = m & 3;
-        if (i >= L.nx || mat == MAT_PEC) continue;
+        if (i >= L.nx) continue;
         const float inv_eps = mat_inv_eps_f(L, mat);
         const float eps_rest = mat_eps_rest_f(L, mat);
         NodeData o;
@@ -790,10 +782,10 @@ struct StripSides {
 // One row's update from its own data (row r), the pairs the rows below and
 // above send it, the x-neighbours across lanes, and the companion row.
 // Every node of the row is updated without branching on its kind: for nodes
-// that hold nothing (conductors, padding, rows or columns outside the domain)
-// the result is a finite value that no valid node ever reads -- a valid node
-// next to such a node takes an edge or conductor rule instead -- and
-// store_row_masked writes zeros for them.
+// outside the domain (padding, rows or columns beyond its edges) the result
+// is a finite value that no valid node ever reads -- a valid node next to
+// such a node takes an edge rule instead -- and mask_row writes zeros for
+// the padding.
 // Per-node material coefficients of a row (scaled as stored: 1 / (6 eps) and
 // 6 (eps - 2/3)); the companion row is vacuum.
 template <int V, bool STRIP>
@@ -859,10 +851,10 @@ __device__ __forceinline__ void row_update_k(const Lattice &L, int i0, int r, ty
 // One row's update from its own data (row r), the pairs the rows below and
 // above send it, the x-neighbours across lanes, and the companion row.
 // Every node of the row is updated without branching on its kind: for nodes
-// that hold nothing (conductors, padding, rows or columns outside the domain)
-// the result is a finite value that no valid node ever reads -- a valid node
-// next to such a node takes an edge or conductor rule instead -- and
-// store_row_masked writes zeros for them.
+// outside the domain (padding, rows or columns beyond its edges) the result
+// is a finite value that no valid node ever reads -- a valid node next to
+// such a node takes an edge rule instead -- and mask_row writes zeros for
+// the padding.
 template <typename NeqT, int V, bool STRIP>
 __device__ __forceinline__ void row_update(const Lattice &L, int i0, int r, typename MaskVec<V>::type mv,
                                            const RowData<V> &cur, const SideRow<V> &below, const SideRow<V> &above,
@@ -882,21 +874,19 @@ __device__ __forceinline__ void round_row(RowData<V> &r)
         for (int v = 0; v < V; ++v) r.n[q][v] = rt<NeqT>(r.n[q][v]);
 }
 
-// Zeros for nodes that hold nothing (conductors; padding past nx), as the
-// one-step kernels leave them.
+// Zeros for the padding past nx, as the one-step kernels leave it.
 template <int V>
-__device__ __forceinline__ void mask_row(const Lattice &L, int i0, typename MaskVec<V>::type mv, bool strip,
-                                         RowData<V> &o)
+__device__ __forceinline__ void mask_row(const Lattice &L, int i0, RowData<V> &o)
 {
     bool all = true;
 #pragma unroll
-    for (int v = 0; v < V; ++v) all = all && i0 + v < L.nx && (strip || ((mv >> (8 * v)) & 3) != MAT_PEC);
-    // most rows hold neither conductor nor outside nodes in any lane: skip
-    // the selects for the whole wavefront
+    for (int v = 0; v < V; ++v) all = all && i0 + v < L.nx;
+    // only the wavefronts at the right edge hold padding: the others skip
+    // the selects
     if (__builtin_amdgcn_ballot_w64(!all) == 0) return;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        const bool keep = i0 + v < L.nx && (strip || ((mv >> (8 * v)) & 3) != MAT_PEC);
+        const bool keep = i0 + v < L.nx;
         o.ez[v] = keep ? o.ez[v] : 0.0f;
         o.hx[v] = keep ? o.hx[v] : 0.0f;
         o.hy[v] = keep ? o.hy[v] : 0.0f;
@@ -969,7 +959,7 @@ __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__re
         round_row<NeqT, V>(c1);
         if (one && j0 == 0) {
             RowData<V> c = c1;
-            mask_row<V>(L, i0, 0, true, c);
+            mask_row<V>(L, i0, c);
             if (out_lane) store_row_at<NeqT, V>(DF + (size_t)L.ny * L.sf, Pu, (unsigned)i0, c, L.stream_stores);
         }
         s0.lo = side_of(c0, N_EPY, N_HYPY);
@@ -979,7 +969,7 @@ __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__re
         if (!one && j0 == 0) {
             RowData<V> c2;
             row_update<NeqT, V, true>(L, i0, L.ny, 0, c1, SideRow<V>{}, SideRow<V>{}, StripSides<V>{}, einc1, c2);
-            mask_row<V>(L, i0, 0, true, c2);
+            mask_row<V>(L, i0, c2);
             if (out_lane)
                 store_row_at<NeqT, V>(DF + (size_t)L.ny * L.sf, Pu, (unsigned)i0, c2, L.stream_stores);
         }
@@ -1047,7 +1037,7 @@ __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__re
                 // a single step: this row's result is the new state
                 if (out_lane && r1 >= j0 && r1 < j0 + H && r1 < L.ny) {
                     RowData<V> o = b_new;
-                    mask_row<V>(L, i0, m_cur, false, o);
+                    mask_row<V>(L, i0, o);
                     store_row_at<NeqT, V>(DF + (size_t)r1 * L.sf, Pu, (unsigned)i0, o, L.stream_stores);
                 }
             }
@@ -1069,7 +1059,7 @@ __device__ __forceinline__ void two_step_wave(const Lattice &L, const void *__re
                 const SideRow<V> b_side = side_of(b_new, AQA, AQB);
                 row_update_k<NeqT, V, false>(L, i0, r2, m_prev, ie_prev, er_prev, b_cur,
                                              DIR > 0 ? b_behind : b_side, DIR > 0 ? b_side : b_behind, s1, einc1, o);
-                mask_row<V>(L, i0, m_prev, false, o);
+                mask_row<V>(L, i0, o);
                 if (out_lane && r2 < L.ny)
                     store_row_at<NeqT, V>(DF + (size_t)r2 * L.sf, Pu, (unsigned)i0, o, L.stream_stores);
             }
@@ -1223,7 +1213,7 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
             c = c2;
         }
         if (j0 == 0) {
-            mask_row<V>(L, i0, 0, true, c);
+            mask_row<V>(L, i0, c);
             if (out_lane) store_row_at<NeqT, V>(DF + (size_t)L.ny * L.sf, Pu, (unsigned)i0, c, L.stream_stores);
         }
     }
@@ -1297,7 +1287,7 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
                         round_row<NeqT, V>(o);
                         keep_mid(s + 1, rs, o, mk[s]);
                     } else {
-                        mask_row<V>(L, i0, mk[s], false, o);
+                        mask_row<V>(L, i0, o);
                         if (out_lane && rs < L.ny)
                             store_row_at<NeqT, V>(DF + (size_t)rs * L.sf, Pu, (unsigned)i0, o, L.stream_stores);
                     }
@@ -1860,9 +1850,10 @@ __global__ void k_fields_out(Lattice L, const FT *__restrict__ fld, double *ez, 
     const size_t P = L.plane;
     const size_t c = at(i, j, L.sfld);
     const size_t o = (size_t)j * L.nx + i;
-    // TE^z: the dual storage holds (Hz, -Ex, -Ey); report (Hz, Ex, Ey)
+    // TE^z: the dual storage holds (Hz, -Ex, -Ey); report (Hz, Ex, Ey);
+    // conductor nodes report zero fields
     const double sxy = L.te ? -1.0 : 1.0;
-    const double fs = field_scale<FT>();
+    const double fs = (L.mask[node(L, i, j)] & 3) == MAT_PEC ? 0.0 : field_scale<FT>();
     ez[o] = fs * (double)fld[c];
     hx[o] = sxy * fs * (double)fld[P + c];
     hy[o] = sxy * fs * (double)fld[2 * P + c];

@@ -189,22 +189,12 @@ void material_map(const Plan &q, uint8_t *mat, size_t row_stride)
     }
 }
 
-// Mask bytes: material id plus conductor-neighbour bits.
+// Mask bytes: the material id (the contour-stencil bit is added with the
+// contour table).
 void build_mask(const Plan &q, std::vector<uint8_t> &mask)
 {
     mask.assign((size_t)q.ny * q.pitch, 0);
     material_map(q, mask.data(), q.pitch);
-    auto pec = [&](int i, int j) {
-        return i >= 0 && j >= 0 && i < q.nx && j < q.ny && (mask[(size_t)j * q.pitch + i] & 3) == MAT_PEC;
-    };
-    for (int j = 0; j < q.ny; ++j)
-        for (int i = 0; i < q.nx; ++i) {
-            uint8_t &m = mask[(size_t)j * q.pitch + i];
-            if (pec(i - 1, j)) m |= NB_PEC_XM;
-            if (pec(i + 1, j)) m |= NB_PEC_XP;
-            if (pec(i, j - 1)) m |= NB_PEC_YM;
-            if (pec(i, j + 1)) m |= NB_PEC_YP;
-        }
 }
 
 // Contour (Sec. II.B): N_c midpoint samples on the circle of radius R_c.
@@ -317,6 +307,11 @@ Lattice lattice_of(const Plan &q, const uint8_t *dmask)
         L.inv_eps_f[k] = (float)(1.0 / (6.0 * q.eps[k]));
         L.eps_rest_f[k] = (float)(6.0 * L.eps_rest[k]);
     }
+    // a conductor node's electric field is zero (Sec. II: E_z^tot = 0), the
+    // update's limit of infinite permittivity; the FP64 kernel sets it to 0
+    // after the moment, as the oracle does
+    L.inv_eps_f[MAT_PEC] = 0.0f;
+    L.eps_rest_f[MAT_PEC] = 0.0f;
     L.te = q.prob.polarization == JLB_TE ? 1 : 0;
     L.stream_stores = 2 * q.state_bytes > CACHE_RESIDENT_BYTES ? 1 : 0;
     return L;

@@ -8,16 +8,10 @@
 
 namespace jlb {
 
-// Material id in the low two bits of a mask byte.
+// Material id in the low two bits of a mask byte.  A conductor node (id 3)
+// is updated like the others with a zero electric field (its coefficient
+// 1/eps on the moment that carries the permittivity is 0).
 enum : uint8_t { MAT_VACUUM = 0, MAT_REGION2 = 1, MAT_REGION3 = 2, MAT_PEC = 3 };
-// Conductor-neighbour bits: the neighbour a population is pulled from is a
-// perfect conductor.  Named by the population that is affected.
-enum : uint8_t {
-    NB_PEC_XM = 1u << 2,  // node (i-1, j): affects the +x populations
-    NB_PEC_XP = 1u << 3,  // node (i+1, j): affects the -x populations
-    NB_PEC_YM = 1u << 4,  // node (i, j-1): affects the +y populations
-    NB_PEC_YP = 1u << 5,  // node (i, j+1): affects the -y populations
-};
 // The node is a corner of some contour sample's bilinear stencil.
 enum : uint8_t { MASK_CONTOUR = 1u << 6 };
 
@@ -51,11 +45,11 @@ struct Lattice {
     size_t plane;         // offset between planes inside a row: pitch
     size_t sf, sn, sfld;  // row strides in elements (see above)
     const uint8_t *mask;  // [ny][pitch]
-    double eps[4];        // permittivity per material id (id 3 unused)
+    double eps[4];        // permittivity per material id (id 3, a conductor: 1, unused)
     double eps_rest[4];   // eps - 2/3: coefficient of Ez in the rest e-population's equilibrium
     double inv_eps[4];    // 1 / eps (the FP32 / BF16 update multiplies by it)
     float inv_eps_f[4];   // FP32 / BF16: 1 / (6 eps) and 6 (eps - 2/3), rounded once on the host
-    float eps_rest_f[4];  // (those states keep one sixth of the fields)
+    float eps_rest_f[4];  // (those states keep one sixth of the fields); conductor: 0 and 0
     int stream_stores;    // 1: write the next state past the caches (state larger than the Infinity Cache)
     int te;               // 1: TE^z, stored as (Hz, -Ex, -Ey) in the (Ez, Hx, Hy) slots
 };

@@ -165,22 +165,32 @@ def _fig_sw(jlb, eps1, phi0, res=50.0):
     return peak
 
 
+# Largest error over the peak intensity each case is held to: about 1.5 times
+# what it measures at lambda_eps / dx = 50, and never above the paper's 5 %
+# (measured: 1.9 %, 0.8 % for eps_r1 = 1; 0.3 %, 0.7 % for 2; 2.2 %, 3.1 % for
+# 5, at phi0 = 0 and -pi/4).
+SW_BARS = {(1.0, 0.0): 0.03, (1.0, -math.pi / 4): 0.015, (2.0, 0.0): 0.01, (2.0, -math.pi / 4): 0.015,
+           (5.0, 0.0): 0.035, (5.0, -math.pi / 4): 0.05}
+
+
 @pytest.mark.parametrize("eps1", [1.0, 2.0, 5.0])
 @pytest.mark.parametrize("phi0", [0.0, -math.pi / 4])
 def test_far_field_reproduces_the_papers_validation(jlb, eps1, phi0):
     """Sec. IV.A.1 (Fig. SW): metallo-dielectric Janus, a = lambda, lambda_eps / dx
     = 50, L / a = 10, against the analytic scattered series (Eq. constants_Bm_Dm
-    and the Hankel asymptotics).  The paper reports per-angle relative errors
-    generally below 5 %, larger where the intensity varies sharply.  With the
-    staircase boundary of the lattice here the error at this resolution is 1-6 % of
-    the peak intensity, and up to 16 % for eps_r1 = 5 at phi0 = -pi/4 (a
-    resonant body, 4.5 internal wavelengths across); held here to 20 %."""
-    assert _fig_sw(jlb, eps1, phi0) < 0.20
+    and the Hankel asymptotics).  The paper reports per-angle errors generally
+    below 5 %; each case here is held to its own bar, all within 5 % of the
+    peak intensity."""
+    assert _fig_sw(jlb, eps1, phi0) < SW_BARS[(eps1, phi0)]
 
 
-def test_far_field_error_falls_with_resolution(jlb):
-    """The eps_r1 = 5 discrepancy is discretisation: at lambda_eps / dx = 75 the
-    error of the phi0 = 0 case drops from about 6 % to about 3 % of the peak."""
-    e50 = _fig_sw(jlb, 5.0, 0.0, 50.0)
-    e75 = _fig_sw(jlb, 5.0, 0.0, 75.0)
-    assert e75 < 0.7 * e50
+def test_far_field_error_with_resolution(jlb):
+    """Refining lambda_eps / dx from 50 to 75 lowers the vacuum-half case's error
+    (staircase and dispersion are discretisation errors), and the eps_r1 = 5,
+    phi0 = -pi/4 case -- a conductor face on the lattice diagonal -- stays
+    within the paper's 5 % at 50, 75 and 100 without growing."""
+    e50 = _fig_sw(jlb, 1.0, 0.0, 50.0)
+    e75 = _fig_sw(jlb, 1.0, 0.0, 75.0)
+    assert e75 < 0.85 * e50
+    d = [_fig_sw(jlb, 5.0, -math.pi / 4, r) for r in (50.0, 75.0, 100.0)]
+    assert max(d) < 0.05 and d[2] <= d[0]
