@@ -144,6 +144,81 @@ def _wall_fit(lam, nx, steps):
     return r.x - pf, a / 2.0, res
 
 
+def test_open_top_and_bottom_edges_pass_the_plane_wave_exactly():
+    """Sec. III: the wave enters on the left and the other edges let outgoing
+    waves leave.  The incident plane wave is uniform in y, so in an empty
+    domain every row must equal the solution of a domain periodic in y: the
+    top and bottom edges (extrapolation relaxed against the companion row)
+    must not disturb it at all."""
+    nx, ny = 300, 40
+    p = W.problem(nx=nx, ny=ny, radius=2.0, kind="homogeneous", eps1=1.0, wavelength=40.0, steps=1500,
+                  avg_periods=0)
+    mat = np.zeros((ny, nx), np.uint8)
+    r = O.solve(p, mat=mat)
+    rp = O.solve(p, mat=mat, boundary="x_open_y_periodic")
+    scale = np.abs(rp["ez"]).max()
+    assert scale > 0.9
+    for f in ("ez", "hx", "hy"):
+        assert np.abs(r[f] - rp[f]).max() <= 1e-13 * scale, f
+
+
+def _edge_pulse(ny, steps, nx=200, x0=100.0, y0=90.0, sigma=4.0):
+    """A Gaussian E_z pulse (equilibrium, H = 0) in an empty domain with open
+    edges and no incident wave."""
+    jj, ii = np.mgrid[0:ny, 0:nx]
+    ez = np.exp(-((ii - x0) ** 2 + (jj - y0) ** 2) / (2 * sigma ** 2))
+    st = np.zeros((11, ny, nx))
+    st[0] = (1.0 - 2.0 / 3.0) * ez
+    st[1:5] = ez / 6.0
+    p = W.problem(nx=nx, ny=ny, radius=2.0, kind="homogeneous", eps1=1.0, wavelength=40.0, steps=steps,
+                  avg_periods=0, ramp_periods=0, e0=1e-300)
+    return O.solve(p, mat=np.zeros((ny, nx), np.uint8), state=st)
+
+
+@pytest.mark.parametrize("steps", [200, 260])
+def test_open_edge_reflects_no_more_than_a_first_order_absorbing_edge(steps):
+    """Sec. III: first-order extrapolation at the open edges, residual
+    reflections small.  A pulse 29.5 cells below the top edge sends rays at
+    every incidence angle up to theta_max = acos(29.5 / (steps / 3)); the
+    energy the edge sends back (this domain minus one whose top edge lies
+    300 rows further up) is at most what the first-order absorbing edge of
+    Engquist and Majda reflects, amplitude tan^2(theta / 2), for rays spread
+    evenly over those angles.  Normal incidence alone reflects nothing
+    (test_open_boundary_reflection_below_papers_level)."""
+    a, b = _edge_pulse(120, steps), _edge_pulse(420, steps)
+    refl = 0.5 * sum(np.sum((a[f] - b[f][:120]) ** 2) for f in ("ez", "hx", "hy"))
+    crossed = 0.5 * sum(np.sum(b[f][120:] ** 2) for f in ("ez", "hx", "hy"))
+    tmax = math.acos((119.5 - 90.0) / (steps / 3.0))
+    th = np.linspace(0.0, tmax, 4001)
+    em1 = np.trapezoid(np.tan(th / 2.0) ** 4, th) / tmax
+    assert crossed > 0.3 * 0.5 * sum(np.sum(b[f] ** 2) for f in ("ez", "hx", "hy"))
+    assert refl / crossed < em1, (refl / crossed, em1)
+
+
+def test_energy_weights_the_electric_field_by_eps():
+    """The energy diagnostic (Sec. III: the total field energy approaches a
+    constant) is W = sum (eps E_z^2 + H^2) / 2.  A standing wave in a
+    periodic uniform eps = 4 box trades electric for magnetic energy every
+    quarter period; only with the electric part weighted by eps is W
+    constant (here to the lattice's O((k dx)^2) = 1e-2 level: 1.5e-3 over
+    four periods).  Without the weight, W would swing by (eps - 1) / (eps + 1)
+    = 60 %."""
+    n, eps, lam = 128, 4.0, 64.0
+    k = 2 * math.pi / lam
+    ii = np.mgrid[0:8, 0:n][1]
+    ez = np.cos(k * ii)
+    st = np.zeros((11, 8, n))
+    st[0] = (eps - 2.0 / 3.0) * ez
+    st[1:5] = ez / 6.0
+    period = 3.0 * math.sqrt(eps) * lam
+    p = W.problem(nx=n, ny=8, radius=2.0, kind="homogeneous", eps1=eps, wavelength=40.0, steps=int(4 * period),
+                  avg_periods=0, ramp_periods=0, e0=1e-300)
+    w = O.solve(p, boundary="periodic", mat=np.full((8, n), 1, np.uint8), state=st, energy=True, fields=False)["energy"]
+    assert (w.max() - w.min()) / w.mean() < 5e-3
+    # the electric energy at t = 0 reappears as magnetic energy a quarter period later
+    assert abs(w[0] - 0.5 * eps * np.sum(ez ** 2)) / w[0] < 5e-3
+
+
 def test_flat_conductor_wall_reflects_totally():
     """Sec. II: E_z = 0 on the conductor.  A plane wave meeting a flat
     conductor (conductor nodes from x = x_c on) reflects totally: in front of
