@@ -7,7 +7,10 @@ last 5 periods -> contour reduction to F~x, F~y, M~z -- for the dielectric
 Janus cylinder eps1 = 2.25 / eps2 = 4.0, phi0 = 30 deg, a = 64 on a
 1024 x 1024 grid, lambda = 128.  value = lattice updates per second
 (nx * ny * steps per solve / wall time per solve, conductor nodes included).
-Prints ONE JSON line.
+The same line carries, in extra, the rest of the metric measured on the same
+GPU: config 4's design map (solves/hour, against one-at-a-time FP64 solves)
+and config 5's serving run on the first 64 of its seeded arrivals (p50 / p99
+latency, throughput).  Prints ONE JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
 
@@ -21,6 +24,8 @@ Other modes (one JSON line each):
                                           reference alone (for rocprofv3 passes)
     --summarize DIR --out FILE            turn rocprofv3 CSV output into a
                                           short text summary under profiles/
+    --record-traffic / --record-valu KEY  merge FETCH_SIZE / WRITE_SIZE or VALU
+                                          counter passes into profiles/*.json
 """
 from __future__ import annotations
 
@@ -37,11 +42,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+# FP32 vector issue peak for this arithmetic: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz, one FP32 add or multiply per lane per cycle.  The update uses
+# neither packed FP32 (left out of every build) nor FMA contraction (off, so
+# that every kernel variant rounds the same operations the same way), so the
+# 157.3 TFLOP/s of packed FMA is out of its reach.
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP32 / BF16 deviation update, interior node: three rest populations (5 each),
+# four outgoing pairs (3 each), the three moments (4 + 1, 4 + 1, 4 + 1) and the
+# eight new deviations (2 x 4 + 4): adds, subtracts and multiplies
+FLOPS_PER_LUP = {"fp32": 54, "bf16": 54}
 BYTES_PER_LUP = {"fp64": 177, "fp32": 89, "bf16": 57}
 KERNEL_NAME = {"fp64": "k_step_f64", "fp32": "k_step_neq*<float>", "bf16": "k_step_neq*<__bf16>"}
 TWO_STEP_KERNEL_NAME = {"fp32": "k_step2_neq<float>", "bf16": "k_step2_neq<__bf16>"}
 MULTI_STEP_KERNEL_NAME = {"fp32": "k_stepm_neq<float>", "bf16": "k_stepm_neq<__bf16>"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "step_valu.json")
 DEVICE_SRC = os.path.join(ROOT, "paper_2509_22308_amd", "csrc", "jlb_device.hip")
 
 
@@ -67,6 +83,20 @@ def measured_traffic(precision: str, variant: int):
         return None
     e = t.get("config2", {}).get(precision, {}).get(str(variant))
     return e.get("hbm_bytes_per_launch") if e else None
+
+
+def measured_valu(precision: str, variant: int):
+    """VALU counters per launch of the step kernel from the committed summary
+    (VALUBusy, VALU instructions, waves), or None when they were taken on a
+    different kernel source."""
+    try:
+        with open(VALU_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("config2", {}).get(precision, {}).get(str(variant))
 
 
 def _chosen_kernels(jlb, prob, ws, prec: str, launches: int):
@@ -125,7 +155,6 @@ def gpu_leg(args):
     depth = {1: 1, 2: 2}.get(main_kind) or jlb.jlb_multi_step_shape(main_variant)[0]
     launch_ms = sum(r.main_ms for r in results) / sum(r.main_launches for r in results)
     bytes_per_pass = r0.bytes_per_step
-    achieved = depth * bytes_per_pass / (launch_ms * 1e-3) / 1e9
     extra = {"forces": {"fx": r0.fx, "fy": r0.fy, "tz": r0.tz}, "loop_ms_per_solve": loop_ms,
              "state_passes_per_solve": passes, "graph_used": r0.graph_used,
              "main_stretch": {"kind": {1: "single step", 2: "two-step", 3: "multi-step"}[main_kind],
@@ -192,20 +221,55 @@ def gpu_leg(args):
     else:
         kname = KERNEL_NAME[args.precision]
         index = main_variant
-    roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.precision, index),
-            "steps_per_launch": depth, "algorithmic_bytes_per_launch": depth * bytes_per_pass,
-            "launch_ms": launch_ms, "launches_per_solve": r0.main_launches,
-            "per_pass_gbs": bytes_per_pass / (launch_ms * 1e-3) / 1e9,
-            "per_pass_frac": bytes_per_pass / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "note": f"achieved = {BYTES_PER_LUP[args.precision]} B per lattice update x {depth} x nx x ny updates "
-                    "per launch / mean launch duration (HIP events around the graph-replayed periods before the "
-                    "window, over the timed solves).  Temporal blocking reads and writes the state once per "
-                    "launch, so achieved exceeds the HBM peak when it pays: per_pass_gbs counts the state once "
-                    "(the least a launch must move) and traffic is the measured HBM bytes per launch.  Config 2 "
-                    "(FP32 state 2 x 46 MB) stays in the 256 MB Infinity Cache between launches; the HBM-bound "
-                    "figures are extra.grid4096_*"}
+    roof = roofline(args.precision, kname, index, depth, bytes_per_pass, p["nx"] * p["ny"], launch_ms,
+                    r0.main_launches)
+    return p, value, ms_per_solve, roof, extra
+
+
+def roofline(precision, kname, index, depth, bytes_per_pass, nodes, launch_ms, launches_per_solve):
+    """Roofline of the dominant kernel against the resource that bounds it.
+
+    A launch advances the state by `depth` lattice steps; it must read and
+    write the state once (bytes_per_pass), and it performs depth x nodes
+    lattice updates of FLOPS_PER_LUP operations each.  The VALU counter pass
+    of profiles/step_valu.json (VALUBusy: the share of the launch's cycles
+    the SIMDs spend issuing vector ALU instructions) decides the bound: at
+    0.6 or more the launch is bound by VALU issue and is placed against the
+    FP32 issue peak with its algorithmic operations; otherwise against the
+    HBM peak with one state pass per launch."""
+    secs = launch_ms * 1e-3
+    per_pass_gbs = bytes_per_pass / secs / 1e9
+    flops = FLOPS_PER_LUP.get(precision, 0) * depth * nodes
+    tflops = flops / secs / 1e12
+    valu = measured_valu(precision, index)
+    traffic = measured_traffic(precision, index)
+    valu_bound = valu is not None and valu.get("valu_busy", 0.0) >= 0.6 and flops > 0
+    if valu_bound:
+        head = {"bound": "alu", "achieved": tflops, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tflops / VALU_FP32_PEAK_TFLOPS}
+    else:
+        head = {"bound": "hbm", "achieved": per_pass_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": per_pass_gbs / HBM_PEAK_GBS}
+    head.update({
+        "traffic": traffic, "kernel": kname, "steps_per_launch": depth, "launch_ms": launch_ms,
+        "launches_per_solve": launches_per_solve,
+        "algorithmic_flops_per_launch": flops, "flops_per_update": FLOPS_PER_LUP.get(precision),
+        "per_pass": {"bytes": bytes_per_pass, "gbs": per_pass_gbs, "frac_of_hbm": per_pass_gbs / HBM_PEAK_GBS},
+        "equiv_gbs": depth * bytes_per_pass / secs / 1e9,
+        "counters": valu,
+        "note": ("bound from the VALUBusy counter of the same kernel source (profiles/step_valu.json). achieved = "
+                 f"{FLOPS_PER_LUP.get(precision)} FP32 operations per lattice update x {depth} x nx x ny updates per "
+                 "launch / mean launch duration (HIP events around the graph-replayed periods before the window), "
+                 f"peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = {VALU_FP32_PEAK_TFLOPS:.1f} TFLOP/s (no packed "
+                 "FP32, no FMA contraction). per_pass: one read and one write of the state per launch against 8 "
+                 "TB/s. equiv_gbs: the algorithmic bytes of every update the launch performs (temporal blocking "
+                 "moves them once per launch). traffic: FETCH_SIZE + WRITE_SIZE per launch, scaled by a copy "
+                 "kernel of known size: bytes leaving L2, Infinity-Cache hits included (not DRAM bytes).")
+                if valu_bound else
+                ("achieved = one read and one write of the state per launch / mean launch duration against 8 TB/s; "
+                 "traffic: FETCH_SIZE + WRITE_SIZE per launch scaled by a copy kernel (bytes leaving L2)."),
+    })
+    return head
     return p, value, ms_per_solve, roof, extra
 
 
@@ -243,6 +307,14 @@ def base_line(args, metric_value, ms, config, roof=None, cpu=None, extra=None, d
 
 def run_default(args):
     p, value, ms, roof, extra = gpu_leg(args)
+    if not args.quick:
+        # the rest of the metric, on the same GPU: design-map solves/hour
+        # (config 4, all 576 solves) and serving p50 / p99 (config 5, the
+        # first 64 arrivals of its seeded sequence)
+        print("[bench] design map (config 4)", file=sys.stderr, flush=True)
+        extra["design_map"] = design_map_leg(args.precision)
+        print("[bench] serving (config 5, 64 requests)", file=sys.stderr, flush=True)
+        extra["serving"] = serve_leg(args.precision, 64, 16, 256, 256, "fifo")
     cpu = None if args.no_cpu else cpu_leg(p)
     if cpu is not None:
         # the same oracle on one host thread, a shorter sample
@@ -266,19 +338,21 @@ def _kernel_choice(jlb, prec: str) -> dict:
                               else "single steps")}
 
 
-def run_designmap(args):
+def design_map_leg(precision: str, fraction: float = 1.0):
+    """Config 4: the design map through the engine, and the one-at-a-time
+    plain FP64 baseline on the same GPU (a sample stratified by radius,
+    extrapolated by lattice-update count)."""
     import torch
 
     import paper_2509_22308_amd as jlb
     import workloads
     from paper_2509_22308_amd.serve import run_design_map
 
-    torch.cuda.set_device(0)
     probs = workloads.config4_sweep()
-    if args.fraction < 1.0:
-        probs = probs[:: max(1, int(round(1.0 / args.fraction)))]
-    jlb.jlb_autotune(jlb.make_problem(probs[0], args.precision), 10)
-    out = run_design_map(probs, args.precision)
+    if fraction < 1.0:
+        probs = probs[:: max(1, int(round(1.0 / fraction)))]
+    jlb.jlb_autotune(jlb.make_problem(probs[0], precision), 10)
+    out = run_design_map(probs, precision)
     # baseline: one-at-a-time plain FP64 solves on the same GPU, timed on a
     # seeded sample stratified by radius, extrapolated by LUP count
     order = sorted(range(len(probs)), key=lambda k: probs[k]["radius"])
@@ -297,32 +371,48 @@ def run_designmap(args):
                                              len(probs) / (total / base_lups) * 3600.0,
                                              "sample": "4 solves stratified by radius"},
              "failed": sum(1 for r in out["results"] if r["status"] != "done"),
-             "kernels": _kernel_choice(jlb, args.precision)}
-    config = {"workload": f"config 4 design map: {len(probs)} dielectric Janus solves, eps2/eps1 1.1..10 "
-                          f"(16 log-spaced) x 36 orientations, a ~ U{{32..128}}, grid 8a, lambda 2a, 52 periods",
-              "precision": args.precision}
-    return base_line(args, out["lups"], 1e3 * out["wall_s"], config, extra=extra)
+             "kernels": _kernel_choice(jlb, precision), "lups": out["lups"], "precision": precision,
+             "workload": f"config 4 design map: {len(probs)} dielectric Janus solves, eps2/eps1 1.1..10 "
+                         f"(16 log-spaced) x 36 orientations, a ~ U{{32..128}}, grid 8a, lambda 2a, 52 periods"}
+    return extra
 
 
-def run_serve(args):
+def run_designmap(args):
     import torch
+    torch.cuda.set_device(0)
+    extra = design_map_leg(args.precision, args.fraction)
+    config = {"workload": extra["workload"], "precision": args.precision}
+    return base_line(args, extra["lups"], 1e3 * extra["wall_s"], config, extra=extra)
 
+
+def serve_leg(precision: str, requests: int, a_min: int, a_max: int, slots: int, policy: str):
+    """Config 5: seeded Poisson arrivals served by the engine (continuous
+    batching, byte-budget admission); latency from arrival to completion."""
     import paper_2509_22308_amd as jlb
     import workloads
     from paper_2509_22308_amd.serve import serve
 
-    torch.cuda.set_device(0)
-    reqs = workloads.config5_requests(n_req=args.requests, a_min=args.a_min, a_max=args.a_max)
-    jlb.jlb_autotune(jlb.make_problem(reqs[0][1], args.precision), 10)
-    out = serve(reqs, args.precision, max_slots=args.slots, policy=args.policy)
+    reqs = workloads.config5_requests(n_req=requests, a_min=a_min, a_max=a_max)
+    jlb.jlb_autotune(jlb.make_problem(reqs[0][1], precision), 10)
+    out = serve(reqs, precision, max_slots=slots, policy=policy)
     extra = {k: out[k] for k in ("requests", "completed", "wall_s", "p50_s", "p99_s", "mean_s", "queue_p50_s",
-                                 "queue_p99_s", "solves_per_hour", "offered_lups", "peak_resident", "budget_bytes",
-                                 "policy", "max_slots")}
-    extra["kernels"] = _kernel_choice(jlb, args.precision)
-    config = {"workload": f"config 5 serving: {args.requests} Poisson arrivals at 20/s (seed 22308), dielectric "
-                          f"Janus a ~ U{{{args.a_min}..{args.a_max}}}, grid 8a, eps ~ U[1.5,10], lambda 2a, "
-                          "52 periods, byte-budget admission", "precision": args.precision}
-    return base_line(args, out["throughput_lups"], 1e3 * out["wall_s"], config, extra=extra)
+                                 "queue_p99_s", "submit_delay_p50_s", "submit_delay_p99_s", "solves_per_hour",
+                                 "throughput_lups", "offered_lups", "peak_resident", "budget_bytes", "policy",
+                                 "max_slots")}
+    extra["kernels"] = _kernel_choice(jlb, precision)
+    extra["precision"] = precision
+    extra["workload"] = (f"config 5 serving: the first {requests} of the seeded Poisson arrivals at 20/s "
+                         f"(seed 22308), dielectric Janus a ~ U{{{a_min}..{a_max}}}, grid 8a, eps ~ U[1.5,10], "
+                         "lambda 2a, 52 periods, byte-budget admission")
+    return extra
+
+
+def run_serve(args):
+    import torch
+    torch.cuda.set_device(0)
+    extra = serve_leg(args.precision, args.requests, args.a_min, args.a_max, args.slots, args.policy)
+    config = {"workload": extra["workload"], "precision": args.precision}
+    return base_line(args, extra["throughput_lups"], 1e3 * extra["wall_s"], config, extra=extra)
 
 
 def run_kernel_only(args):
@@ -447,6 +537,38 @@ def record_traffic(args):
     print(json.dumps(entry))
 
 
+def record_valu(args):
+    """VALU counters per launch of the step kernel from one rocprofv3 --pmc
+    pass of --kernel-only (VALUBusy, SQ_INSTS_VALU, SQ_WAVES,
+    GRBM_GUI_ACTIVE), merged into the VALU file under (workload, precision,
+    variant) with the kernel source hash."""
+    vals = {c: _counter_means(args.valu_dir, c) for c in ("VALUBusy", "SQ_INSTS_VALU", "SQ_WAVES", "GRBM_GUI_ACTIVE")}
+
+    def step(table):
+        v = [x for k, x in table.items() if "k_step" in k]
+        if len(v) != 1:
+            raise SystemExit(f"expected one step kernel, found {list(table)}")
+        return v[0]
+
+    busy = step(vals["VALUBusy"])
+    insts, waves = step(vals["SQ_INSTS_VALU"]), step(vals["SQ_WAVES"])
+    entry = {"variant": args.variant, "valu_busy": busy / 100.0, "valu_insts_per_launch": insts,
+             "waves_per_launch": waves, "valu_insts_per_wave": insts / waves if waves else None,
+             "gui_active_cycles": step(vals["GRBM_GUI_ACTIVE"]), "command": args.command}
+    try:
+        with open(args.out) as f:
+            t = json.load(f)
+    except OSError:
+        t = {}
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        t = {}
+    t["kernel_source_sha256_16"] = kernel_source_hash()
+    t.setdefault(args.record_valu, {}).setdefault(args.precision, {})[str(args.variant)] = entry
+    with open(args.out, "w") as f:
+        json.dump(t, f, indent=1, sort_keys=True)
+    print(json.dumps(entry))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,7 +582,8 @@ def main():
     ap.add_argument("--a-max", type=int, default=64)
     ap.add_argument("--policy", default="fifo", choices=["fifo", "sjf"], help="serve: engine admission order")
     ap.add_argument("--slots", type=int, default=256, help="serve: most solves resident at once")
-    ap.add_argument("--quick", action="store_true", help="skip the extra precision, 4096^2 and copy figures")
+    ap.add_argument("--quick", action="store_true",
+                    help="skip the extra precision, 4096^2, copy, design-map and serving figures")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--kernel-only", action="store_true")
     ap.add_argument("--launches", type=int, default=50)
@@ -470,6 +593,8 @@ def main():
     ap.add_argument("--multi-step", type=int, default=-1, help="kernel-only: time this multi-step variant instead")
     ap.add_argument("--summarize", default=None)
     ap.add_argument("--record-traffic", default=None, help="workload key (config2, grid4096): merge counter passes")
+    ap.add_argument("--record-valu", default=None, help="workload key (config2): merge a VALU counter pass")
+    ap.add_argument("--valu-dir", default=None)
     ap.add_argument("--fetch-dir", default=None)
     ap.add_argument("--write-dir", default=None)
     ap.add_argument("--command", default="")
@@ -480,6 +605,9 @@ def main():
         return
     if args.record_traffic:
         record_traffic(args)
+        return
+    if args.record_valu:
+        record_valu(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library runs each solve on a single MI355X (independent solves "

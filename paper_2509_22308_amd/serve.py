@@ -68,7 +68,8 @@ def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, ma
     admits them as memory and slots free up (in arrival order, or smallest
     work first with policy "sjf") and steps every resident solve together.
     Latency = completion time - arrival time; queue wait = admission time -
-    arrival time.
+    submission time (the engine's clocks); submission delay = submission
+    time - arrival time (the host loop submits between engine calls).
     """
     reqs = sorted(requests, key=lambda r: r[0])
     budget = _engine_budget([p for _, p in reqs], precision, budget_bytes)
@@ -88,7 +89,9 @@ def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, ma
         now = time.perf_counter() - t0
         while k < len(reqs) and reqs[k][0] * time_scale <= now:
             t = eng.submit(make_problem(reqs[k][1], precision))
-            outstanding[t] = (k, reqs[k][0] * time_scale)
+            # arrival -> submission: the time the request waited for the
+            # host loop, which is inside eng.run while earlier work runs
+            outstanding[t] = (k, reqs[k][0] * time_scale, time.perf_counter() - t0)
             k += 1
         st = eng.stats()
         if st["resident"] == 0 and st["queued"] == 0:
@@ -101,15 +104,16 @@ def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, ma
         for t in list(outstanding):
             status, res = eng.poll(t)
             if status in ("done", "failed", "cancelled"):
-                idx, arr = outstanding.pop(t)
+                idx, arr, sub = outstanding.pop(t)
                 # the engine's own clocks: submit -> done (total_ms), admit -> done (loop_ms)
                 done.append({"index": idx, "status": status, "arrival_s": arr, "done_s": now,
                              "latency_s": now - arr, "queue_s": max(0.0, (res.total_ms - res.loop_ms) * 1e-3),
-                             "fx": res.fx, "fy": res.fy, "tz": res.tz})
+                             "submit_delay_s": sub - arr, "fx": res.fx, "fy": res.fy, "tz": res.tz})
     wall = time.perf_counter() - t0
     eng.close()
     lat = np.array([d["latency_s"] for d in done if d["status"] == "done"])
     wait = np.array([d["queue_s"] for d in done if d["status"] == "done"])
+    sub = np.array([d["submit_delay_s"] for d in done if d["status"] == "done"])
     lups = float(sum(p["nx"] * p["ny"] * p["steps"] for _, p in reqs))
     span = reqs[-1][0] * time_scale if reqs else 0.0
     return {
@@ -119,6 +123,8 @@ def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, ma
         "mean_s": float(lat.mean()) if len(lat) else None,
         "queue_p50_s": float(np.percentile(wait, 50)) if len(wait) else None,
         "queue_p99_s": float(np.percentile(wait, 99)) if len(wait) else None,
+        "submit_delay_p50_s": float(np.percentile(sub, 50)) if len(sub) else None,
+        "submit_delay_p99_s": float(np.percentile(sub, 99)) if len(sub) else None,
         "policy": policy, "max_slots": max_slots,
         "throughput_lups": lups / wall, "solves_per_hour": len(lat) / wall * 3600.0,
         "offered_lups": lups / span if span > 0 else None, "peak_resident": peak, "budget_bytes": budget,
