@@ -54,16 +54,22 @@ VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 FLOPS_PER_LUP = {"fp32": 54, "bf16": 54}
 BYTES_PER_LUP = {"fp64": 177, "fp32": 89, "bf16": 57}
 KERNEL_NAME = {"fp64": "k_step_f64", "fp32": "k_step_neq*<float>", "bf16": "k_step_neq*<__bf16>"}
-TWO_STEP_KERNEL_NAME = {"fp32": "k_step2_neq<float>", "bf16": "k_step2_neq<__bf16>"}
+TWO_STEP_KERNEL_NAME = {"fp64": "k_step2_f64", "fp32": "k_step2_neq<float>", "bf16": "k_step2_neq<__bf16>"}
 MULTI_STEP_KERNEL_NAME = {"fp32": "k_stepm_neq<float>", "bf16": "k_stepm_neq<__bf16>"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "step_valu.json")
-DEVICE_SRC = os.path.join(ROOT, "paper_2509_22308_amd", "csrc", "jlb_device.hip")
+DEVICE_SRCS = [os.path.join(ROOT, "paper_2509_22308_amd", "csrc", n)
+               for n in ("jlb_device.hip", "jlb_device_f64.hip", "jlb_device_common.h", "jlb_internal.h")]
 
 
 def kernel_source_hash() -> str:
-    with open(DEVICE_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of every source the device code is built from: counters recorded
+    for another hash describe other kernels and are not used."""
+    h = hashlib.sha256()
+    for path in DEVICE_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _workspace(jlb, prob):
@@ -106,7 +112,7 @@ def _chosen_kernels(jlb, prob, ws, prec: str, launches: int):
     best, tune = jlb.jlb_autotune(prob, launches, ws)
     one = jlb.jlb_time_step_kernel(prob, 5, 4 * launches, ws)
     two = multi = None
-    if prec != "fp64" and jlb.jlb_get_two_step_variant(jlb.PRECISIONS[prec]) >= 0:
+    if jlb.jlb_get_two_step_variant(jlb.PRECISIONS[prec]) >= 0:
         two = jlb.jlb_time_two_step_kernel(prob, 5, 2 * launches, ws)
     if prec != "fp64" and jlb.jlb_get_multi_step_variant(jlb.PRECISIONS[prec]) >= 0:
         multi = jlb.jlb_time_multi_step_kernel(prob, 5, launches, ws)
@@ -126,7 +132,7 @@ def gpu_leg(args):
     # the autotuner picks the step kernels (tile shape; single, two- or multi-step)
     # for this device and grid
     variant, tune_ms = jlb.jlb_autotune(prob, 20, ws)
-    two_variant = jlb.jlb_get_two_step_variant(jlb.PRECISIONS[args.precision]) if args.precision != "fp64" else -1
+    two_variant = jlb.jlb_get_two_step_variant(jlb.PRECISIONS[args.precision])
     multi_variant = jlb.jlb_get_multi_step_variant(jlb.PRECISIONS[args.precision]) if args.precision != "fp64" else -1
     lups_per_solve = p["nx"] * p["ny"] * p["steps"]
 
@@ -161,7 +167,8 @@ def gpu_leg(args):
                               "ms_per_solve": r0.main_ms, "launches_per_solve": r0.main_launches},
              "step_variant": jlb.STEP_VARIANTS.get(jlb.jlb_get_step_variant(jlb.PRECISIONS[args.precision]))
              if args.precision != "fp64" else jlb.FP64_STEP_VARIANTS.get(variant),
-             "two_step_variant": jlb.TWO_STEP_VARIANTS.get(two_variant) if two_variant >= 0 else None,
+             "two_step_variant": (jlb.FP64_TWO_STEP_VARIANTS if args.precision == "fp64" else jlb.TWO_STEP_VARIANTS
+                                  ).get(two_variant) if two_variant >= 0 else None,
              "multi_step_variant": jlb.MULTI_STEP_VARIANTS.get(multi_variant) if multi_variant >= 0 else None,
              "autotune_ms_per_step": [round(m, 5) for m in tune_ms],
              "step_kernel_ms_alone": jlb.jlb_time_step_kernel(prob, 20, 200, ws)}
@@ -187,9 +194,10 @@ def gpu_leg(args):
                        "glups": nodes / (one * 1e-3) / 1e9, "gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}}
             if two is not None:
                 gbs2 = nodes * BYTES_PER_LUP[prec] / (two * 1e-3) / 1e9
-                ent["two_step"] = {"variant": jlb.TWO_STEP_VARIANTS.get(jlb.jlb_get_two_step_variant(
-                    jlb.PRECISIONS[prec])), "ms_per_launch": two, "glups": 2 * nodes / (two * 1e-3) / 1e9,
-                    "gbs": gbs2, "hbm_frac": gbs2 / HBM_PEAK_GBS}
+                names = jlb.FP64_TWO_STEP_VARIANTS if prec == "fp64" else jlb.TWO_STEP_VARIANTS
+                ent["two_step"] = {"variant": names.get(jlb.jlb_get_two_step_variant(jlb.PRECISIONS[prec])),
+                                   "ms_per_launch": two, "glups": 2 * nodes / (two * 1e-3) / 1e9,
+                                   "gbs": gbs2, "hbm_frac": gbs2 / HBM_PEAK_GBS}
             if multi is not None:
                 mv = jlb.jlb_get_multi_step_variant(jlb.PRECISIONS[prec])
                 depth, _ = jlb.jlb_multi_step_shape(mv)
@@ -216,7 +224,8 @@ def gpu_leg(args):
         kname = f"{MULTI_STEP_KERNEL_NAME[args.precision]} ({jlb.MULTI_STEP_VARIANTS.get(main_variant)})"
         index = len(jlb.STEP_VARIANTS) + len(jlb.TWO_STEP_VARIANTS) + main_variant
     elif main_kind == 2:
-        kname = f"{TWO_STEP_KERNEL_NAME[args.precision]} ({jlb.TWO_STEP_VARIANTS.get(main_variant)})"
+        names = jlb.FP64_TWO_STEP_VARIANTS if args.precision == "fp64" else jlb.TWO_STEP_VARIANTS
+        kname = f"{TWO_STEP_KERNEL_NAME[args.precision]} ({names.get(main_variant)})"
         index = len(jlb.STEP_VARIANTS) + main_variant
     else:
         kname = KERNEL_NAME[args.precision]

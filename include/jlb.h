@@ -329,12 +329,24 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * 7 V1 H8 X8 LA2, 8 V1 H4 X8 LA2, 9 V1 H16 X8 LA2.  Default: 4 (set -1 for
  * single steps only).
  *
+ * FP64 has two-step kernels too (JLB_FP64_TWO_STEP_VARIANTS of them, one
+ * node per lane, H rows per wavefront, 4 halo columns per side, registers
+ * for two or (W3) three wavefronts per SIMD, LA2 as above): 0 H8, 1 H10,
+ * 2 H12, 3 H16, 4 H8 W3, 5 H12 W3, 6 H8 LA2, 7 H12 LA2 (default 1).  An
+ * FP64 solve uses the selected one for its graph-captured periods, inside
+ * the averaging window too (there it also writes the field planes of both
+ * levels), but not with the plateau stop, and single steps elsewhere;
+ * results equal single steps bit for bit.  The engine runs its FP64 solves
+ * on single steps.
+ *
  * jlb_autotune times every single-step variant of prob->precision on prob's
  * grid (`launches` timed launches each, after 2 warm-up launches; workspace
- * as for jlb_solve) and makes the fastest the current choice; for FP32 /
- * BF16 it then times the two-step variants and selects the fastest of them
- * when its time per lattice step beats the best single step (else turns
- * two-step kernels off), then the multi-step variants the grid allows and
+ * as for jlb_solve) and makes the fastest the current choice; it then times
+ * the two-step variants and selects the fastest of them when its time per
+ * lattice step beats the best single step (else turns two-step kernels off;
+ * for FP64 *best_variant is then JLB_FP64_STEP_VARIANTS + the two-step
+ * index, and ms_per_variant holds the FP64 two-step times after the
+ * single-step ones); for FP32 / BF16 it then times the multi-step variants the grid allows and
  * selects the fastest of them when its time per lattice step beats the best
  * so far (else turns them off); a three-step variant's time counts 3 % more
  * (over a whole solve its extra state passes and launches cost more than the
@@ -349,6 +361,7 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
 #define JLB_STEP_VARIANTS 7
 #define JLB_FP64_STEP_VARIANTS 3
 #define JLB_TWO_STEP_VARIANTS 10
+#define JLB_FP64_TWO_STEP_VARIANTS 8
 int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t launches,
                  int32_t *best_variant, double *ms_per_variant, void *stream);
 
@@ -359,8 +372,7 @@ int jlb_set_two_step_variant(int32_t precision, int32_t variant);
 int jlb_get_two_step_variant(int32_t precision, int32_t *variant);
 /*
  * Mean time of one launch of the current two-step kernel (two lattice
- * steps), as jlb_time_step_kernel.  JLB_E_ARG for FP64 or when two-step
- * kernels are off.
+ * steps), as jlb_time_step_kernel.  JLB_E_ARG when two-step kernels are off.
  */
 int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t warmup,
                              int32_t launches, double *ms_per_launch, void *stream);

@@ -13,7 +13,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjlb.so")
-SOURCES = ["jlb_device.hip", "jlb_host.cpp", "jlb_engine.cpp", "jlb_trajectory.cpp"]
+SOURCES = ["jlb_device.hip", "jlb_device_f64.hip", "jlb_host.cpp", "jlb_engine.cpp", "jlb_trajectory.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

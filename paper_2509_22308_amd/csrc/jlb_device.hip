@@ -55,191 +55,13 @@
 #include <mutex>
 #include <type_traits>
 
+#include "jlb_device_common.h"
 #include "jlb_internal.h"
 
 namespace jlb {
 
 namespace {
 
-// Stores of the next state are read only in the next step.  When the state
-// is larger than the 256 MB Infinity Cache they stream past the caches
-// (non-temporal); when it fits, ordinary stores keep it cache-resident for
-// the next step.  The choice is per launch (Lattice::stream_stores).
-template <typename T> __device__ __forceinline__ void put(T *p, T v, bool stream)
-{
-    if (stream) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
-
-constexpr int BX = 64;  // one wavefront per row segment
-constexpr int BY = 4;   // four rows per block
-
-// Material parameters by id.  Ids vary per lane; the compiler would turn a
-// select among the uniform values back into an indexed vector load (whose
-// wait also waits for every load issued before it, look-ahead rows
-// included), so the values pass through readfirstlane first.
-__device__ __forceinline__ float uniform(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
-__device__ __forceinline__ double uniform(double x)
-{
-    const long long b = __double_as_longlong(x);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
-    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-template <typename R> __device__ __forceinline__ R mat_pick(const double (&v)[4], int mat)
-{
-    const R v0 = uniform((R)v[0]), v1 = uniform((R)v[1]), v2 = uniform((R)v[2]), v3 = uniform((R)v[3]);
-    return mat == 0 ? v0 : mat == 1 ? v1 : mat == 2 ? v2 : v3;
-}
-__device__ __forceinline__ double mat_eps(const Lattice &L, int mat) { return mat_pick<double>(L.eps, mat); }
-__device__ __forceinline__ double mat_eps_rest(const Lattice &L, int mat) { return mat_pick<double>(L.eps_rest, mat); }
-// FP32 coefficients: picked among the host-rounded float copies, so the
-// select runs on 32-bit values and needs no conversion per node.
-__device__ __forceinline__ float mat_pick_f(const float (&v)[4], int mat)
-{
-    const float v0 = uniform(v[0]), v1 = uniform(v[1]), v2 = uniform(v[2]), v3 = uniform(v[3]);
-    return mat == 0 ? v0 : mat == 1 ? v1 : mat == 2 ? v2 : v3;
-}
-__device__ __forceinline__ float mat_eps_rest_f(const Lattice &L, int mat) { return mat_pick_f(L.eps_rest_f, mat); }
-__device__ __forceinline__ float mat_inv_eps_f(const Lattice &L, int mat) { return mat_pick_f(L.inv_eps_f, mat); }
-
-// Mask index of node (i, j).
-__device__ __forceinline__ size_t node(const Lattice &L, int i, int j) { return (size_t)j * L.pitch + i; }
-// Index of node (i, j) in plane 0 of a row-interleaved array with row stride S.
-__device__ __forceinline__ size_t at(int i, int j, size_t S) { return (size_t)j * S + i; }
-
-// Workgroups are handed to the eight XCDs in turn (block b on XCD b mod 8),
-// and each XCD has its own L2.  Renumbering so that XCD x works through one
-// contiguous range of tiles keeps the halo rows that adjacent tiles share
-// inside one L2.  The map is a bijection of [0, nb).
-constexpr int NUM_XCD = 8;
-__device__ __forceinline__ int xcd_tile(int b, int nb)
-{
-    const int x = b % NUM_XCD, k = b / NUM_XCD;
-    const int per = nb / NUM_XCD, rem = nb % NUM_XCD;
-    return x * per + min(x, rem) + k;
-}
-
-// Tile coordinates of this block in a 2-D grid.  A cache-resident state
-// (no streaming stores) gains from XCD-contiguous tiles; a state streamed
-// from HBM runs faster with every XCD on neighbouring rows (the plain order).
-__device__ __forceinline__ void block_tile(const Lattice &L, int &tx, int &ty)
-{
-    const int nb = gridDim.x * gridDim.y;
-    const int b = blockIdx.y * gridDim.x + blockIdx.x;
-    const int t = L.stream_stores ? b : xcd_tile(b, nb);
-    tx = t % gridDim.x;
-    ty = t / gridDim.x;
-}
-
-__device__ __forceinline__ int batch_tile(const SolveDesc *D, int b, int nb, int remap)
-{
-    return remap ? xcd_tile(b, nb) : b;
-}
-
-// ---------------------------------------------------------------------------
-// FP64, 11 populations.  Evaluation order and groupings match the plain
-// definition so that results are reproducible to the last bits; no FMA
-// contraction.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void f64_node(const Lattice &L, const double *__restrict__ src, double *__restrict__ dst,
-                                         double *__restrict__ fields, double einc, int i, int j)
-{
-#pragma clang fp contract(off)
-    const size_t P = L.plane;
-    const size_t c = at(i, j, L.sf);
-    const double keep = 1.0 - OPEN_DELTA;
-    double f[11];
-    double eps = 1.0, eps_rest = 1.0 - 2.0 / 3.0;
-    bool conductor = false;
-
-    f[0] = src[0 * P + c];
-    f[5] = src[5 * P + c];
-    f[8] = src[8 * P + c];
-    if (j == L.ny) {
-        // incident-wave companion row: vacuum, uniform in y, nothing enters on the right
-        f[3] = src[3 * P + c];
-        f[4] = src[4 * P + c];
-        f[9] = src[9 * P + c];
-        f[10] = src[10 * P + c];
-        if (i == 0) { f[1] = einc / 3.0; f[6] = 0.0; }
-        else { f[1] = src[1 * P + c - 1]; f[6] = src[6 * P + c - 1]; }
-        if (i == L.nx - 1) { f[2] = 0.0; f[7] = 0.0; }
-        else { f[2] = src[2 * P + c + 1]; f[7] = src[7 * P + c + 1]; }
-    } else {
-        const int mat = L.mask[node(L, i, j)] & 3;
-        conductor = mat == MAT_PEC;
-        eps = mat_eps(L, mat);
-        eps_rest = mat_eps_rest(L, mat);
-        const size_t strip = at(i, L.ny, L.sf);
-        // +x populations come from (i-1, j)
-        if (i == 0) { f[1] = einc / 3.0; f[6] = 0.0; }
-        else { f[1] = src[1 * P + c - 1]; f[6] = src[6 * P + c - 1]; }
-        // -x populations come from (i+1, j)
-        if (i == L.nx - 1) { f[2] = keep * src[2 * P + c]; f[7] = keep * src[7 * P + c]; }
-        else { f[2] = src[2 * P + c + 1]; f[7] = src[7 * P + c + 1]; }
-        // +y populations come from (i, j-1)
-        if (j == 0) {
-            f[3] = keep * src[3 * P + c] + OPEN_DELTA * src[3 * P + strip];
-            f[9] = keep * src[9 * P + c] + OPEN_DELTA * src[9 * P + strip];
-        } else { f[3] = src[3 * P + c - L.sf]; f[9] = src[9 * P + c - L.sf]; }
-        // -y populations come from (i, j+1)
-        if (j == L.ny - 1) {
-            f[4] = keep * src[4 * P + c] + OPEN_DELTA * src[4 * P + strip];
-            f[10] = keep * src[10 * P + c] + OPEN_DELTA * src[10 * P + strip];
-        } else { f[4] = src[4 * P + c + L.sf]; f[10] = src[10 * P + c + L.sf]; }
-    }
-
-    const double dz = f[0] + f[1] + f[2] + (f[3] + f[4]);
-    double ez, hx, hy;
-    double q[11];
-    if (L.te) {  // (Hz, -Ex, -Ey): the in-plane fields carry eps
-        ez = dz;
-        hx = (f[5] + f[6] + f[7] + (f[3] - f[4])) / eps;
-        hy = (f[8] + (f[9] + f[10]) + (f[2] - f[1])) / eps;
-        if (conductor) { hx = 0.0; hy = 0.0; }  // Ex = Ey = 0
-        q[0] = ez / 3.0;
-        q[5] = eps_rest * hx;
-        q[8] = eps_rest * hy;
-    } else {
-        ez = dz / eps;
-        hx = f[5] + f[6] + f[7] + (f[3] - f[4]);
-        hy = f[8] + (f[9] + f[10]) + (f[2] - f[1]);
-        if (conductor) ez = 0.0;  // Ez = 0
-        q[0] = eps_rest * ez;
-        q[5] = hx / 3.0;
-        q[8] = hy / 3.0;
-    }
-    q[1] = (ez - hy) / 6.0;
-    q[2] = (ez + hy) / 6.0;
-    q[3] = (ez + hx) / 6.0;
-    q[4] = (ez - hx) / 6.0;
-    q[6] = hx / 6.0;
-    q[7] = hx / 6.0;
-    q[9] = hy / 6.0;
-    q[10] = hy / 6.0;
-#pragma unroll
-    for (int k = 0; k < 11; ++k) put(&dst[k * P + c], 2.0 * q[k] - f[k], L.stream_stores);
-    if (fields) {  // row ny: the incident wave's fields (read by the far-field phasors)
-        const size_t cf = at(i, j, L.sfld);
-        fields[0 * P + cf] = ez;
-        fields[1 * P + cf] = hx;
-        fields[2 * P + cf] = hy;
-    }
-}
-
-template <int CX, int R>
-__global__ __launch_bounds__(CX *R) void k_step_f64(Lattice L, const double *__restrict__ src,
-                                                     double *__restrict__ dst, double *__restrict__ fields, double einc)
-{
-    int tx, ty;
-    block_tile(L, tx, ty);
-    const int i = tx * CX + threadIdx.x;
-    const int j = ty * R + threadIdx.y;
-    if (i >= L.nx || j > L.ny) return;
-    f64_node(L, src, dst, fields, einc, i, j);
-}
 
 // ---------------------------------------------------------------------------
 // FP32 / BF16: fields + deviations from equilibrium.
@@ -550,18 +372,6 @@ struct RowData {
     float n[8][V];
 };
 
-// x-neighbour exchange across the wavefront with DPP wave shifts (a VALU
-// move, no LDS traffic): lane k receives the value of lane k - 1
-// (from_left) or of lane k + 1 (from_right); the end lanes, which have no
-// such neighbour in the wavefront, receive 0 (callers load or ignore it).
-__device__ __forceinline__ float from_left(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
-}
-__device__ __forceinline__ float from_right(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
-}
 
 template <typename NeqT, int V>
 __device__ __forceinline__ void load_row(const float *F, const NeqT *N, size_t P, size_t cf, size_t cn, RowData<V> &r)
@@ -1862,18 +1672,6 @@ __global__ void k_fields_out(Lattice L, const FT *__restrict__ fld, double *ez, 
 dim3 step_grid(const Lattice &L) { return dim3((L.nx + BX - 1) / BX, (L.ny + 1 + BY - 1) / BY); }
 
 }  // namespace
-
-hipError_t launch_step_f64(const Lattice &L, const double *src, double *dst, double *fields, double einc,
-                           hipStream_t s, int variant)
-{
-    auto grid = [&](int cx, int r) { return dim3((L.nx + cx - 1) / cx, (L.ny + 1 + r - 1) / r); };
-    switch (variant) {
-    case F64_W256_R1: hipLaunchKernelGGL((k_step_f64<256, 1>), grid(256, 1), dim3(256, 1), 0, s, L, src, dst, fields, einc); break;
-    case F64_W256_R2: hipLaunchKernelGGL((k_step_f64<256, 2>), grid(256, 2), dim3(256, 2), 0, s, L, src, dst, fields, einc); break;
-    default: hipLaunchKernelGGL((k_step_f64<BX, 4>), grid(BX, 4), dim3(BX, 4), 0, s, L, src, dst, fields, einc); break;
-    }
-    return hipGetLastError();
-}
 
 hipError_t launch_step_neq(int precision, const Lattice &L, const void *src, void *dst, double einc, hipStream_t s,
                            int variant)

@@ -23,6 +23,7 @@ namespace jlb {
 static_assert(JLB_STEP_VARIANTS == NEQ_VARIANTS, "single-step variant count");
 static_assert(JLB_FP64_STEP_VARIANTS == F64_VARIANTS, "FP64 variant count");
 static_assert(JLB_TWO_STEP_VARIANTS == TWO_STEP_VARIANTS, "two-step variant count");
+static_assert(JLB_FP64_TWO_STEP_VARIANTS == F64_TWO_STEP_VARIANTS, "FP64 two-step variant count");
 static_assert(JLB_STATIC_SCRATCH_BYTES == STATIC_SCRATCH_BYTES, "library-held scratch size");
 
 // ---------------------------------------------------------------------------
@@ -237,9 +238,9 @@ double incident(const Plan &q, int64_t n)
 // ---------------------------------------------------------------------------
 
 static std::atomic<int> g_variant[3] = {{0}, {NEQ_DIRECT}, {NEQ_DIRECT}};
-// Two-step kernel variant per precision for the steps outside the averaging
-// window, -1 = off (FP64 has none).
-static std::atomic<int> g_two[3] = {{-1}, {TWO_V1_H8_X8}, {TWO_V1_H8_X8}};
+// Two-step kernel variant per precision, -1 = off (FP64: F64TwoStepVariant,
+// used for the graph-replayed periods before the averaging window).
+static std::atomic<int> g_two[3] = {{F64_TWO_H10_X4}, {TWO_V1_H8_X8}, {TWO_V1_H8_X8}};
 
 int step_variant(int precision) { return g_variant[precision].load(std::memory_order_relaxed); }
 void set_step_variant(int precision, int v) { g_variant[precision].store(v, std::memory_order_relaxed); }
@@ -422,8 +423,11 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
     // pairs and a chunk leaves state n in buffer n % 2, as single steps do;
     // it is also the spacing of the plateau check points
     const int64_t chunk = q.T % 4 == 0 ? q.T : q.T % 2 == 0 ? 2 * q.T : 4 * q.T;
-    // two-step kernels: FP32 / BF16
-    const int two = q.prob.precision == JLB_FP64 ? -1 : two_step_variant(q.prob.precision);
+    // two-step kernels (FP64: not with the plateau search, whose check
+    // points read the field planes of single levels)
+    const bool f64 = q.prob.precision == JLB_FP64;
+    const int two = f64 && q.prob.plateau_tol > 0.0 ? -1 : two_step_variant(q.prob.precision);
+    auto two_in = [&](int) { return two >= 0; };
     // multi-step kernels (depth S) for the captured chunks: chunk / S launches
     // must be a whole, even number (the chunk then leaves state n in buffer
     // n % 2), and a row segment must not reach both the bottom and the top row
@@ -504,18 +508,29 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
                     return fail(JLB_E_DEVICE, "multi-step launch: %s", hipGetErrorString(e));
                 }
             }
-        } else if (two >= 0) {
+        } else if (two_in(which)) {
             // launch m takes state n0 + 2m from buffer (n0 + m) % 2 to the
-            // other one; inside the window it also leaves the contour-stencil
-            // fields of level n0 + 2m + 1 in mid, and both levels are
-            // accumulated after it
+            // other one; inside the window it also leaves the fields of level
+            // n0 + 2m + 1 (FP32 / BF16: at the contour stencil, in mid; FP64:
+            // the field planes of both levels), and both levels are
+            // accumulated after it, in order
             float *mid = (float *)(ws + q.off_mid);
             for (int64_t m = 0; m < chunk / 2; ++m) {
                 const int64_t n = n0 + 2 * m;
                 void *dst = ws + q.off_state[(n0 + m + 1) & 1];
-                hipError_t e = launch_step2_neq(q.prob.precision, L, ws + q.off_state[(n0 + m) & 1], dst,
-                                                incident(q, n), incident(q, n + 1), which == 1 ? mid : nullptr, s, two);
-                if (e == hipSuccess && which == 1) e = launch_contour2(L, mid, dst, C, s);
+                hipError_t e;
+                if (f64) {
+                    double *fl1 = which == 1 ? (double *)fields_ptr(q, ws, n + 1) : nullptr;
+                    double *fl2 = which == 1 ? (double *)fields_ptr(q, ws, n + 2) : nullptr;
+                    e = launch_step2_f64(L, (const double *)(ws + q.off_state[(n0 + m) & 1]), (double *)dst,
+                                         incident(q, n), incident(q, n + 1), fl1, fl2, s, two);
+                    if (e == hipSuccess && which == 1) e = launch_contour(q.prob.precision, L, fl1, C, s);
+                    if (e == hipSuccess && which == 1) e = launch_contour(q.prob.precision, L, fl2, C, s);
+                } else {
+                    e = launch_step2_neq(q.prob.precision, L, ws + q.off_state[(n0 + m) & 1], dst, incident(q, n),
+                                         incident(q, n + 1), which == 1 ? mid : nullptr, s, two);
+                    if (e == hipSuccess && which == 1) e = launch_contour2(L, mid, dst, C, s);
+                }
                 if (e != hipSuccess) {
                     hipGraph_t dummy;
                     (void)hipStreamEndCapture(s, &dummy);
@@ -572,7 +587,7 @@ int run_solve(const Plan &q, char *ws, jlb_result *res, double *ez, double *hx, 
             }
             if (which == 0) main_launches += main_per_chunk;
             graph_used = 1;
-            passes += multi >= 0 ? chunk / depth : two >= 0 ? chunk / 2 : chunk;
+            passes += multi >= 0 ? chunk / depth : two_in(which) ? chunk / 2 : chunk;
             n += chunk;
             if (!in_window && check_level(n)) rc = plateau_check(n);
             continue;
@@ -862,8 +877,11 @@ static int time_step_kernel(const jlb_problem *prob, void *workspace, size_t wor
             for (int k = 0; k < depth; ++k) einc[k] = incident(q, depth * n + k);
             e = launch_stepm_neq(q.prob.precision, L, src, dst, einc, nullptr, 0, own, variant);
         } else if (kind == 2) {
-            e = launch_step2_neq(q.prob.precision, L, src, dst, incident(q, 2 * n), incident(q, 2 * n + 1), nullptr, own,
-                                 variant);
+            e = q.prob.precision == JLB_FP64
+                    ? launch_step2_f64(L, (const double *)src, (double *)dst, incident(q, 2 * n), incident(q, 2 * n + 1),
+                                       nullptr, nullptr, own, variant)
+                    : launch_step2_neq(q.prob.precision, L, src, dst, incident(q, 2 * n), incident(q, 2 * n + 1),
+                                       nullptr, own, variant);
         } else {
             e = launch_step(q, L, src, dst, nullptr, incident(q, n), own, variant);
         }
@@ -907,7 +925,7 @@ int jlb_time_two_step_kernel(const jlb_problem *prob, void *workspace, size_t wo
 {
     clear_error();
     if (!prob) return fail(JLB_E_ARG, "null problem");
-    if (prob->precision != JLB_FP32 && prob->precision != JLB_BF16) return fail(JLB_E_ARG, "two-step kernels are FP32 / BF16");
+    if (prob->precision < 0 || prob->precision > 2) return fail(JLB_E_ARG, "unknown precision");
     const int v = two_step_variant(prob->precision);
     if (v < 0) return fail(JLB_E_ARG, "no two-step variant selected");
     return time_step_kernel(prob, workspace, workspace_bytes, warmup, launches, v, 2, ms_per_launch, stream);
@@ -961,7 +979,24 @@ int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_byte
     }
     set_step_variant(prob->precision, bv);
     *best_variant = bv;
-    if (prob->precision == JLB_FP64) return JLB_OK;
+    if (prob->precision == JLB_FP64) {
+        // FP64 two-step kernels, compared per lattice step
+        int b2 = -1;
+        for (int v = 0; v < F64_TWO_STEP_VARIANTS; ++v) {
+            double ms = 0.0;
+            int rc = time_step_kernel(prob, workspace, workspace_bytes, 2, launches, v, 2, &ms, stream);
+            if (rc) return rc;
+            ms *= 0.5;
+            if (ms_per_variant) ms_per_variant[F64_VARIANTS + v] = ms;
+            if (ms < best) {
+                best = ms;
+                b2 = v;
+            }
+        }
+        set_two_step_variant(prob->precision, b2);
+        if (b2 >= 0) *best_variant = F64_VARIANTS + b2;
+        return JLB_OK;
+    }
     // two-step kernels, compared per lattice step
     int b2 = -1;
     for (int v = 0; v < TWO_STEP_VARIANTS; ++v) {
@@ -1018,9 +1053,9 @@ int jlb_set_step_variant(int32_t precision, int32_t variant)
 int jlb_set_two_step_variant(int32_t precision, int32_t variant)
 {
     clear_error();
-    if (precision < 0 || precision > 2 || variant < -1 || variant >= TWO_STEP_VARIANTS ||
-        (precision == JLB_FP64 && variant != -1))
-        return fail(JLB_E_ARG, "precision 1..2 and variant -1..%d (FP64: -1 only)", TWO_STEP_VARIANTS - 1);
+    const int nvar = precision == JLB_FP64 ? F64_TWO_STEP_VARIANTS : TWO_STEP_VARIANTS;
+    if (precision < 0 || precision > 2 || variant < -1 || variant >= nvar)
+        return fail(JLB_E_ARG, "precision 0..2 and variant -1..%d", nvar - 1);
     set_two_step_variant(precision, variant);
     return JLB_OK;
 }

@@ -72,12 +72,20 @@ def test_far_field_entry_checks_its_arguments_before_the_device():
         assert rc == -1 and "n_angles" in J.jlb_last_error()
 
 
-def test_two_step_timing_refuses_fp64_before_the_device():
-    import ctypes
-    prob = J.make_problem(dict(W.config1(), polarization="te"), "fp64")
-    ms = ctypes.c_double(0.0)
-    assert J.load().jlb_time_two_step_kernel(ctypes.byref(prob), None, 0, 0, 1, ctypes.byref(ms), None) == -1
-    assert "FP32 / BF16" in J.jlb_last_error()
+def test_fp64_two_step_variant_range_is_checked_before_the_device():
+    before = J.jlb_get_two_step_variant(0)
+    try:
+        n = len(J.FP64_TWO_STEP_VARIANTS)
+        for v in range(-1, n):
+            J.jlb_set_two_step_variant(0, v)
+            assert J.jlb_get_two_step_variant(0) == v
+        with pytest.raises(J.JlbError):
+            J.jlb_set_two_step_variant(0, n)
+        with pytest.raises(J.JlbError):
+            J.jlb_set_two_step_variant(1, 10)
+    finally:
+        J.jlb_set_two_step_variant(0, before)
+    assert len(J.FP64_TWO_STEP_VARIANTS) == 8
 
 
 def test_multi_step_variant_table_and_argument_checks():

@@ -182,6 +182,40 @@ def test_step_kernel_variants_give_identical_results(jlb, precision):
 
 
 @pytest.mark.parametrize("polarization", ["tm", "te"])
+def test_fp64_two_step_kernels_equal_single_steps(jlb, polarization):
+    """FP64 two steps per launch (the graph-replayed periods before the
+    window): every variant equals the single-step solve bit for bit, fields
+    and forces (ragged strips and row segments, a conductor, all four edges,
+    the companion row, a short top segment of four rows)."""
+    two0 = jlb.jlb_get_two_step_variant(0)
+    cases = [W.problem(nx=203, ny=150, radius=20.0, kind="metallo_dielectric_janus", eps1=3.0, phi0_deg=110.0,
+                       wavelength=40.0, steps=840, avg_periods=1),
+             W.problem(nx=130, ny=171, radius=16.0, kind="dielectric_janus", eps1=2.0, eps2=6.0, phi0_deg=45.0,
+                       wavelength=40.0, steps=720, avg_periods=1),
+             W.problem(nx=530, ny=97, radius=20.0, kind="metallo_dielectric_janus", eps1=4.0, phi0_deg=315.0,
+                       wavelength=40.0, steps=720, avg_periods=1),
+             W.problem(nx=64, ny=20, radius=3.0, kind="dielectric_janus", eps1=2.0, eps2=3.0, phi0_deg=60.0,
+                       wavelength=40.0, steps=720, avg_periods=1, contour_offset=2.0)]
+    cases = [dict(p, polarization=polarization) for p in cases]
+    try:
+        for p in cases:
+            _print_case(f"fp64 two-step {polarization}", p)
+            jlb.jlb_set_two_step_variant(0, -1)
+            ref = jlb.solve(p, "fp64", fields=True)
+            assert ref["state_passes"] == p["steps"] and ref["main_kind"] == 1
+            for v in range(len(jlb.FP64_TWO_STEP_VARIANTS)):
+                jlb.jlb_set_two_step_variant(0, v)
+                o = jlb.solve(p, "fp64", fields=True)
+                assert (o["main_kind"], o["main_variant"]) == (2, v) and o["state_passes"] < p["steps"], v
+                for q in ("fx", "fy", "tz", "energy_final"):
+                    assert o[q] == ref[q], (v, q, o[q], ref[q])
+                for f in ("ez", "hx", "hy"):
+                    assert np.array_equal(o[f], ref[f]), (v, f, np.abs(o[f] - ref[f]).max())
+    finally:
+        jlb.jlb_set_two_step_variant(0, two0)
+
+
+@pytest.mark.parametrize("polarization", ["tm", "te"])
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_two_step_kernels_equal_single_steps(jlb, precision, polarization):
     """A two-step launch (temporal blocking) takes the state from n to n + 2
