@@ -330,9 +330,11 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * single steps only).
  *
  * FP64 has two-step kernels too (JLB_FP64_TWO_STEP_VARIANTS of them, one
- * node per lane, H rows per wavefront, 4 halo columns per side, registers
- * for two or (W3) three wavefronts per SIMD, LA2 as above): 0 H8, 1 H10,
- * 2 H12, 3 H16, 4 H8 W3, 5 H12 W3, 6 H8 LA2, 7 H12 LA2 (default 1).  An
+ * node per lane, H rows per wavefront, X4 / X8 halo columns per side (X8:
+ * every strip stores whole 128-byte lines, which pays on grids streamed
+ * from HBM), registers for two or (W3) three wavefronts per SIMD, LA2 as
+ * above): 0 H10 X4, 1 H12 X4, 2 H12 X4 W3, 3 H12 X4 LA2, 4 H6 X8, 5 H8 X8,
+ * 6 H8 X8 LA2, 7 H12 X8 (default 0).  An
  * FP64 solve uses the selected one for its graph-captured periods, inside
  * the averaging window too (there it also writes the field planes of both
  * levels), but not with the plateau stop, and single steps elsewhere;

@@ -224,6 +224,9 @@ __device__ __forceinline__ void f64_two_step_wave(const Lattice &L, const double
         if constexpr (LA == 2) load(first + 2 * DIR, a_far, m_far);
         Send b_behind{};
         Pops b_cur{};
+        // unrolled whole: the rows in flight then rotate through registers
+        // instead of being copied, which would wait for their loads
+#pragma unroll
         for (int k = 0; k < H + 2; ++k) {
             const int r1 = first + DIR * k;
             Pops a_next;
@@ -298,25 +301,26 @@ __global__ __launch_bounds__(64 * F64_TWO_WAVES, W) void k_step2_f64(Lattice L, 
 
 template <typename F> void f64_two_dispatch(int variant, F &&go)
 {
+    using H6 = std::integral_constant<int, 6>;
     using H8 = std::integral_constant<int, 8>;
     using H10 = std::integral_constant<int, 10>;
     using H12 = std::integral_constant<int, 12>;
-    using H16 = std::integral_constant<int, 16>;
     using X4 = std::integral_constant<int, 4>;
+    using X8 = std::integral_constant<int, 8>;
     using W2 = std::integral_constant<int, 2>;
     using W3 = std::integral_constant<int, 3>;
     using A0 = std::integral_constant<int, 0>;
     using A1 = std::integral_constant<int, 1>;
     using A2 = std::integral_constant<int, 2>;
     switch (variant) {
-    case F64_TWO_H8_X4: go(H8{}, X4{}, W2{}, A1{}); break;
     case F64_TWO_H10_X4: go(H10{}, X4{}, W2{}, A1{}); break;
     case F64_TWO_H12_X4: go(H12{}, X4{}, W2{}, A1{}); break;
-    case F64_TWO_H16_X4: go(H16{}, X4{}, W2{}, A1{}); break;
-    case F64_TWO_H8_X4_W3: go(H8{}, X4{}, W3{}, A0{}); break;
     case F64_TWO_H12_X4_W3: go(H12{}, X4{}, W3{}, A0{}); break;
-    case F64_TWO_H8_X4_LA2: go(H8{}, X4{}, W2{}, A2{}); break;
-    default: go(H12{}, X4{}, W2{}, A2{}); break;
+    case F64_TWO_H12_X4_LA2: go(H12{}, X4{}, W2{}, A2{}); break;
+    case F64_TWO_H6_X8: go(H6{}, X8{}, W2{}, A1{}); break;
+    case F64_TWO_H8_X8: go(H8{}, X8{}, W2{}, A1{}); break;
+    case F64_TWO_H8_X8_LA2: go(H8{}, X8{}, W2{}, A2{}); break;
+    default: go(H12{}, X8{}, W2{}, A1{}); break;
     }
 }
 

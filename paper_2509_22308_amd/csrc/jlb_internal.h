@@ -89,19 +89,22 @@ enum F64Variant { F64_R4 = 0, F64_W256_R1 = 1, F64_W256_R2 = 2, F64_VARIANTS = 3
 // dst must differ), bit for bit equal to two launch_step_f64 launches.
 // fields1 / fields2 (both null, or two distinct field buffers): the field
 // planes of levels n + 1 and n + 2, as launch_step_f64 writes them.
-// Variants: H output rows per wavefront, HX = 4 halo columns per side (56
-// output columns, 64-byte aligned strips), registers for two or (W3) three
-// wavefronts per SIMD, input rows loaded one row (two: LA2) ahead of their
-// first use (W3: after the row before is done).
+// Variants: H output rows per wavefront; HX = 4 halo columns per side (56
+// output columns: 64-byte aligned strips, the least halo work; the best on
+// a cache-resident state) or 8 (48 output columns: every strip's stores
+// cover whole 128-byte lines; the best on a state streamed from HBM);
+// registers for two or (W3) three wavefronts per SIMD; input rows loaded
+// one row (two: LA2) ahead of their first use (W3: after the row before is
+// done).
 enum F64TwoStepVariant {
-    F64_TWO_H8_X4 = 0,
-    F64_TWO_H10_X4 = 1,
-    F64_TWO_H12_X4 = 2,
-    F64_TWO_H16_X4 = 3,
-    F64_TWO_H8_X4_W3 = 4,
-    F64_TWO_H12_X4_W3 = 5,
-    F64_TWO_H8_X4_LA2 = 6,
-    F64_TWO_H12_X4_LA2 = 7,
+    F64_TWO_H10_X4 = 0,
+    F64_TWO_H12_X4 = 1,
+    F64_TWO_H12_X4_W3 = 2,
+    F64_TWO_H12_X4_LA2 = 3,
+    F64_TWO_H6_X8 = 4,
+    F64_TWO_H8_X8 = 5,
+    F64_TWO_H8_X8_LA2 = 6,
+    F64_TWO_H12_X8 = 7,
     F64_TWO_STEP_VARIANTS = 8
 };
 hipError_t launch_step2_f64(const Lattice &L, const double *src, double *dst, double einc0, double einc1,
