@@ -334,17 +334,21 @@ def run_default(args):
     return base_line(args, value, ms, config, roof, cpu, extra)
 
 
-def _kernel_choice(jlb, prec: str) -> dict:
-    """The step kernels the autotuner left selected for prec."""
+def _kernel_choice(jlb, prec: str, four_step=None) -> dict:
+    """The step kernels the autotuner left selected for prec, and the engine's
+    four-step shape as it timed it on the resident mix (four_step: the
+    engine's report)."""
     if prec == "fp64":
         return {"single_step": jlb.FP64_STEP_VARIANTS.get(jlb.jlb_get_step_variant(0))}
     p = jlb.PRECISIONS[prec]
     two, multi = jlb.jlb_get_two_step_variant(p), jlb.jlb_get_multi_step_variant(p)
+    shape = four_step["variant"] if four_step and four_step.get("variant") else None
     return {"single_step": jlb.STEP_VARIANTS.get(jlb.jlb_get_step_variant(p)),
             "two_step": jlb.TWO_STEP_VARIANTS.get(two) if two >= 0 else None,
             "multi_step": jlb.MULTI_STEP_VARIANTS.get(multi) if multi >= 0 else None,
-            "engine_rounds": ("four-step H16 X4, two-step for each solve's last one to three steps" if two >= 0
-                              else "single steps")}
+            "engine_rounds": (f"{shape}, two-step for each solve's last one to three steps" if two >= 0 and shape
+                              else "two-step" if two >= 0 else "single steps"),
+            "engine_four_step_timing": four_step}
 
 
 def design_map_leg(precision: str, fraction: float = 1.0):
@@ -380,7 +384,8 @@ def design_map_leg(precision: str, fraction: float = 1.0):
                                              len(probs) / (total / base_lups) * 3600.0,
                                              "sample": "4 solves stratified by radius"},
              "failed": sum(1 for r in out["results"] if r["status"] != "done"),
-             "kernels": _kernel_choice(jlb, precision), "lups": out["lups"], "precision": precision,
+             "kernels": _kernel_choice(jlb, precision, out.get("four_step")), "lups": out["lups"],
+             "precision": precision,
              "workload": f"config 4 design map: {len(probs)} dielectric Janus solves, eps2/eps1 1.1..10 "
                          f"(16 log-spaced) x 36 orientations, a ~ U{{32..128}}, grid 8a, lambda 2a, 52 periods"}
     return extra
@@ -408,7 +413,7 @@ def serve_leg(precision: str, requests: int, a_min: int, a_max: int, slots: int,
                                  "queue_p99_s", "submit_delay_p50_s", "submit_delay_p99_s", "solves_per_hour",
                                  "throughput_lups", "offered_lups", "peak_resident", "budget_bytes", "policy",
                                  "max_slots")}
-    extra["kernels"] = _kernel_choice(jlb, precision)
+    extra["kernels"] = _kernel_choice(jlb, precision, out.get("four_step"))
     extra["precision"] = precision
     extra["workload"] = (f"config 5 serving: the first {requests} of the seeded Poisson arrivals at 20/s "
                          f"(seed 22308), dielectric Janus a ~ U{{{a_min}..{a_max}}}, grid 8a, eps ~ U[1.5,10], "

@@ -480,14 +480,32 @@ int jlb_engine_stats(jlb_engine *eng, int32_t *queued, int32_t *resident, int32_
 int jlb_engine_set_policy(jlb_engine *eng, int32_t policy, int32_t max_slots);
 /*
  * Four-step rounds (on by default): with `on`, the engine's FP32 / BF16
- * solves that use two-step kernels take one batched four-step launch
- * (multi-step variant 2, S4 H16 X4) per round of four steps while four more
- * levels remain (inside the averaging window too); with many solves resident
- * that variant has the least halo work per update, whatever jlb_autotune
- * chose for a single solve.  Results are the same bits either way.  Takes
- * effect at the next chunk.  JLB_E_ARG for a null engine.
+ * solves that use two-step kernels take one batched four-step launch per
+ * round of four steps while four more levels remain (inside the averaging
+ * window too), in the shape jlb_engine_four_step_choice reports.  Results
+ * are the same bits either way.  Takes effect at the next chunk.  JLB_E_ARG
+ * for a null engine.
  */
 int jlb_engine_set_four_step(jlb_engine *eng, int32_t on);
+
+/*
+ * The engine's four-step shape.  With four-step rounds on, the engine times
+ * the batched launch of each four-step variant (0 S4 H10 X4, 1 S4 H12 X4,
+ * 2 S4 H16 X4, 5 S4 H12 X8) over the resident solves of a precision that
+ * are in four-step mode for the whole next chunk and have ny >= 20, and
+ * runs the fastest; it times them again when that set's node count changes
+ * by more than a factor of 2.  Before its first timing it runs variant 2.
+ * The timing launches change no result.
+ *   precision       JLB_FP32 or JLB_BF16
+ *   *variant        (host) the multi-step variant the engine runs for that
+ *                   precision (-1: no four-step rounds)
+ *   ms_per_variant  (host, optional; JLB_MULTI_STEP_VARIANTS entries) the
+ *                   last timing's mean ms per batched launch, 0 where not timed
+ *   *tunings        (host, optional) timings taken so far, all precisions
+ * JLB_E_ARG for a null engine or variant pointer, or FP64.
+ */
+int jlb_engine_four_step_choice(jlb_engine *eng, int32_t precision, int32_t *variant, double *ms_per_variant,
+                                int32_t *tunings);
 
 /* Releases every resource of the engine. */
 int jlb_engine_destroy(jlb_engine *eng);

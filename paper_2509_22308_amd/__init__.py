@@ -124,6 +124,8 @@ def load():
             "jlb_engine_destroy": ([_vp], ctypes.c_int),
             "jlb_engine_set_policy": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
             "jlb_engine_set_four_step": ([_vp, ctypes.c_int32], ctypes.c_int),
+            "jlb_engine_four_step_choice": ([_vp, ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_double),
+                                             _P(ctypes.c_int32)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -416,6 +418,16 @@ class Engine:
     def set_four_step(self, on: bool):
         """Four-step rounds for the two-step solves (on by default)."""
         _check(load().jlb_engine_set_four_step(self._h, int(bool(on))))
+
+    def four_step_choice(self, precision: str = "fp32") -> dict:
+        """The four-step shape the engine runs for precision, the last timing's
+        ms per batched launch of each candidate and the timings taken so far."""
+        v, n = ctypes.c_int32(-1), ctypes.c_int32(0)
+        ms = (ctypes.c_double * len(MULTI_STEP_VARIANTS))()
+        _check(load().jlb_engine_four_step_choice(self._h, PRECISIONS[precision], ctypes.byref(v), ms, ctypes.byref(n)))
+        return {"variant": MULTI_STEP_VARIANTS.get(v.value) if v.value >= 0 else None,
+                "ms_per_launch": {MULTI_STEP_VARIANTS[k]: ms[k] for k in range(len(ms)) if ms[k] > 0.0},
+                "tunings": n.value}
 
     def stats(self) -> dict:
         q, r, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

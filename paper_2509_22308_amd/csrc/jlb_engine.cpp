@@ -8,7 +8,8 @@
 // lattice steps is captured once in a hipGraph and replayed while the set of
 // resident solves is unchanged.  The chunk is K / 4 rounds of four steps:
 // one batched four-step launch over the (strip, row segment) items of the
-// FP32 / BF16 solves with at least four levels to go, then the batched
+// FP32 / BF16 solves with at least four levels to go (its shape timed on
+// the resident mix), then the batched
 // contour launch of the averaged levels among them (the launch keeps its
 // intermediate levels' contour fields when one is averaged), two double steps
 // for the others, and the four-step solves' advance-by-four launch.  In a double step, solves on single steps (FP64, or
@@ -100,6 +101,13 @@ struct jlb_engine {
     // chunk holds items for: 1 two-step, 2 four-step, 3 both
     std::vector<uint8_t> part;
     bool four_step = true;  // four-step rounds for two-step solves
+    // the four-step shape per precision, chosen by timing the batched launch
+    // on the resident mix (-1: not timed yet), the times of the last timing
+    // and the four-step nodes it was taken on
+    int mchoice[3] = {-1, -1, -1};
+    double mtune_ms[3][MULTI_STEP_VARIANTS] = {};
+    double mtune_nodes[3] = {0.0, 0.0, 0.0};
+    int ntunes = 0;
     int max_nc = 0;
     int remap = 0;
     bool dirty = true;
@@ -110,15 +118,18 @@ struct jlb_engine {
 
 namespace {
 
-// The engine steps in rounds of four, and with many solves resident its
-// launches hold far more wavefronts than the device runs at once, so the
-// halo work per update decides: it takes the four-step variant with the
-// least of it (16-row segments, 4 halo columns).  The autotuner's multi-step
-// choice, made on one solve's grid, is about latency instead and does not
-// apply here.
-int engine_multi_variant(bool on)
+// The engine steps in rounds of four.  Which four-step shape is fastest
+// depends on the resident mix (a few small solves are latency-bound, many
+// large ones bound by the halo work per update), so the engine times the
+// candidates on the mix itself (tune_four_step); until then it takes the
+// one with the least halo work (16-row segments, 4 halo columns).
+constexpr int FOUR_STEP_CANDIDATES[] = {MULTI_S4_H10_X4, MULTI_S4_H12_X4, MULTI_S4_H16_X4, MULTI_S4_H12_X8};
+constexpr int FOUR_STEP_MAX_ROWS = 16;  // the tallest candidate's segment
+
+int engine_multi_variant(const jlb_engine *e, int p)
 {
-    return on ? MULTI_S4_H16_X4 : -1;
+    if (!e->four_step) return -1;
+    return e->mchoice[p] >= 0 ? e->mchoice[p] : MULTI_S4_H16_X4;
 }
 
 // Which batched launches a resident solve needs over the next chunk of
@@ -276,7 +287,7 @@ int rebuild(jlb_engine *e)
     for (int p = 0; p < 3; ++p) {
         e->variant[p] = jlb::step_variant(p);
         e->two[p] = p == JLB_FP64 ? -1 : jlb::two_step_variant(p);
-        e->multi[p] = e->two[p] >= 0 ? engine_multi_variant(e->four_step) : -1;
+        e->multi[p] = e->two[p] >= 0 ? engine_multi_variant(e, p) : -1;
     }
     e->any_single = e->any_two = e->any_multi = false;
     e->part.assign(ns, 0);
@@ -430,6 +441,85 @@ hipError_t launch_quad_step(jlb_engine *e)
     for (int k = 0; k < 2 && err == hipSuccess; ++k) err = launch_double_step(e);
     if (e->any_multi && err == hipSuccess) err = launch_advance(e->d_desc, ns, 2, e->s);
     return err;
+}
+
+// Times the batched four-step launch of every candidate shape over the
+// solves of each FP32 / BF16 precision that are in four-step mode for the
+// whole next chunk (those every candidate can take: ny >= 20), when that
+// set's node count differs by more than a factor of 2 from the one of the
+// last timing, and keeps the fastest.  The timed launches write only what
+// the next real launch writes again before anything reads it (the other
+// state buffer, the window's intermediate contour fields); no solve's step
+// counter moves.  *changed: a precision's shape changed (the caller
+// rebuilds).
+int tune_four_step(jlb_engine *e, bool &changed)
+{
+    changed = false;
+    if (!e->four_step || !e->any_multi) return JLB_OK;
+    const bool row_major = e->remap == 0;  // the order rebuild() uses for this residency
+    for (int p = 1; p < 3; ++p) {
+        if (e->multi[p] < 0) continue;
+        std::vector<int> ks;
+        double nodes = 0.0;
+        for (size_t k = 0; k < e->resident.size(); ++k) {
+            const Plan &q = e->reqs[e->resident[k]].plan;
+            if (q.prob.precision != p || !(e->part[k] & 2) || q.ny < FOUR_STEP_MAX_ROWS + 4) continue;
+            ks.push_back((int)k);
+            nodes += (double)q.nx * q.ny;
+        }
+        if (ks.empty()) continue;
+        const double last = e->mtune_nodes[p];
+        if (last > 0.0 && nodes <= 2.0 * last && 2.0 * nodes >= last) continue;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        hipError_t err = hipEventCreate(&ev0);
+        if (err == hipSuccess) err = hipEventCreate(&ev1);
+        double ms_of[MULTI_STEP_VARIANTS] = {};
+        int best = -1;
+        for (int v : FOUR_STEP_CANDIDATES) {
+            if (err != hipSuccess) break;
+            std::vector<Tile> items;
+            for (int k : ks) {
+                const Plan &q = e->reqs[e->resident[k]].plan;
+                int mx, my;
+                multi_step_grid(v, q.nx, q.ny, mx, my);
+                if (row_major) {
+                    for (int y = 0; y < my; ++y)
+                        for (int x = 0; x < mx; ++x) items.push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
+                } else {
+                    for (int x = 0; x < mx; ++x)
+                        for (int y = 0; y < my; ++y) items.push_back(Tile{(uint32_t)k, (uint16_t)x, (uint16_t)y});
+                }
+            }
+            Tile *d_items = nullptr;
+            err = hipMallocAsync((void **)&d_items, sizeof(Tile) * items.size(), e->s);
+            if (err == hipSuccess)
+                err = hipMemcpyAsync(d_items, items.data(), sizeof(Tile) * items.size(), hipMemcpyHostToDevice, e->s);
+            const int n = (int)items.size();
+            if (err == hipSuccess) err = launch_stepm_batch(p, v, e->d_desc, d_items, n, e->remap, e->s);  // warm-up
+            if (err == hipSuccess) err = hipEventRecord(ev0, e->s);
+            constexpr int TIMED = 3;
+            for (int i = 0; i < TIMED && err == hipSuccess; ++i)
+                err = launch_stepm_batch(p, v, e->d_desc, d_items, n, e->remap, e->s);
+            if (err == hipSuccess) err = hipEventRecord(ev1, e->s);
+            if (err == hipSuccess) err = hipEventSynchronize(ev1);
+            float ms = 0.0f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev0, ev1);
+            if (d_items) (void)hipFreeAsync(d_items, e->s);
+            if (err != hipSuccess) break;
+            ms_of[v] = ms / TIMED;
+            if (best < 0 || ms_of[v] < ms_of[best]) best = v;
+        }
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (err == hipSuccess) err = hipStreamSynchronize(e->s);
+        if (err != hipSuccess) return fail(JLB_E_DEVICE, "engine four-step timing: %s", hipGetErrorString(err));
+        std::copy(ms_of, ms_of + MULTI_STEP_VARIANTS, e->mtune_ms[p]);
+        e->mtune_nodes[p] = nodes;
+        e->ntunes += 1;
+        if (best != e->multi[p]) changed = true;
+        e->mchoice[p] = best;
+    }
+    return JLB_OK;
 }
 
 int capture(jlb_engine *e)
@@ -590,6 +680,14 @@ int jlb_engine_run(jlb_engine *e, int64_t steps, int32_t *active)
             rc = rebuild(e);
             if (rc) return rc;
         }
+        // the four-step shape for this mix
+        bool retuned = false;
+        rc = tune_four_step(e, retuned);
+        if (rc) return rc;
+        if (retuned) {
+            rc = rebuild(e);
+            if (rc) return rc;
+        }
         // whole double steps
         const int64_t k = std::min<int64_t>(CHUNK, (steps - done + 1) / 2 * 2);
         if (k == CHUNK) {
@@ -689,6 +787,18 @@ int jlb_engine_set_four_step(jlb_engine *e, int32_t on)
         e->four_step = on != 0;
         e->dirty = true;
     }
+    return JLB_OK;
+}
+
+int jlb_engine_four_step_choice(jlb_engine *e, int32_t precision, int32_t *variant, double *ms_per_variant,
+                                int32_t *tunings)
+{
+    clear_error();
+    if (!e || !variant) return fail(JLB_E_ARG, "null argument");
+    if (precision != JLB_FP32 && precision != JLB_BF16) return fail(JLB_E_ARG, "four-step rounds are FP32 / BF16");
+    *variant = jlb::two_step_variant(precision) >= 0 ? engine_multi_variant(e, precision) : -1;
+    if (ms_per_variant) std::copy(e->mtune_ms[precision], e->mtune_ms[precision] + MULTI_STEP_VARIANTS, ms_per_variant);
+    if (tunings) *tunings = e->ntunes;
     return JLB_OK;
 }
 

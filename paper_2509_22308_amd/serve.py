@@ -54,10 +54,11 @@ def run_design_map(problems, precision: str = "fp32", budget_bytes: int | None =
     for t in tickets:
         status, res = eng.poll(t)
         results.append(dict(res.as_dict(), status=status))
+    four = eng.four_step_choice(precision) if precision != "fp64" else None
     eng.close()
     lups = float(sum(p["nx"] * p["ny"] * p["steps"] for p in problems))
     return {"results": results, "wall_s": wall, "lups": lups / wall, "solves_per_hour": len(problems) / wall * 3600.0,
-            "peak_resident": peak, "budget_bytes": budget}
+            "peak_resident": peak, "budget_bytes": budget, "four_step": four}
 
 
 def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, max_slots: int = 256,
@@ -110,6 +111,7 @@ def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, ma
                              "latency_s": now - arr, "queue_s": max(0.0, (res.total_ms - res.loop_ms) * 1e-3),
                              "submit_delay_s": sub - arr, "fx": res.fx, "fy": res.fy, "tz": res.tz})
     wall = time.perf_counter() - t0
+    four = eng.four_step_choice(precision) if precision != "fp64" else None
     eng.close()
     lat = np.array([d["latency_s"] for d in done if d["status"] == "done"])
     wait = np.array([d["queue_s"] for d in done if d["status"] == "done"])
@@ -128,5 +130,5 @@ def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, ma
         "policy": policy, "max_slots": max_slots,
         "throughput_lups": lups / wall, "solves_per_hour": len(lat) / wall * 3600.0,
         "offered_lups": lups / span if span > 0 else None, "peak_resident": peak, "budget_bytes": budget,
-        "done": sorted(done, key=lambda d: d["index"]),
+        "four_step": four, "done": sorted(done, key=lambda d: d["index"]),
     }

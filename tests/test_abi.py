@@ -123,7 +123,11 @@ def test_multi_step_variant_table_and_argument_checks():
 
 
 def test_engine_four_step_switch_checks_its_engine():
-    assert J.load().jlb_engine_set_four_step(None, 1) == -1
+    import ctypes
+    lib = J.load()
+    assert lib.jlb_engine_set_four_step(None, 1) == -1
+    v = ctypes.c_int32(0)
+    assert lib.jlb_engine_four_step_choice(None, 1, ctypes.byref(v), None, None) == -1
 
 
 def test_workspace_grows_with_precision_and_grid():

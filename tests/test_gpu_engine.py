@@ -184,6 +184,42 @@ def test_four_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, four, 
         assert b["steps_done"] == s["steps_done"]
 
 
+def test_engine_times_its_four_step_shape_on_the_mix(jlb, two_step):
+    """The engine times each four-step shape's batched launch on the resident
+    mix, runs the fastest, and still equals the single solves bit for bit."""
+    prec = jlb.PRECISIONS["bf16"]
+    multi0 = jlb.jlb_get_multi_step_variant(prec)
+    probs = _mix()
+    try:
+        two_step(-1)
+        jlb.jlb_set_multi_step_variant(prec, -1)
+        single = [jlb.solve(p, "bf16") for p in probs]
+        two_step(4)
+        eng = jlb.Engine(8 << 30, 64)
+        assert eng.four_step_choice("bf16")["tunings"] == 0
+        tickets = [eng.submit(jlb.make_problem(p, "bf16")) for p in probs]
+        eng.run(128)
+        choice = eng.four_step_choice("bf16")
+        for _ in range(1000):
+            st = eng.stats()
+            if st["queued"] == 0 and st["resident"] == 0:
+                break
+            eng.run(256)
+        batched = [eng.poll(t)[1].as_dict() for t in tickets]
+        eng.close()
+    finally:
+        jlb.jlb_set_multi_step_variant(prec, multi0)
+    print(f"[engine] four-step choice {choice}", flush=True)
+    times = choice["ms_per_launch"]
+    assert choice["tunings"] >= 1
+    assert sorted(times) == sorted(["four-step H10 X4", "four-step H12 X4", "four-step H16 X4", "four-step H12 X8"])
+    assert all(t > 0.0 for t in times.values())
+    assert choice["variant"] == min(times, key=times.get)
+    for s, b in zip(single, batched):
+        for q in ("fx", "fy", "tz", "energy_final"):
+            assert s[q] == b[q], (q, s[q], b[q])
+
+
 def test_two_step_and_single_step_solves_share_an_engine(jlb, two_step):
     """FP64 solves on single steps and FP32 / BF16 solves on two-step launches
     in one engine, admitted at different times: each equals its single solve."""

@@ -47,6 +47,9 @@ class FakeEngine:
         if max_slots:
             self.slots = max_slots
 
+    def four_step_choice(self, precision="fp32"):
+        return {"variant": "four-step H16 X4", "ms_per_launch": {}, "tunings": 0}
+
     def close(self):
         pass
 
