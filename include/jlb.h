@@ -339,7 +339,8 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * the averaging window too (there it also writes the field planes of both
  * levels), but not with the plateau stop, and single steps elsewhere;
  * results equal single steps bit for bit.  The engine runs its FP64 solves
- * on single steps.
+ * on the selected FP64 two-step variant too (batched over the resident
+ * solves), or on single steps when it is -1.
  *
  * jlb_autotune times every single-step variant of prob->precision on prob's
  * grid (`launches` timed launches each, after 2 warm-up launches; workspace

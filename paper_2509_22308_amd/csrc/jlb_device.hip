@@ -911,12 +911,6 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq(Lattice L, co
     two_step_wave<NeqT, V, H, HX, LA>(L, srcv, dstv, einc0, einc1, mid, sx, sy, false);
 }
 
-// Source value of a batched solve at its step n (ramp table, then one period).
-__device__ __forceinline__ double batch_incident(const SolveDesc &d, int64_t n)
-{
-    return n < d.ramp_end ? d.src_tab[n] : d.src_tab[d.ramp_end + n % d.T];
-}
-
 // A two-step solve takes a multi-step launch while mdepth more levels remain
 // (inside the averaging window too: the launch keeps its intermediate levels'
 // contour fields and a batched contour launch accumulates the levels).
@@ -1189,8 +1183,8 @@ __global__ __launch_bounds__(CX *R) void k_step_f64_batch(SolveDesc *__restrict_
     const int j = t.ty * R + threadIdx.y;
     if (i >= d.L.nx || j > d.L.ny) return;
     const bool in_window = n + 1 > d.steps - d.window;
-    f64_node(d.L, (const double *)d.state[d.cur], (double *)d.state[d.cur ^ 1], in_window ? d.fields : nullptr,
-             batch_incident(d, n), i, j);
+    f64_node(d.L, (const double *)d.state[d.cur], (double *)d.state[d.cur ^ 1],
+             in_window ? d.fields + (size_t)((n + 1) & 1) * d.fields_level : nullptr, batch_incident(d, n), i, j);
 }
 
 template <typename NeqT>
@@ -1358,7 +1352,7 @@ __global__ void k_contour_batch(SolveDesc *__restrict__ D)
     if (d.two || n >= d.steps || !(n + 1 > d.steps - d.window)) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.C.n) return;
-    if (d.precision == 0) contour_sample_f64(d.L, d.fields, d.C, k);
+    if (d.precision == 0) contour_sample_f64(d.L, d.fields + (size_t)((n + 1) & 1) * d.fields_level, d.C, k);
     else contour_sample_f32(d.L, reinterpret_cast<const float *>(d.state[d.cur ^ 1]), d.L.sfld, d.C, k);
 }
 
@@ -1372,8 +1366,15 @@ __global__ void k_contour2_batch(SolveDesc *__restrict__ D)
     if (!d.two || n >= d.steps || multi_mode(d, n)) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.C.n) return;
-    const float *next = reinterpret_cast<const float *>(d.state[d.cur ^ 1]);
     const bool one = d.steps - n == 1;
+    if (d.precision == 0) {  // FP64: the field planes of each level, by level parity
+        if (n + 1 > d.steps - d.window)
+            contour_sample_f64(d.L, d.fields + (size_t)((n + 1) & 1) * d.fields_level, d.C, k);
+        if (!one && n + 2 > d.steps - d.window)
+            contour_sample_f64(d.L, d.fields + (size_t)((n + 2) & 1) * d.fields_level, d.C, k);
+        return;
+    }
+    const float *next = reinterpret_cast<const float *>(d.state[d.cur ^ 1]);
     if (n + 1 > d.steps - d.window) {
         if (one) contour_sample_f32(d.L, next, d.L.sfld, d.C, k);
         else contour_sample_f32(d.L, d.mid, 3 * d.L.plane, d.C, k);

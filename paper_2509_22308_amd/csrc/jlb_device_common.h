@@ -60,6 +60,12 @@ __device__ __forceinline__ size_t node(const Lattice &L, int i, int j) { return 
 // Index of node (i, j) in plane 0 of a row-interleaved array with row stride S.
 __device__ __forceinline__ size_t at(int i, int j, size_t S) { return (size_t)j * S + i; }
 
+// Source value of a batched solve at its step n (ramp table, then one period).
+__device__ __forceinline__ double batch_incident(const SolveDesc &d, int64_t n)
+{
+    return n < d.ramp_end ? d.src_tab[n] : d.src_tab[d.ramp_end + n % d.T];
+}
+
 // Workgroups are handed to the eight XCDs in turn (block b on XCD b mod 8),
 // and each XCD has its own L2.  Renumbering so that XCD x works through one
 // contiguous range of tiles keeps the halo rows that adjacent tiles share

@@ -155,12 +155,13 @@ __device__ __forceinline__ void f64_row_update(const Lattice &L, int i, int j, u
 // after it (0, keeping its registers free during the arithmetic so that
 // three wavefronts fit a SIMD).
 // FL: the field planes of both levels are written (fl1: n + 1, fl2: n + 2),
-// every node the launch owns, the companion row included.
+// every node the launch owns, the companion row included.  one: a single
+// step (a solve's last one), whose level n + 1 is the new state.
 template <int H, int HX, int LA, bool FL>
 __device__ __forceinline__ void f64_two_step_wave(const Lattice &L, const double *__restrict__ src,
                                                   double *__restrict__ dst, double *__restrict__ fl1,
                                                   double *__restrict__ fl2, double einc0, double einc1, int sx,
-                                                  int sy)
+                                                  int sy, bool one)
 {
     constexpr int OW = 64 - 2 * HX;
     static_assert(HX >= 2 && OW > 0, "two-step strip shape");
@@ -200,7 +201,11 @@ __device__ __forceinline__ void f64_two_step_wave(const Lattice &L, const double
         f64_row_update<true>(L, i, L.ny, 0, c0, Send{}, Send{}, StripSend{}, einc0, c1, fld);
         s0 = StripSend{send_up(c0), send_down(c0)};
         s1 = StripSend{send_up(c1), send_down(c1)};
-        if (j0 == 0) {
+        if (one && j0 == 0 && out_lane) {
+            store(L.ny, c1);
+            if (FL) store_fields(fl1, L.ny, fld);
+        }
+        if (!one && j0 == 0) {
             if (FL && out_lane) store_fields(fl1, L.ny, fld);
             Pops c2;
             f64_row_update<true>(L, i, L.ny, 0, c1, Send{}, Send{}, StripSend{}, einc1, c2, fld);
@@ -249,9 +254,12 @@ __device__ __forceinline__ void f64_two_step_wave(const Lattice &L, const double
             const Send a_side = to_behind(a_ahead);
             f64_row_update<false>(L, i, r1, m_cur, a_cur, DIR > 0 ? a_behind : a_side, DIR > 0 ? a_side : a_behind,
                                   s0, einc0, b_new, fld);
-            if (FL && out_lane && r1 >= j0 && r1 < j0 + H && r1 < L.ny) store_fields(fl1, r1, fld);
+            if (out_lane && r1 >= j0 && r1 < j0 + H && r1 < L.ny) {
+                if (FL) store_fields(fl1, r1, fld);
+                if (one) store(r1, b_new);  // a single step: this row's result is the new state
+            }
             // step n + 1 -> n + 2 on the row behind r1
-            if (k >= 2) {
+            if (!one && k >= 2) {
                 const int r2 = r1 - DIR;
                 Pops o;
                 const Send b_side = to_behind(b_new);
@@ -296,7 +304,36 @@ __global__ __launch_bounds__(64 * F64_TWO_WAVES, W) void k_step2_f64(Lattice L, 
     const int w = __builtin_amdgcn_readfirstlane(b * F64_TWO_WAVES + (int)threadIdx.y);
     if (w >= nsx * nsy) return;  // whole wavefront
     const int sx = L.stream_stores ? w % nsx : w / nsy, sy = L.stream_stores ? w / nsx : w % nsy;
-    f64_two_step_wave<H, HX, LA, FL>(L, src, dst, fl1, fl2, einc0, einc1, sx, sy);
+    f64_two_step_wave<H, HX, LA, FL>(L, src, dst, fl1, fl2, einc0, einc1, sx, sy, false);
+}
+
+// Batched two-step launch: wavefront w takes items[w] (slot, strip, row
+// segment) of a resident FP64 solve at that solve's own step n; the field
+// planes of both levels (by level parity) when either is averaged; a single
+// step when the solve has one left.
+template <int H, int HX, int W, int LA>
+__global__ __launch_bounds__(64 * F64_TWO_WAVES, W) void k_step2_f64_batch(SolveDesc *__restrict__ D,
+                                                                           const Tile *__restrict__ items, int nitems,
+                                                                           int remap)
+{
+    const int b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(b * F64_TWO_WAVES + (int)threadIdx.y);
+    if (w >= nitems) return;
+    const Tile t = items[w];
+    const SolveDesc &d = D[t.slot];
+    const int64_t n = d.n;
+    if (n >= d.steps) return;
+    const bool one = d.steps - n == 1;
+    const double e0 = batch_incident(d, n), e1 = one ? 0.0 : batch_incident(d, n + 1);
+    const double *src = (const double *)d.state[d.cur];
+    double *dst = (double *)d.state[d.cur ^ 1];
+    if (n + 2 > d.steps - d.window) {
+        double *fl1 = d.fields + (size_t)((n + 1) & 1) * d.fields_level;
+        double *fl2 = d.fields + (size_t)((n + 2) & 1) * d.fields_level;
+        f64_two_step_wave<H, HX, LA, true>(d.L, src, dst, fl1, fl2, e0, e1, t.tx, t.ty, one);
+    } else {
+        f64_two_step_wave<H, HX, LA, false>(d.L, src, dst, nullptr, nullptr, e0, e1, t.tx, t.ty, one);
+    }
 }
 
 template <typename F> void f64_two_dispatch(int variant, F &&go)
@@ -325,6 +362,29 @@ template <typename F> void f64_two_dispatch(int variant, F &&go)
 }
 
 }  // namespace
+
+void two_step_shape_f64(int variant, int nx, int ny, int &nsx, int &nsy)
+{
+    f64_two_dispatch(variant, [&](auto htag, auto xtag, auto, auto) {
+        constexpr int H = decltype(htag)::value, HX = decltype(xtag)::value;
+        nsx = (nx + (64 - 2 * HX) - 1) / (64 - 2 * HX);
+        nsy = (ny + H - 1) / H;
+    });
+}
+
+hipError_t launch_step2_f64_batch(int variant, SolveDesc *d, const Tile *items, int nitems, int remap, hipStream_t s)
+{
+    if (variant < 0 || variant >= F64_TWO_STEP_VARIANTS) return hipErrorInvalidValue;
+    if (nitems <= 0) return hipSuccess;
+    const int blocks = (nitems + F64_TWO_WAVES - 1) / F64_TWO_WAVES;
+    f64_two_dispatch(variant, [&](auto htag, auto xtag, auto wtag, auto atag) {
+        constexpr int H = decltype(htag)::value, HX = decltype(xtag)::value, W = decltype(wtag)::value;
+        constexpr int LA = decltype(atag)::value;
+        hipLaunchKernelGGL((k_step2_f64_batch<H, HX, W, LA>), dim3(blocks), dim3(64, F64_TWO_WAVES), 0, s, d, items,
+                           nitems, remap);
+    });
+    return hipGetLastError();
+}
 
 hipError_t launch_step_f64(const Lattice &L, const double *src, double *dst, double *fields, double einc,
                            hipStream_t s, int variant)

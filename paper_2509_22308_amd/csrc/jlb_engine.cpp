@@ -12,11 +12,13 @@
 // the resident mix), then the batched
 // contour launch of the averaged levels among them (the launch keeps its
 // intermediate levels' contour fields when one is averaged), two double steps
-// for the others, and the four-step solves' advance-by-four launch.  In a double step, solves on single steps (FP64, or
-// with two-step kernels off) take two rounds of one launch per precision
-// over their tiles, one batched contour launch and one advance launch, and
-// FP32 / BF16 solves take one batched two-step launch over their items, one
-// two-level contour launch and one advance-by-two launch.  Each kernel skips
+// for the others, and the four-step solves' advance-by-four launch.  In a
+// double step, solves on single steps (two-step kernels off for their
+// precision) take two rounds of one launch per precision over their tiles,
+// one batched contour launch and one advance launch, and the others take
+// one batched two-step launch per precision over their items (FP64: writing
+// both levels' field planes when either is averaged), one two-level contour
+// launch and one advance-by-two launch.  Each kernel skips
 // the solves that are not its own at their current step.  Solves that finish inside a chunk idle
 // (their tiles return at once) until the chunk boundary, where the engine
 // reduces their contour sums, returns their memory and admits waiting
@@ -286,8 +288,8 @@ int rebuild(jlb_engine *e)
     e->remap = stream_stores ? 0 : 1;
     for (int p = 0; p < 3; ++p) {
         e->variant[p] = jlb::step_variant(p);
-        e->two[p] = p == JLB_FP64 ? -1 : jlb::two_step_variant(p);
-        e->multi[p] = e->two[p] >= 0 ? engine_multi_variant(e, p) : -1;
+        e->two[p] = jlb::two_step_variant(p);
+        e->multi[p] = p != JLB_FP64 && e->two[p] >= 0 ? engine_multi_variant(e, p) : -1;
     }
     e->any_single = e->any_two = e->any_multi = false;
     e->part.assign(ns, 0);
@@ -302,6 +304,7 @@ int rebuild(jlb_engine *e)
         d.state[1] = r.ws + q.off_state[1];
         d.cur = r.cur;
         d.fields = q.prob.precision == JLB_FP64 ? (double *)(r.ws + q.off_fields) : nullptr;
+        d.fields_level = (size_t)3 * q.plane;
         d.mid = q.prob.precision == JLB_FP64 ? nullptr : (float *)(r.ws + q.off_mid);
         d.src_tab = (const double *)(r.ws + q.ws_bytes);
         d.ramp_end = r.ramp_end;
@@ -320,7 +323,8 @@ int rebuild(jlb_engine *e)
             // one wavefront per (strip, row segment), in the order the
             // single-solve launch uses for this residency
             int nsx, nsy;
-            two_step_shape(e->two[p], q.nx, q.ny, nsx, nsy);
+            if (p == JLB_FP64) two_step_shape_f64(e->two[p], q.nx, q.ny, nsx, nsy);
+            else two_step_shape(e->two[p], q.nx, q.ny, nsx, nsy);
             if (part & 1) {
                 e->any_two = true;
                 if (stream_stores) {
@@ -417,10 +421,12 @@ hipError_t launch_double_step(jlb_engine *e)
         if (err == hipSuccess) err = launch_advance(e->d_desc, ns, 0, e->s);
     }
     if (e->any_two && err == hipSuccess) {
-        for (int p = 1; p < 3 && err == hipSuccess; ++p)
+        for (int p = 0; p < 3 && err == hipSuccess; ++p)
             if (e->nitems[p] > 0)
-                err = launch_step2_batch(p, e->two[p], e->d_desc, e->d_tiles + e->item_off[p], e->nitems[p], e->remap,
-                                         e->s);
+                err = p == JLB_FP64 ? launch_step2_f64_batch(e->two[p], e->d_desc, e->d_tiles + e->item_off[p],
+                                                             e->nitems[p], e->remap, e->s)
+                                    : launch_step2_batch(p, e->two[p], e->d_desc, e->d_tiles + e->item_off[p],
+                                                         e->nitems[p], e->remap, e->s);
         if (err == hipSuccess) err = launch_contour2_batch(e->d_desc, ns, e->max_nc, e->s);
         if (err == hipSuccess) err = launch_advance(e->d_desc, ns, 1, e->s);
     }
@@ -563,10 +569,12 @@ int harvest(jlb_engine *e)
         const double f0 = M_PI * q.prob.radius * q.prob.e0 * q.prob.e0 / 4.0;
         err = launch_reduce(C, 1.0 / (double)q.window, f0, 2.0 * f0 * q.prob.radius, (double *)(r.ws + q.off_out), e->s);
         if (err == hipSuccess) {
-            // the final fields: FP64 keeps them in its field planes (written through the window), the
-            // others in the state buffer that holds the last level
+            // the final fields: FP64 keeps them in the field planes of the last level's parity
+            // (written through the window), the others in the state buffer that holds the last level
             const Lattice L = lattice_of(q, (const uint8_t *)(r.ws + q.off_mask));
-            const void *fld = q.prob.precision == JLB_FP64 ? (const void *)(r.ws + q.off_fields) : r.ws + q.off_state[r.cur];
+            const void *fld = q.prob.precision == JLB_FP64
+                                  ? (const void *)(r.ws + q.off_fields + (size_t)(q.prob.steps & 1) * 3 * q.plane * sizeof(double))
+                                  : r.ws + q.off_state[r.cur];
             err = launch_energy(q.prob.precision, L, fld, (double *)(r.ws + q.off_parts), q.nparts,
                                 (double *)(r.ws + q.off_out) + 6, e->s);
         }

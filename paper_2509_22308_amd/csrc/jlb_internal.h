@@ -198,7 +198,9 @@ hipError_t launch_fields_out(int precision, const Lattice &L, const void *fields
 struct SolveDesc {
     Lattice L;
     char *state[2];
-    double *fields;          // FP64: field planes written inside the averaging window
+    double *fields;          // FP64: field planes written inside the averaging window, level t at
+                             // fields + (t & 1) * fields_level
+    size_t fields_level;
     float *mid;              // FP32 / BF16 two-step solves: middle-level fields of the contour-stencil nodes
     const double *src_tab;   // incident values: [ramp_end] ramp steps, then [T] by n mod T
     int64_t ramp_end, T;
@@ -231,6 +233,11 @@ hipError_t launch_step2_batch(int precision, int variant, SolveDesc *d, const Ti
                               hipStream_t s);
 // Strip and segment counts of a two-step variant for an nx x ny lattice.
 void two_step_shape(int variant, int nx, int ny, int &nsx, int &nsy);
+// FP64 two-step launches over the FP64 solves with two == 1, one wavefront
+// per item (slot, strip tx, row segment ty) of the given FP64 variant; the
+// strips and segments of a grid.
+hipError_t launch_step2_f64_batch(int variant, SolveDesc *d, const Tile *items, int nitems, int remap, hipStream_t s);
+void two_step_shape_f64(int variant, int nx, int ny, int &nsx, int &nsy);
 hipError_t launch_contour2_batch(SolveDesc *d, int nslots, int max_nc, hipStream_t s);
 // After a batched multi-step launch: the averaged levels of each solve in
 // multi mode, in time order.

@@ -152,6 +152,26 @@ def test_two_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, precisi
             assert s[q] == b[q], (precision, variant, q, s[q], b[q])
 
 
+@pytest.mark.parametrize("chunk", [256, 130])
+@pytest.mark.parametrize("variant", [0, 2, 4, 6])
+def test_fp64_two_step_engine_equals_single_solves_bit_for_bit(jlb, variant, chunk):
+    """Batched FP64 two-step launches (every solve at its own step, ramp and
+    window included, both levels' field planes by level parity, a window
+    start between the two levels of a launch, a final single step for an
+    odd count) equal single-step solves: forces and final energy."""
+    v0 = jlb.jlb_get_two_step_variant(0)
+    try:
+        jlb.jlb_set_two_step_variant(0, -1)
+        single = [jlb.solve(p, "fp64") for p in _mix()]
+        jlb.jlb_set_two_step_variant(0, variant)
+        batched = _run_engine(jlb, [jlb.make_problem(p, "fp64") for p in _mix()], chunk=chunk)
+    finally:
+        jlb.jlb_set_two_step_variant(0, v0)
+    for s, b in zip(single, batched):
+        for q in ("fx", "fy", "tz", "fx_raw", "fy_raw", "tz_raw", "energy_final"):
+            assert s[q] == b[q], (variant, chunk, q, s[q], b[q])
+
+
 @pytest.mark.parametrize("four", [True, False])
 @pytest.mark.parametrize("chunk", [256, 130])
 def test_four_step_engine_equals_single_solves_bit_for_bit(jlb, two_step, four, chunk):
