@@ -78,8 +78,9 @@ def _workspace(jlb, prob):
 
 
 def measured_traffic(precision: str, variant: int):
-    """HBM bytes per launch of the step kernel from the committed counter
-    summary, or None when it was taken on a different kernel source."""
+    """Bytes per launch of the step kernel leaving L2 (to the Infinity Cache
+    and HBM), from the committed counter summary, or None when it was taken
+    on a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -88,7 +89,7 @@ def measured_traffic(precision: str, variant: int):
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     e = t.get("config2", {}).get(precision, {}).get(str(variant))
-    return e.get("hbm_bytes_per_launch") if e else None
+    return e.get("l2_egress_bytes_per_launch") if e else None
 
 
 def measured_valu(precision: str, variant: int):
@@ -517,7 +518,7 @@ def _counter_means(d: str, counter: str) -> dict:
 
 
 def record_traffic(args):
-    """HBM bytes per launch of the step kernel from a FETCH_SIZE and a
+    """Bytes per launch of the step kernel leaving L2, from a FETCH_SIZE and a
     WRITE_SIZE pass of --kernel-only, each scaled so that the plain copy
     kernel of the same run reads its known byte count, merged into the
     traffic file under (workload, precision, variant)."""
@@ -536,7 +537,7 @@ def record_traffic(args):
     w_kib, w_scale = pick(write, copy_bytes)
     entry = {"variant": args.variant, "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
              "fetch_scale": f_scale, "write_scale": w_scale,
-             "hbm_bytes_per_launch": f_kib * 1024.0 * f_scale + w_kib * 1024.0 * w_scale, "command": args.command}
+             "l2_egress_bytes_per_launch": f_kib * 1024.0 * f_scale + w_kib * 1024.0 * w_scale, "command": args.command}
     try:
         with open(args.out) as f:
             t = json.load(f)
