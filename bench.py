@@ -475,7 +475,8 @@ def run_kernel_only(args):
 
 def summarize(args):
     """Short text summary of rocprofv3 CSV output (kernel stats or counters)."""
-    lines = [f"# rocprofv3 summary of {args.summarize}", f"command: {args.command}" if args.command else "", ""]
+    lines = [f"# rocprofv3 summary ({os.path.basename(os.path.normpath(args.summarize))})",
+             f"command: {args.command}" if args.command else "", ""]
     stats = glob.glob(os.path.join(args.summarize, "**", "*kernel_stats.csv"), recursive=True)
     for path in stats:
         with open(path) as f:
