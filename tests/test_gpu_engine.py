@@ -281,6 +281,37 @@ def test_smallest_work_first_admission(jlb):
     eng.close()
 
 
+def test_a_failing_solve_does_not_stop_the_others(jlb):
+    """Failure handling, forced from the host: a request whose fields
+    overflow (a finite but huge amplitude, 1e200, in FP32) comes back with
+    non-finite forces: a single solve returns JLB_E_NONFINITE, and in the
+    engine the request ends "failed" while the rest of the mix finishes,
+    each equal to its single solve."""
+    probs = _mix()[:3]
+    bad = dict(probs[1], e0=1e200)
+    single = [jlb.solve(p, "fp32") for p in probs]
+    with pytest.raises(jlb.JlbError) as err:
+        jlb.solve(bad, "fp32")
+    assert err.value.code == -7
+    eng = jlb.Engine(8 << 30, 64)
+    tickets = [eng.submit(jlb.make_problem(p, "fp32")) for p in probs]
+    bad_ticket = eng.submit(jlb.make_problem(bad, "fp32"))
+    for _ in range(1000):
+        st = eng.stats()
+        if st["queued"] == 0 and st["resident"] == 0:
+            break
+        eng.run(256)
+    assert eng.poll(bad_ticket)[0] == "failed"
+    for t, s in zip(tickets, single):
+        status, res = eng.poll(t)
+        assert status == "done"
+        b = res.as_dict()
+        for q in ("fx", "fy", "tz", "energy_final"):
+            assert s[q] == b[q], (q, s[q], b[q])
+    assert eng.stats()["finished"] == 4
+    eng.close()
+
+
 def test_engine_rejects_the_plateau_stop(jlb):
     eng = jlb.Engine(1 << 30, 2)
     with pytest.raises(jlb.JlbError) as ei:
