@@ -131,9 +131,22 @@ __device__ __forceinline__ Coef coef_tm(float inv_eps6, float eps_rest6)
 {
     return Coef{inv_eps6, SIXTH, eps_rest6, 2.0f};
 }
+__device__ __forceinline__ Coef coef_te(float inv_eps6, float eps_rest6)
+{
+    return Coef{SIXTH, inv_eps6, 2.0f, eps_rest6};
+}
 __device__ __forceinline__ Coef coef_of(const Lattice &L, float inv_eps6, float eps_rest6)
 {
-    return L.te ? Coef{SIXTH, inv_eps6, 2.0f, eps_rest6} : coef_tm(inv_eps6, eps_rest6);
+    return L.te ? coef_te(inv_eps6, eps_rest6) : coef_tm(inv_eps6, eps_rest6);
+}
+// TEM: the polarisation fixed when the kernel is compiled (0 TM^z, 1 TE^z),
+// which spares the per-node choice, or read from the lattice (2).
+template <int TEM>
+__device__ __forceinline__ Coef coef_pick(const Lattice &L, float inv_eps6, float eps_rest6)
+{
+    if constexpr (TEM == 0) return coef_tm(inv_eps6, eps_rest6);
+    else if constexpr (TEM == 1) return coef_te(inv_eps6, eps_rest6);
+    else return coef_of(L, inv_eps6, eps_rest6);
 }
 
 // The post-collision pair a node sends along an axis: the e population and
@@ -616,7 +629,7 @@ __device__ __forceinline__ void row_coefs(const Lattice &L, typename MaskVec<V>:
 
 // One row's update with its material coefficients given (a sweep that
 // updates the same row at several levels picks them once).
-template <typename NeqT, int V, bool STRIP>
+template <typename NeqT, int V, bool STRIP, int TEM = 2>
 __device__ __forceinline__ void row_update_k(const Lattice &L, int i0, int r, typename MaskVec<V>::type mv,
                                              const float (&ie)[V], const float (&er)[V], const RowData<V> &cur,
                                              const SideRow<V> &below, const SideRow<V> &above,
@@ -647,7 +660,7 @@ __device__ __forceinline__ void row_update_k(const Lattice &L, int i0, int r, ty
         const float e_px = v == 0 ? xl_e : ee[v - 1], hx_px = v == 0 ? xl_h : eh[v - 1];
         const float e_mx = v == V - 1 ? xr_e : we[v + 1], hx_mx = v == V - 1 ? xr_h : wh[v + 1];
         NodeData res;
-        neq_pulled<STRIP>(L, i, r, m, coef_of(L, ie[v], er[v]), o, e_px, hx_px, e_mx, hx_mx, below.e[v], below.h[v],
+        neq_pulled<STRIP>(L, i, r, m, coef_pick<TEM>(L, ie[v], er[v]), o, e_px, hx_px, e_mx, hx_mx, below.e[v], below.h[v],
                           above.e[v], above.h[v], Pair{inc.lo.e[v], inc.lo.h[v]}, Pair{inc.hi.e[v], inc.hi.h[v]}, einc,
                           res);
         out.ez[v] = res.ez;
@@ -952,7 +965,7 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES) void k_step2_neq_batch(SolveDe
 // averaging window) the fields at n + 1 .. n + S - 1 of the contour-stencil
 // nodes of the segment's own rows are written to mid, level after level
 // (mid_level floats apart, each 3 planes row-interleaved, row stride 3 pitch).
-template <typename NeqT, int V, int H, int HX, int S, bool MID>
+template <typename NeqT, int V, int H, int HX, int S, bool MID, int TEM = 2>
 __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__restrict__ srcv,
                                                 void *__restrict__ dstv, const float (&einc)[S], float *__restrict__ mid,
                                                 size_t mid_level, int sx, int sy)
@@ -1069,7 +1082,7 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
             {
                 const SideRow<V> side = side_of(a_ahead, AQA, AQB);
                 row_coefs<V, false>(L, mk[0], kie[0], ker[0]);
-                row_update_k<NeqT, V, false>(L, i0, r1, mk[0], kie[0], ker[0], a_cur, DIR > 0 ? a_behind : side,
+                row_update_k<NeqT, V, false, TEM>(L, i0, r1, mk[0], kie[0], ker[0], a_cur, DIR > 0 ? a_behind : side,
                                              DIR > 0 ? side : a_behind, StripSides<V>{edge[0], edge[0]}, einc[0], nw);
                 round_row<NeqT, V>(nw);
                 keep_mid(1, r1, nw, mk[0]);
@@ -1083,7 +1096,7 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
                 if (go) {
                     const int rs = r1 - s * DIR;
                     const SideRow<V> side = side_of(nw, AQA, AQB);
-                    row_update_k<NeqT, V, false>(L, i0, rs, mk[s], kie[s], ker[s], lv_cur[s],
+                    row_update_k<NeqT, V, false, TEM>(L, i0, rs, mk[s], kie[s], ker[s], lv_cur[s],
                                                  DIR > 0 ? lv_behind[s] : side,
                                                DIR > 0 ? side : lv_behind[s], StripSides<V>{edge[s], edge[s]},
                                                einc[s], o);
@@ -1127,7 +1140,7 @@ __device__ __forceinline__ void multi_step_wave(const Lattice &L, const void *__
 template <int S> struct Incident {
     float v[S];
 };
-template <typename NeqT, int V, int H, int HX, int S, int W, bool MID>
+template <typename NeqT, int V, int H, int HX, int S, int W, bool MID, int TEM>
 __global__ __launch_bounds__(64 * TWO_STEP_WAVES, W) void k_stepm_neq(Lattice L, const void *__restrict__ srcv,
                                                                      void *__restrict__ dstv, Incident<S> einc,
                                                                      float *__restrict__ mid, size_t mid_level,
@@ -1139,7 +1152,7 @@ __global__ __launch_bounds__(64 * TWO_STEP_WAVES, W) void k_stepm_neq(Lattice L,
     const int w = __builtin_amdgcn_readfirstlane(b * TWO_STEP_WAVES + (int)threadIdx.y);
     if (w >= nsx * nsy) return;  // whole wavefront
     const int sx = L.stream_stores ? w % nsx : w / nsy, sy = L.stream_stores ? w / nsx : w % nsy;
-    multi_step_wave<NeqT, V, H, HX, S, MID>(L, srcv, dstv, einc.v, mid, mid_level, sx, sy);
+    multi_step_wave<NeqT, V, H, HX, S, MID, TEM>(L, srcv, dstv, einc.v, mid, mid_level, sx, sy);
 }
 
 // Batched multi-step launch: wavefront w takes items[w] of a resident solve
@@ -1833,12 +1846,23 @@ hipError_t launch_stepm_neq(int precision, const Lattice &L, const void *src, vo
             const int nsx = (L.nx + two_step_width<V, HX>() - 1) / two_step_width<V, HX>();
             const int nsy = (L.ny + H - 1) / H;
             const int blocks = (nsx * nsy + TWO_STEP_WAVES - 1) / TWO_STEP_WAVES;
-            if (mid)
-                hipLaunchKernelGGL((k_stepm_neq<T, V, H, HX, S, W, true>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0,
-                                   s, L, src, dst, e, mid, mid_level, nsx, nsy);
-            else
-                hipLaunchKernelGGL((k_stepm_neq<T, V, H, HX, S, W, false>), dim3(blocks), dim3(64, TWO_STEP_WAVES), 0,
-                                   s, L, src, dst, e, nullptr, (size_t)0, nsx, nsy);
+            // the polarisation as a kernel instance (no per-node choice)
+            auto go = [&](auto mtag, auto ptag) {
+                constexpr bool MID = decltype(mtag)::value;
+                constexpr int TEM = decltype(ptag)::value;
+                hipLaunchKernelGGL((k_stepm_neq<T, V, H, HX, S, W, MID, TEM>), dim3(blocks),
+                                   dim3(64, TWO_STEP_WAVES), 0, s, L, src, dst, e, MID ? mid : nullptr,
+                                   MID ? mid_level : (size_t)0, nsx, nsy);
+            };
+            using TM = std::integral_constant<int, 0>;
+            using TE = std::integral_constant<int, 1>;
+            if (mid) {
+                if (L.te) go(std::true_type{}, TE{});
+                else go(std::true_type{}, TM{});
+            } else {
+                if (L.te) go(std::false_type{}, TE{});
+                else go(std::false_type{}, TM{});
+            }
         });
     };
     if (precision == 1) run(float{});

@@ -8,11 +8,11 @@
 //   8 hy_r 9 hy_{+y} 10 hy_{-y}):
 // a node gathers the post-collision populations that stream into it (the
 // pull, with the edge rules), forms the moments and stores f* = 2 f^eq - f.
-// Both kernels call the same collision with the same operands and without
-// FMA contraction, so a two-step launch equals two one-step launches bit for
-// bit.  Conductor nodes (Sec. II,
-// E_z^tot = 0) are updated like the others with their electric field set to
-// zero, the limit of infinite permittivity.
+// Both kernels call the same collision (f64_collide: reciprocals rounded
+// once in place of the divisions) with the same operands and without FMA
+// contraction, so a two-step launch equals two one-step launches bit for
+// bit.  Conductor nodes (Sec. II, E_z^tot = 0) are updated like the others
+// with their electric field set to zero, the limit of infinite permittivity.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -45,8 +45,8 @@ __global__ __launch_bounds__(CX *R) void k_step_f64(Lattice L, const double *__r
 // Step n -> n + 1 runs on rows j0 - 1 .. j0 + H and every column of the
 // strip, step n + 1 -> n + 2 on rows j0 .. j0 + H - 1 and the output
 // columns.  The wavefront sweeps the rows holding, at level n, all 11
-// populations of the row being updated and of the next one (a third in
-// flight) and, of the row behind, only the two populations it sends to the
+// populations of the row being updated and of the next one (one or two more
+// in flight) and, of the row behind, only the two populations it sends to the
 // row being updated; likewise at level n + 1.  x-neighbours come from the
 // adjacent lanes through DPP wave shifts.  Rows beyond the domain's edges
 // are loaded from a clamped address and never used: edge rows take their
