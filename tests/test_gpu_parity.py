@@ -195,7 +195,13 @@ def test_fp64_two_step_kernels_equal_single_steps(jlb, polarization):
              W.problem(nx=530, ny=97, radius=20.0, kind="metallo_dielectric_janus", eps1=4.0, phi0_deg=315.0,
                        wavelength=40.0, steps=720, avg_periods=1),
              W.problem(nx=64, ny=20, radius=3.0, kind="dielectric_janus", eps1=2.0, eps2=3.0, phi0_deg=60.0,
-                       wavelength=40.0, steps=720, avg_periods=1, contour_offset=2.0)]
+                       wavelength=40.0, steps=720, avg_periods=1, contour_offset=2.0),
+             # near the smallest grids the checks accept: one strip spans the
+             # grid, and a five-row segment reaches the top edge
+             W.problem(nx=20, ny=17, radius=2.0, kind="metallo_dielectric_janus", eps1=2.0, phi0_deg=30.0,
+                       wavelength=20.0, steps=240, avg_periods=1, contour_offset=1.6),
+             W.problem(nx=17, ny=20, radius=2.0, kind="metallo_dielectric_janus", eps1=2.0, phi0_deg=200.0,
+                       wavelength=20.0, steps=241, avg_periods=1, contour_offset=1.6)]
     cases = [dict(p, polarization=polarization) for p in cases]
     try:
         for p in cases:
