@@ -91,11 +91,11 @@ def test_te_far_field_matches_the_oracle(jlb, refs, precision):
 
 
 def test_te_and_tm_share_an_engine(jlb):
-    """TE^z and TM^z solves in one engine, FP32 / BF16 on the two-step
-    kernels and FP64 on single steps: each result equals its own jlb_solve
-    bit for bit."""
-    probs = [CASES["config1"], W.config1(), CASES["ragged-djc"], W.small_mdjc(4.0, 30.0, a=16)]
-    precs = ["fp32", "fp32", "bf16", "fp64"]
+    """TE^z and TM^z solves in one engine, FP32 / BF16 on the two- and
+    four-step kernels and FP64 on its two-step kernel, in both polarisations:
+    each result equals its own jlb_solve bit for bit."""
+    probs = [CASES["config1"], W.config1(), CASES["ragged-djc"], W.small_mdjc(4.0, 30.0, a=16), CASES["mdjc"]]
+    precs = ["fp32", "fp32", "bf16", "fp64", "fp64"]
     prec = jlb.PRECISIONS["fp32"]
     before = jlb.jlb_get_two_step_variant(prec)
     try:
