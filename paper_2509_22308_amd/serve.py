@@ -62,7 +62,7 @@ def run_design_map(problems, precision: str = "fp32", budget_bytes: int | None =
 
 
 def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, max_slots: int = 256,
-          steps_per_call: int = 256, time_scale: float = 1.0, policy: str = "fifo") -> dict:
+          steps_per_call: int = 128, time_scale: float = 1.0, policy: str = "fifo") -> dict:
     """Replay (arrival_seconds, problem) requests in wall-clock time.
 
     Requests are submitted when their arrival time has passed; the engine
@@ -70,7 +70,8 @@ def serve(requests, precision: str = "fp32", budget_bytes: int | None = None, ma
     work first with policy "sjf") and steps every resident solve together.
     Latency = completion time - arrival time; queue wait = admission time -
     submission time (the engine's clocks); submission delay = submission
-    time - arrival time (the host loop submits between engine calls).
+    time - arrival time (the host loop submits between engine calls, each
+    one captured chunk of steps_per_call steps by default).
     """
     reqs = sorted(requests, key=lambda r: r[0])
     budget = _engine_budget([p for _, p in reqs], precision, budget_bytes)
