@@ -14,7 +14,8 @@ for the two buffers) is written with non-temporal stores and the multi-step
 sweeps run row-major; a 1792^2 lattice takes that path in every precision.
 
 A config-3 point (metallo-dielectric Janus eps 4, phi0 = 30 deg, a = 48,
-768^2, 52 periods) gives the third row of the reduced-precision error table.
+768^2, 52 periods) gives the third row of the reduced-precision error table,
+and config 5's largest request (2048^2, a = 256) the largest grid.
 """
 import numpy as np
 import pytest
@@ -97,6 +98,25 @@ def test_streaming_store_path_matches_the_oracle(jlb, oracle, precision):
     check("stream1792", precision, g, ref)
     # the wave has reached the body and the top and bottom edges
     assert np.abs(ref["ez"][:, 100:200]).max() > 0.5 and np.abs(ref["ez"][[0, -1], :300]).max() > 0.5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_largest_serving_request_matches_the_oracle(jlb, oracle, precision):
+    """Config 5's largest request at its full grid: a = 256 centred in 2048^2,
+    lambda = 2a (dielectric Janus eps 9 / 2, 137 deg), cut to three periods
+    (the ramp, one more, the averaged one; 52 in a served request) so that
+    the oracle finishes in under a minute.  Every precision streams its
+    stores at this size."""
+    a = 256
+    p = W.problem(nx=8 * a, ny=8 * a, radius=float(a), kind="dielectric_janus", eps1=9.0, eps2=2.0,
+                  phi0_deg=137.0, wavelength=2.0 * a, steps=W.steps_for(2.0 * a, 3), avg_periods=1)
+    assert 2 * _state_bytes(p["nx"], p["ny"], precision) > CACHE_RESIDENT_BYTES
+    print(f"[case] largest serving request 2048^2 {precision}", flush=True)
+    ref = _oracle_run(oracle, "serve2048", p)
+    g = jlb.solve(p, precision, fields=True)
+    check("serve2048", precision, g, ref)
+    # by the averaged period the wave has crossed the body
+    assert np.abs(ref["ez"][:, 1024 + a:1024 + a + 64]).max() > 0.3
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
