@@ -116,6 +116,18 @@ def test_fp64_symmetric_bodies_have_zero_lift_and_torque_on_gpu(jlb):
         assert r["fx"] > 0.1 and abs(r["fy"]) < 1e-13 and abs(r["tz"]) < 1e-13, (kind, deg, r)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_no_scatterer_feels_no_force_on_gpu(jlb, precision):
+    """The degenerate body (eps = 1 everywhere): forces and torque vanish to
+    each precision's absolute floor, in both polarisations."""
+    for pol in ("tm", "te"):
+        p = W.problem(nx=160, ny=160, radius=20.0, kind="homogeneous", eps1=1.0, wavelength=40.0,
+                      steps=W.steps_for(40.0, 20), avg_periods=5, polarization=pol)
+        r = jlb.solve(p, precision)
+        for q in ("fx", "fy", "tz"):
+            assert abs(r[q]) <= force_bound(precision, 0.0), (pol, precision, q, r[q])
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("case", ["config1", "djc", "mdjc"])
 def test_reduced_precision_forces_within_targets(jlb, oracle, precision, case):

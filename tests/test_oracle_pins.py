@@ -470,6 +470,17 @@ def test_diagonal_conductor_wall_keeps_the_field_energy(eps):
         assert w.min() / w[0] > 0.9, (eps, angle, w.min() / w[0])
 
 
+def test_no_scatterer_feels_no_force():
+    """The degenerate body: eps = 1 everywhere.  The incident wave is then the
+    whole field, the averaged stress on the contour has no net flux (Sec.
+    II.B), and every force and the torque vanish to rounding."""
+    for a in (10, 20):
+        p = W.problem(nx=8 * a, ny=8 * a, radius=float(a), kind="homogeneous", eps1=1.0, wavelength=2.0 * a,
+                      steps=W.steps_for(2.0 * a, 20), avg_periods=5)
+        r = O.solve(p, fields=False)
+        assert abs(r["fx"]) < 1e-12 and abs(r["fy"]) < 1e-12 and abs(r["tz"]) < 1e-12, (a, r)
+
+
 def test_homogeneous_pec_cylinder_matches_series():
     """Textbook PEC series vs the oracle at a = 24, lambda = 48: the staircase
     error falls with the radius (4.9 %, 2.1 %, 2.4 %, 1.2 % at a = 8, 16, 24,
