@@ -312,6 +312,14 @@ def test_a_failing_solve_does_not_stop_the_others(jlb):
     eng.close()
 
 
+def test_an_empty_engine_runs_and_reports_nothing(jlb):
+    eng = jlb.Engine(1 << 28, 4)
+    assert eng.run(256) == 0
+    assert eng.stats() == {"queued": 0, "resident": 0, "finished": 0, "bytes_in_use": 0}
+    assert eng.four_step_choice("fp32")["tunings"] == 0
+    eng.close()
+
+
 def test_engine_rejects_the_plateau_stop(jlb):
     eng = jlb.Engine(1 << 30, 2)
     with pytest.raises(jlb.JlbError) as ei:

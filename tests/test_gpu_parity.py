@@ -117,6 +117,21 @@ def test_fp64_symmetric_bodies_have_zero_lift_and_torque_on_gpu(jlb):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_shortest_solve_matches_oracle(jlb, oracle, precision):
+    """The fewest steps the checks accept: the ramp period, then the averaged
+    period (no period before the window; the window is one captured chunk)."""
+    p = W.problem(nx=128, ny=112, radius=14.0, kind="metallo_dielectric_janus", eps1=3.0, phi0_deg=60.0,
+                  wavelength=40.0, steps=240, avg_periods=1)
+    _print_case(f"shortest-{precision}", p)
+    g = jlb.solve(p, precision, fields=True)
+    r = oracle.solve(p)
+    if precision == "fp64":
+        _check_fp64(g, r, "shortest")
+    else:
+        check("shortest", precision, g, r)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 def test_no_scatterer_feels_no_force_on_gpu(jlb, precision):
     """The degenerate body (eps = 1 everywhere): forces and torque vanish to
     each precision's absolute floor, in both polarisations."""
