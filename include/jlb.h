@@ -309,7 +309,9 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  *           stores), one row per thread, 64 x 4 thread blocks;
  *   3/4     the same with 256 x 1 thread blocks;  5/6  with 256 x 2.
  * FP64 (JLB_FP64_STEP_VARIANTS): 0 / 1 / 2 one node per thread in 64 x 4 /
- * 256 x 1 / 256 x 2 thread blocks.
+ * 256 x 1 / 256 x 2 thread blocks; 3 / 4 two adjacent nodes per thread
+ * (16-byte loads and stores) in 64 x 4 / 256 x 1 thread blocks.  The batched
+ * engine runs variants 3 and 4 as variant 0.
  * The choice is process-wide per precision (default 0 until jlb_autotune or
  * jlb_set_step_variant picks another).
  *
@@ -362,7 +364,7 @@ int jlb_time_step_kernel(const jlb_problem *prob, void *workspace, size_t worksp
  * JLB_TWO_STEP_VARIANTS + JLB_MULTI_STEP_VARIANTS entries are always enough).
  */
 #define JLB_STEP_VARIANTS 7
-#define JLB_FP64_STEP_VARIANTS 3
+#define JLB_FP64_STEP_VARIANTS 5
 #define JLB_TWO_STEP_VARIANTS 10
 #define JLB_FP64_TWO_STEP_VARIANTS 8
 int jlb_autotune(const jlb_problem *prob, void *workspace, size_t workspace_bytes, int32_t launches,

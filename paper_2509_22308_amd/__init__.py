@@ -250,7 +250,7 @@ def jlb_time_step_kernel(prob: jlb_problem, warmup: int, launches: int, workspac
 
 STEP_VARIANTS = {0: "direct 64x4", 1: "2-wide tile 64x4", 2: "4-wide tile 64x4", 3: "2-wide tile 256x1",
                  4: "4-wide tile 256x1", 5: "2-wide tile 256x2", 6: "4-wide tile 256x2"}
-FP64_STEP_VARIANTS = {0: "direct 64x4", 1: "direct 256x1", 2: "direct 256x2"}
+FP64_STEP_VARIANTS = {0: "direct 64x4", 1: "direct 256x1", 2: "direct 256x2", 3: "2-node 64x4", 4: "2-node 256x1"}
 FP64_TWO_STEP_VARIANTS = {0: "FP64 two-step H10 X4", 1: "FP64 two-step H12 X4", 2: "FP64 two-step H12 X4 W3",
                           3: "FP64 two-step H12 X4 LA2", 4: "FP64 two-step H6 X8", 5: "FP64 two-step H8 X8",
                           6: "FP64 two-step H8 X8 LA2", 7: "FP64 two-step H12 X8"}

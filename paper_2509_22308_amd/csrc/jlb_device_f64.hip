@@ -37,6 +37,178 @@ __global__ __launch_bounds__(CX *R) void k_step_f64(Lattice L, const double *__r
 }
 
 // ---------------------------------------------------------------------------
+// One step, two adjacent nodes per thread.  Every plane moves with one
+// 16-byte access per lane, half the memory instructions of one node per
+// thread.  Of the populations that cross between the two nodes of a lane,
+// each node takes its partner's directly; those that cross between lanes
+// come from the adjacent lane through DPP wave shifts (two 32-bit halves per
+// double), and the wavefront's end lanes load theirs.  Each node gathers its
+// pulls and edge rules as f64_node does and takes the same collision, so the
+// result equals the one-node kernels' bit for bit.  Whole wavefronts run to
+// the end (the shifts need every lane); lanes past the lattice load from a
+// clamped address and store nothing.
+// ---------------------------------------------------------------------------
+
+typedef double __attribute__((ext_vector_type(2))) Double2;
+
+__device__ __forceinline__ Double2 ld2(const double *p) { return *reinterpret_cast<const Double2 *>(p); }
+
+// Lane k receives lane k - 1's v (from_left) or lane k + 1's (from_right);
+// the end lane, which has no such neighbour in the wavefront, receives edge.
+__device__ __forceinline__ double shift64(double v, double edge, bool left)
+{
+    const long long b = __double_as_longlong(v), e = __double_as_longlong(edge);
+    const int blo = (int)(b & 0xffffffff), bhi = (int)(b >> 32);
+    const int elo = (int)(e & 0xffffffff), ehi = (int)(e >> 32);
+    int lo, hi;
+    if (left) {
+        lo = __builtin_amdgcn_update_dpp(elo, blo, 0x138, 0xf, 0xf, false);
+        hi = __builtin_amdgcn_update_dpp(ehi, bhi, 0x138, 0xf, 0xf, false);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(elo, blo, 0x130, 0xf, 0xf, false);
+        hi = __builtin_amdgcn_update_dpp(ehi, bhi, 0x130, 0xf, 0xf, false);
+    }
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+template <int CX, int R>
+__global__ __launch_bounds__(CX *R) void k_step_f64_pair(Lattice L, const double *__restrict__ src,
+                                                          double *__restrict__ dst, double *__restrict__ fields,
+                                                          double einc)
+{
+#pragma clang fp contract(off)
+    static_assert(CX % 64 == 0, "whole wavefronts along a row");
+    int tx, ty;
+    block_tile(L, tx, ty);
+    const int i = 2 * (tx * CX + (int)threadIdx.x);  // nodes i and i + 1
+    const int j = ty * R + (int)threadIdx.y;
+    const int lane = (int)threadIdx.x & 63;
+    const bool valid = i < L.nx && j <= L.ny;
+    const bool second = i + 1 < L.nx;  // node i + 1 is in the lattice
+    const int ic = min(i, (L.nx - 1) & ~1), jc = min(j, L.ny);
+    const size_t P = L.plane;
+    const size_t c = at(ic, jc, L.sf);
+    const double keep = 1.0 - OPEN_DELTA;
+
+    // populations 1, 6 (moving +x) and 2, 7 (moving -x) of both nodes: what
+    // the x-neighbours pull
+    const Double2 p1 = ld2(src + 1 * P + c), p6 = ld2(src + 6 * P + c);
+    const Double2 p2 = ld2(src + 2 * P + c), p7 = ld2(src + 7 * P + c);
+    // the wavefront's end lanes load the values from beyond it
+    double e1 = 0.0, e6 = 0.0, e2 = 0.0, e7 = 0.0;
+    if (lane == 0 && ic > 0) { e1 = src[1 * P + c - 1]; e6 = src[6 * P + c - 1]; }
+    if (lane == 63 && ic + 2 < L.nx) { e2 = src[2 * P + c + 2]; e7 = src[7 * P + c + 2]; }
+    const double l1 = shift64(p1.y, e1, true), l6 = shift64(p6.y, e6, true);    // node i - 1
+    const double r2 = shift64(p2.x, e2, false), r7 = shift64(p7.x, e7, false);  // node i + 2
+
+    const Double2 o0 = ld2(src + 0 * P + c), o5 = ld2(src + 5 * P + c), o8 = ld2(src + 8 * P + c);
+    double f[2][11];
+    double inv_eps[2] = {1.0, 1.0}, eps_rest[2] = {1.0 - 2.0 / 3.0, 1.0 - 2.0 / 3.0};
+    bool conductor[2] = {false, false};
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        f[v][0] = v ? o0.y : o0.x;
+        f[v][5] = v ? o5.y : o5.x;
+        f[v][8] = v ? o8.y : o8.x;
+    }
+    // +x populations come from the node on the left; node 0 takes the source
+    f[0][1] = l1; f[0][6] = l6;
+    f[1][1] = p1.x; f[1][6] = p6.x;
+    if (ic == 0) { f[0][1] = einc / 3.0; f[0][6] = 0.0; }
+    if (jc == L.ny) {
+        // incident-wave companion row: vacuum, uniform in y, nothing enters on the right
+        const Double2 q3 = ld2(src + 3 * P + c), q4 = ld2(src + 4 * P + c);
+        const Double2 q9 = ld2(src + 9 * P + c), q10 = ld2(src + 10 * P + c);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            f[v][3] = v ? q3.y : q3.x;
+            f[v][4] = v ? q4.y : q4.x;
+            f[v][9] = v ? q9.y : q9.x;
+            f[v][10] = v ? q10.y : q10.x;
+        }
+        f[0][2] = p2.y; f[0][7] = p7.y;
+        f[1][2] = r2; f[1][7] = r7;
+        if (ic == L.nx - 1) { f[0][2] = 0.0; f[0][7] = 0.0; }
+        if (ic + 1 == L.nx - 1) { f[1][2] = 0.0; f[1][7] = 0.0; }
+    } else {
+        const unsigned short mm = *reinterpret_cast<const unsigned short *>(L.mask + node(L, ic, jc));
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int mat = (mm >> (8 * v)) & 3;
+            conductor[v] = mat == MAT_PEC;
+            inv_eps[v] = mat_inv_eps(L, mat);
+            eps_rest[v] = mat_eps_rest(L, mat);
+        }
+        // -x populations come from the node on the right; the last node keeps its own
+        f[0][2] = p2.y; f[0][7] = p7.y;
+        f[1][2] = r2; f[1][7] = r7;
+        if (ic == L.nx - 1) { f[0][2] = keep * p2.x; f[0][7] = keep * p7.x; }
+        if (ic + 1 == L.nx - 1) { f[1][2] = keep * p2.y; f[1][7] = keep * p7.y; }
+        const size_t strip = at(ic, L.ny, L.sf);
+        // +y populations come from (i, j - 1)
+        if (jc == 0) {
+            const Double2 a3 = ld2(src + 3 * P + c), a9 = ld2(src + 9 * P + c);
+            const Double2 s3 = ld2(src + 3 * P + strip), s9 = ld2(src + 9 * P + strip);
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                f[v][3] = keep * (v ? a3.y : a3.x) + OPEN_DELTA * (v ? s3.y : s3.x);
+                f[v][9] = keep * (v ? a9.y : a9.x) + OPEN_DELTA * (v ? s9.y : s9.x);
+            }
+        } else {
+            const Double2 b3 = ld2(src + 3 * P + c - L.sf), b9 = ld2(src + 9 * P + c - L.sf);
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                f[v][3] = v ? b3.y : b3.x;
+                f[v][9] = v ? b9.y : b9.x;
+            }
+        }
+        // -y populations come from (i, j + 1)
+        if (jc == L.ny - 1) {
+            const Double2 a4 = ld2(src + 4 * P + c), a10 = ld2(src + 10 * P + c);
+            const Double2 s4 = ld2(src + 4 * P + strip), s10 = ld2(src + 10 * P + strip);
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                f[v][4] = keep * (v ? a4.y : a4.x) + OPEN_DELTA * (v ? s4.y : s4.x);
+                f[v][10] = keep * (v ? a10.y : a10.x) + OPEN_DELTA * (v ? s10.y : s10.x);
+            }
+        } else {
+            const Double2 t4 = ld2(src + 4 * P + c + L.sf), t10 = ld2(src + 10 * P + c + L.sf);
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                f[v][4] = v ? t4.y : t4.x;
+                f[v][10] = v ? t10.y : t10.x;
+            }
+        }
+    }
+    double out[2][11], ez[2], hx[2], hy[2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) f64_collide(L, f[v], inv_eps[v], eps_rest[v], conductor[v], out[v], ez[v], hx[v], hy[v]);
+    if (!valid) return;
+    if (second) {
+#pragma unroll
+        for (int k = 0; k < 11; ++k) {
+            Double2 w;
+            w.x = out[0][k];
+            w.y = out[1][k];
+            put(reinterpret_cast<Double2 *>(dst + k * P + c), w, L.stream_stores);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 11; ++k) put(&dst[k * P + c], out[0][k], L.stream_stores);
+    }
+    if (fields) {
+        const size_t cf = at(ic, jc, L.sfld);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            if (v == 1 && !second) break;
+            fields[0 * P + cf + v] = ez[v];
+            fields[1 * P + cf + v] = hx[v];
+            fields[2 * P + cf + v] = hy[v];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Two steps per launch.  A launch reads the state at n once and writes the
 // state at n + 2 once: the bytes of one step for two lattice updates.
 //
@@ -390,9 +562,13 @@ hipError_t launch_step_f64(const Lattice &L, const double *src, double *dst, dou
                            hipStream_t s, int variant)
 {
     auto grid = [&](int cx, int r) { return dim3((L.nx + cx - 1) / cx, (L.ny + 1 + r - 1) / r); };
+    // two nodes per thread: each block covers twice its width in columns
+    auto grid2 = [&](int cx, int r) { return dim3((L.nx + 2 * cx - 1) / (2 * cx), (L.ny + 1 + r - 1) / r); };
     switch (variant) {
     case F64_W256_R1: hipLaunchKernelGGL((k_step_f64<256, 1>), grid(256, 1), dim3(256, 1), 0, s, L, src, dst, fields, einc); break;
     case F64_W256_R2: hipLaunchKernelGGL((k_step_f64<256, 2>), grid(256, 2), dim3(256, 2), 0, s, L, src, dst, fields, einc); break;
+    case F64_PAIR_R4: hipLaunchKernelGGL((k_step_f64_pair<BX, 4>), grid2(BX, 4), dim3(BX, 4), 0, s, L, src, dst, fields, einc); break;
+    case F64_PAIR_W256_R1: hipLaunchKernelGGL((k_step_f64_pair<256, 1>), grid2(256, 1), dim3(256, 1), 0, s, L, src, dst, fields, einc); break;
     default: hipLaunchKernelGGL((k_step_f64<BX, 4>), grid(BX, 4), dim3(BX, 4), 0, s, L, src, dst, fields, einc); break;
     }
     return hipGetLastError();

@@ -83,8 +83,10 @@ enum NeqVariant {
     NEQ_TILE_V4_W256_R2 = 6,
     NEQ_VARIANTS = 7
 };
-// FP64 step variants: one node per thread in 64 x 4, 256 x 1 or 256 x 2 thread blocks.
-enum F64Variant { F64_R4 = 0, F64_W256_R1 = 1, F64_W256_R2 = 2, F64_VARIANTS = 3 };
+// FP64 step variants: one node per thread in 64 x 4, 256 x 1 or 256 x 2 thread
+// blocks; two adjacent nodes per thread (16-byte accesses) in 64 x 4 or
+// 256 x 1 thread blocks.
+enum F64Variant { F64_R4 = 0, F64_W256_R1 = 1, F64_W256_R2 = 2, F64_PAIR_R4 = 3, F64_PAIR_W256_R1 = 4, F64_VARIANTS = 5 };
 // FP64 two steps per launch: state n in src -> state n + 2 in dst (src and
 // dst must differ), bit for bit equal to two launch_step_f64 launches.
 // fields1 / fields2 (both null, or two distinct field buffers): the field

@@ -185,27 +185,39 @@ def test_config2_full_size_properties(jlb):
 def test_step_kernel_variants_give_identical_results(jlb, precision):
     """Every thread-to-node mapping the autotuner may pick computes the same
     arithmetic: fields and forces agree bit for bit (ragged sizes, conductor
-    links, all four edges)."""
+    links, all four edges).  Two- and multi-step launches are switched off,
+    so every step runs on the variant under test."""
     prec = jlb.PRECISIONS[precision]
     before = jlb.jlb_get_step_variant(prec)
+    two0 = jlb.jlb_get_two_step_variant(prec)
+    multi0 = jlb.jlb_get_multi_step_variant(prec) if precision != "fp64" else -1
     cases = [W.problem(nx=203, ny=150, radius=20.0, kind="metallo_dielectric_janus", eps1=3.0, phi0_deg=110.0,
                        wavelength=40.0, steps=700, avg_periods=1),
              W.problem(nx=130, ny=171, radius=16.0, kind="dielectric_janus", eps1=2.0, eps2=6.0, phi0_deg=45.0,
                        wavelength=40.0, steps=650, avg_periods=1)]
     try:
+        jlb.jlb_set_two_step_variant(prec, -1)
+        if precision != "fp64":
+            jlb.jlb_set_multi_step_variant(prec, -1)
         for p in cases:
             outs = []
             names = jlb.FP64_STEP_VARIANTS if precision == "fp64" else jlb.STEP_VARIANTS
             for v in range(len(names)):
+                _print_case(f"{precision} step variant {v}", p)
                 jlb.jlb_set_step_variant(prec, v)
-                outs.append(jlb.solve(p, precision, fields=True))
-            for o in outs[1:]:
-                for q in ("fx", "fy", "tz"):
-                    assert o[q] == outs[0][q]
+                o = jlb.solve(p, precision, fields=True)
+                assert (o["main_kind"], o["main_variant"]) == (1, v) and o["state_passes"] == p["steps"], v
+                outs.append(o)
+            for v, o in enumerate(outs[1:], 1):
+                for q in ("fx", "fy", "tz", "energy_final"):
+                    assert o[q] == outs[0][q], (v, q)
                 for f in ("ez", "hx", "hy"):
-                    assert np.array_equal(o[f], outs[0][f])
+                    assert np.array_equal(o[f], outs[0][f]), (v, f, np.abs(o[f] - outs[0][f]).max())
     finally:
         jlb.jlb_set_step_variant(prec, before)
+        jlb.jlb_set_two_step_variant(prec, two0)
+        if precision != "fp64":
+            jlb.jlb_set_multi_step_variant(prec, multi0)
 
 
 @pytest.mark.parametrize("polarization", ["tm", "te"])
