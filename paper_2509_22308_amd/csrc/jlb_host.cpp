@@ -280,6 +280,17 @@ hipStream_t own_stream()
 // One solve on prepared device memory
 // ---------------------------------------------------------------------------
 
+// Largest state pair (both buffers) a single solve runs cache-resident:
+// ordinary stores and the XCD-contiguous work order; larger ones stream
+// their stores past the caches in plain order.  FP32 / BF16 sweeps stay
+// faster resident up to 192 MiB (7-15 % at 174-190 MiB, measured against
+// streaming); the FP64 two-step sweep already ran 2.5 % slower resident at
+// 185 MiB (1024^2), so FP64 switches at 160 MiB.
+size_t resident_limit(int precision)
+{
+    return precision == JLB_FP64 ? CACHE_RESIDENT_BYTES : (size_t)192 << 20;
+}
+
 Lattice lattice_of(const Plan &q, const uint8_t *dmask)
 {
     Lattice L{};
@@ -314,7 +325,7 @@ Lattice lattice_of(const Plan &q, const uint8_t *dmask)
     L.inv_eps_f[MAT_PEC] = 0.0f;
     L.eps_rest_f[MAT_PEC] = 0.0f;
     L.te = q.prob.polarization == JLB_TE ? 1 : 0;
-    L.stream_stores = 2 * q.state_bytes > CACHE_RESIDENT_BYTES ? 1 : 0;
+    L.stream_stores = 2 * q.state_bytes > resident_limit(q.prob.precision) ? 1 : 0;
     return L;
 }
 

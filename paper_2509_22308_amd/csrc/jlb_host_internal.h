@@ -47,6 +47,9 @@ void build_mask(const Plan &q, std::vector<uint8_t> &mask);
 void build_contour(const Plan &q, ContourHost &c);
 double incident(const Plan &q, int64_t n);
 hipStream_t own_stream();
+// Largest state pair (bytes, both buffers) a single solve of this precision
+// keeps cache-resident.
+size_t resident_limit(int precision);
 Lattice lattice_of(const Plan &q, const uint8_t *dmask);
 ContourDev contour_of(const Plan &q, char *ws);
 int upload_setup(const Plan &q, char *ws, hipStream_t s);

@@ -9,9 +9,10 @@ within 1e-3 / 1e-2 (plus absolute floors) and every field's error over the
 field scale within the same targets, each printed.  FP32 runs in the launch
 configuration the benchmark times (four-step H10 X4 kernels).
 
-The streaming-store path: a state above the Infinity-Cache threshold (160 MiB
-for the two buffers) is written with non-temporal stores and the multi-step
-sweeps run row-major; a 1792^2 lattice takes that path in every precision.
+The streaming-store path: a single solve whose two state buffers exceed
+the cache-resident limit (160 MiB in FP64, 192 MiB in FP32 / BF16) writes
+its state with non-temporal stores and runs its sweeps row-major; a 1920^2
+lattice takes that path in every precision.
 
 A config-3 point (metallo-dielectric Janus eps 4, phi0 = 30 deg, a = 48,
 768^2, 52 periods) gives the third row of the reduced-precision error table,
@@ -25,7 +26,8 @@ from precision import check
 
 pytestmark = pytest.mark.gpu
 
-CACHE_RESIDENT_BYTES = 160 << 20
+# the library's cache-resident limits for a single solve's two state buffers
+RESIDENT_LIMIT = {"fp64": 160 << 20, "fp32": 192 << 20, "bf16": 192 << 20}
 
 
 @pytest.fixture(scope="module")
@@ -80,22 +82,22 @@ def test_config2_itself_matches_the_oracle(jlb, oracle, precision):
     if precision != "fp64":
         assert (g["main_kind"], g["main_variant"]) == (3, 0)
     if precision == "fp64":
-        assert 2 * _state_bytes(1024, 1024, "fp64") > CACHE_RESIDENT_BYTES  # config 2 FP64 streams its stores
+        assert 2 * _state_bytes(1024, 1024, "fp64") > RESIDENT_LIMIT["fp64"]  # config 2 FP64 streams its stores
     check("config2", precision, g, ref)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 def test_streaming_store_path_matches_the_oracle(jlb, oracle, precision):
-    """1792^2 with the body near the left edge, so the wave reaches it within
+    """1920^2 with the body near the left edge, so the wave reaches it within
     eight periods: MDJC eps 4, phi0 = 30 deg, a = 48, lambda = 48."""
-    p = W.problem(nx=1792, ny=1792, radius=48.0, kind="metallo_dielectric_janus", eps1=4.0, phi0_deg=30.0,
-                  wavelength=48.0, steps=8 * 144, avg_periods=2, cx=150.0, cy=895.5)
-    assert 2 * _state_bytes(p["nx"], p["ny"], precision) > CACHE_RESIDENT_BYTES
+    p = W.problem(nx=1920, ny=1920, radius=48.0, kind="metallo_dielectric_janus", eps1=4.0, phi0_deg=30.0,
+                  wavelength=48.0, steps=8 * 144, avg_periods=2, cx=150.0, cy=959.5)
+    assert 2 * _state_bytes(p["nx"], p["ny"], precision) > RESIDENT_LIMIT[precision]
     print(f"[case] streaming stores {precision}", flush=True)
-    ref = _oracle_run(oracle, "stream1792", p)
+    ref = _oracle_run(oracle, "stream1920", p)
     g = jlb.solve(p, precision, fields=True)
     assert g["graph_used"] == 1
-    check("stream1792", precision, g, ref)
+    check("stream1920", precision, g, ref)
     # the wave has reached the body and the top and bottom edges
     assert np.abs(ref["ez"][:, 100:200]).max() > 0.5 and np.abs(ref["ez"][[0, -1], :300]).max() > 0.5
 
@@ -110,7 +112,7 @@ def test_largest_serving_request_matches_the_oracle(jlb, oracle, precision):
     a = 256
     p = W.problem(nx=8 * a, ny=8 * a, radius=float(a), kind="dielectric_janus", eps1=9.0, eps2=2.0,
                   phi0_deg=137.0, wavelength=2.0 * a, steps=W.steps_for(2.0 * a, 3), avg_periods=1)
-    assert 2 * _state_bytes(p["nx"], p["ny"], precision) > CACHE_RESIDENT_BYTES
+    assert 2 * _state_bytes(p["nx"], p["ny"], precision) > RESIDENT_LIMIT[precision]
     print(f"[case] largest serving request 2048^2 {precision}", flush=True)
     ref = _oracle_run(oracle, "serve2048", p)
     g = jlb.solve(p, precision, fields=True)
