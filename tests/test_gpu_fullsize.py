@@ -16,7 +16,8 @@ lattice takes that path in every precision.
 
 A config-3 point (metallo-dielectric Janus eps 4, phi0 = 30 deg, a = 48,
 768^2, 52 periods) gives the third row of the reduced-precision error table,
-and config 5's largest request (2048^2, a = 256) the largest grid.
+config 5's largest request (2048^2, a = 256) the largest grid, and config 2
+in TE^z the other polarisation at full size.
 """
 import numpy as np
 import pytest
@@ -84,6 +85,18 @@ def test_config2_itself_matches_the_oracle(jlb, oracle, precision):
     if precision == "fp64":
         assert 2 * _state_bytes(1024, 1024, "fp64") > RESIDENT_LIMIT["fp64"]  # config 2 FP64 streams its stores
     check("config2", precision, g, ref)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_config2_te_matches_the_oracle(jlb, oracle, precision):
+    """Config 2 in TE^z (Hz, Ex, Ey on the same lattice and update), the
+    whole 20000-step solve against the oracle's TE^z form, with the TM^z
+    bars.  FP32 / BF16 run the four-step kernel's TE^z instances."""
+    p = dict(W.config2(), polarization="te")
+    print(f"[case] config2 TE full size {precision}", flush=True)
+    ref = _oracle_run(oracle, "config2-te", p)
+    g = jlb.solve(p, precision, fields=True)
+    check("config2-te", precision, g, ref)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
